@@ -1,0 +1,229 @@
+"""Benchmark of the tiled-sCOLA hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+
+A benchmark "step" is one batch: the whole KDK evolution (initial deposit and Poisson solve,
+then n_steps fused particle steps each followed by the Poisson solve of the next force) of
+every sCOLA box of the workload, from inputs already resident in HBM (the set-up
+Psi1/Psi2/Phi_BC^0 computed once before timing).  value = box particles x KDK steps per
+second over the K timed batches.  One JSON line is printed.
+
+Workloads (particles per side, box side, tiling):
+  c2  500 Mpc/h, 128^3 particles, 4^3 tiles of 32^3 + 16 buffer (64^3 boxes), 20 steps, FP32
+  c1  200 Mpc/h, 64^3 particles, 2^3 tiles of 32^3 + 8 buffer (48^3 boxes), 10 steps, FP64
+      per-tile (the plain path)
+Roofline: the dominant kernel is the fused particle step; its algorithmic traffic is 96 B
+per particle (x_res and p_res read and written in FP32, Psi1 and Psi2 read in FP64), timed
+with HIP events around single launches on the stream it runs on.
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def build_sim(S, wl, precision=None, schedule=None):
+    if wl.mixed:
+        tiles = [((x, y, z), c, b) for x, y, z, c, b in wl.mixed]
+    else:
+        tiles = S.uniform_tiling(wl.Np, wl.tiles_per_side, wl.buffer)
+    prec = precision or wl.precision
+    sch = schedule or ("per_tile" if prec == "fp64" else "batched")
+    return S.Simulation(wl.L, wl.Np, tiles, wl.n_steps, a_i=wl.a_i, a_f=wl.a_f,
+                        precision=prec, schedule=sch)
+
+
+def time_evolve(torch, sim, steps, warmup):
+    for _ in range(warmup):
+        sim.evolve()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        sim.evolve()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(stop) / steps, wall
+
+
+def time_kernel(torch, fn, reps):
+    """Average duration of one launch, HIP events around each call on the current stream."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    ts = sorted(a.elapsed_time(b) for a, b in evs)
+    return sum(ts) / len(ts), ts[len(ts) // 2]
+
+
+def cpu_baseline(wl, budget_s=20.0):
+    """The FP64 oracle on a bounded sample: one box of the workload, as many KDK steps of
+    the workload's schedule as fit the budget, single thread."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:          # pragma: no cover
+        threadpool_limits = None
+    import numpy as np
+
+    import synthetic
+    from oracle.cosmology import Cosmology, cola_schedule
+    from oracle.run import setup_full_box
+    from oracle.scola import box_force, lattice_positions
+    from oracle.tiling import Tile, boundary_potential0, extract_box_field
+
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    try:
+        c = Cosmology()
+        Np = wl.Np
+        phi1, phi2, psi1, psi2 = setup_full_box(synthetic.white_noise(Np, 42), wl.L, c, wl.a_i)
+        n = Np // wl.tiles_per_side
+        tile = Tile((0, 0, 0), n, wl.buffer)
+        M = tile.M
+        s1 = extract_box_field(psi1, tile).reshape(3, -1)
+        s2 = extract_box_field(psi2, tile).reshape(3, -1)
+        bc0 = boundary_potential0(phi1, tile)
+        steps, _ = cola_schedule(c, wl.a_i, wl.a_f, wl.n_steps)
+        q = lattice_positions(M).reshape(3, -1)
+        x_res = np.zeros_like(q)
+        p_res = np.zeros_like(q)
+        u = q - steps[0]["D1"] * s1 + steps[0]["D2"] * s2
+        t0 = time.perf_counter()
+        g, _, _ = box_force(u, M, steps[0]["D1"] * bc0)
+        done = 0
+        for st in steps:
+            p_res += st["beta"] * (g - st["D1"] * s1 + (st["D2"] - st["D1"] ** 2) * s2)
+            x_res += st["alpha"] * p_res
+            u = q - st["D1_next"] * s1 + st["D2_next"] * s2 + x_res
+            g, _, _ = box_force(u, M, st["D1_next"] * bc0)
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
+    finally:
+        if ctx is not None:
+            ctx.unregister() if hasattr(ctx, "unregister") else None
+    return dict(value=M ** 3 * done / dt, unit="particle-steps/s", cores=1, kind="oracle",
+                sample=f"one {M}^3 box of {wl.name}, {done} KDK steps (force evaluation "
+                       f"included), FP64 NumPy, 1 thread, {platform.processor() or 'host CPU'}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the boxes are independent and this build has "
+              "no multi-GPU path (see the design notes for how it would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2003_04925_amd as S
+    import synthetic
+    torch.cuda.set_device(0)
+    wl = synthetic.WORKLOADS[args.workload]
+    sim = build_sim(S, wl)
+    info = sim.info()
+    P = info["n_particles"]
+    w = torch.from_numpy(synthetic.white_noise(wl.Np, 42)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.setup(w)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    ms, wall = time_evolve(torch, sim, args.steps, args.warmup)
+    value = P * wl.n_steps / (ms * 1e-3)
+
+    # end to end: set-up + evolution + outputs (positions and density)
+    pos = torch.empty((3, wl.Np, wl.Np, wl.Np), dtype=sim.real, device="cuda")
+    dens = torch.empty((wl.Np,) * 3, dtype=sim.real, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.setup(w)
+    sim.evolve()
+    sim.output(pos=pos, density=dens)
+    torch.cuda.synchronize()
+    e2e_s = time.perf_counter() - t0
+
+    # dominant kernel: the fused particle step, single launches timed with events
+    tab = sim.step_table()
+    k = wl.n_steps // 2
+    row = tab[k]
+    sim.setup(w)
+    sim.op_deposit(row[3], row[4])
+    sim.op_poisson(row[3])
+    step_avg, step_med = time_kernel(
+        torch, lambda: sim.op_step(row[1], 0.0, row[3], row[4], row[3], row[4], True), 20)
+    pois_avg, _ = time_kernel(torch, lambda: sim.op_poisson(row[3]), 20)
+    algo_bytes = 96 * P if sim.precision == "fp32" else 144 * P
+    achieved = algo_bytes / (step_avg * 1e-3) / 1e9
+
+    result = {
+        "metric": "particle-steps/s",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if sim.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: L={wl.L:g} Mpc/h, {wl.Np}^3 particles, "
+                               f"{info['n_tiles']} boxes, {wl.n_steps} KDK steps, "
+                               f"{sim.precision} {('per-tile' if sim.precision == 'fp64' else 'batched')}",
+                   "box_particles": P, "n_tiles": info["n_tiles"],
+                   "oversimulation_r": info["r"], "n_steps": wl.n_steps},
+        "useful_particle_steps_per_s": wl.Np ** 3 * wl.n_steps / (ms * 1e-3),
+        "end_to_end_s": e2e_s,
+        "setup_s_first_call": setup_s,
+        "kernels_ms": {"particle_step": step_avg, "particle_step_median": step_med,
+                       "poisson_3pass": pois_avg},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_particles<float,1> (fused interp+kick+drift+deposit)",
+                     "algorithmic_bytes_per_launch": algo_bytes},
+    }
+    if not args.no_fp64 and args.workload == "c2":
+        wl1 = synthetic.WORKLOADS["c1"]
+        sim64 = build_sim(S, wl1)
+        w1 = torch.from_numpy(synthetic.white_noise(wl1.Np, 42)).cuda()
+        sim64.setup(w1)
+        ms64, _ = time_evolve(torch, sim64, 3, 1)
+        result["fp64_per_tile"] = {"workload": "c1: 64^3 particles, 8 boxes of 48^3, 10 "
+                                               "steps, FP64 per-tile schedule",
+                                   "value": sim64.info()["n_particles"] * wl1.n_steps /
+                                   (ms64 * 1e-3), "unit": "particle-steps/s"}
+        sim32 = build_sim(S, wl1, precision="fp32", schedule="batched")
+        sim32.setup(w1)
+        ms32, _ = time_evolve(torch, sim32, 3, 1)
+        result["fp32_batched_same_workload"] = {
+            "workload": "c1 in FP32 batched", "value": sim32.info()["n_particles"] *
+            wl1.n_steps / (ms32 * 1e-3), "speedup_vs_fp64_per_tile": ms64 / ms32}
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

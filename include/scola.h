@@ -1,0 +1,218 @@
+/*
+ * scola.h -- C ABI of the MI355X tiled-sCOLA engine (libscola.so).
+ *
+ * Method: Leclercq et al., "Perfectly parallel cosmological simulations using spatial
+ * comoving Lagrangian acceleration" (arXiv:2003.04925).  A periodic cube of side L holding
+ * N_p^3 particles on a Lagrangian lattice is split into cubic tiles (Sec. 3.2, B.1); every
+ * tile plus a buffer of particles forms an sCOLA box that is evolved on its own through
+ * COLA kick-drift steps (Sec. 3.4, App. A-B) with a Dirichlet Poisson solver by DST-I whose
+ * boundary potential is the linearly evolving full-box LPT potential (Sec. 3.4.2 eq. LEP,
+ * App. C).  The core particles' final positions and momenta and their CiC density are the
+ * outputs (Sec. 3.2, B.2).
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns scola_status (0 = SCOLA_OK, < 0 = error).  On error nothing has been
+ *    launched unless stated otherwise, and scola_last_error() holds a message (per thread).
+ *  - Pointers named d_* are device pointers (HIP, the device current when the plan was
+ *    created).  The caller owns them and every workspace; the plan owns its host tables
+ *    and a few small device tables (tile table, block maps, twiddles, eigenvalues).
+ *  - Work is enqueued on the given stream and is asynchronous; the call returns once it is
+ *    enqueued.  Calls on one plan must not overlap in time (the plan holds the step state).
+ *  - 3-D arrays are C order [x][y][z] (z fastest).  Component arrays are [3][n].
+ *  - Lengths inside the workspace are in lattice cells (Delta q = L / N_p); outputs are in
+ *    Mpc/h.  Time is the scale factor a; H0 = 1.
+ *  - Box layout: a box of M = core_n + 2 buffer particles per side holds its particles at
+ *    local positions i + 1/2; PM nodes sit at integer local positions, the Dirichlet problem
+ *    has M - 1 unknowns per side and the potential is padded to [-1, M+1] (FDA order 2,
+ *    N_ghost = 1).  M must be a multiple of 16 in [16, 128].
+ */
+#ifndef SCOLA_H
+#define SCOLA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SCOLA_OK = 0,
+  SCOLA_EINVAL = -1,       /* an argument is out of range or inconsistent */
+  SCOLA_ENOMEM = -2,       /* host or plan-owned device allocation failed */
+  SCOLA_EDEVICE = -3,      /* a HIP call failed (launch, copy, event) */
+  SCOLA_ESTATE = -4,       /* call order violated (e.g. evolve before setup) */
+  SCOLA_EUNSUPPORTED = -5  /* valid request outside what this build implements */
+} scola_status;
+
+enum { SCOLA_FP32 = 0, SCOLA_FP64 = 1 };           /* particle/mesh arithmetic */
+enum { SCOLA_BATCHED = 0, SCOLA_PER_TILE = 1 };    /* all tiles per launch, or one tile */
+
+/* Flat LambdaCDM (Sec. 4: Planck 2015 values; Omega_L = 1 - Omega_m). */
+typedef struct {
+  double Omega_m, Omega_b, h, n_s, sigma8, T_cmb;
+} scola_cosmology;
+
+/* One tile (Sec. 3.2, B.1): core particles [core_lo, core_lo + core_n) per axis of the
+ * global lattice (indices, wrapped mod N_p), surrounded by `buffer` particles per side. */
+typedef struct {
+  int32_t core_lo[3];
+  int32_t core_n;
+  int32_t buffer;
+} scola_tile;
+
+/* Run parameters (Sec. 3, Sec. 4). */
+typedef struct {
+  double L;                /* box side, Mpc/h, > 0 */
+  int32_t Np;              /* particles per side; the LPT grid has N = N_p nodes; power of
+                              two in [8, 1024] */
+  int32_t N_out;           /* output density grid per side (0 -> N_p) */
+  int32_t n_steps;         /* KDK steps, linearly spaced in a (Sec. 4), >= 1 */
+  double a_i, a_f;         /* initial / final scale factor, 0 < a_i < a_f */
+  int32_t precision;       /* SCOLA_FP32 or SCOLA_FP64 */
+  int32_t schedule;        /* SCOLA_BATCHED or SCOLA_PER_TILE */
+  int32_t want_momenta;    /* nonzero: evaluate the last force and apply the final half
+                              kick and L+ (App. B) so momenta are available */
+} scola_config;
+
+typedef struct scola_plan scola_plan;
+
+/* Byte offsets of the arrays held in the caller's workspace (for inspection and for
+ * operator-level calls).  P = total box particles, G = sum (M-1)^3, H = sum (M+3)^3,
+ * N = N_p, R = real type of the plan (float or double). */
+typedef struct {
+  size_t psi1, psi2;       /* double [3][P]: Psi1 = grad phi1, Psi2 = grad phi2 (cells) */
+  size_t x_res, p_res;     /* R [3][P]: COLA residual position and momentum (cells) */
+  size_t rho;              /* int64 [G]: fixed-point CiC mass, SCOLA_FIXED_ONE per particle */
+  size_t work;             /* R [G]: sine-space scratch of the Poisson solve */
+  size_t phi;              /* R [H]: potential on the padded node grid [-1, M+1]^3 */
+  size_t bc0;              /* double [H]: Phi_BC^0 (LEP boundary potential at D1 = 1) */
+  size_t dropped;          /* int64 [n_tiles]: fixed-point mass dropped by the deposits since
+                              the last reset (scola_evolve and scola_op_deposit reset it) */
+  size_t phi1, phi2;       /* double [N^3]: Lagrangian potentials (Sec. 3.1, A.2) */
+  size_t cbuf;             /* double2 [N^3]: FFT scratch */
+  size_t outgrid;          /* int64 [N_out^3]: fixed-point output density */
+  size_t total;            /* workspace size in bytes */
+  int64_t n_particles;     /* P */
+  int64_t n_nodes;         /* G */
+  int64_t n_padded;        /* H */
+} scola_layout;
+
+#define SCOLA_FIXED_BITS 40  /* CiC weights are accumulated as round(w * 2^40) in int64 */
+
+/* Fill out[0 .. tiles_per_side^3) with the uniform tiling of Sec. 3.2 (B.1): cores of
+ * N_p / tiles_per_side particles, order x-major.  Np must be a multiple of tiles_per_side.
+ * capacity = number of elements of out. */
+scola_status scola_uniform_tiling(int32_t Np, int32_t tiles_per_side, int32_t buffer,
+                                  scola_tile* out, int32_t capacity);
+
+/* Validate the configuration and build a plan: host FP64 scalars (growth factors D1, D2
+ * of App. A eqs. VD1/VD2 normalised to D1(a_i) = 1; modified time factors of App. B with
+ * n_LPT = -2.5; sigma_8 normalisation of the Eisenstein-Hu no-wiggle spectrum) and the
+ * device tile table.  The tiles must cover the lattice exactly once.  *out receives the
+ * plan (NULL on error).  The current HIP device becomes the plan's device. */
+scola_status scola_plan_create(const scola_config* cfg, const scola_cosmology* cosmo,
+                               const scola_tile* tiles, int32_t n_tiles, scola_plan** out);
+
+scola_status scola_plan_destroy(scola_plan* plan);
+
+/* Bytes of device workspace the caller must provide (256-byte aligned base). */
+scola_status scola_workspace_size(const scola_plan* plan, size_t* bytes);
+scola_status scola_workspace_layout(const scola_plan* plan, scola_layout* out);
+
+/* The whole run: scola_setup, scola_evolve, scola_output.  tile_subset (host array of
+ * n_subset tile indices, or NULL for all) restricts the evolution and outputs to those
+ * tiles (Sec. 5.1, node failures: any tile can be recomputed alone, with bitwise the same
+ * result as in the full run); other tiles' output entries are left untouched and the
+ * density is not produced (d_density must then be NULL).
+ * d_white_noise: double [N_p^3] unit white noise (Sec. 3.1, A.1).
+ * d_pos: R [3][N_p^3] final positions in [0, L) Mpc/h at the global lattice index.
+ * d_mom: R [3][N_p^3] final momenta p = dx/da / drift_prefactor (Mpc/h, H0 = 1), or NULL;
+ *        requires cfg.want_momenta.
+ * d_density: R [N_out^3] CiC density contrast of the core particles (Sec. 4.1), or NULL. */
+scola_status scola_forward(scola_plan* plan, const double* d_white_noise, void* d_pos,
+                           void* d_mom, void* d_density, const int32_t* tile_subset,
+                           int32_t n_subset, void* d_workspace, hipStream_t stream);
+
+/* Steps A.1-A.2 and C.1-C.3 (Sec. 3.1, 3.3) in FP64: white noise -> delta_i via the
+ * Eisenstein-Hu spectrum (convolution approach), phi1 and phi2 with the FDA-2 kernel,
+ * Psi1 and Psi2 for every box particle and Phi_BC^0 on every box's padded shell.  Also
+ * resets x_res = p_res = 0 (operator L-, App. B). */
+scola_status scola_setup(scola_plan* plan, const double* d_white_noise, void* d_workspace,
+                         hipStream_t stream);
+
+/* Step D (Sec. 3.4): the KDK operator E~ of App. B for every tile of tile_subset (NULL =
+ * all), starting with L- (x_res = p_res = 0 at a_i), so it can be repeated on the state
+ * left by scola_setup.  With cfg.want_momenta the final half kick and L+ are applied and
+ * p_res then holds the full momentum p. */
+scola_status scola_evolve(scola_plan* plan, const int32_t* tile_subset, int32_t n_subset,
+                          void* d_workspace, hipStream_t stream);
+
+/* Step B.2 (Sec. 3.2): core particles' positions/momenta to global lattice order, and the
+ * periodic CiC density of the core particles on N_out^3 nodes (all tiles must have been
+ * evolved for the density).  Any output pointer may be NULL. */
+scola_status scola_output(scola_plan* plan, void* d_pos, void* d_mom, void* d_density,
+                          const int32_t* tile_subset, int32_t n_subset,
+                          void* d_workspace, hipStream_t stream);
+
+/* Operator-level entry points on the workspace state (used by the parity tests; the
+ * forward pass is built from the same kernels).
+ *
+ * scola_op_deposit: B^sCOLA (Sec. 3.4.1) -- clears rho and deposits every box particle at
+ *   u = q - D1 Psi1 + D2 Psi2 + x_res onto interior nodes [1, M-1]^3; mass that would land
+ *   elsewhere is dropped and counted in `dropped`.
+ * scola_op_poisson: App. C -- delta = rho / 2^40 - 1, delta' = delta - Delta Phi_BCs with
+ *   Phi_BCs = D1_bc Phi_BC^0, forward DST-I, division by the FDA-2 eigenvalues, inverse
+ *   DST-I; writes phi on [-1, M+1]^3 with the shell set to D1_bc Phi_BC^0 (Sec. 3.4.2).
+ *   rho is left zeroed for the next deposit.
+ * scola_op_step: one fused kick-drift (App. B eqs. K_COLA, D_COLA with the sCOLA kick of
+ *   App. A eq. kick-scola): gradient of phi and CiC interpolation at
+ *   u = q - D1 Psi1 + D2 Psi2 + x_res, p_res += beta (g - D1 Psi1 + (D2 - D1^2) Psi2),
+ *   x_res += alpha p_res, then (if deposit) deposit at u' = q - D1n Psi1 + D2n Psi2 +
+ *   x_res into rho (which must be zero, as scola_op_poisson leaves it).
+ * scola_op_final_kick: the last half kick (same as the kick above) followed by L+:
+ *   p_res <- p_res + c1 Psi1 + c2 Psi2. */
+scola_status scola_op_deposit(scola_plan* plan, double D1, double D2, void* d_workspace,
+                              hipStream_t stream);
+scola_status scola_op_poisson(scola_plan* plan, double D1_bc, void* d_workspace,
+                              hipStream_t stream);
+scola_status scola_op_step(scola_plan* plan, double beta, double alpha, double D1, double D2,
+                           double D1n, double D2n, int32_t deposit, void* d_workspace,
+                           hipStream_t stream);
+scola_status scola_op_final_kick(scola_plan* plan, double beta, double D1, double D2,
+                                 double c1, double c2, void* d_workspace, hipStream_t stream);
+
+/* Host FP64 scalar tables of the plan.
+ * scola_step_table: n_steps rows of 8 doubles
+ *   {a_D, beta, alpha, D1(a_D), D2(a_D), D1(a_next), D2(a_next), a_next}
+ *   (App. B: step k kicks from t_{k-1/2} (t_0 for k = 0) to t_{k+1/2} with the force at
+ *   t_k, then drifts from t_k to t_{k+1}); then one row for the final half kick
+ *   {a_f, beta, D1, D2, c1, c2, 0, 0} with c1, c2 the L+ coefficients.
+ *   rows_capacity >= n_steps + 1.
+ * scola_power_spectrum: P_lin(k, a = 1) in (Mpc/h)^3 at the n given k (h/Mpc), host
+ *   arrays, as used by scola_setup (before the growth scaling to a_i). */
+scola_status scola_step_table(const scola_plan* plan, double* rows, int32_t rows_capacity);
+scola_status scola_power_spectrum(const scola_plan* plan, const double* k, double* out,
+                                  int32_t n);
+
+/* Host-only versions of the two tables above, without a plan or a device (same numbers
+ * as the plan computes): rows as in scola_step_table for cfg->n_steps steps; P_lin(k, 1). */
+scola_status scola_schedule_table(const scola_config* cfg, const scola_cosmology* cosmo,
+                                  double* rows, int32_t rows_capacity);
+scola_status scola_linear_power(const scola_cosmology* cosmo, const double* k, double* out,
+                                int32_t n);
+
+/* Diagnostics of the plan: number of tiles, total box particles, r and p (Sec. 3.2). */
+scola_status scola_plan_info(const scola_plan* plan, int32_t* n_tiles, int64_t* n_particles,
+                             double* oversimulation_r, double* parallel_p);
+
+const char* scola_status_string(scola_status s);
+const char* scola_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCOLA_H */

@@ -1,0 +1,262 @@
+"""MI355X tiled-sCOLA engine (arXiv:2003.04925): Python front end of libscola.so.
+
+The simulation runs in hand-written HIP kernels behind the C ABI of include/scola.h; this
+package only allocates device memory with torch, marshals arguments and exposes the
+results as torch tensors on the GPU.  There is no CPU path.
+"""
+import ctypes
+from dataclasses import dataclass
+
+from . import _lib
+from ._lib import (SCOLA_BATCHED, SCOLA_FP32, SCOLA_FP64, SCOLA_PER_TILE, FIXED_BITS,
+                   ScolaError)
+
+__all__ = ["Simulation", "CosmologyParams", "uniform_tiling", "particle_order", "schedule_table",
+           "linear_power", "ScolaError", "SCOLA_FP32", "SCOLA_FP64", "SCOLA_BATCHED",
+           "SCOLA_PER_TILE", "FIXED_BITS"]
+
+
+@dataclass
+class CosmologyParams:
+    """Flat LambdaCDM; defaults: Omega_m and sigma_8 of the benchmark workloads, the other
+    values of the paper's Planck 2015 set (Sec. 4)."""
+    Omega_m: float = 0.31
+    Omega_b: float = 0.0486
+    h: float = 0.6774
+    n_s: float = 0.9667
+    sigma8: float = 0.81
+    T_cmb: float = 2.7255
+
+    def c(self):
+        return _lib.Cosmology(self.Omega_m, self.Omega_b, self.h, self.n_s, self.sigma8,
+                              self.T_cmb)
+
+
+def particle_order(M):
+    """Storage slot (inside a box's particle range) of every lattice site, sites flattened
+    in lattice order [i][j][k].  The library keeps a box's particles in 4 x 8 x 8 bricks
+    (one thread block each); this is only the index map, for inspecting the workspace."""
+    import numpy as np
+    i, j, k = np.meshgrid(np.arange(M), np.arange(M), np.arange(M), indexing="ij")
+    nb = M // 8
+    brick = ((i // 4) * nb + j // 8) * nb + k // 8
+    w = ((i % 4) * 8 + j % 8) * 8 + k % 8
+    return (brick * 256 + w).ravel()
+
+
+def uniform_tiling(Np, tiles_per_side, buffer):
+    """List of (core_lo (3,), core_n, buffer) from the library's uniform tiling."""
+    n = tiles_per_side ** 3
+    arr = (_lib.Tile * n)()
+    _lib.check(_lib.lib().scola_uniform_tiling(Np, tiles_per_side, buffer, arr, n))
+    return [(tuple(t.core_lo), t.core_n, t.buffer) for t in arr]
+
+
+def _config(L, Np, n_steps, a_i, a_f, precision, schedule, want_momenta, N_out):
+    prec = {"fp32": SCOLA_FP32, "fp64": SCOLA_FP64}[precision]
+    sch = {"batched": SCOLA_BATCHED, "per_tile": SCOLA_PER_TILE}[schedule]
+    return _lib.Config(float(L), int(Np), int(N_out or 0), int(n_steps), float(a_i),
+                       float(a_f), prec, sch, 1 if want_momenta else 0)
+
+
+def schedule_table(n_steps, a_i=0.05, a_f=1.0, cosmology=None):
+    """Host FP64 KDK scalar rows (see scola_schedule_table); no device needed."""
+    import numpy as np
+    cfg = _config(1.0, 8, n_steps, a_i, a_f, "fp64", "batched", False, 0)
+    cosmo = (cosmology or CosmologyParams()).c()
+    out = np.zeros((n_steps + 1, 8))
+    _lib.check(_lib.lib().scola_schedule_table(
+        ctypes.byref(cfg), ctypes.byref(cosmo),
+        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n_steps + 1))
+    return out
+
+
+def linear_power(k, cosmology=None):
+    """P_lin(k, a = 1) of the library (host FP64)."""
+    import numpy as np
+    k = np.ascontiguousarray(k, dtype=np.float64)
+    out = np.zeros_like(k)
+    cosmo = (cosmology or CosmologyParams()).c()
+    _lib.check(_lib.lib().scola_linear_power(
+        ctypes.byref(cosmo), k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), k.size))
+    return out
+
+
+class Simulation:
+    """A tiled-sCOLA run on one GPU (one plan + one workspace).
+
+    tiles: list of (core_lo (3 ints), core_n, buffer); or use uniform_tiling().
+    precision: "fp32" (state and meshes in FP32, Psi and positions FP64) or "fp64".
+    schedule: "batched" (all boxes per launch) or "per_tile" (box after box).
+    """
+
+    def __init__(self, L, Np, tiles, n_steps, a_i=0.05, a_f=1.0, precision="fp32",
+                 schedule="batched", want_momenta=False, N_out=None, cosmology=None,
+                 device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("a HIP device is required (the engine has no CPU path)")
+        self.torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else device)
+        torch.cuda.set_device(self.device)
+        torch.cuda.init()
+        self.L, self.Np, self.n_steps = float(L), int(Np), int(n_steps)
+        self.N_out = int(N_out or Np)
+        self.precision = precision
+        self.real = torch.float64 if precision == "fp64" else torch.float32
+        self.want_momenta = bool(want_momenta)
+        self.tiles = [(tuple(int(c) for c in lo), int(n), int(b)) for lo, n, b in tiles]
+        cfg = _config(L, Np, n_steps, a_i, a_f, precision, schedule, want_momenta, N_out)
+        cosmo = (cosmology or CosmologyParams()).c()
+        arr = (_lib.Tile * len(self.tiles))()
+        for i, (lo, n, b) in enumerate(self.tiles):
+            arr[i].core_lo[:] = lo
+            arr[i].core_n = n
+            arr[i].buffer = b
+        plan = ctypes.c_void_p()
+        _lib.check(_lib.lib().scola_plan_create(ctypes.byref(cfg), ctypes.byref(cosmo), arr,
+                                                len(self.tiles), ctypes.byref(plan)))
+        self._plan = plan
+        lay = _lib.Layout()
+        _lib.check(_lib.lib().scola_workspace_layout(plan, ctypes.byref(lay)))
+        self.layout = lay
+        self.workspace = torch.empty(lay.total + 256, dtype=torch.uint8, device=self.device)
+        shift = (-self.workspace.data_ptr()) % 256
+        self._ws_off = shift
+        self._ws = ctypes.c_void_p(self.workspace.data_ptr() + shift)
+
+    def __del__(self):
+        plan = getattr(self, "_plan", None)
+        if plan is not None and plan.value:
+            try:
+                _lib.lib().scola_plan_destroy(plan)
+            except Exception:
+                pass
+            self._plan = None
+
+    # --- helpers ---------------------------------------------------------------------
+    def _stream(self):
+        return ctypes.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    @staticmethod
+    def _subset(tile_subset):
+        if tile_subset is None:
+            return None, 0
+        arr = (ctypes.c_int32 * len(tile_subset))(*[int(t) for t in tile_subset])
+        return arr, len(tile_subset)
+
+    def view(self, name):
+        """torch view of one workspace array (see scola_layout)."""
+        t = self.torch
+        lay = self.layout
+        P, G, H, N = lay.n_particles, lay.n_nodes, lay.n_padded, self.Np
+        rb = 8 if self.precision == "fp64" else 4
+        spec = {
+            "psi1": (t.float64, (3, P)), "psi2": (t.float64, (3, P)),
+            "x_res": (self.real, (3, P)), "p_res": (self.real, (3, P)),
+            "rho": (t.int64, (G,)), "work": (self.real, (G,)), "phi": (self.real, (H,)),
+            "bc0": (t.float64, (H,)), "dropped": (t.int64, (len(self.tiles),)),
+            "phi1": (t.float64, (N, N, N)), "phi2": (t.float64, (N, N, N)),
+            "outgrid": (t.int64, (self.N_out,) * 3),
+        }[name]
+        dtype, shape = spec
+        nbytes = 1
+        for s in shape:
+            nbytes *= s
+        nbytes *= {t.float64: 8, t.float32: 4, t.int64: 8}[dtype] if dtype != self.real else rb
+        off = self._ws_off + getattr(lay, name)
+        return self.workspace[off:off + nbytes].view(dtype).view(shape)
+
+    def _ptr(self, x, dtype, shape):
+        if x is None:
+            return None
+        assert x.is_cuda and x.dtype == dtype and x.is_contiguous(), (x.dtype, dtype)
+        assert tuple(x.shape) == tuple(shape), (tuple(x.shape), shape)
+        return ctypes.c_void_p(x.data_ptr())
+
+    # --- the run ---------------------------------------------------------------------
+    def forward(self, white_noise, tile_subset=None, density=True, momenta=None):
+        """Run set-up, evolution and outputs.  Returns dict(pos, mom, density)."""
+        t = self.torch
+        Np = self.Np
+        momenta = self.want_momenta if momenta is None else momenta
+        pos = t.empty((3, Np, Np, Np), dtype=self.real, device=self.device)
+        mom = t.empty_like(pos) if momenta else None
+        dens = (t.empty((self.N_out,) * 3, dtype=self.real, device=self.device)
+                if density and tile_subset is None else None)
+        sub, n = self._subset(tile_subset)
+        _lib.check(_lib.lib().scola_forward(
+            self._plan, self._ptr(white_noise, t.float64, (Np, Np, Np)),
+            self._ptr(pos, self.real, pos.shape), self._ptr(mom, self.real, pos.shape)
+            if mom is not None else None,
+            self._ptr(dens, self.real, (self.N_out,) * 3) if dens is not None else None,
+            sub, n, self._ws, self._stream()))
+        return dict(pos=pos, mom=mom, density=dens)
+
+    def setup(self, white_noise):
+        t = self.torch
+        _lib.check(_lib.lib().scola_setup(
+            self._plan, self._ptr(white_noise, t.float64, (self.Np,) * 3), self._ws,
+            self._stream()))
+
+    def evolve(self, tile_subset=None):
+        sub, n = self._subset(tile_subset)
+        _lib.check(_lib.lib().scola_evolve(self._plan, sub, n, self._ws, self._stream()))
+
+    def output(self, pos=None, mom=None, density=None, tile_subset=None):
+        sub, n = self._subset(tile_subset)
+        shp = (3, self.Np, self.Np, self.Np)
+        _lib.check(_lib.lib().scola_output(
+            self._plan, self._ptr(pos, self.real, shp), self._ptr(mom, self.real, shp),
+            self._ptr(density, self.real, (self.N_out,) * 3), sub, n, self._ws,
+            self._stream()))
+
+    def op_deposit(self, D1, D2):
+        _lib.check(_lib.lib().scola_op_deposit(self._plan, D1, D2, self._ws, self._stream()))
+
+    def op_poisson(self, D1_bc):
+        _lib.check(_lib.lib().scola_op_poisson(self._plan, D1_bc, self._ws, self._stream()))
+
+    def op_step(self, beta, alpha, D1, D2, D1n, D2n, deposit=True):
+        _lib.check(_lib.lib().scola_op_step(self._plan, beta, alpha, D1, D2, D1n, D2n,
+                                            1 if deposit else 0, self._ws, self._stream()))
+
+    def op_final_kick(self, beta, D1, D2, c1, c2):
+        _lib.check(_lib.lib().scola_op_final_kick(self._plan, beta, D1, D2, c1, c2, self._ws,
+                                                  self._stream()))
+
+    def step_table(self):
+        import numpy as np
+        out = np.zeros((self.n_steps + 1, 8))
+        _lib.check(_lib.lib().scola_step_table(
+            self._plan, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.n_steps + 1))
+        return out
+
+    def info(self):
+        nt = ctypes.c_int32()
+        np_ = ctypes.c_int64()
+        r = ctypes.c_double()
+        p = ctypes.c_double()
+        _lib.check(_lib.lib().scola_plan_info(self._plan, ctypes.byref(nt), ctypes.byref(np_),
+                                              ctypes.byref(r), ctypes.byref(p)))
+        return dict(n_tiles=nt.value, n_particles=np_.value, r=r.value, p=p.value)
+
+    def box_particles(self, arr, t):
+        """Particle array [..., P] (workspace order) -> box t's sites in lattice order,
+        shape [..., M, M, M]."""
+        po, M, _, _ = self.box_slices()[t]
+        return arr[..., po + particle_order(M)].reshape(arr.shape[:-1] + (M, M, M))
+
+    def box_slices(self):
+        """Per tile: (particle offset, M, interior-node offset, padded-node offset)."""
+        out = []
+        P = G = H = 0
+        for lo, n, b in self.tiles:
+            M = n + 2 * b
+            out.append((P, M, G, H))
+            P += M ** 3
+            G += (M - 1) ** 3
+            H += (M + 3) ** 3
+        return out

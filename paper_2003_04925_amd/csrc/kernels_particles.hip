@@ -1,0 +1,414 @@
+// Particle kernels of the sCOLA step: CiC deposit (B^sCOLA, Sec. 3.4.1), the fused
+// gradient + CiC interpolation + COLA kick + drift + deposit (App. A eq. kick-scola,
+// App. B eqs. K_COLA and D_COLA), and the untiling of the core particles with the output
+// CiC density (Sec. 3.2 B.2, Sec. 4.1).
+//
+// Layout: structure of arrays [3][P] over all boxes, box after box, particles of a box in
+// lattice order (z fastest), so a 256-thread block reads 256 consecutive elements of each
+// of the 12 particle streams.  Psi1 and Psi2 stay FP64 and every particle position is
+// formed in FP64 (u = q - D1 Psi1 + D2 Psi2 + x_res) before its cell index is taken, so
+// cell indices do not depend on the state precision.
+//
+// The deposit accumulates round(w * 2^40) in 64-bit integers: sums are exact and
+// independent of the order of the atomics, which makes every run bitwise reproducible and
+// a box computed alone bitwise equal to the same box in a batch.  The eighth corner gets
+// 2^40 minus the other seven, so every particle carries exactly one unit of mass, split
+// between deposited and dropped (outside the interior nodes).
+#include <type_traits>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace scola {
+
+namespace {
+
+__device__ inline int logical_block(const BlockMap& m) {
+  const int b = blockIdx.x;
+  if (!m.xcd_remap) return b;
+  const int per = gridDim.x >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+inline unsigned padded_grid(const BlockMap& m) {
+  if (!m.xcd_remap) return (unsigned)m.count;
+  return (unsigned)(((m.count + 7) / 8) * 8);
+}
+
+// Fixed-point CiC weights of the 8 corners (offset bits x = 4, y = 2, z = 1).
+__device__ inline void fixed_weights(double fx, double fy, double fz, long long (&w)[8]) {
+  long long sum = 0;
+#pragma unroll
+  for (int c = 0; c < 7; ++c) {
+    const double wx = (c & 4) ? fx : 1.0 - fx;
+    const double wy = (c & 2) ? fy : 1.0 - fy;
+    const double wz = (c & 1) ? fz : 1.0 - fz;
+    w[c] = __double2ll_rn(wx * wy * wz * kFixedOne);
+    sum += w[c];
+  }
+  w[7] = (long long)kFixedOne - sum;
+}
+
+// Corner range of one particle's CiC footprint restricted to interior nodes [1, n]:
+// returns false when the particle deposits nothing (outside the box, or NaN).
+__device__ inline bool deposit_footprint(int M, double ux, double uy, double uz, int (&j0)[3],
+                                         double (&f)[3]) {
+  const double hi = (double)M + 1.0;
+  if (!(ux >= -1.0 && ux < hi && uy >= -1.0 && uy < hi && uz >= -1.0 && uz < hi))
+    return false;
+  const double u[3] = {ux, uy, uz};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double fl = floor(u[c]);
+    j0[c] = (int)fl;
+    f[c] = u[c] - fl;
+  }
+  return true;
+}
+
+__device__ inline int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+constexpr int kWindow = 4096;   // int64 LDS accumulators per block (32 KiB)
+
+// B^sCOLA for the 256 particles of one block (one Lagrangian brick): CiC of every particle
+// onto interior nodes [1, M-1]^3 of its box, privatised in an LDS window that covers the
+// block's Eulerian footprint, then one global atomic per touched node.  Blocks whose
+// footprint exceeds the window add straight into global memory.  Integer sums make both
+// paths give identical results.  Returns the fixed-point mass this thread dropped.
+// Must be called by all threads of the block.
+__device__ inline long long deposit_block(unsigned long long* __restrict__ rho, int M,
+                                          bool active, double ux, double uy, double uz,
+                                          unsigned long long* win, int* bounds) {
+  const int n = M - 1;
+  int j0[3] = {0, 0, 0};
+  double f[3] = {0, 0, 0};
+  const bool in = active && deposit_footprint(M, ux, uy, uz, j0, f);
+  long long w[8];
+  if (in) fixed_weights(f[0], f[1], f[2], w);
+  // interior corner range of this particle (empty when lo > hi)
+  int lo[3], hi[3];
+  bool any = in;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    lo[c] = max(j0[c], 1);
+    hi[c] = min(j0[c] + 1, n);
+    any = any && lo[c] <= hi[c];
+  }
+  if (threadIdx.x < 6) bounds[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -0x7fffffff;
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int a = wave_min(any ? lo[c] : 0x7fffffff);
+    const int b = wave_max(any ? hi[c] : -0x7fffffff);
+    if ((threadIdx.x & 63) == 0) {
+      atomicMin(bounds + c, a);
+      atomicMax(bounds + 3 + c, b);
+    }
+  }
+  __syncthreads();
+  const int lx = bounds[0], ly = bounds[1], lz = bounds[2];
+  const int wx = bounds[3] - lx + 1, wy = bounds[4] - ly + 1, wz = bounds[5] - lz + 1;
+  const bool empty = wx <= 0 || wy <= 0 || wz <= 0;
+  const int vol = empty ? 0 : wx * wy * wz;
+  const bool use_lds = !empty && vol <= kWindow;
+  if (use_lds) {
+    for (int e = threadIdx.x; e < vol; e += blockDim.x) win[e] = 0ull;
+    __syncthreads();
+  }
+  long long dropped = 0;
+  if (in) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int nx = j0[0] + ((c >> 2) & 1), ny = j0[1] + ((c >> 1) & 1), nz = j0[2] + (c & 1);
+      const bool inside = nx >= 1 && nx <= n && ny >= 1 && ny <= n && nz >= 1 && nz <= n;
+      if (!inside) {
+        dropped += w[c];
+      } else if (w[c] != 0) {
+        if (use_lds)
+          atomicAdd(win + ((nx - lx) * wy + (ny - ly)) * wz + (nz - lz), (unsigned long long)w[c]);
+        else
+          atomicAdd(rho + ((int64_t)(nx - 1) * n + (ny - 1)) * n + (nz - 1),
+                    (unsigned long long)w[c]);
+      }
+    }
+  } else if (active) {
+    dropped = (long long)kFixedOne;            // the whole particle lies outside
+  }
+  if (use_lds) {
+    __syncthreads();
+    const int wyz = wy * wz;
+    for (int e = threadIdx.x; e < vol; e += blockDim.x) {
+      const unsigned long long v = win[e];
+      if (v != 0ull) {
+        const int ex = e / wyz, r = e - ex * wyz, ey = r / wz, ez = r - ey * wz;
+        atomicAdd(rho + ((int64_t)(lx + ex - 1) * n + (ly + ey - 1)) * n + (lz + ez - 1), v);
+      }
+    }
+  }
+  return dropped;
+}
+
+// grad^sCOLA + B-bar^sCOLA: central-difference gradient of the padded potential on nodes
+// [0, M]^3, CiC-interpolated at u; corners outside [0, M]^3 contribute nothing.
+template <typename T>
+__device__ inline void gather_force(const T* __restrict__ phi, int M, double ux, double uy,
+                                    double uz, T (&g)[3]) {
+  g[0] = g[1] = g[2] = T(0);
+  const double hi = (double)M + 1.0;
+  if (!(ux >= -1.0 && ux < hi && uy >= -1.0 && uy < hi && uz >= -1.0 && uz < hi)) return;
+  const double flx = floor(ux), fly = floor(uy), flz = floor(uz);
+  const int jx = (int)flx, jy = (int)fly, jz = (int)flz;
+  const T fx = (T)(ux - flx), fy = (T)(uy - fly), fz = (T)(uz - flz);
+  const int Mp = M + 3;
+  T wx[2] = {T(1) - fx, fx}, wy[2] = {T(1) - fy, fy}, wz[2] = {T(1) - fz, fz};
+  int cxs[2], cys[2], czs[2];
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    const int nx = jx + d, ny = jy + d, nz = jz + d;
+    if (nx < 0 || nx > M) wx[d] = T(0);
+    if (ny < 0 || ny > M) wy[d] = T(0);
+    if (nz < 0 || nz > M) wz[d] = T(0);
+    // clamp so that reads stay inside the padded grid; clamped corners have zero weight
+    cxs[d] = min(max(nx, 0), M) + 1;
+    cys[d] = min(max(ny, 0), M) + 1;
+    czs[d] = min(max(nz, 0), M) + 1;
+  }
+  T gx = 0, gy = 0, gz = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
+    const T w = wx[dx] * wy[dy] * wz[dz];
+    const int64_t o = ((int64_t)cxs[dx] * Mp + cys[dy]) * Mp + czs[dz];
+    gx += w * (phi[o + (int64_t)Mp * Mp] - phi[o - (int64_t)Mp * Mp]);
+    gy += w * (phi[o + Mp] - phi[o - Mp]);
+    gz += w * (phi[o + 1] - phi[o - 1]);
+  }
+  g[0] = T(0.5) * gx;
+  g[1] = T(0.5) * gy;
+  g[2] = T(0.5) * gz;
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlock) k_particles(ParticleArgs<T> a, BlockMap m) {
+  const int L = logical_block(m);
+  if (L >= m.count) return;
+  const int b = m.base + L;
+  const int ti = m.tile[b];
+  const TileDesc t = a.tiles[ti];
+  const int M = t.M;
+  const int64_t pl = (int64_t)m.local[b] * kBlock + threadIdx.x;   // one brick per block
+  const int64_t p = t.p_off + pl;
+  const int64_t P = a.P;
+  int i, j, k;
+  brick_site(pl, M, i, j, k);
+  const double q[3] = {i + 0.5, j + 0.5, k + 0.5};
+  double s1[3], s2[3];
+  T xr[3], pr[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    s1[c] = a.psi1[c * P + p];
+    s2[c] = a.psi2[c * P + p];
+    if (MODE == kInit) {
+      // operator L- (App. B): at t_0 the particles sit on their LPT trajectory and the
+      // residual momentum is zero
+      xr[c] = T(0);
+      a.xres[c * P + p] = T(0);
+      a.pres[c * P + p] = T(0);
+    } else {
+      xr[c] = a.xres[c * P + p];
+    }
+  }
+  const StepScalars sc = a.sc;
+  double u[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) u[c] = q[c] - sc.D1 * s1[c] + sc.D2 * s2[c] + (double)xr[c];
+  if (MODE != kDepositOnly && MODE != kInit) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pr[c] = a.pres[c * P + p];
+    T g[3];
+    gather_force<T>(a.phi + t.h_off, M, u[0], u[1], u[2], g);
+    const double d2 = sc.D2 - sc.D1 * sc.D1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      pr[c] += (T)sc.beta * (g[c] - (T)(sc.D1 * s1[c] - d2 * s2[c]));
+    if (MODE == kFinalKick) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.pres[c * P + p] = pr[c] + (T)(sc.c1 * s1[c] + sc.c2 * s2[c]);
+      return;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xr[c] += (T)sc.alpha * pr[c];
+      a.xres[c * P + p] = xr[c];
+      a.pres[c * P + p] = pr[c];
+    }
+    if (MODE == kStepNoDeposit) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c] = q[c] - sc.D1n * s1[c] + sc.D2n * s2[c] + (double)xr[c];
+  }
+  __shared__ unsigned long long win[kWindow];
+  __shared__ int bounds[6];
+  __shared__ unsigned long long block_drop;
+  if (threadIdx.x == 0) block_drop = 0ull;
+  const long long drop = deposit_block(a.rho + t.g_off, M, true, u[0], u[1], u[2], win, bounds);
+  if (drop != 0) atomicAdd(&block_drop, (unsigned long long)drop);
+  __syncthreads();
+  if (threadIdx.x == 0 && block_drop != 0ull) atomicAdd(a.dropped + ti, block_drop);
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+__device__ inline int wrapi(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+// B.2: core particles -> global lattice order; optional periodic CiC of the core
+// particles on the N_out^3 output grid (nodes at integer multiples of L / N_out).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_output(OutputArgs<T> a, BlockMap m, int density) {
+  const int L = logical_block(m);
+  if (L >= m.count) return;
+  const int b = m.base + L;
+  const TileDesc t = a.tiles[m.tile[b]];
+  const int M = t.M;
+  const int64_t pl = (int64_t)m.local[b] * kBlock + threadIdx.x;
+  int i, j, k;
+  brick_site(pl, M, i, j, k);
+  const int lo = t.core_lo[0], hi = t.core_lo[0] + t.core_n;
+  if (i < lo || i >= hi || j < lo || j >= hi || k < lo || k >= hi) return;
+  const int64_t p = t.p_off + pl;
+  const int64_t P = a.P;
+  const int Np = a.Np;
+  const int64_t gidx = ((int64_t)wrapi(t.origin[0] + i, Np) * Np + wrapi(t.origin[1] + j, Np)) *
+                           Np + wrapi(t.origin[2] + k, Np);
+  const int64_t Np3 = (int64_t)Np * Np * Np;
+  const int idx[3] = {i, j, k};
+  double ug[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double u = idx[c] + 0.5 - a.D1 * a.psi1[c * P + p] + a.D2 * a.psi2[c * P + p] +
+                     (double)a.xres[c * P + p];
+    ug[c] = t.origin[c] + u;
+    if (a.pos) {
+      double x = fmod(ug[c], (double)Np);
+      if (x < 0) x += Np;
+      T xl = (T)(x * a.cell);
+      if (xl >= (T)a.L) xl = T(0);          // rounding up to L wraps to 0
+      a.pos[c * Np3 + gidx] = xl;
+    }
+    if (a.mom) a.mom[c * Np3 + gidx] = (T)((double)a.pres[c * P + p] * a.cell);
+  }
+  if (density) {
+    const double s = (double)a.N_out / (double)Np;
+    const int No = a.N_out;
+    double f[3];
+    int j0[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double uo = ug[c] * s;
+      const double fl = floor(uo);
+      f[c] = uo - fl;
+      j0[c] = wrapi((int)fmod(fl, (double)No), No);
+    }
+    long long w[8];
+    fixed_weights(f[0], f[1], f[2], w);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int nx = (j0[0] + ((c >> 2) & 1)) % No, ny = (j0[1] + ((c >> 1) & 1)) % No,
+                nz = (j0[2] + (c & 1)) % No;
+      if (w[c] != 0)
+        atomicAdd(a.grid + ((int64_t)nx * No + ny) * No + nz, (unsigned long long)w[c]);
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_density_convert(const unsigned long long* __restrict__ grid, T* out,
+                                  int64_t n, double scale) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (T)((double)(long long)grid[i] * kFixedInv * scale - 1.0);
+}
+
+}  // namespace
+
+hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)(blocks < 65536 ? blocks : 65536)),
+                     dim3(kBlock), 0, s, p, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_particles(const ParticleArgs<T>& a, int mode, const BlockMap& m,
+                            hipStream_t s) {
+  if (m.count <= 0) return hipSuccess;
+  const dim3 grid(padded_grid(m)), block(kBlock);
+  switch (mode) {
+    case kDepositOnly:
+      hipLaunchKernelGGL((k_particles<T, kDepositOnly>), grid, block, 0, s, a, m);
+      break;
+    case kStep:
+      hipLaunchKernelGGL((k_particles<T, kStep>), grid, block, 0, s, a, m);
+      break;
+    case kStepNoDeposit:
+      hipLaunchKernelGGL((k_particles<T, kStepNoDeposit>), grid, block, 0, s, a, m);
+      break;
+    case kFinalKick:
+      hipLaunchKernelGGL((k_particles<T, kFinalKick>), grid, block, 0, s, a, m);
+      break;
+    case kInit:
+      hipLaunchKernelGGL((k_particles<T, kInit>), grid, block, 0, s, a, m);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_output(const OutputArgs<T>& a, const BlockMap& m, bool density,
+                         T* density_out, hipStream_t s) {
+  const int64_t n_out = (int64_t)a.N_out * a.N_out * a.N_out;
+  if (density) {
+    hipError_t e = launch_zero_u64(a.grid, n_out, s);
+    if (e != hipSuccess) return e;
+  }
+  if (m.count > 0)
+    hipLaunchKernelGGL(k_output<T>, dim3(padded_grid(m)), dim3(kBlock), 0, s, a, m,
+                       density ? 1 : 0);
+  if (density) {
+    const double r = (double)a.N_out / (double)a.Np;
+    const int64_t blocks = (n_out + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_density_convert<T>,
+                       dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(kBlock), 0, s,
+                       a.grid, density_out, n_out, r * r * r);
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_particles<float>(const ParticleArgs<float>&, int, const BlockMap&,
+                                            hipStream_t);
+template hipError_t launch_particles<double>(const ParticleArgs<double>&, int,
+                                             const BlockMap&, hipStream_t);
+template hipError_t launch_output<float>(const OutputArgs<float>&, const BlockMap&, bool,
+                                         float*, hipStream_t);
+template hipError_t launch_output<double>(const OutputArgs<double>&, const BlockMap&, bool,
+                                          double*, hipStream_t);
+
+}  // namespace scola

@@ -1,0 +1,360 @@
+// Dirichlet Poisson solve of every sCOLA box by type-I discrete sine transforms (App. C).
+//
+// A box of M particles per side has n = M - 1 interior PM nodes per side.  Three passes
+// over the (n)^3 mesh of every box, all boxes in one launch each:
+//   P1  per x-plane: fixed-point mass -> delta, delta' = delta - Delta Phi_BCs (App. C.1),
+//       forward DST-I along z then y, in LDS;
+//   P2  per (y, 32 z-columns): forward DST-I along x, division by the FDA-2 eigenvalue sum
+//       times the inverse normalisation 8/M^3 (App. C.2, eq. Poisson_sine_space), inverse
+//       DST-I along x;
+//   P3  per x-plane: inverse DST-I along y then z, and the potential written to the padded
+//       node grid [-1, M+1]^3 with the shell filled from Phi_BCs (Sec. 3.4.2).
+//
+// Every 1-D DST-I of length n = M - 1 is computed through a complex FFT of length 2M of the
+// odd extension (0, a_1..a_n, 0, -a_n..-a_1) + i (same for a second line b): its transform
+// is Z_k = -2i S[a]_k + 2 S[b]_k, so two sine transforms come from one FFT.  The FFT of
+// length 2M = 32 R (R = M / 16 in 1..8) runs on a half wavefront (32 lanes) entirely in
+// registers: each lane holds R points, an R-point DFT across registers, a twiddle, then a
+// 32-point radix-2 decimation-in-frequency FFT across lanes with xor shuffles.
+#include <type_traits>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace scola {
+
+namespace {
+
+template <typename T>
+using cx = typename std::conditional<std::is_same<T, float>::value, float2, double2>::type;
+
+template <typename C>
+__device__ inline C c_add(C a, C b) {
+  C r;
+  r.x = a.x + b.x;
+  r.y = a.y + b.y;
+  return r;
+}
+template <typename C>
+__device__ inline C c_sub(C a, C b) {
+  C r;
+  r.x = a.x - b.x;
+  r.y = a.y - b.y;
+  return r;
+}
+template <typename C>
+__device__ inline C c_mul(C a, C b) {
+  C r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+
+__device__ inline int bitrev5(int l) { return (int)(__brev((unsigned)l) >> 27); }
+
+// Logical block index: hardware dispatches consecutive workgroups round-robin over the 8
+// XCDs, so logical = (b % 8) * (grid / 8) + b / 8 gives each XCD a contiguous run of
+// logical blocks, i.e. whole boxes, and keeps a box's mesh in one L2.
+__device__ inline int logical_block(const BlockMap& m) {
+  const int b = blockIdx.x;
+  if (!m.xcd_remap) return b;
+  const int per = gridDim.x >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+// FFT of length 32R on one half wavefront; lane l holds x[32 n2 + l], n2 < R.  On return
+// lane l holds Z[k1 + R bitrev5(l)] in x[k1].  tw = W_{32R}^m, m < 32R (in LDS).
+template <int R, typename T>
+__device__ inline void halfwave_fft(cx<T> (&x)[R], const cx<T>* __restrict__ tw, int l) {
+  cx<T> y[R];
+  if constexpr (R == 1) {
+    y[0] = x[0];
+  } else {
+    cx<T> wr[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) wr[m] = tw[m * 32];       // W_R^m
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) {
+      cx<T> acc = x[0];
+#pragma unroll
+      for (int n2 = 1; n2 < R; ++n2) acc = c_add(acc, c_mul(x[n2], wr[(n2 * k1) % R]));
+      y[k1] = acc;
+    }
+#pragma unroll
+    for (int k1 = 1; k1 < R; ++k1) y[k1] = c_mul(y[k1], tw[l * k1]);   // W_N^(n1 k1)
+  }
+#pragma unroll
+  for (int s = 16; s >= 1; s >>= 1) {
+    const bool upper = (l & s) != 0;
+    const cx<T> w = tw[(l & (s - 1)) * (16 / s) * R];                  // W_{2s}^(l mod s)
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) {
+      cx<T> p;
+      p.x = __shfl_xor(y[k1].x, s);
+      p.y = __shfl_xor(y[k1].y, s);
+      y[k1] = upper ? c_mul(c_sub(p, y[k1]), w) : c_add(y[k1], p);
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < R; ++k1) x[k1] = y[k1];
+}
+
+// In-place DST-I (unnormalised, eq. DST_delta) of two lines a, b of n = 16R - 1 values at
+// stride `stride` in LDS; output k (1..n) is multiplied by sa(k) / sb(k).
+template <int R, typename T, typename SA, typename SB>
+__device__ inline void dst_pair(T* la, T* lb, int stride, bool has_b, const cx<T>* tw, int l,
+                                SA sa, SB sb) {
+  constexpr int M = 16 * R;
+  cx<T> x[R];
+#pragma unroll
+  for (int n2 = 0; n2 < R; ++n2) {
+    const int m = 32 * n2 + l;
+    cx<T> v;
+    v.x = T(0);
+    v.y = T(0);
+    if (m != 0 && m != M) {
+      const bool lo = m < M;
+      const int idx = lo ? m - 1 : 2 * M - m - 1;
+      const T sg = lo ? T(1) : T(-1);
+      v.x = sg * la[idx * stride];
+      if (has_b) v.y = sg * lb[idx * stride];
+    }
+    x[n2] = v;
+  }
+  halfwave_fft<R, T>(x, tw, l);
+  const int br = bitrev5(l);
+#pragma unroll
+  for (int k1 = 0; k1 < R; ++k1) {
+    const int k = k1 + R * br;
+    if (k >= 1 && k <= M - 1) {
+      la[(k - 1) * stride] = T(-0.5) * x[k1].y * sa(k);
+      if (has_b) lb[(k - 1) * stride] = T(0.5) * x[k1].x * sb(k);
+    }
+  }
+}
+
+// DST-I along z (rows) then y (columns) of an n x n plane in LDS (row pitch n).
+template <int R, typename T>
+__device__ inline void plane_dst(T* plane, const cx<T>* tw) {
+  constexpr int n = 16 * R - 1;
+  const int hw = threadIdx.x >> 5, l = threadIdx.x & 31;
+  auto one = [](int) { return T(1); };
+#pragma unroll 2
+  for (int p = hw; p < 8 * R; p += 8)
+    dst_pair<R, T>(plane + 2 * p * n, plane + (2 * p + 1) * n, 1, 2 * p + 1 < n, tw, l, one,
+                   one);
+  __syncthreads();
+#pragma unroll 2
+  for (int p = hw; p < 8 * R; p += 8)
+    dst_pair<R, T>(plane + 2 * p, plane + 2 * p + 1, n, 2 * p + 1 < n, tw, l, one, one);
+  __syncthreads();
+}
+
+template <typename T>
+__device__ inline void load_twiddles(cx<T>* tw, const MeshArgs<T>& a, const TileDesc& t) {
+  const cx<T>* src = reinterpret_cast<const cx<T>*>(a.twiddles) + t.tw_off;
+  for (int i = threadIdx.x; i < 2 * t.M; i += blockDim.x) tw[i] = src[i];
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m) {
+  const int L = logical_block(m);
+  if (L >= m.count) return;
+  const int b = m.base + L;
+  const TileDesc t = a.tiles[m.tile[b]];
+  const int x = m.local[b];
+  constexpr int M = 16 * R, n = M - 1, Mp = M + 3;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
+  T* plane = reinterpret_cast<T*>(smem + 2 * kMaxM * sizeof(cx<T>));
+  load_twiddles(tw, a, t);
+  const int64_t base = t.g_off + (int64_t)x * n * n;
+  const double* bc = a.bc0 + t.h_off;
+  const double D1 = a.D1_bc;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int y = e / n, z = e - (e / n) * n;
+    const long long r = (long long)a.rho[base + e];
+    a.rho[base + e] = 0ull;
+    double d = (double)r * kFixedInv - 1.0;
+    // delta' = delta - Delta Phi_BCs: face-layer neighbours of the first interior layer
+    // (padded index = node index + 1; interior node index = array index + 1)
+    if (x == 0) d -= D1 * bc[((int64_t)1 * Mp + y + 2) * Mp + z + 2];
+    if (x == n - 1) d -= D1 * bc[((int64_t)(M + 1) * Mp + y + 2) * Mp + z + 2];
+    if (y == 0) d -= D1 * bc[((int64_t)(x + 2) * Mp + 1) * Mp + z + 2];
+    if (y == n - 1) d -= D1 * bc[((int64_t)(x + 2) * Mp + M + 1) * Mp + z + 2];
+    if (z == 0) d -= D1 * bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + 1];
+    if (z == n - 1) d -= D1 * bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + M + 1];
+    plane[e] = (T)d;
+  }
+  __syncthreads();
+  plane_dst<R, T>(plane, tw);
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) a.work[base + e] = plane[e];
+}
+
+template <int R, typename T>
+__device__ inline void pencil_solve(T* tile, int pitch, int cw, int y, int z0, const T* ev,
+                                    const cx<T>* tw) {
+  constexpr int M = 16 * R;
+  const int hw = threadIdx.x >> 5, l = threadIdx.x & 31;
+  const T norm = T(8.0 / ((double)M * M * M));
+  const T ly = ev[y];
+#pragma unroll
+  for (int it = 0; it < kPencilChunk / 16; ++it) {
+    const int p = hw + 8 * it;
+    if (2 * p < cw) {
+      const T lza = ev[z0 + 2 * p];
+      const T lzb = 2 * p + 1 < cw ? ev[z0 + 2 * p + 1] : T(-1);
+      auto sa = [&](int k) { return norm / (ev[k - 1] + ly + lza); };
+      auto sb = [&](int k) { return norm / (ev[k - 1] + ly + lzb); };
+      dst_pair<R, T>(tile + 2 * p, tile + 2 * p + 1, pitch, 2 * p + 1 < cw, tw, l, sa, sb);
+    }
+  }
+  __syncthreads();
+  auto one = [](int) { return T(1); };
+#pragma unroll
+  for (int it = 0; it < kPencilChunk / 16; ++it) {
+    const int p = hw + 8 * it;
+    if (2 * p < cw)
+      dst_pair<R, T>(tile + 2 * p, tile + 2 * p + 1, pitch, 2 * p + 1 < cw, tw, l, one, one);
+  }
+  __syncthreads();
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(kBlock) k_poisson_p2(MeshArgs<T> a, BlockMap m) {
+  const int L = logical_block(m);
+  if (L >= m.count) return;
+  const int b = m.base + L;
+  const TileDesc t = a.tiles[m.tile[b]];
+  constexpr int M = 16 * R, n = M - 1;
+  const int nch = (n + kPencilChunk - 1) / kPencilChunk;
+  const int y = m.local[b] / nch, ch = m.local[b] - (m.local[b] / nch) * nch;
+  const int z0 = ch * kPencilChunk, cw = min(kPencilChunk, n - z0);
+  constexpr int pitch = kPencilChunk + 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
+  T* tile = reinterpret_cast<T*>(smem + 2 * kMaxM * sizeof(cx<T>));
+  load_twiddles(tw, a, t);
+  const int64_t base = t.g_off + (int64_t)y * n + z0;
+  for (int e = threadIdx.x; e < n * cw; e += blockDim.x) {
+    const int x = e / cw, zc = e - (e / cw) * cw;
+    tile[x * pitch + zc] = a.work[base + (int64_t)x * n * n + zc];
+  }
+  __syncthreads();
+  const T* ev = a.eigen + t.ev_off;
+  pencil_solve<R, T>(tile, pitch, cw, y, z0, ev, tw);
+  for (int e = threadIdx.x; e < n * cw; e += blockDim.x) {
+    const int x = e / cw, zc = e - (e / cw) * cw;
+    a.work[base + (int64_t)x * n * n + zc] = tile[x * pitch + zc];
+  }
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(kBlock) k_poisson_p3(MeshArgs<T> a, BlockMap m) {
+  const int L = logical_block(m);
+  if (L >= m.count) return;
+  const int b = m.base + L;
+  const TileDesc t = a.tiles[m.tile[b]];
+  const int local = m.local[b];
+  constexpr int M = 16 * R, n = M - 1, Mp = M + 3;
+  const double* bc = a.bc0 + t.h_off;
+  T* phi = a.phi + t.h_off;
+  const double D1 = a.D1_bc;
+  if (local >= n) {
+    // one of the four shell planes a = 0, 1, M+1, M+2 (node -1, 0, M, M+1)
+    const int s = local - n;
+    const int A = s < 2 ? s : M + s - 1;
+    for (int e = threadIdx.x; e < Mp * Mp; e += blockDim.x)
+      phi[(int64_t)A * Mp * Mp + e] = (T)(D1 * bc[(int64_t)A * Mp * Mp + e]);
+    return;
+  }
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
+  T* plane = reinterpret_cast<T*>(smem + 2 * kMaxM * sizeof(cx<T>));
+  load_twiddles(tw, a, t);
+  const int x = local;
+  const int64_t base = t.g_off + (int64_t)x * n * n;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) plane[e] = a.work[base + e];
+  __syncthreads();
+  plane_dst<R, T>(plane, tw);
+  const int A = x + 2;
+  for (int e = threadIdx.x; e < Mp * Mp; e += blockDim.x) {
+    const int B = e / Mp, C = e - (e / Mp) * Mp;
+    const int64_t o = (int64_t)A * Mp * Mp + e;
+    if (B >= 2 && B <= M && C >= 2 && C <= M)
+      phi[o] = plane[(B - 2) * n + (C - 2)];
+    else
+      phi[o] = (T)(D1 * bc[o]);
+  }
+}
+
+inline unsigned padded_grid(const BlockMap& m) {
+  if (!m.xcd_remap) return (unsigned)m.count;
+  return (unsigned)(((m.count + 7) / 8) * 8);
+}
+
+}  // namespace
+
+template <typename T>
+size_t poisson_lds_bytes(int M) {
+  const int n = M - 1;
+  const size_t tw = 2 * kMaxM * sizeof(cx<T>);
+  const size_t plane = (size_t)n * n * sizeof(T);
+  const size_t pencil = (size_t)n * (kPencilChunk + 1) * sizeof(T);
+  return tw + (plane > pencil ? plane : pencil);
+}
+
+namespace {
+
+template <typename T, int R>
+hipError_t launch_poisson_R(const MeshArgs<T>& a, const BlockMap& p1, const BlockMap& p2,
+                            const BlockMap& p3, hipStream_t s) {
+  const size_t lds = poisson_lds_bytes<T>(16 * R);
+  if (lds > 65536) {
+    static bool done = false;     // allow more than 64 KiB of dynamic LDS (160 KiB on gfx950)
+    if (!done) {
+      hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p1<T, R>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p2<T, R>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p3<T, R>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      (void)hipGetLastError();
+      done = true;
+    }
+  }
+  if (p1.count > 0)
+    hipLaunchKernelGGL((k_poisson_p1<T, R>), dim3(padded_grid(p1)), dim3(kBlock), lds, s, a, p1);
+  if (p2.count > 0)
+    hipLaunchKernelGGL((k_poisson_p2<T, R>), dim3(padded_grid(p2)), dim3(kBlock), lds, s, a, p2);
+  if (p3.count > 0)
+    hipLaunchKernelGGL((k_poisson_p3<T, R>), dim3(padded_grid(p3)), dim3(kBlock), lds, s, a, p3);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_poisson(const MeshArgs<T>& a, int M, const BlockMap& p1, const BlockMap& p2,
+                          const BlockMap& p3, hipStream_t s) {
+  switch (M) {
+    case 16: return launch_poisson_R<T, 1>(a, p1, p2, p3, s);
+    case 32: return launch_poisson_R<T, 2>(a, p1, p2, p3, s);
+    case 48: return launch_poisson_R<T, 3>(a, p1, p2, p3, s);
+    case 64: return launch_poisson_R<T, 4>(a, p1, p2, p3, s);
+    case 80: return launch_poisson_R<T, 5>(a, p1, p2, p3, s);
+    case 96: return launch_poisson_R<T, 6>(a, p1, p2, p3, s);
+    case 112: return launch_poisson_R<T, 7>(a, p1, p2, p3, s);
+    case 128: return launch_poisson_R<T, 8>(a, p1, p2, p3, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_poisson<float>(const MeshArgs<float>&, int, const BlockMap&,
+                                          const BlockMap&, const BlockMap&, hipStream_t);
+template hipError_t launch_poisson<double>(const MeshArgs<double>&, int, const BlockMap&,
+                                           const BlockMap&, const BlockMap&, hipStream_t);
+template size_t poisson_lds_bytes<float>(int);
+template size_t poisson_lds_bytes<double>(int);
+
+}  // namespace scola

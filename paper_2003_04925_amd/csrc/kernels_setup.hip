@@ -1,0 +1,284 @@
+// FP64 set-up kernels: Gaussian initial conditions, Lagrangian potentials phi1 / phi2 on
+// the periodic LPT grid, per-box Psi1 / Psi2 and the LEP boundary potential Phi_BC^0.
+//
+// Paper: Sec. 3.1 (A.1 convolution approach; A.2 Poisson-like equations LPTpotential1/2,
+// second-order source by nine 1-D gradient operations), Sec. 3.3 (C.1-C.3: exact Psi in
+// the box, Phi_BCs interpolated from the LPT grid to the PM grid), Sec. 4 (FDA order 2).
+#include "common.h"
+#include "kernels.h"
+
+namespace scola {
+
+namespace {
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ inline int wrap(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+// Batched complex FFT (FP64, power-of-two length n) along one axis of an n^3 array held as
+// [outer][n][inner].  Each block transforms `lines` lines staged in LDS with a radix-2
+// Stockham pass per stage.  sign = -1 forward, +1 inverse (unnormalised).
+__global__ void __launch_bounds__(kBlock) k_fft_axis(double2* __restrict__ data, int n,
+                                                      int log2n, int64_t inner, int lines,
+                                                      double sign) {
+  extern __shared__ double2 lds[];
+  double2* buf0 = lds;
+  double2* buf1 = lds + (size_t)lines * n;
+  const int64_t total_lines = (int64_t)n * n;       // n^3 / n
+  const int64_t first = (int64_t)blockIdx.x * lines;
+  const int tid = threadIdx.x;
+  const int count = lines * n;
+  // element e of the block -> (line b, position i) with coalesced global addresses
+  auto address = [&](int e, int& b, int& i) -> int64_t {
+    if (inner == 1) {
+      b = e / n;
+      i = e % n;
+      return (first + b) * n + i;
+    }
+    b = e % lines;
+    i = e / lines;
+    const int64_t line = first + b;
+    const int64_t o = line / inner, c = line % inner;
+    return o * n * inner + (int64_t)i * inner + c;
+  };
+  for (int e = tid; e < count; e += blockDim.x) {
+    int b, i;
+    const int64_t a = address(e, b, i);
+    if (first + b < total_lines) buf0[b * n + i] = data[a];
+  }
+  __syncthreads();
+  double2* src = buf0;
+  double2* dst = buf1;
+  const int half = n / 2;
+  for (int ns = 1; ns < n; ns <<= 1) {
+    for (int e = tid; e < lines * half; e += blockDim.x) {
+      const int b = e / half, j = e % half;
+      const int k = j & (ns - 1);
+      double s, c;
+      sincospi(sign * (double)k / (double)ns, &s, &c);
+      const double2 x0 = src[b * n + j];
+      const double2 x1 = cmul(src[b * n + j + half], make_double2(c, s));
+      const int o = b * n + ((j - k) << 1) + k;
+      dst[o] = make_double2(x0.x + x1.x, x0.y + x1.y);
+      dst[o + ns] = make_double2(x0.x - x1.x, x0.y - x1.y);
+    }
+    __syncthreads();
+    double2* t = src;
+    src = dst;
+    dst = t;
+  }
+  for (int e = tid; e < count; e += blockDim.x) {
+    int b, i;
+    const int64_t a = address(e, b, i);
+    if (first + b < total_lines) data[a] = src[b * n + i];
+  }
+}
+
+__global__ void k_real_to_complex(const double* __restrict__ in, double2* __restrict__ out,
+                                  int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = make_double2(in[i], 0.0);
+}
+
+__global__ void k_take_real(const double2* __restrict__ in, double* __restrict__ out,
+                            double scale, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i].x * scale;
+}
+
+// Fourier symbol of the FDA-2 Laplacian, one-cell spacing: -4 sum sin^2(pi m / N).
+__device__ inline double fda2_symbol(int mx, int my, int mz, int N) {
+  double sx = sinpi((double)mx / N), sy = sinpi((double)my / N), sz = sinpi((double)mz / N);
+  return -4.0 * (sx * sx + sy * sy + sz * sz);
+}
+
+__device__ inline int signed_mode(int i, int N) { return i < N / 2 ? i : i - N; }
+
+// A.1 + A.2 (first order): multiply FFT(w) by sqrt(P(k, a_i) N^3 / L^3) and divide by the
+// FDA-2 Laplacian symbol; the zero mode is set to zero.
+__global__ void k_ic_filter(double2* __restrict__ c, int N, double L, double amplitude,
+                            double ns, double Om, double Ob, double h, double Tcmb,
+                            double growth2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n3 = (int64_t)N * N * N;
+  if (i >= n3) return;
+  const int ix = (int)(i / ((int64_t)N * N)), iy = (int)((i / N) % N), iz = (int)(i % N);
+  const int mx = signed_mode(ix, N), my = signed_mode(iy, N), mz = signed_mode(iz, N);
+  if (mx == 0 && my == 0 && mz == 0) {
+    c[i] = make_double2(0.0, 0.0);
+    return;
+  }
+  const double kf = 2.0 * M_PI / L;
+  const double k = kf * sqrt((double)mx * mx + (double)my * my + (double)mz * mz);
+  const double T = eh_nowiggle_transfer(k, Om, Ob, h, Tcmb);
+  const double P = amplitude * pow(k, ns) * T * T * growth2;
+  const double f = sqrt(P * (double)N * N * N / (L * L * L)) / fda2_symbol(mx, my, mz, N);
+  c[i] = make_double2(c[i].x * f, c[i].y * f);
+}
+
+// Division by the FDA-2 Laplacian symbol (A.2, second order), zero mode to zero.
+__global__ void k_inverse_laplacian(double2* __restrict__ c, int N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n3 = (int64_t)N * N * N;
+  if (i >= n3) return;
+  const int ix = (int)(i / ((int64_t)N * N)), iy = (int)((i / N) % N), iz = (int)(i % N);
+  const int mx = signed_mode(ix, N), my = signed_mode(iy, N), mz = signed_mode(iz, N);
+  if (mx == 0 && my == 0 && mz == 0) {
+    c[i] = make_double2(0.0, 0.0);
+    return;
+  }
+  const double inv = 1.0 / fda2_symbol(mx, my, mz, N);
+  c[i] = make_double2(c[i].x * inv, c[i].y * inv);
+}
+
+// Second-order source sum_{i>j} [phi_,ii phi_,jj - phi_,ij^2] with phi_,ij = D_i D_j phi,
+// D the order-2 central difference (wide stencils), periodic; written as complex input of
+// the next FFT.
+__global__ void k_second_order_source(const double* __restrict__ phi, double2* __restrict__ out,
+                                      int N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n3 = (int64_t)N * N * N;
+  if (i >= n3) return;
+  const int x = (int)(i / ((int64_t)N * N)), y = (int)((i / N) % N), z = (int)(i % N);
+  auto P = [&](int dx, int dy, int dz) {
+    return phi[((int64_t)wrap(x + dx, N) * N + wrap(y + dy, N)) * N + wrap(z + dz, N)];
+  };
+  const double c0 = P(0, 0, 0);
+  const double xx = 0.25 * (P(2, 0, 0) - 2.0 * c0 + P(-2, 0, 0));
+  const double yy = 0.25 * (P(0, 2, 0) - 2.0 * c0 + P(0, -2, 0));
+  const double zz = 0.25 * (P(0, 0, 2) - 2.0 * c0 + P(0, 0, -2));
+  const double xy = 0.25 * (P(1, 1, 0) - P(1, -1, 0) - P(-1, 1, 0) + P(-1, -1, 0));
+  const double xz = 0.25 * (P(1, 0, 1) - P(1, 0, -1) - P(-1, 0, 1) + P(-1, 0, -1));
+  const double yz = 0.25 * (P(0, 1, 1) - P(0, 1, -1) - P(0, -1, 1) + P(0, -1, -1));
+  const double s = yy * xx - xy * xy + zz * xx - xz * xz + zz * yy - yz * yz;
+  out[i] = make_double2(s, 0.0);
+}
+
+// C.1-C.2: Psi1 = D phi1 and Psi2 = D phi2 at every box particle (LPT nodes coincide with
+// the particles, so no interpolation); also the operator L- (x_res = p_res = 0).
+template <typename T>
+__global__ void k_extract_psi(const TileDesc* __restrict__ tiles,
+                              const int* __restrict__ blk_tile, const int* __restrict__ blk_first,
+                              const double* __restrict__ phi1, const double* __restrict__ phi2,
+                              double* __restrict__ psi1, double* __restrict__ psi2,
+                              T* __restrict__ xres, T* __restrict__ pres, int N, int64_t P) {
+  const TileDesc t = tiles[blk_tile[blockIdx.x]];
+  const int64_t pl = (int64_t)blk_first[blockIdx.x] * kBlock + threadIdx.x;
+  const int M = t.M;
+  const int64_t M3 = (int64_t)M * M * M;
+  if (pl >= M3) return;
+  int i, j, k;
+  brick_site(pl, M, i, j, k);
+  const int gx = wrap(t.origin[0] + i, N), gy = wrap(t.origin[1] + j, N),
+            gz = wrap(t.origin[2] + k, N);
+  auto at = [&](const double* f, int x, int y, int z) {
+    return f[((int64_t)wrap(x, N) * N + wrap(y, N)) * N + wrap(z, N)];
+  };
+  const int64_t p = t.p_off + pl;
+  psi1[p] = 0.5 * (at(phi1, gx + 1, gy, gz) - at(phi1, gx - 1, gy, gz));
+  psi1[P + p] = 0.5 * (at(phi1, gx, gy + 1, gz) - at(phi1, gx, gy - 1, gz));
+  psi1[2 * P + p] = 0.5 * (at(phi1, gx, gy, gz + 1) - at(phi1, gx, gy, gz - 1));
+  psi2[p] = 0.5 * (at(phi2, gx + 1, gy, gz) - at(phi2, gx - 1, gy, gz));
+  psi2[P + p] = 0.5 * (at(phi2, gx, gy + 1, gz) - at(phi2, gx, gy - 1, gz));
+  psi2[2 * P + p] = 0.5 * (at(phi2, gx, gy, gz + 1) - at(phi2, gx, gy, gz - 1));
+  for (int c = 0; c < 3; ++c) {
+    xres[c * P + p] = T(0);
+    pres[c * P + p] = T(0);
+  }
+}
+
+// C.3: Phi_BC^0 at the padded PM nodes j in [-1, M+1]^3 outside [1, M-1]^3: trilinear
+// interpolation of phi1 at the PM node, i.e. the mean of the 8 LPT nodes around it (PM
+// nodes sit half a cell from the LPT nodes).  Interior entries are set to zero.
+__global__ void k_boundary_potential(const TileDesc* __restrict__ tiles, int n_tiles,
+                                     const double* __restrict__ phi1, double* __restrict__ bc0,
+                                     int N) {
+  const int ti = blockIdx.y;
+  if (ti >= n_tiles) return;
+  const TileDesc t = tiles[ti];
+  const int Mp = t.M + 3;
+  const int64_t n = (int64_t)Mp * Mp * Mp;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(e / ((int64_t)Mp * Mp)) - 1, b = (int)((e / Mp) % Mp) - 1,
+              c = (int)(e % Mp) - 1;
+    double v = 0.0;
+    const bool inside = a >= 1 && a <= t.M - 1 && b >= 1 && b <= t.M - 1 && c >= 1 &&
+                        c <= t.M - 1;
+    if (!inside) {
+      const int gx = t.origin[0] + a, gy = t.origin[1] + b, gz = t.origin[2] + c;
+      for (int dx = -1; dx <= 0; ++dx)
+        for (int dy = -1; dy <= 0; ++dy)
+          for (int dz = -1; dz <= 0; ++dz)
+            v += phi1[((int64_t)wrap(gx + dx, N) * N + wrap(gy + dy, N)) * N +
+                      wrap(gz + dz, N)];
+      v *= 0.125;
+    }
+    bc0[t.h_off + e] = v;
+  }
+}
+
+inline unsigned grid1(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t fft3d(double2* c, int N, double sign, hipStream_t s) {
+  int log2n = 0;
+  while ((1 << log2n) < N) ++log2n;
+  const int lines = N >= 1024 ? 1 : 1024 / N;     // 32 KiB of LDS per block
+  const size_t lds = (size_t)2 * lines * N * sizeof(double2);
+  const int64_t total_lines = (int64_t)N * N;
+  const unsigned blocks = (unsigned)((total_lines + lines - 1) / lines);
+  const int64_t inners[3] = {(int64_t)N * N, N, 1};   // axes x, y, z
+  for (int ax = 0; ax < 3; ++ax) {
+    hipLaunchKernelGGL(k_fft_axis, dim3(blocks), dim3(kBlock), lds, s, c, N, log2n,
+                       inners[ax], lines, sign);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_setup_potentials(const SetupArgs& a, hipStream_t s) {
+  const int N = a.N;
+  const int64_t n3 = (int64_t)N * N * N;
+  hipLaunchKernelGGL(k_real_to_complex, dim3(grid1(n3)), dim3(kBlock), 0, s, a.white_noise,
+                     a.cbuf, n3);
+  hipError_t e = fft3d(a.cbuf, N, -1.0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ic_filter, dim3(grid1(n3)), dim3(kBlock), 0, s, a.cbuf, N, a.L,
+                     a.amplitude, a.ns, a.Om, a.Ob, a.h, a.Tcmb, a.growth2);
+  if ((e = fft3d(a.cbuf, N, +1.0, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_take_real, dim3(grid1(n3)), dim3(kBlock), 0, s, a.cbuf, a.phi1,
+                     1.0 / (double)n3, n3);
+  hipLaunchKernelGGL(k_second_order_source, dim3(grid1(n3)), dim3(kBlock), 0, s, a.phi1,
+                     a.cbuf, N);
+  if ((e = fft3d(a.cbuf, N, -1.0, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_inverse_laplacian, dim3(grid1(n3)), dim3(kBlock), 0, s, a.cbuf, N);
+  if ((e = fft3d(a.cbuf, N, +1.0, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_take_real, dim3(grid1(n3)), dim3(kBlock), 0, s, a.cbuf, a.phi2,
+                     1.0 / (double)n3, n3);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_setup_boxes(const BoxSetupArgs& a, T* xres, T* pres, hipStream_t s) {
+  if (a.n_blocks > 0)
+    hipLaunchKernelGGL(k_extract_psi<T>, dim3(a.n_blocks), dim3(kBlock), 0, s, a.tiles,
+                       a.blk_tile, a.blk_first, a.phi1, a.phi2, a.psi1, a.psi2, xres, pres,
+                       a.N, a.P);
+  hipLaunchKernelGGL(k_boundary_potential, dim3(64, a.n_tiles), dim3(kBlock), 0, s, a.tiles,
+                     a.n_tiles, a.phi1, a.bc0, a.N);
+  return hipGetLastError();
+}
+
+template hipError_t launch_setup_boxes<float>(const BoxSetupArgs&, float*, float*, hipStream_t);
+template hipError_t launch_setup_boxes<double>(const BoxSetupArgs&, double*, double*,
+                                               hipStream_t);
+
+}  // namespace scola

@@ -1,0 +1,852 @@
+// C ABI of the tiled-sCOLA engine: plan construction (validation, host FP64 scalar tables,
+// device tile table and block maps), workspace layout, and the orchestration of the set-up,
+// the KDK step loop and the outputs.  See include/scola.h for the contract.
+#include "scola.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "host_math.h"
+#include "kernels.h"
+
+using namespace scola;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct ScolaError : std::runtime_error {
+  scola_status code;
+  ScolaError(scola_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(scola_status c, const std::string& m) { throw ScolaError(c, m); }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess)
+    fail(SCOLA_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <typename F>
+scola_status guarded(F f) {
+  try {
+    f();
+    return SCOLA_OK;
+  } catch (const ScolaError& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return SCOLA_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return SCOLA_EINVAL;
+  }
+}
+
+// Block maps of one kernel family over all tiles.  Tiles are laid out size class by size
+// class (classes in increasing M), so every class is one contiguous block range.
+struct Maps {
+  std::vector<int> tile, local;
+  std::vector<int> first;    // per tile: first block of that tile
+  std::vector<int> count;    // per tile: number of blocks
+  std::vector<int> class_M, class_first, class_count;
+  int* d_tile = nullptr;
+  int* d_local = nullptr;
+};
+
+}  // namespace
+
+struct scola_plan {
+  scola_config cfg{};
+  scola_cosmology cosmo{};
+  std::vector<scola_tile> tiles;
+  std::vector<TileDesc> desc;
+  Background bg;
+  int device = 0;
+  int max_M = 0;
+  int64_t P = 0, G = 0, H = 0;
+  std::vector<double> table;          // (n_steps + 1) x 8 scalar rows
+  std::vector<double> D1, D2;         // growth at t_0 .. t_n
+  scola_layout lay{};
+  TileDesc* d_tiles = nullptr;
+  void* d_twiddles = nullptr;
+  void* d_eigen = nullptr;
+  Maps part, p1, p2, p3;
+  bool is64 = false;
+  // call-order state, keyed by the workspace it refers to
+  const void* setup_ws = nullptr;
+};
+
+namespace {
+
+void build_maps(Maps& m, const std::vector<TileDesc>& desc,
+                const std::function<int(const TileDesc&)>& units) {
+  m.tile.clear();
+  m.local.clear();
+  m.class_M.clear();
+  m.class_first.clear();
+  m.class_count.clear();
+  m.first.assign(desc.size(), 0);
+  m.count.assign(desc.size(), 0);
+  std::vector<int> sizes;
+  for (auto& d : desc) sizes.push_back(d.M);
+  std::sort(sizes.begin(), sizes.end());
+  sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+  for (int M : sizes) {
+    m.class_M.push_back(M);
+    m.class_first.push_back((int)m.tile.size());
+    for (size_t t = 0; t < desc.size(); ++t) {
+      if (desc[t].M != M) continue;
+      const int n = units(desc[t]);
+      m.first[t] = (int)m.tile.size();
+      m.count[t] = n;
+      for (int i = 0; i < n; ++i) {
+        m.tile.push_back((int)t);
+        m.local.push_back(i);
+      }
+    }
+    m.class_count.push_back((int)m.tile.size() - m.class_first.back());
+  }
+}
+
+void upload_maps(Maps& m) {
+  const size_t n = std::max<size_t>(1, m.tile.size());
+  hip_check(hipMalloc(&m.d_tile, n * sizeof(int)), "hipMalloc(block map)");
+  hip_check(hipMalloc(&m.d_local, n * sizeof(int)), "hipMalloc(block map)");
+  if (!m.tile.empty()) {
+    hip_check(hipMemcpy(m.d_tile, m.tile.data(), m.tile.size() * sizeof(int),
+                        hipMemcpyHostToDevice), "hipMemcpy(block map)");
+    hip_check(hipMemcpy(m.d_local, m.local.data(), m.local.size() * sizeof(int),
+                        hipMemcpyHostToDevice), "hipMemcpy(block map)");
+  }
+}
+
+void free_maps(Maps& m) {
+  if (m.d_tile) hipFree(m.d_tile);
+  if (m.d_local) hipFree(m.d_local);
+  m.d_tile = m.d_local = nullptr;
+}
+
+BlockMap full_map(const Maps& m) {
+  BlockMap b;
+  b.tile = m.d_tile;
+  b.local = m.d_local;
+  b.base = 0;
+  b.count = (int)m.tile.size();
+  return b;
+}
+
+BlockMap tile_map(const Maps& m, int t) {
+  BlockMap b;
+  b.tile = m.d_tile;
+  b.local = m.d_local;
+  b.base = m.first[t];
+  b.count = m.count[t];
+  return b;
+}
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+void validate(const scola_config& c, const scola_cosmology& cs, const scola_tile* tiles,
+              int n_tiles) {
+  if (!(c.L > 0)) fail(SCOLA_EINVAL, "L must be > 0");
+  if (!is_pow2(c.Np) || c.Np < 8 || c.Np > 1024)
+    fail(SCOLA_EINVAL, "Np must be a power of two in [8, 1024]");
+  if (c.N_out < 0 || c.N_out > 2048) fail(SCOLA_EINVAL, "N_out must be in [0, 2048]");
+  if (c.n_steps < 1) fail(SCOLA_EINVAL, "n_steps must be >= 1");
+  if (!(c.a_i > 0 && c.a_i < c.a_f)) fail(SCOLA_EINVAL, "need 0 < a_i < a_f");
+  if (c.precision != SCOLA_FP32 && c.precision != SCOLA_FP64)
+    fail(SCOLA_EINVAL, "precision must be SCOLA_FP32 or SCOLA_FP64");
+  if (c.schedule != SCOLA_BATCHED && c.schedule != SCOLA_PER_TILE)
+    fail(SCOLA_EINVAL, "schedule must be SCOLA_BATCHED or SCOLA_PER_TILE");
+  if (!(cs.Omega_m > 0 && cs.Omega_m <= 1 && cs.Omega_b >= 0 && cs.Omega_b < cs.Omega_m &&
+        cs.h > 0 && cs.sigma8 > 0 && cs.T_cmb > 0))
+    fail(SCOLA_EINVAL, "cosmology out of range");
+  if (!tiles || n_tiles < 1) fail(SCOLA_EINVAL, "need at least one tile");
+  const int Np = c.Np;
+  std::vector<uint8_t> cover((size_t)Np * Np * Np, 0);
+  for (int t = 0; t < n_tiles; ++t) {
+    const scola_tile& s = tiles[t];
+    const int M = s.core_n + 2 * s.buffer;
+    if (s.core_n < 1 || s.buffer < 0) fail(SCOLA_EINVAL, "tile core_n >= 1, buffer >= 0");
+    if (M % 16 != 0 || M < 16 || M > kMaxM)
+      fail(SCOLA_EUNSUPPORTED, "tile " + std::to_string(t) + ": M = core_n + 2 buffer = " +
+                                   std::to_string(M) + " must be a multiple of 16 in [16, 128]");
+    if (s.core_n > Np || M > 4 * Np)
+      fail(SCOLA_EINVAL, "tile " + std::to_string(t) + " larger than the lattice");
+    for (int a = 0; a < 3; ++a)
+      if (s.core_lo[a] < 0 || s.core_lo[a] >= Np)
+        fail(SCOLA_EINVAL, "tile core_lo must be in [0, Np)");
+    for (int i = 0; i < s.core_n; ++i)
+      for (int j = 0; j < s.core_n; ++j)
+        for (int k = 0; k < s.core_n; ++k) {
+          const size_t x = (s.core_lo[0] + i) % Np, y = (s.core_lo[1] + j) % Np,
+                       z = (s.core_lo[2] + k) % Np;
+          uint8_t& o = cover[(x * Np + y) * Np + z];
+          if (o) fail(SCOLA_EINVAL, "tiles overlap (tile " + std::to_string(t) + ")");
+          o = 1;
+        }
+  }
+  for (uint8_t o : cover)
+    if (!o) fail(SCOLA_EINVAL, "tiles do not cover the lattice");
+}
+
+template <typename T>
+void upload_tables(scola_plan* p) {
+  // twiddles W_{2M}^m and FDA-2 eigenvalues -4 sin^2(pi l / (2M)) per distinct M (FP64 on
+  // the host, stored in the plan's precision)
+  std::map<int, std::pair<int, int>> offs;
+  std::vector<T> tw, ev;
+  for (auto& d : p->desc) {
+    if (offs.count(d.M)) continue;
+    const int tw_off = (int)(tw.size() / 2), ev_off = (int)ev.size();
+    const int N = 2 * d.M;
+    for (int m = 0; m < N; ++m) {
+      tw.push_back((T)std::cos(2.0 * M_PI * m / N));
+      tw.push_back((T)(-std::sin(2.0 * M_PI * m / N)));
+    }
+    for (int l = 1; l < d.M; ++l) {
+      const double s = std::sin(M_PI * l / (2.0 * d.M));
+      ev.push_back((T)(-4.0 * s * s));
+    }
+    offs[d.M] = {tw_off, ev_off};
+  }
+  for (auto& d : p->desc) {
+    d.tw_off = offs[d.M].first;
+    d.ev_off = offs[d.M].second;
+  }
+  hip_check(hipMalloc(&p->d_twiddles, tw.size() * sizeof(T)), "hipMalloc(twiddles)");
+  hip_check(hipMemcpy(p->d_twiddles, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice),
+            "hipMemcpy(twiddles)");
+  hip_check(hipMalloc(&p->d_eigen, ev.size() * sizeof(T)), "hipMalloc(eigen)");
+  hip_check(hipMemcpy(p->d_eigen, ev.data(), ev.size() * sizeof(T), hipMemcpyHostToDevice),
+            "hipMemcpy(eigen)");
+}
+
+void compute_step_table(const scola_config& c, const Background& bg, std::vector<double>& table,
+                        std::vector<double>& D1out, std::vector<double>& D2out);
+
+void build_step_table(scola_plan* p) {
+  compute_step_table(p->cfg, p->bg, p->table, p->D1, p->D2);
+}
+
+void compute_step_table(const scola_config& c, const Background& bg, std::vector<double>& table,
+                        std::vector<double>& D1out, std::vector<double>& D2out) {
+  const int n = c.n_steps;
+  std::vector<double> t(n + 1), half(n);
+  for (int k = 0; k <= n; ++k) t[k] = c.a_i + (c.a_f - c.a_i) * k / n;
+  for (int k = 0; k < n; ++k) half[k] = 0.5 * (t[k] + t[k + 1]);
+  std::vector<double> q(t);
+  q.push_back(c.a_i);
+  std::vector<double> D1, dD1, D2, dD2;
+  bg.growth(q, D1, dD1, D2, dD2);
+  const double n1 = D1[n + 1];                      // D1 normalised to 1 at a_i
+  D1out.assign(n + 1, 0.0);
+  D2out.assign(n + 1, 0.0);
+  for (int k = 0; k <= n; ++k) {
+    D1out[k] = D1[k] / n1;
+    D2out[k] = D2[k] / (n1 * n1);
+  }
+  const double nlpt = -2.5;   // App. B: u(a) = a^n_LPT with the paper's n_LPT = -2.5
+  table.assign((size_t)(n + 1) * 8, 0.0);
+  for (int k = 0; k < n; ++k) {
+    double* r = &table[(size_t)k * 8];
+    const double aKi = k == 0 ? t[0] : half[k - 1];
+    r[0] = t[k];
+    r[1] = bg.beta_tilde(aKi, half[k], t[k], nlpt);
+    r[2] = bg.alpha_tilde(t[k], t[k + 1], half[k], nlpt);
+    r[3] = D1out[k];
+    r[4] = D2out[k];
+    r[5] = D1out[k + 1];
+    r[6] = D2out[k + 1];
+    r[7] = t[k + 1];
+  }
+  double* r = &table[(size_t)n * 8];
+  const double af = t[n];
+  const double inv_drift = af * af * af * bg.E(af);   // 1 / drift prefactor
+  r[0] = af;
+  r[1] = bg.beta_tilde(half[n - 1], af, af, nlpt);
+  r[2] = D1out[n];
+  r[3] = D2out[n];
+  r[4] = -dD1[n] / n1 * inv_drift;                       // L+ : p_LPT coefficients
+  r[5] = dD2[n] / (n1 * n1) * inv_drift;
+}
+
+void build_layout(scola_plan* p) {
+  const size_t R = p->is64 ? 8 : 4;
+  const int64_t N = p->cfg.Np;
+  const int64_t No = p->cfg.N_out;
+  scola_layout& l = p->lay;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  l.psi1 = take(3 * (size_t)p->P * 8);
+  l.psi2 = take(3 * (size_t)p->P * 8);
+  l.x_res = take(3 * (size_t)p->P * R);
+  l.p_res = take(3 * (size_t)p->P * R);
+  l.rho = take((size_t)p->G * 8);
+  l.work = take((size_t)p->G * R);
+  l.phi = take((size_t)p->H * R);
+  l.bc0 = take((size_t)p->H * 8);
+  l.dropped = take(p->desc.size() * 8);
+  l.phi1 = take((size_t)(N * N * N) * 8);
+  l.phi2 = take((size_t)(N * N * N) * 8);
+  l.cbuf = take((size_t)(N * N * N) * 16);
+  l.outgrid = take((size_t)(No * No * No) * 8);
+  l.total = off;
+  l.n_particles = p->P;
+  l.n_nodes = p->G;
+  l.n_padded = p->H;
+}
+
+Background background_of(const scola_cosmology& c) {
+  Background bg;
+  bg.Om = c.Omega_m;
+  bg.Ob = c.Omega_b;
+  bg.h = c.h;
+  bg.ns = c.n_s;
+  bg.sigma8 = c.sigma8;
+  bg.Tcmb = c.T_cmb;
+  bg.normalise();
+  return bg;
+}
+
+char* ws_ptr(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
+void check_ws(const scola_plan* p, void* ws) {
+  if (!p) fail(SCOLA_EINVAL, "plan is NULL");
+  if (!ws) fail(SCOLA_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) fail(SCOLA_EINVAL, "workspace must be 256-byte aligned");
+  int dev = -1;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (dev != p->device) fail(SCOLA_EINVAL, "current device differs from the plan's device");
+}
+
+std::vector<int> subset_list(const scola_plan* p, const int32_t* subset, int32_t n) {
+  std::vector<int> out;
+  if (!subset) {
+    for (size_t t = 0; t < p->desc.size(); ++t) out.push_back((int)t);
+    return out;
+  }
+  if (n < 1) fail(SCOLA_EINVAL, "n_subset must be >= 1");
+  std::vector<uint8_t> seen(p->desc.size(), 0);
+  for (int i = 0; i < n; ++i) {
+    if (subset[i] < 0 || subset[i] >= (int)p->desc.size()) fail(SCOLA_EINVAL, "tile index out of range");
+    if (seen[subset[i]]) fail(SCOLA_EINVAL, "duplicate tile in subset");
+    seen[subset[i]] = 1;
+    out.push_back(subset[i]);
+  }
+  return out;
+}
+
+template <typename T>
+MeshArgs<T> mesh_args(scola_plan* p, void* ws, double D1_bc) {
+  MeshArgs<T> a;
+  a.tiles = p->d_tiles;
+  a.rho = reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.rho));
+  a.work = reinterpret_cast<T*>(ws_ptr(ws, p->lay.work));
+  a.phi = reinterpret_cast<T*>(ws_ptr(ws, p->lay.phi));
+  a.bc0 = reinterpret_cast<const double*>(ws_ptr(ws, p->lay.bc0));
+  a.twiddles = p->d_twiddles;
+  a.eigen = reinterpret_cast<const T*>(p->d_eigen);
+  a.D1_bc = D1_bc;
+  return a;
+}
+
+template <typename T>
+ParticleArgs<T> particle_args(scola_plan* p, void* ws, const StepScalars& sc) {
+  ParticleArgs<T> a;
+  a.tiles = p->d_tiles;
+  a.psi1 = reinterpret_cast<const double*>(ws_ptr(ws, p->lay.psi1));
+  a.psi2 = reinterpret_cast<const double*>(ws_ptr(ws, p->lay.psi2));
+  a.xres = reinterpret_cast<T*>(ws_ptr(ws, p->lay.x_res));
+  a.pres = reinterpret_cast<T*>(ws_ptr(ws, p->lay.p_res));
+  a.phi = reinterpret_cast<const T*>(ws_ptr(ws, p->lay.phi));
+  a.rho = reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.rho));
+  a.dropped = reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped));
+  a.P = p->P;
+  a.sc = sc;
+  return a;
+}
+
+// One call of each kernel family over a set of tiles: all in one launch (batched) or one
+// launch per tile.
+template <typename T>
+struct Runner {
+  scola_plan* p;
+  void* ws;
+  hipStream_t s;
+  std::vector<int> tiles;
+  bool batched;
+
+  std::vector<BlockMap> maps(const Maps& m) const {
+    std::vector<BlockMap> out;
+    if (batched) {
+      out.push_back(full_map(m));
+    } else {
+      for (int t : tiles) out.push_back(tile_map(m, t));
+    }
+    return out;
+  }
+  void particles(int mode, const StepScalars& sc) {
+    ParticleArgs<T> a = particle_args<T>(p, ws, sc);
+    for (auto& m : maps(p->part)) hip_check(launch_particles<T>(a, mode, m, s), "particle kernel");
+  }
+  void poisson(double D1_bc) {
+    MeshArgs<T> a = mesh_args<T>(p, ws, D1_bc);
+    if (batched) {
+      for (size_t c = 0; c < p->p1.class_M.size(); ++c) {
+        auto cls = [&](const Maps& m) {
+          BlockMap b = full_map(m);
+          b.base = m.class_first[c];
+          b.count = m.class_count[c];
+          return b;
+        };
+        hip_check(launch_poisson<T>(a, p->p1.class_M[c], cls(p->p1), cls(p->p2), cls(p->p3), s),
+                  "poisson kernels");
+      }
+    } else {
+      for (int t : tiles)
+        hip_check(launch_poisson<T>(a, p->desc[t].M, tile_map(p->p1, t), tile_map(p->p2, t),
+                                    tile_map(p->p3, t), s), "poisson kernels");
+    }
+  }
+};
+
+template <typename T>
+void do_setup(scola_plan* p, const double* w, void* ws, hipStream_t s) {
+  SetupArgs a;
+  a.white_noise = w;
+  a.cbuf = reinterpret_cast<double2*>(ws_ptr(ws, p->lay.cbuf));
+  a.phi1 = reinterpret_cast<double*>(ws_ptr(ws, p->lay.phi1));
+  a.phi2 = reinterpret_cast<double*>(ws_ptr(ws, p->lay.phi2));
+  a.N = p->cfg.Np;
+  a.L = p->cfg.L;
+  a.amplitude = p->bg.amplitude;
+  a.ns = p->bg.ns;
+  a.Om = p->bg.Om;
+  a.Ob = p->bg.Ob;
+  a.h = p->bg.h;
+  a.Tcmb = p->bg.Tcmb;
+  // P_lin(k, a_i) = P_lin(k, 1) (D1(a_i) / D1(1))^2 with D1 normalised at a_i
+  std::vector<double> q = {p->cfg.a_i, 1.0}, D1, dD1, D2, dD2;
+  p->bg.growth(q, D1, dD1, D2, dD2);
+  a.growth2 = (D1[0] / D1[1]) * (D1[0] / D1[1]);
+  hip_check(launch_setup_potentials(a, s), "set-up potentials");
+  BoxSetupArgs b;
+  b.tiles = p->d_tiles;
+  b.n_tiles = (int)p->desc.size();
+  b.blk_tile = p->part.d_tile;
+  b.blk_first = p->part.d_local;
+  b.n_blocks = (int)p->part.tile.size();
+  b.phi1 = a.phi1;
+  b.phi2 = a.phi2;
+  b.psi1 = reinterpret_cast<double*>(ws_ptr(ws, p->lay.psi1));
+  b.psi2 = reinterpret_cast<double*>(ws_ptr(ws, p->lay.psi2));
+  b.bc0 = reinterpret_cast<double*>(ws_ptr(ws, p->lay.bc0));
+  b.N = p->cfg.Np;
+  b.P = p->P;
+  hip_check(launch_setup_boxes<T>(b, reinterpret_cast<T*>(ws_ptr(ws, p->lay.x_res)),
+                                  reinterpret_cast<T*>(ws_ptr(ws, p->lay.p_res)), s),
+            "set-up boxes");
+  hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.rho)),
+                            p->G, s), "zero rho");
+}
+
+StepScalars row_scalars(const scola_plan* p, int k) {
+  const double* r = &p->table[(size_t)k * 8];
+  StepScalars sc{};
+  sc.beta = r[1];
+  sc.alpha = r[2];
+  sc.D1 = r[3];
+  sc.D2 = r[4];
+  sc.D1n = r[5];
+  sc.D2n = r[6];
+  return sc;
+}
+
+template <typename T>
+void do_evolve(scola_plan* p, const std::vector<int>& tiles, void* ws, hipStream_t s) {
+  const bool batched = p->cfg.schedule == SCOLA_BATCHED && tiles.size() == p->desc.size();
+  hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped)),
+                            (int64_t)p->desc.size(), s), "zero dropped");
+  const int n = p->cfg.n_steps;
+  auto run = [&](const std::vector<int>& set, bool b) {
+    Runner<T> r{p, ws, s, set, b};
+    StepScalars init{};
+    init.D1 = p->D1[0];
+    init.D2 = p->D2[0];
+    r.particles(kInit, init);               // L-: x_res = p_res = 0, deposit x_LPT(t_0)
+    r.poisson(p->D1[0]);
+    for (int k = 0; k < n; ++k) {
+      const bool need_force = k < n - 1 || p->cfg.want_momenta;
+      r.particles(need_force ? kStep : kStepNoDeposit, row_scalars(p, k));
+      if (need_force) r.poisson(p->D1[k + 1]);
+    }
+    if (p->cfg.want_momenta) {
+      const double* f = &p->table[(size_t)n * 8];
+      StepScalars sc{};
+      sc.beta = f[1];
+      sc.D1 = f[2];
+      sc.D2 = f[3];
+      sc.c1 = f[4];
+      sc.c2 = f[5];
+      r.particles(kFinalKick, sc);
+    }
+  };
+  if (batched) {
+    run(tiles, true);
+  } else {
+    for (int t : tiles) run(std::vector<int>{t}, false);   // plain per-tile schedule
+  }
+}
+
+template <typename T>
+void do_output(scola_plan* p, void* pos, void* mom, void* dens, const std::vector<int>& tiles,
+               void* ws, hipStream_t s) {
+  OutputArgs<T> a;
+  a.tiles = p->d_tiles;
+  a.psi1 = reinterpret_cast<const double*>(ws_ptr(ws, p->lay.psi1));
+  a.psi2 = reinterpret_cast<const double*>(ws_ptr(ws, p->lay.psi2));
+  a.xres = reinterpret_cast<const T*>(ws_ptr(ws, p->lay.x_res));
+  a.pres = reinterpret_cast<const T*>(ws_ptr(ws, p->lay.p_res));
+  a.pos = reinterpret_cast<T*>(pos);
+  a.mom = reinterpret_cast<T*>(mom);
+  a.grid = reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.outgrid));
+  a.P = p->P;
+  a.Np = p->cfg.Np;
+  a.N_out = p->cfg.N_out;
+  a.D1 = p->D1[p->cfg.n_steps];
+  a.D2 = p->D2[p->cfg.n_steps];
+  a.cell = p->cfg.L / p->cfg.Np;
+  a.L = p->cfg.L;
+  const bool all = tiles.size() == p->desc.size();
+  if (all) {
+    hip_check(launch_output<T>(a, full_map(p->part), dens != nullptr,
+                               reinterpret_cast<T*>(dens), s), "output kernel");
+  } else {
+    for (int t : tiles)
+      hip_check(launch_output<T>(a, tile_map(p->part, t), false, nullptr, s), "output kernel");
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* scola_status_string(scola_status s) {
+  switch (s) {
+    case SCOLA_OK: return "SCOLA_OK";
+    case SCOLA_EINVAL: return "SCOLA_EINVAL";
+    case SCOLA_ENOMEM: return "SCOLA_ENOMEM";
+    case SCOLA_EDEVICE: return "SCOLA_EDEVICE";
+    case SCOLA_ESTATE: return "SCOLA_ESTATE";
+    case SCOLA_EUNSUPPORTED: return "SCOLA_EUNSUPPORTED";
+  }
+  return "unknown scola_status";
+}
+
+const char* scola_last_error(void) { return g_last_error.c_str(); }
+
+scola_status scola_uniform_tiling(int32_t Np, int32_t tps, int32_t buffer, scola_tile* out,
+                                  int32_t capacity) {
+  return guarded([&] {
+    if (Np < 1 || tps < 1 || Np % tps) fail(SCOLA_EINVAL, "Np must be a multiple of tiles_per_side");
+    if (buffer < 0) fail(SCOLA_EINVAL, "buffer must be >= 0");
+    if (!out || capacity < tps * tps * tps) fail(SCOLA_EINVAL, "output capacity too small");
+    const int n = Np / tps;
+    int i = 0;
+    for (int x = 0; x < tps; ++x)
+      for (int y = 0; y < tps; ++y)
+        for (int z = 0; z < tps; ++z) {
+          scola_tile& t = out[i++];
+          t.core_lo[0] = x * n;
+          t.core_lo[1] = y * n;
+          t.core_lo[2] = z * n;
+          t.core_n = n;
+          t.buffer = buffer;
+        }
+  });
+}
+
+scola_status scola_plan_create(const scola_config* cfg, const scola_cosmology* cosmo,
+                               const scola_tile* tiles, int32_t n_tiles, scola_plan** out) {
+  if (out) *out = nullptr;
+  scola_plan* p = nullptr;
+  scola_status st = guarded([&] {
+    if (!cfg || !cosmo || !out) fail(SCOLA_EINVAL, "NULL argument");
+    validate(*cfg, *cosmo, tiles, n_tiles);
+    p = new scola_plan();
+    p->cfg = *cfg;
+    if (p->cfg.N_out == 0) p->cfg.N_out = cfg->Np;
+    p->cosmo = *cosmo;
+    p->is64 = cfg->precision == SCOLA_FP64;
+    p->tiles.assign(tiles, tiles + n_tiles);
+    hip_check(hipGetDevice(&p->device), "hipGetDevice");
+    p->bg = background_of(*cosmo);
+    int64_t P = 0, G = 0, H = 0;
+    for (int t = 0; t < n_tiles; ++t) {
+      const scola_tile& s = tiles[t];
+      TileDesc d{};
+      d.M = s.core_n + 2 * s.buffer;
+      for (int a = 0; a < 3; ++a) {
+        d.origin[a] = s.core_lo[a] - s.buffer;
+        d.core_lo[a] = s.buffer;
+      }
+      d.core_n = s.core_n;
+      d.p_off = P;
+      d.g_off = G;
+      d.h_off = H;
+      P += (int64_t)d.M * d.M * d.M;
+      G += (int64_t)(d.M - 1) * (d.M - 1) * (d.M - 1);
+      H += (int64_t)(d.M + 3) * (d.M + 3) * (d.M + 3);
+      p->max_M = std::max(p->max_M, d.M);
+      p->desc.push_back(d);
+    }
+    p->P = P;
+    p->G = G;
+    p->H = H;
+    build_step_table(p);
+    build_layout(p);
+    if (p->is64)
+      upload_tables<double>(p);
+    else
+      upload_tables<float>(p);
+    build_maps(p->part, p->desc, [](const TileDesc& d) { return d.M * d.M * d.M / kBlock; });
+    build_maps(p->p1, p->desc, [](const TileDesc& d) { return d.M - 1; });
+    build_maps(p->p2, p->desc, [](const TileDesc& d) {
+      return (d.M - 1) * ((d.M - 1 + kPencilChunk - 1) / kPencilChunk);
+    });
+    build_maps(p->p3, p->desc, [](const TileDesc& d) { return d.M - 1 + 4; });
+    upload_maps(p->part);
+    upload_maps(p->p1);
+    upload_maps(p->p2);
+    upload_maps(p->p3);
+    hip_check(hipMalloc(&p->d_tiles, p->desc.size() * sizeof(TileDesc)), "hipMalloc(tiles)");
+    hip_check(hipMemcpy(p->d_tiles, p->desc.data(), p->desc.size() * sizeof(TileDesc),
+                        hipMemcpyHostToDevice), "hipMemcpy(tiles)");
+    *out = p;
+  });
+  if (st != SCOLA_OK && p) scola_plan_destroy(p);
+  return st;
+}
+
+scola_status scola_plan_destroy(scola_plan* p) {
+  if (!p) return SCOLA_OK;
+  free_maps(p->part);
+  free_maps(p->p1);
+  free_maps(p->p2);
+  free_maps(p->p3);
+  if (p->d_tiles) hipFree(p->d_tiles);
+  if (p->d_twiddles) hipFree(p->d_twiddles);
+  if (p->d_eigen) hipFree(p->d_eigen);
+  delete p;
+  return SCOLA_OK;
+}
+
+scola_status scola_workspace_size(const scola_plan* p, size_t* bytes) {
+  return guarded([&] {
+    if (!p || !bytes) fail(SCOLA_EINVAL, "NULL argument");
+    *bytes = p->lay.total;
+  });
+}
+
+scola_status scola_workspace_layout(const scola_plan* p, scola_layout* out) {
+  return guarded([&] {
+    if (!p || !out) fail(SCOLA_EINVAL, "NULL argument");
+    *out = p->lay;
+  });
+}
+
+scola_status scola_setup(scola_plan* p, const double* w, void* ws, hipStream_t s) {
+  return guarded([&] {
+    check_ws(p, ws);
+    if (!w) fail(SCOLA_EINVAL, "white noise is NULL");
+    if (p->is64)
+      do_setup<double>(p, w, ws, s);
+    else
+      do_setup<float>(p, w, ws, s);
+    p->setup_ws = ws;
+  });
+}
+
+scola_status scola_evolve(scola_plan* p, const int32_t* subset, int32_t n_subset, void* ws,
+                          hipStream_t s) {
+  return guarded([&] {
+    check_ws(p, ws);
+    if (p->setup_ws != ws) fail(SCOLA_ESTATE, "scola_setup has not run on this workspace");
+    const std::vector<int> tiles = subset_list(p, subset, n_subset);
+    if (p->is64)
+      do_evolve<double>(p, tiles, ws, s);
+    else
+      do_evolve<float>(p, tiles, ws, s);
+  });
+}
+
+scola_status scola_output(scola_plan* p, void* pos, void* mom, void* dens,
+                          const int32_t* subset, int32_t n_subset, void* ws, hipStream_t s) {
+  return guarded([&] {
+    check_ws(p, ws);
+    const std::vector<int> tiles = subset_list(p, subset, n_subset);
+    if (dens && tiles.size() != p->desc.size())
+      fail(SCOLA_EINVAL, "the density needs every tile (pass d_density = NULL with a subset)");
+    if (mom && !p->cfg.want_momenta) fail(SCOLA_EINVAL, "d_mom needs cfg.want_momenta");
+    if (p->is64)
+      do_output<double>(p, pos, mom, dens, tiles, ws, s);
+    else
+      do_output<float>(p, pos, mom, dens, tiles, ws, s);
+  });
+}
+
+scola_status scola_forward(scola_plan* p, const double* w, void* pos, void* mom, void* dens,
+                           const int32_t* subset, int32_t n_subset, void* ws, hipStream_t s) {
+  scola_status st = scola_setup(p, w, ws, s);
+  if (st != SCOLA_OK) return st;
+  st = scola_evolve(p, subset, n_subset, ws, s);
+  if (st != SCOLA_OK) return st;
+  return scola_output(p, pos, mom, dens, subset, n_subset, ws, s);
+}
+
+scola_status scola_op_deposit(scola_plan* p, double D1, double D2, void* ws, hipStream_t s) {
+  return guarded([&] {
+    check_ws(p, ws);
+    hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.rho)),
+                              p->G, s), "zero rho");
+    hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped)),
+                              (int64_t)p->desc.size(), s), "zero dropped");
+    StepScalars sc{};
+    sc.D1 = D1;
+    sc.D2 = D2;
+    if (p->is64) {
+      Runner<double> r{p, ws, s, subset_list(p, nullptr, 0), true};
+      r.particles(kDepositOnly, sc);
+    } else {
+      Runner<float> r{p, ws, s, subset_list(p, nullptr, 0), true};
+      r.particles(kDepositOnly, sc);
+    }
+  });
+}
+
+scola_status scola_op_poisson(scola_plan* p, double D1_bc, void* ws, hipStream_t s) {
+  return guarded([&] {
+    check_ws(p, ws);
+    if (p->is64) {
+      Runner<double> r{p, ws, s, subset_list(p, nullptr, 0), true};
+      r.poisson(D1_bc);
+    } else {
+      Runner<float> r{p, ws, s, subset_list(p, nullptr, 0), true};
+      r.poisson(D1_bc);
+    }
+  });
+}
+
+scola_status scola_op_step(scola_plan* p, double beta, double alpha, double D1, double D2,
+                           double D1n, double D2n, int32_t deposit, void* ws, hipStream_t s) {
+  return guarded([&] {
+    check_ws(p, ws);
+    StepScalars sc{};
+    sc.beta = beta;
+    sc.alpha = alpha;
+    sc.D1 = D1;
+    sc.D2 = D2;
+    sc.D1n = D1n;
+    sc.D2n = D2n;
+    const int mode = deposit ? kStep : kStepNoDeposit;
+    if (p->is64) {
+      Runner<double> r{p, ws, s, subset_list(p, nullptr, 0), true};
+      r.particles(mode, sc);
+    } else {
+      Runner<float> r{p, ws, s, subset_list(p, nullptr, 0), true};
+      r.particles(mode, sc);
+    }
+  });
+}
+
+scola_status scola_op_final_kick(scola_plan* p, double beta, double D1, double D2, double c1,
+                                 double c2, void* ws, hipStream_t s) {
+  return guarded([&] {
+    check_ws(p, ws);
+    StepScalars sc{};
+    sc.beta = beta;
+    sc.D1 = D1;
+    sc.D2 = D2;
+    sc.c1 = c1;
+    sc.c2 = c2;
+    if (p->is64) {
+      Runner<double> r{p, ws, s, subset_list(p, nullptr, 0), true};
+      r.particles(kFinalKick, sc);
+    } else {
+      Runner<float> r{p, ws, s, subset_list(p, nullptr, 0), true};
+      r.particles(kFinalKick, sc);
+    }
+  });
+}
+
+scola_status scola_step_table(const scola_plan* p, double* rows, int32_t cap) {
+  return guarded([&] {
+    if (!p || !rows) fail(SCOLA_EINVAL, "NULL argument");
+    if (cap < p->cfg.n_steps + 1) fail(SCOLA_EINVAL, "rows_capacity < n_steps + 1");
+    std::memcpy(rows, p->table.data(), p->table.size() * sizeof(double));
+  });
+}
+
+scola_status scola_power_spectrum(const scola_plan* p, const double* k, double* out, int32_t n) {
+  return guarded([&] {
+    if (!p || (n > 0 && (!k || !out))) fail(SCOLA_EINVAL, "NULL argument");
+    for (int i = 0; i < n; ++i) out[i] = p->bg.power(k[i]);
+  });
+}
+
+scola_status scola_schedule_table(const scola_config* cfg, const scola_cosmology* cosmo,
+                                  double* rows, int32_t cap) {
+  return guarded([&] {
+    if (!cfg || !cosmo || !rows) fail(SCOLA_EINVAL, "NULL argument");
+    if (cfg->n_steps < 1 || !(cfg->a_i > 0 && cfg->a_i < cfg->a_f))
+      fail(SCOLA_EINVAL, "need n_steps >= 1 and 0 < a_i < a_f");
+    if (cap < cfg->n_steps + 1) fail(SCOLA_EINVAL, "rows_capacity < n_steps + 1");
+    Background bg = background_of(*cosmo);
+    std::vector<double> table, D1, D2;
+    compute_step_table(*cfg, bg, table, D1, D2);
+    std::memcpy(rows, table.data(), table.size() * sizeof(double));
+  });
+}
+
+scola_status scola_linear_power(const scola_cosmology* cosmo, const double* k, double* out,
+                                int32_t n) {
+  return guarded([&] {
+    if (!cosmo || (n > 0 && (!k || !out))) fail(SCOLA_EINVAL, "NULL argument");
+    Background bg = background_of(*cosmo);
+    for (int i = 0; i < n; ++i) out[i] = bg.power(k[i]);
+  });
+}
+
+scola_status scola_plan_info(const scola_plan* p, int32_t* n_tiles, int64_t* n_particles,
+                             double* r, double* pp) {
+  return guarded([&] {
+    if (!p) fail(SCOLA_EINVAL, "NULL plan");
+    const double np3 = (double)p->cfg.Np * p->cfg.Np * p->cfg.Np;
+    if (n_tiles) *n_tiles = (int32_t)p->desc.size();
+    if (n_particles) *n_particles = p->P;
+    if (r) *r = (double)p->P / np3;
+    if (pp) *pp = np3 * p->desc.size() / (double)p->P;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,250 @@
+"""GPU parity of the HIP path against the FP64 oracle, operator by operator and end to end.
+
+Every GPU call goes through the C ABI (libscola.so via the ctypes binding).  Inputs are
+seeded and synthetic; the oracle gets the same inputs.  Tolerances:
+  * integer work (fixed-point mass, conservation): exact;
+  * FP64 path: 1e-9 relative (the fixed-point deposit quantises weights to 2^-40);
+  * FP32 path: potential 3e-5 of its maximum; one step from an identical state moves
+    positions by less than 1e-5 cell away from the oracle (the bar is 1e-4 cell).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+FIX = 2.0 ** 40
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def make_sim(torch, precision="fp32", Np=32, L=128.0, tps=2, buffer=8, n_steps=4,
+             schedule="batched", want_momenta=False):
+    import paper_2003_04925_amd as S
+    tiles = S.uniform_tiling(Np, tps, buffer)
+    return S.Simulation(L, Np, tiles, n_steps, precision=precision, schedule=schedule,
+                        want_momenta=want_momenta)
+
+
+def oracle_setup(Np, L, seed):
+    from oracle.cosmology import Cosmology
+    from oracle.run import setup_full_box
+    c = Cosmology()
+    return setup_full_box(synthetic.white_noise(Np, seed), L, c, 0.05)
+
+
+def oracle_tile(sim, t):
+    from oracle.tiling import Tile
+    lo, n, b = sim.tiles[t]
+    return Tile(tuple(lo), n, b)
+
+
+def box(arr, off, M):
+    """Box particles of a workspace array, in lattice order (3, M, M, M)."""
+    from paper_2003_04925_amd import particle_order
+    return arr[:, off + particle_order(M)].reshape(3, M, M, M)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_setup_matches_oracle(torch, precision):
+    from oracle.tiling import boundary_potential0, extract_box_field
+    say("setup parity", precision)
+    sim = make_sim(torch, precision)
+    w = synthetic.white_noise(32, 11)
+    sim.setup(torch.from_numpy(w).cuda())
+    torch.cuda.synchronize()
+    phi1, phi2, psi1, psi2 = oracle_setup(32, 128.0, 11)
+    np.testing.assert_allclose(sim.view("phi1").cpu().numpy(), phi1, atol=1e-12 * np.abs(phi1).max())
+    np.testing.assert_allclose(sim.view("phi2").cpu().numpy(), phi2, atol=1e-11 * np.abs(phi2).max())
+    g1 = sim.view("psi1").cpu().numpy()
+    g2 = sim.view("psi2").cpu().numpy()
+    bc = sim.view("bc0").cpu().numpy()
+    for t, (po, M, go, ho) in enumerate(sim.box_slices()):
+        tile = oracle_tile(sim, t)
+        np.testing.assert_allclose(box(g1, po, M), extract_box_field(psi1, tile),
+                                   atol=1e-12 * np.abs(psi1).max())
+        np.testing.assert_allclose(box(g2, po, M), extract_box_field(psi2, tile),
+                                   atol=1e-11 * np.abs(psi2).max())
+        np.testing.assert_allclose(bc[ho:ho + (M + 3) ** 3].reshape((M + 3,) * 3),
+                                   boundary_potential0(phi1, tile), atol=1e-12 * np.abs(phi1).max())
+    assert float(sim.view("x_res").abs().max()) == 0.0
+
+
+def seeded_state(sim, torch, seed, spread=2.0, pscale=1.0):
+    P = sim.layout.n_particles
+    xr = synthetic.uniform((3, P), -spread, spread, seed)
+    pr = synthetic.normal((3, P), pscale, seed + 1)
+    sim.view("x_res").copy_(torch.from_numpy(xr).to(sim.real))
+    sim.view("p_res").copy_(torch.from_numpy(pr).to(sim.real))
+    torch.cuda.synchronize()
+    # the oracle sees exactly the values the GPU holds
+    return (sim.view("x_res").double().cpu().numpy(), sim.view("p_res").double().cpu().numpy())
+
+
+def box_positions(sim, psi1, psi2, xr, t, D1, D2):
+    """Oracle positions of box t in lattice order (3, M^3), from workspace arrays."""
+    from oracle.scola import lattice_positions
+    po, M, _, _ = sim.box_slices()[t]
+    q = lattice_positions(M).reshape(3, -1)
+    b = lambda a: box(a, po, M).reshape(3, -1)
+    return q - D1 * b(psi1) + D2 * b(psi2) + b(xr)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_deposit_matches_oracle_and_conserves_mass(torch, precision):
+    from oracle.scola import box_deposit
+    say("deposit parity", precision)
+    sim = make_sim(torch, precision)
+    sim.setup(torch.from_numpy(synthetic.white_noise(32, 12)).cuda())
+    xr, _ = seeded_state(sim, torch, 5, spread=3.0)
+    D1, D2 = 4.0, -7.0
+    sim.op_deposit(D1, D2)
+    torch.cuda.synchronize()
+    rho = sim.view("rho").cpu().numpy()
+    dropped = sim.view("dropped").cpu().numpy()
+    g1 = sim.view("psi1").cpu().numpy()
+    g2 = sim.view("psi2").cpu().numpy()
+    for t, (po, M, go, ho) in enumerate(sim.box_slices()):
+        r = rho[go:go + (M - 1) ** 3]
+        # every particle carries exactly 2^40 units, deposited or dropped (integer identity)
+        assert int(r.sum()) + int(dropped[t]) == M ** 3 * (1 << 40)
+        u = box_positions(sim, g1, g2, xr, t, D1, D2)
+        want, _ = box_deposit(u, M)
+        got = r.reshape((M - 1,) * 3).astype(np.float64) / FIX - 1.0
+        np.testing.assert_allclose(got, want, atol=1e-9)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_poisson_matches_oracle(torch, precision):
+    from oracle.poisson import dirichlet_potential
+    say("poisson parity", precision)
+    sim = make_sim(torch, precision)
+    sim.setup(torch.from_numpy(synthetic.white_noise(32, 13)).cuda())
+    xr, _ = seeded_state(sim, torch, 6, spread=2.0)
+    sim.op_deposit(3.0, -4.0)
+    torch.cuda.synchronize()
+    rho = sim.view("rho").cpu().numpy().copy()
+    D1 = 3.0
+    sim.op_poisson(D1)
+    torch.cuda.synchronize()
+    phi = sim.view("phi").double().cpu().numpy()
+    bc = sim.view("bc0").cpu().numpy()
+    assert int(np.abs(sim.view("rho").cpu().numpy()).max()) == 0     # left zeroed
+    tol = 1e-10 if precision == "fp64" else 3e-5
+    for t, (po, M, go, ho) in enumerate(sim.box_slices()):
+        delta = rho[go:go + (M - 1) ** 3].reshape((M - 1,) * 3) / FIX - 1.0
+        want = dirichlet_potential(delta, D1 * bc[ho:ho + (M + 3) ** 3].reshape((M + 3,) * 3))
+        got = phi[ho:ho + (M + 3) ** 3].reshape((M + 3,) * 3)
+        err = np.abs(got - want).max() / np.abs(want).max()
+        say("  tile", t, "rel err", err)
+        assert err < tol
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("M_buffer", [(2, 8), (1, 24)])
+def test_one_step_from_identical_state(torch, precision, M_buffer):
+    from oracle.scola import box_deposit, box_gradient, box_interpolate
+    tps, buf = M_buffer
+    say("one-step parity", precision, "tiles/side", tps, "buffer", buf)
+    Np = 32
+    sim = make_sim(torch, precision, Np=Np, tps=tps, buffer=buf)
+    sim.setup(torch.from_numpy(synthetic.white_noise(Np, 14)).cuda())
+    xr, pr = seeded_state(sim, torch, 7, spread=2.0, pscale=0.5)
+    D1, D2, D1n, D2n = 3.0, -4.0, 3.5, -5.3
+    beta, alpha = -0.05, 1.7
+    sim.op_deposit(D1, D2)
+    sim.op_poisson(D1)
+    torch.cuda.synchronize()
+    phi = sim.view("phi").double().cpu().numpy()
+    g1 = sim.view("psi1").cpu().numpy()
+    g2 = sim.view("psi2").cpu().numpy()
+    sim.op_step(beta, alpha, D1, D2, D1n, D2n, deposit=True)
+    torch.cuda.synchronize()
+    xr2 = sim.view("x_res").double().cpu().numpy()
+    pr2 = sim.view("p_res").double().cpu().numpy()
+    rho = sim.view("rho").cpu().numpy()
+    xtol = 1e-10 if precision == "fp64" else 1e-5
+    for t, (po, M, go, ho) in enumerate(sim.box_slices()):
+        b = lambda a: box(a, po, M).reshape(3, -1)
+        u = box_positions(sim, g1, g2, xr, t, D1, D2)
+        g = box_interpolate(box_gradient(phi[ho:ho + (M + 3) ** 3].reshape((M + 3,) * 3)), u)
+        p_want = b(pr) + beta * (g - D1 * b(g1) + (D2 - D1 ** 2) * b(g2))
+        x_want = b(xr) + alpha * p_want
+        perr = np.abs(b(pr2) - p_want).max()
+        xerr = np.abs(b(xr2) - x_want).max()
+        say("  tile", t, "max |dx| cells", xerr, "max |dp|", perr)
+        assert xerr < xtol
+        assert perr < xtol / alpha * 2
+        u2 = box_positions(sim, g1, g2, xr2, t, D1n, D2n)
+        want, _ = box_deposit(u2, M)
+        got = rho[go:go + (M - 1) ** 3].reshape((M - 1,) * 3) / FIX - 1.0
+        np.testing.assert_allclose(got, want, atol=1e-9)
+
+
+def test_fp64_run_matches_oracle_end_to_end(torch):
+    from oracle.run import run_scola
+    from oracle.tiling import uniform_tiling as otiling
+    say("end-to-end fp64 per-tile vs oracle")
+    Np, L, n = 32, 128.0, 4
+    sim = make_sim(torch, "fp64", Np=Np, L=L, n_steps=n, schedule="per_tile", want_momenta=True)
+    w = synthetic.white_noise(Np, 15)
+    out = sim.forward(torch.from_numpy(w).cuda())
+    torch.cuda.synchronize()
+    ora = run_scola(w, L, otiling(Np, 2, 8), n_steps=n, want_momenta=True)
+    cell = L / Np
+    d = (out["pos"].cpu().numpy() - ora["pos"]) / cell
+    d = (d + Np / 2) % Np - Np / 2
+    say("  max |dx| cells", np.abs(d).max())
+    assert np.abs(d).max() < 1e-8
+    np.testing.assert_allclose(out["mom"].cpu().numpy(), ora["mom"],
+                               atol=1e-8 * np.abs(ora["mom"]).max())
+    np.testing.assert_allclose(out["density"].cpu().numpy(), ora["density"], atol=1e-9)
+
+
+def test_fp32_batched_run_close_to_oracle(torch):
+    from oracle.run import run_scola
+    from oracle.tiling import uniform_tiling as otiling
+    say("end-to-end fp32 batched vs oracle")
+    Np, L, n = 32, 128.0, 4
+    sim = make_sim(torch, "fp32", Np=Np, L=L, n_steps=n)
+    w = synthetic.white_noise(Np, 15)
+    out = sim.forward(torch.from_numpy(w).cuda())
+    torch.cuda.synchronize()
+    ora = run_scola(w, L, otiling(Np, 2, 8), n_steps=n)
+    cell = L / Np
+    d = (out["pos"].double().cpu().numpy() - ora["pos"]) / cell
+    d = (d + Np / 2) % Np - Np / 2
+    say("  max |dx| cells", np.abs(d).max(), "p99.9", np.quantile(np.abs(d), 0.999))
+    assert np.abs(d).max() < 1e-3
+    assert np.abs(out["density"].double().cpu().numpy() - ora["density"]).max() < 1e-3
+
+
+def test_determinism_and_tile_recompute(torch):
+    say("determinism / tile subset")
+    Np = 32
+    sim = make_sim(torch, "fp32", Np=Np, n_steps=3)
+    w = torch.from_numpy(synthetic.white_noise(Np, 16)).cuda()
+    a = sim.forward(w)["pos"].clone()
+    b = sim.forward(w)["pos"].clone()
+    assert torch.equal(a, b)
+    sub = sim.forward(w, tile_subset=[5])["pos"]
+    lo, n, _ = sim.tiles[5]
+    sl = (slice(None),) + tuple(slice(c, c + n) for c in lo)
+    assert torch.equal(sub[sl], a[sl])
+    per = make_sim(torch, "fp32", Np=Np, n_steps=3, schedule="per_tile")
+    c = per.forward(w)["pos"]
+    assert torch.equal(c, a)
