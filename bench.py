@@ -127,6 +127,9 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="set-up, then only the single-launch kernel timings and a "
+                         "1 GiB device copy that calibrates the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the boxes are independent and this build has "
@@ -149,6 +152,20 @@ def main():
     sim.setup(w)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    if args.kernels_only:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        tab = sim.step_table()
+        row = tab[wl.n_steps // 2]
+        sim.evolve()
+        for _ in range(args.steps):
+            sim.op_poisson(row[3])
+            sim.op_step(row[1], row[2], row[3], row[4], row[3], row[4], True)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernels_only": True, "workload": wl.name}), flush=True)
+        return
     ms, wall = time_evolve(torch, sim, args.steps, args.warmup)
     value = P * wl.n_steps / (ms * 1e-3)
 

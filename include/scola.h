@@ -85,7 +85,7 @@ typedef struct scola_plan scola_plan;
 typedef struct {
   size_t psi1, psi2;       /* double [3][P]: Psi1 = grad phi1, Psi2 = grad phi2 (cells) */
   size_t x_res, p_res;     /* R [3][P]: COLA residual position and momentum (cells) */
-  size_t rho;              /* int64 [G]: fixed-point CiC mass, SCOLA_FIXED_ONE per particle */
+  size_t rho;              /* int64 [G]: fixed-point CiC mass, 2^fixed_bits per particle */
   size_t work;             /* R [G]: sine-space scratch of the Poisson solve */
   size_t phi;              /* R [H]: potential on the padded node grid [-1, M+1]^3 */
   size_t bc0;              /* double [H]: Phi_BC^0 (LEP boundary potential at D1 = 1) */
@@ -98,9 +98,10 @@ typedef struct {
   int64_t n_particles;     /* P */
   int64_t n_nodes;         /* G */
   int64_t n_padded;        /* H */
+  int32_t fixed_bits;      /* one particle's mass in rho: 2^40 (FP64 plans) or 2^30 (FP32) */
 } scola_layout;
 
-#define SCOLA_FIXED_BITS 40  /* CiC weights are accumulated as round(w * 2^40) in int64 */
+#define SCOLA_FIXED_BITS 40  /* output-density CiC weights are accumulated as round(w 2^40) */
 
 /* Fill out[0 .. tiles_per_side^3) with the uniform tiling of Sec. 3.2 (B.1): cores of
  * N_p / tiles_per_side particles, order x-major.  Np must be a multiple of tiles_per_side.

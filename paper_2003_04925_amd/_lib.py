@@ -47,7 +47,7 @@ class Layout(ctypes.Structure):
                 ("psi1", "psi2", "x_res", "p_res", "rho", "work", "phi", "bc0", "dropped",
                  "phi1", "phi2", "cbuf", "outgrid", "total")] + \
                [("n_particles", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
-                ("n_padded", ctypes.c_int64)]
+                ("n_padded", ctypes.c_int64), ("fixed_bits", ctypes.c_int32)]
 
 
 _lib = None

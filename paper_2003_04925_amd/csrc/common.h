@@ -8,9 +8,23 @@
 
 namespace scola {
 
-constexpr int kFixedBits = 40;                       // CiC weights as round(w * 2^40)
+constexpr int kFixedBits = 40;                       // output-grid CiC weights, 2^40
 constexpr double kFixedOne = 1099511627776.0;        // 2^40
 constexpr double kFixedInv = 1.0 / 1099511627776.0;
+
+// Fixed-point unit of one particle's mass in the box meshes: 2^40 for FP64 plans (weights
+// formed in FP64), 2^30 for FP32 plans (weights formed in FP32 and converted with one
+// 32-bit instruction; the quantum 2^-30 is far below the FP32 weight rounding).
+template <typename T>
+struct MeshFixed;
+template <>
+struct MeshFixed<double> {
+  static constexpr int bits = 40;
+};
+template <>
+struct MeshFixed<float> {
+  static constexpr int bits = 30;
+};
 constexpr int kMaxM = 128;                            // boxes of 16..128 particles per side
 constexpr int kBlock = 256;                           // threads of every mesh/particle block
 
@@ -33,6 +47,40 @@ struct StepScalars {
   double beta, alpha, D1, D2, D1n, D2n;
   double c1, c2;            // L+ coefficients (final kick only)
 };
+
+// Cross-lane exchange v[lane ^ S] within 32-lane groups without LDS traffic: xor 1 and 2
+// are DPP quad permutations; xor 4 = (xor 3 quad reverse) then (xor 7 half-row mirror);
+// xor 8 = (xor 7 half-row mirror) then (xor 15 row mirror); xor 16 crosses 16-lane rows and
+// uses ds_swizzle in bit-mask mode (and 0x1f, or 0, xor 0x10).
+template <int S>
+__device__ __forceinline__ int lane_xor(int v) {
+  static_assert(S == 1 || S == 2 || S == 4 || S == 8 || S == 16, "xor distance");
+  if constexpr (S == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);
+  if constexpr (S == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);
+  if constexpr (S == 4) {
+    const int t = __builtin_amdgcn_mov_dpp(v, 0x1B, 0xF, 0xF, true);
+    return __builtin_amdgcn_mov_dpp(t, 0x141, 0xF, 0xF, true);
+  }
+  if constexpr (S == 8) {
+    const int t = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);
+    return __builtin_amdgcn_mov_dpp(t, 0x140, 0xF, 0xF, true);
+  }
+  if constexpr (S == 16) return __builtin_amdgcn_ds_swizzle(v, 0x401F);
+  return v;
+}
+
+template <int S>
+__device__ __forceinline__ float lane_xor(float v) {
+  return __int_as_float(lane_xor<S>(__float_as_int(v)));
+}
+
+template <int S>
+__device__ __forceinline__ double lane_xor(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = lane_xor<S>((int)(b & 0xffffffffll));
+  const int hi = lane_xor<S>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 // Particles of a box are stored brick by brick: bricks of 4 x 8 x 8 lattice sites (256
 // particles, one thread block), bricks in lattice order, sites inside a brick in lattice

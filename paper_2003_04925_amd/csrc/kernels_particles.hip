@@ -35,7 +35,47 @@ inline unsigned padded_grid(const BlockMap& m) {
   return (unsigned)(((m.count + 7) / 8) * 8);
 }
 
-// Fixed-point CiC weights of the 8 corners (offset bits x = 4, y = 2, z = 1).
+// Wave-wide min / max: DPP exchanges inside 16-lane rows, then the four row results are
+// read into scalars; the result is uniform across the wave.
+__device__ __forceinline__ int wave_min(int v) {
+  v = min(v, lane_xor<1>(v));
+  v = min(v, lane_xor<2>(v));
+  v = min(v, lane_xor<4>(v));
+  v = min(v, lane_xor<8>(v));
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+__device__ __forceinline__ int wave_max(int v) {
+  v = max(v, lane_xor<1>(v));
+  v = max(v, lane_xor<2>(v));
+  v = max(v, lane_xor<4>(v));
+  v = max(v, lane_xor<8>(v));
+  return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
+constexpr int kWindow = 4096;   // int64 LDS accumulators per block (32 KiB)
+
+// Block-wide bounding box of per-thread integer ranges [lo, hi] (3 axes); threads with
+// any == false do not count.  Must be called by all threads of the block.
+__device__ inline void block_bounds(bool any, const int (&lo)[3], const int (&hi)[3],
+                                    int* bounds) {
+  if (threadIdx.x < 6) bounds[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -0x7fffffff;
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int a = wave_min(any ? lo[c] : 0x7fffffff);
+    const int b = wave_max(any ? hi[c] : -0x7fffffff);
+    if ((threadIdx.x & 63) == 0) {
+      atomicMin(bounds + c, a);
+      atomicMax(bounds + 3 + c, b);
+    }
+  }
+  __syncthreads();
+}
+
+// Fixed-point CiC weights of the 8 corners (offset bits x = 4, y = 2, z = 1); the eighth
+// corner gets the remainder so the eight sum to exactly one unit.
 __device__ inline void fixed_weights(double fx, double fy, double fz, long long (&w)[8]) {
   long long sum = 0;
 #pragma unroll
@@ -47,6 +87,35 @@ __device__ inline void fixed_weights(double fx, double fy, double fz, long long 
     sum += w[c];
   }
   w[7] = (long long)kFixedOne - sum;
+}
+
+template <typename T>
+__device__ inline void mesh_weights(double fx, double fy, double fz, long long (&w)[8]) {
+  if constexpr (MeshFixed<T>::bits == 40) {
+    fixed_weights(fx, fy, fz, w);
+  } else {
+    const float one = (float)(1 << MeshFixed<T>::bits);
+    const float ax[2] = {1.0f - (float)fx, (float)fx}, ay[2] = {1.0f - (float)fy, (float)fy},
+                az[2] = {1.0f - (float)fz, (float)fz};
+    int sum = 0;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      const int v = __float2int_rn(ax[(c >> 2) & 1] * ay[(c >> 1) & 1] * az[c & 1] * one);
+      w[c] = v;
+      sum += v;
+    }
+    w[7] = (1 << MeshFixed<T>::bits) - sum;
+  }
+}
+
+// Row-major decomposition e -> (ex, ey, ez) of a window with rows wy x wz, using FP32
+// reciprocals (exact for windows far below 2^20 entries) instead of integer division.
+__device__ inline void window_coords(int e, int wz, int wyz, float inv_wz, float inv_wyz,
+                                     int& ex, int& ey, int& ez) {
+  ex = (int)(((float)e + 0.5f) * inv_wyz);
+  const int r = e - ex * wyz;
+  ey = (int)(((float)r + 0.5f) * inv_wz);
+  ez = r - ey * wz;
 }
 
 // Corner range of one particle's CiC footprint restricted to interior nodes [1, n]:
@@ -66,18 +135,6 @@ __device__ inline bool deposit_footprint(int M, double ux, double uy, double uz,
   return true;
 }
 
-__device__ inline int wave_min(int v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o));
-  return v;
-}
-__device__ inline int wave_max(int v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
-  return v;
-}
-
-constexpr int kWindow = 4096;   // int64 LDS accumulators per block (32 KiB)
 
 // B^sCOLA for the 256 particles of one block (one Lagrangian brick): CiC of every particle
 // onto interior nodes [1, M-1]^3 of its box, privatised in an LDS window that covers the
@@ -85,6 +142,7 @@ constexpr int kWindow = 4096;   // int64 LDS accumulators per block (32 KiB)
 // footprint exceeds the window add straight into global memory.  Integer sums make both
 // paths give identical results.  Returns the fixed-point mass this thread dropped.
 // Must be called by all threads of the block.
+template <typename T>
 __device__ inline long long deposit_block(unsigned long long* __restrict__ rho, int M,
                                           bool active, double ux, double uy, double uz,
                                           unsigned long long* win, int* bounds) {
@@ -93,7 +151,7 @@ __device__ inline long long deposit_block(unsigned long long* __restrict__ rho, 
   double f[3] = {0, 0, 0};
   const bool in = active && deposit_footprint(M, ux, uy, uz, j0, f);
   long long w[8];
-  if (in) fixed_weights(f[0], f[1], f[2], w);
+  if (in) mesh_weights<T>(f[0], f[1], f[2], w);
   // interior corner range of this particle (empty when lo > hi)
   int lo[3], hi[3];
   bool any = in;
@@ -103,18 +161,7 @@ __device__ inline long long deposit_block(unsigned long long* __restrict__ rho, 
     hi[c] = min(j0[c] + 1, n);
     any = any && lo[c] <= hi[c];
   }
-  if (threadIdx.x < 6) bounds[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -0x7fffffff;
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const int a = wave_min(any ? lo[c] : 0x7fffffff);
-    const int b = wave_max(any ? hi[c] : -0x7fffffff);
-    if ((threadIdx.x & 63) == 0) {
-      atomicMin(bounds + c, a);
-      atomicMax(bounds + 3 + c, b);
-    }
-  }
-  __syncthreads();
+  block_bounds(any, lo, hi, bounds);
   const int lx = bounds[0], ly = bounds[1], lz = bounds[2];
   const int wx = bounds[3] - lx + 1, wy = bounds[4] - ly + 1, wz = bounds[5] - lz + 1;
   const bool empty = wx <= 0 || wy <= 0 || wz <= 0;
@@ -141,15 +188,17 @@ __device__ inline long long deposit_block(unsigned long long* __restrict__ rho, 
       }
     }
   } else if (active) {
-    dropped = (long long)kFixedOne;            // the whole particle lies outside
+    dropped = 1ll << MeshFixed<T>::bits;       // the whole particle lies outside
   }
   if (use_lds) {
     __syncthreads();
     const int wyz = wy * wz;
+    const float inv_wz = 1.0f / (float)wz, inv_wyz = 1.0f / (float)wyz;
     for (int e = threadIdx.x; e < vol; e += blockDim.x) {
       const unsigned long long v = win[e];
       if (v != 0ull) {
-        const int ex = e / wyz, r = e - ex * wyz, ey = r / wz, ez = r - ey * wz;
+        int ex, ey, ez;
+        window_coords(e, wz, wyz, inv_wz, inv_wyz, ex, ey, ez);
         atomicAdd(rho + ((int64_t)(lx + ex - 1) * n + (ly + ey - 1)) * n + (lz + ez - 1), v);
       }
     }
@@ -158,43 +207,90 @@ __device__ inline long long deposit_block(unsigned long long* __restrict__ rho, 
 }
 
 // grad^sCOLA + B-bar^sCOLA: central-difference gradient of the padded potential on nodes
-// [0, M]^3, CiC-interpolated at u; corners outside [0, M]^3 contribute nothing.
-template <typename T>
-__device__ inline void gather_force(const T* __restrict__ phi, int M, double ux, double uy,
-                                    double uz, T (&g)[3]) {
-  g[0] = g[1] = g[2] = T(0);
-  const double hi = (double)M + 1.0;
-  if (!(ux >= -1.0 && ux < hi && uy >= -1.0 && uy < hi && uz >= -1.0 && uz < hi)) return;
-  const double flx = floor(ux), fly = floor(uy), flz = floor(uz);
-  const int jx = (int)flx, jy = (int)fly, jz = (int)flz;
-  const T fx = (T)(ux - flx), fy = (T)(uy - fly), fz = (T)(uz - flz);
-  const int Mp = M + 3;
-  T wx[2] = {T(1) - fx, fx}, wy[2] = {T(1) - fy, fy}, wz[2] = {T(1) - fz, fz};
-  int cxs[2], cys[2], czs[2];
+// [0, M]^3, CiC-interpolated at u; corners outside [0, M]^3 contribute nothing.  `at(x, y,
+// z)` reads the potential at node (x, y, z) in [-1, M+1]^3.
+template <typename T, typename Idx, typename Ld>
+__device__ inline void gather_force(int M, const int (&j0)[3], const T (&fr)[3], Idx idx,
+                                    int sx, int sy, Ld ld, T (&g)[3]) {
+  // idx(x, y, z): storage index of node (x, y, z) in [-1, M+1]^3; neighbours along x, y, z
+  // are at +-sx, +-sy, +-1; ld(i) loads entry i.
+  T w[3][2];
+  int nc[3][2];
 #pragma unroll
-  for (int d = 0; d < 2; ++d) {
-    const int nx = jx + d, ny = jy + d, nz = jz + d;
-    if (nx < 0 || nx > M) wx[d] = T(0);
-    if (ny < 0 || ny > M) wy[d] = T(0);
-    if (nz < 0 || nz > M) wz[d] = T(0);
-    // clamp so that reads stay inside the padded grid; clamped corners have zero weight
-    cxs[d] = min(max(nx, 0), M) + 1;
-    cys[d] = min(max(ny, 0), M) + 1;
-    czs[d] = min(max(nz, 0), M) + 1;
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int n = j0[a] + d;
+      w[a][d] = (n < 0 || n > M) ? T(0) : (d ? fr[a] : T(1) - fr[a]);
+      // clamped corners have zero weight; clamping keeps every read inside [-1, M+1]
+      nc[a][d] = min(max(n, 0), M);
+    }
   }
   T gx = 0, gy = 0, gz = 0;
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
-    const T w = wx[dx] * wy[dy] * wz[dz];
-    const int64_t o = ((int64_t)cxs[dx] * Mp + cys[dy]) * Mp + czs[dz];
-    gx += w * (phi[o + (int64_t)Mp * Mp] - phi[o - (int64_t)Mp * Mp]);
-    gy += w * (phi[o + Mp] - phi[o - Mp]);
-    gz += w * (phi[o + 1] - phi[o - 1]);
+    const T wc = w[0][dx] * w[1][dy] * w[2][dz];
+    const int o = idx(nc[0][dx], nc[1][dy], nc[2][dz]);
+    gx += wc * (ld(o + sx) - ld(o - sx));
+    gy += wc * (ld(o + sy) - ld(o - sy));
+    gz += wc * (ld(o + 1) - ld(o - 1));
   }
   g[0] = T(0.5) * gx;
   g[1] = T(0.5) * gy;
   g[2] = T(0.5) * gz;
+}
+
+// Force at u for the 256 particles of a block: the potential nodes the block's stencils
+// touch are staged once in LDS (coalesced rows along z) and gathered from there; a block
+// whose footprint exceeds the window gathers from global memory.  Must be called by all
+// threads of the block.
+template <typename T>
+__device__ inline void block_force(const T* __restrict__ phi, int M, double ux, double uy,
+                                   double uz, T* win, int* bounds, T (&g)[3]) {
+  g[0] = g[1] = g[2] = T(0);
+  const double hiu = (double)M + 1.0;
+  const bool in = ux >= -1.0 && ux < hiu && uy >= -1.0 && uy < hiu && uz >= -1.0 && uz < hiu;
+  const double u[3] = {ux, uy, uz};
+  int j0[3] = {0, 0, 0};
+  T fr[3] = {T(0), T(0), T(0)};
+  int lo[3], hi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (in) {
+      const double fl = floor(u[a]);
+      j0[a] = (int)fl;
+      fr[a] = (T)(u[a] - fl);
+    }
+    lo[a] = max(j0[a] - 1, -1);
+    hi[a] = min(j0[a] + 2, M + 1);
+  }
+  block_bounds(in, lo, hi, bounds);
+  const int lx = bounds[0], ly = bounds[1], lz = bounds[2];
+  const int wx = bounds[3] - lx + 1, wy = bounds[4] - ly + 1, wz = bounds[5] - lz + 1;
+  const bool empty = wx <= 0 || wy <= 0 || wz <= 0;
+  const int vol = empty ? 0 : wx * wy * wz;
+  const int Mp = M + 3;
+  if (!empty && vol <= kWindow) {
+    const int wyz = wy * wz;
+    const float inv_wz = 1.0f / (float)wz, inv_wyz = 1.0f / (float)wyz;
+#pragma unroll 4
+    for (int e = threadIdx.x; e < vol; e += blockDim.x) {
+      int ex, ey, ez;
+      window_coords(e, wz, wyz, inv_wz, inv_wyz, ex, ey, ez);
+      win[e] = phi[((int64_t)(lx + ex + 1) * Mp + (ly + ey + 1)) * Mp + (lz + ez + 1)];
+    }
+    __syncthreads();
+    if (in)
+      gather_force<T>(M, j0, fr,
+                      [&](int x, int y, int z) { return ((x - lx) * wy + (y - ly)) * wz + (z - lz); },
+                      wyz, wz, [&](int i) { return win[i]; }, g);
+  } else if (in) {
+    gather_force<T>(M, j0, fr,
+                    [&](int x, int y, int z) { return ((x + 1) * Mp + (y + 1)) * Mp + (z + 1); },
+                    Mp * Mp, Mp, [&](int i) { return phi[i]; }, g);
+  }
+  __syncthreads();   // every thread is done with `bounds` and the window before reuse
 }
 
 template <typename T, int MODE>
@@ -231,11 +327,13 @@ __global__ void __launch_bounds__(kBlock) k_particles(ParticleArgs<T> a, BlockMa
   double u[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) u[c] = q[c] - sc.D1 * s1[c] + sc.D2 * s2[c] + (double)xr[c];
+  __shared__ unsigned long long win[kWindow];
+  __shared__ int bounds[6];
   if (MODE != kDepositOnly && MODE != kInit) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) pr[c] = a.pres[c * P + p];
     T g[3];
-    gather_force<T>(a.phi + t.h_off, M, u[0], u[1], u[2], g);
+    block_force<T>(a.phi + t.h_off, M, u[0], u[1], u[2], reinterpret_cast<T*>(win), bounds, g);
     const double d2 = sc.D2 - sc.D1 * sc.D1;
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -255,11 +353,9 @@ __global__ void __launch_bounds__(kBlock) k_particles(ParticleArgs<T> a, BlockMa
 #pragma unroll
     for (int c = 0; c < 3; ++c) u[c] = q[c] - sc.D1n * s1[c] + sc.D2n * s2[c] + (double)xr[c];
   }
-  __shared__ unsigned long long win[kWindow];
-  __shared__ int bounds[6];
   __shared__ unsigned long long block_drop;
   if (threadIdx.x == 0) block_drop = 0ull;
-  const long long drop = deposit_block(a.rho + t.g_off, M, true, u[0], u[1], u[2], win, bounds);
+  const long long drop = deposit_block<T>(a.rho + t.g_off, M, true, u[0], u[1], u[2], win, bounds);
   if (drop != 0) atomicAdd(&block_drop, (unsigned long long)drop);
   __syncthreads();
   if (threadIdx.x == 0 && block_drop != 0ull) atomicAdd(a.dropped + ti, block_drop);

@@ -62,92 +62,136 @@ __device__ inline int logical_block(const BlockMap& m) {
   return (b & 7) * per + (b >> 3);
 }
 
-// FFT of length 32R on one half wavefront; lane l holds x[32 n2 + l], n2 < R.  On return
-// lane l holds Z[k1 + R bitrev5(l)] in x[k1].  tw = W_{32R}^m, m < 32R (in LDS).
-template <int R, typename T>
-__device__ inline void halfwave_fft(cx<T> (&x)[R], const cx<T>* __restrict__ tw, int l) {
-  cx<T> y[R];
-  if constexpr (R == 1) {
-    y[0] = x[0];
-  } else {
-    cx<T> wr[R];
+// One radix-2 decimation-in-frequency stage across lanes (partner lane l ^ S) of K x R
+// independent 32-point transforms.
+template <int S, int R, int K, typename T>
+__device__ __forceinline__ void dif_stage(cx<T> (&x)[K][R], const cx<T>* __restrict__ tw,
+                                          int l) {
+  const bool upper = (l & S) != 0;
+  const cx<T> w = tw[(l & (S - 1)) * (16 / S) * R];                    // W_{2S}^(l mod S)
 #pragma unroll
-    for (int m = 0; m < R; ++m) wr[m] = tw[m * 32];       // W_R^m
-#pragma unroll
-    for (int k1 = 0; k1 < R; ++k1) {
-      cx<T> acc = x[0];
-#pragma unroll
-      for (int n2 = 1; n2 < R; ++n2) acc = c_add(acc, c_mul(x[n2], wr[(n2 * k1) % R]));
-      y[k1] = acc;
-    }
-#pragma unroll
-    for (int k1 = 1; k1 < R; ++k1) y[k1] = c_mul(y[k1], tw[l * k1]);   // W_N^(n1 k1)
-  }
-#pragma unroll
-  for (int s = 16; s >= 1; s >>= 1) {
-    const bool upper = (l & s) != 0;
-    const cx<T> w = tw[(l & (s - 1)) * (16 / s) * R];                  // W_{2s}^(l mod s)
+  for (int k = 0; k < K; ++k)
 #pragma unroll
     for (int k1 = 0; k1 < R; ++k1) {
       cx<T> p;
-      p.x = __shfl_xor(y[k1].x, s);
-      p.y = __shfl_xor(y[k1].y, s);
-      y[k1] = upper ? c_mul(c_sub(p, y[k1]), w) : c_add(y[k1], p);
+      p.x = lane_xor<S>(x[k][k1].x);
+      p.y = lane_xor<S>(x[k][k1].y);
+      x[k][k1] = upper ? c_mul(c_sub(p, x[k][k1]), w) : c_add(x[k][k1], p);
     }
-  }
-#pragma unroll
-  for (int k1 = 0; k1 < R; ++k1) x[k1] = y[k1];
 }
 
-// In-place DST-I (unnormalised, eq. DST_delta) of two lines a, b of n = 16R - 1 values at
-// stride `stride` in LDS; output k (1..n) is multiplied by sa(k) / sb(k).
-template <int R, typename T, typename SA, typename SB>
-__device__ inline void dst_pair(T* la, T* lb, int stride, bool has_b, const cx<T>* tw, int l,
-                                SA sa, SB sb) {
-  constexpr int M = 16 * R;
-  cx<T> x[R];
+// K independent FFTs of length 32R on one half wavefront (interleaved for ILP); lane l holds
+// x[k][n2] = input k at position 32 n2 + l, n2 < R.  On return lane l holds Z_k at
+// position k1 + R bitrev5(l) in x[k][k1].  tw = W_{32R}^m, m < 32R (in LDS).
+template <int R, int K, typename T>
+__device__ __forceinline__ void halfwave_fft(cx<T> (&x)[K][R], const cx<T>* __restrict__ tw, int l) {
+  if constexpr (R > 1) {
+    cx<T> wr[R];
 #pragma unroll
-  for (int n2 = 0; n2 < R; ++n2) {
-    const int m = 32 * n2 + l;
-    cx<T> v;
-    v.x = T(0);
-    v.y = T(0);
-    if (m != 0 && m != M) {
-      const bool lo = m < M;
-      const int idx = lo ? m - 1 : 2 * M - m - 1;
-      const T sg = lo ? T(1) : T(-1);
-      v.x = sg * la[idx * stride];
-      if (has_b) v.y = sg * lb[idx * stride];
+    for (int m = 0; m < R; ++m) wr[m] = tw[m * 32];       // W_R^m
+    cx<T> tl[R];
+#pragma unroll
+    for (int k1 = 1; k1 < R; ++k1) tl[k1] = tw[l * k1];    // W_N^(n1 k1)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      cx<T> y[R];
+#pragma unroll
+      for (int k1 = 0; k1 < R; ++k1) {
+        cx<T> acc = x[k][0];
+#pragma unroll
+        for (int n2 = 1; n2 < R; ++n2) acc = c_add(acc, c_mul(x[k][n2], wr[(n2 * k1) % R]));
+        y[k1] = k1 ? c_mul(acc, tl[k1]) : acc;
+      }
+#pragma unroll
+      for (int k1 = 0; k1 < R; ++k1) x[k][k1] = y[k1];
     }
-    x[n2] = v;
   }
-  halfwave_fft<R, T>(x, tw, l);
+  dif_stage<16, R, K, T>(x, tw, l);
+  dif_stage<8, R, K, T>(x, tw, l);
+  dif_stage<4, R, K, T>(x, tw, l);
+  dif_stage<2, R, K, T>(x, tw, l);
+  dif_stage<1, R, K, T>(x, tw, l);
+}
+
+// In-place DST-I (unnormalised, eq. DST_delta) of K pairs of lines (a_k, b_k), each n =
+// 16R - 1 values at stride `stride` in LDS; output j (1..n) of pair k is multiplied by
+// sa(k, j) / sb(k, j).  Pairs with valid[k] false are neither read nor written.
+template <int R, int K, typename T, typename SA, typename SB>
+__device__ __forceinline__ void dst_pairs(T* const (&la)[K], T* const (&lb)[K], const bool (&valid)[K],
+                                 const bool (&has_b)[K], int stride, const cx<T>* tw, int l,
+                                 SA sa, SB sb) {
+  constexpr int M = 16 * R;
+  cx<T> x[K][R];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int n2 = 0; n2 < R; ++n2) {
+      const int m = 32 * n2 + l;
+      cx<T> v;
+      v.x = T(0);
+      v.y = T(0);
+      if (valid[k] && m != 0 && m != M) {
+        const bool lo = m < M;
+        const int idx = lo ? m - 1 : 2 * M - m - 1;
+        const T sg = lo ? T(1) : T(-1);
+        v.x = sg * la[k][idx * stride];
+        if (has_b[k]) v.y = sg * lb[k][idx * stride];
+      }
+      x[k][n2] = v;
+    }
+  halfwave_fft<R, K, T>(x, tw, l);
   const int br = bitrev5(l);
 #pragma unroll
-  for (int k1 = 0; k1 < R; ++k1) {
-    const int k = k1 + R * br;
-    if (k >= 1 && k <= M - 1) {
-      la[(k - 1) * stride] = T(-0.5) * x[k1].y * sa(k);
-      if (has_b) lb[(k - 1) * stride] = T(0.5) * x[k1].x * sb(k);
+  for (int k = 0; k < K; ++k) {
+    if (!valid[k]) continue;
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) {
+      const int j = k1 + R * br;
+      if (j >= 1 && j <= M - 1) {
+        la[k][(j - 1) * stride] = T(-0.5) * x[k][k1].y * sa(k, j);
+        if (has_b[k]) lb[k][(j - 1) * stride] = T(0.5) * x[k][k1].x * sb(k, j);
+      }
     }
   }
 }
 
-// DST-I along z (rows) then y (columns) of an n x n plane in LDS (row pitch n).
+// DST-I along z (rows) then y (columns) of an n x n plane in LDS (row pitch n): 8R line
+// pairs per direction, R per half wavefront, two at a time.
 template <int R, typename T>
-__device__ inline void plane_dst(T* plane, const cx<T>* tw) {
+__device__ __forceinline__ void plane_dst(T* plane, const cx<T>* tw) {
   constexpr int n = 16 * R - 1;
   const int hw = threadIdx.x >> 5, l = threadIdx.x & 31;
-  auto one = [](int) { return T(1); };
-#pragma unroll 2
-  for (int p = hw; p < 8 * R; p += 8)
-    dst_pair<R, T>(plane + 2 * p * n, plane + (2 * p + 1) * n, 1, 2 * p + 1 < n, tw, l, one,
-                   one);
-  __syncthreads();
-#pragma unroll 2
-  for (int p = hw; p < 8 * R; p += 8)
-    dst_pair<R, T>(plane + 2 * p, plane + 2 * p + 1, n, 2 * p + 1 < n, tw, l, one, one);
-  __syncthreads();
+  auto one = [](int, int) { return T(1); };
+  // two line pairs in flight per half wavefront while registers allow (R <= 4)
+  constexpr int K = R <= 4 ? 2 : 1;
+#pragma unroll 1
+  for (int dir = 0; dir < 2; ++dir) {
+    // dir 0: rows (z lines, stride 1); dir 1: columns (y lines, stride n)
+    const int stride = dir ? n : 1;
+    const int step = dir ? 1 : n;   // distance between consecutive lines
+    if constexpr (K == 2) {
+#pragma unroll
+      for (int i = 0; i < R; i += 2) {
+        const int p0 = hw + 8 * i, p1 = hw + 8 * (i + 1);
+        T* const la[2] = {plane + 2 * p0 * step, plane + 2 * p1 * step};
+        T* const lb[2] = {plane + (2 * p0 + 1) * step, plane + (2 * p1 + 1) * step};
+        const bool valid[2] = {true, i + 1 < R};
+        const bool hb[2] = {2 * p0 + 1 < n, i + 1 < R && 2 * p1 + 1 < n};
+        dst_pairs<R, 2, T>(la, lb, valid, hb, stride, tw, l, one, one);
+      }
+    } else {
+#pragma unroll 1
+      for (int i = 0; i < R; ++i) {
+        const int p0 = hw + 8 * i;
+        T* const la[1] = {plane + 2 * p0 * step};
+        T* const lb[1] = {plane + (2 * p0 + 1) * step};
+        const bool valid[1] = {true};
+        const bool hb[1] = {2 * p0 + 1 < n};
+        dst_pairs<R, 1, T>(la, lb, valid, hb, stride, tw, l, one, one);
+      }
+    }
+    __syncthreads();
+  }
 }
 
 template <typename T>
@@ -171,20 +215,31 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m
   const int64_t base = t.g_off + (int64_t)x * n * n;
   const double* bc = a.bc0 + t.h_off;
   const double D1 = a.D1_bc;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int y = e / n, z = e - (e / n) * n;
-    const long long r = (long long)a.rho[base + e];
-    a.rho[base + e] = 0ull;
-    double d = (double)r * kFixedInv - 1.0;
-    // delta' = delta - Delta Phi_BCs: face-layer neighbours of the first interior layer
-    // (padded index = node index + 1; interior node index = array index + 1)
-    if (x == 0) d -= D1 * bc[((int64_t)1 * Mp + y + 2) * Mp + z + 2];
-    if (x == n - 1) d -= D1 * bc[((int64_t)(M + 1) * Mp + y + 2) * Mp + z + 2];
-    if (y == 0) d -= D1 * bc[((int64_t)(x + 2) * Mp + 1) * Mp + z + 2];
-    if (y == n - 1) d -= D1 * bc[((int64_t)(x + 2) * Mp + M + 1) * Mp + z + 2];
-    if (z == 0) d -= D1 * bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + 1];
-    if (z == n - 1) d -= D1 * bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + M + 1];
-    plane[e] = (T)d;
+  constexpr int kBatch = 8;   // independent loads in flight per thread
+  for (int e0 = 0; e0 < n * n; e0 += kBatch * kBlock) {
+    long long r[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const int e = e0 + q * kBlock + threadIdx.x;
+      r[q] = e < n * n ? (long long)a.rho[base + e] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const int e = e0 + q * kBlock + threadIdx.x;
+      if (e >= n * n) continue;
+      a.rho[base + e] = 0ull;
+      const int y = e / n, z = e - (e / n) * n;
+      double d = (double)r[q] * (1.0 / (double)(1ll << MeshFixed<T>::bits)) - 1.0;
+      // delta' = delta - Delta Phi_BCs: face-layer neighbours of the first interior layer
+      // (padded index = node index + 1; interior node index = array index + 1)
+      if (x == 0) d -= D1 * bc[((int64_t)1 * Mp + y + 2) * Mp + z + 2];
+      if (x == n - 1) d -= D1 * bc[((int64_t)(M + 1) * Mp + y + 2) * Mp + z + 2];
+      if (y == 0) d -= D1 * bc[((int64_t)(x + 2) * Mp + 1) * Mp + z + 2];
+      if (y == n - 1) d -= D1 * bc[((int64_t)(x + 2) * Mp + M + 1) * Mp + z + 2];
+      if (z == 0) d -= D1 * bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + 1];
+      if (z == n - 1) d -= D1 * bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + M + 1];
+      plane[e] = (T)d;
+    }
   }
   __syncthreads();
   plane_dst<R, T>(plane, tw);
@@ -192,31 +247,31 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m
 }
 
 template <int R, typename T>
-__device__ inline void pencil_solve(T* tile, int pitch, int cw, int y, int z0, const T* ev,
+__device__ __forceinline__ void pencil_solve(T* tile, int pitch, int cw, int y, int z0, const T* ev,
                                     const cx<T>* tw) {
   constexpr int M = 16 * R;
   const int hw = threadIdx.x >> 5, l = threadIdx.x & 31;
   const T norm = T(8.0 / ((double)M * M * M));
   const T ly = ev[y];
+  // column pairs (2p, 2p+1) of the chunk, p = hw and hw + 8
+  const int p[2] = {hw, hw + 8};
+  T* const la[2] = {tile + 2 * p[0], tile + 2 * p[1]};
+  T* const lb[2] = {tile + 2 * p[0] + 1, tile + 2 * p[1] + 1};
+  const bool valid[2] = {2 * p[0] < cw, 2 * p[1] < cw};
+  const bool hb[2] = {2 * p[0] + 1 < cw, 2 * p[1] + 1 < cw};
+  T lza[2], lzb[2];
 #pragma unroll
-  for (int it = 0; it < kPencilChunk / 16; ++it) {
-    const int p = hw + 8 * it;
-    if (2 * p < cw) {
-      const T lza = ev[z0 + 2 * p];
-      const T lzb = 2 * p + 1 < cw ? ev[z0 + 2 * p + 1] : T(-1);
-      auto sa = [&](int k) { return norm / (ev[k - 1] + ly + lza); };
-      auto sb = [&](int k) { return norm / (ev[k - 1] + ly + lzb); };
-      dst_pair<R, T>(tile + 2 * p, tile + 2 * p + 1, pitch, 2 * p + 1 < cw, tw, l, sa, sb);
-    }
+  for (int k = 0; k < 2; ++k) {
+    lza[k] = valid[k] ? ev[z0 + 2 * p[k]] : T(-1);
+    lzb[k] = hb[k] ? ev[z0 + 2 * p[k] + 1] : T(-1);
   }
-  __syncthreads();
-  auto one = [](int) { return T(1); };
-#pragma unroll
-  for (int it = 0; it < kPencilChunk / 16; ++it) {
-    const int p = hw + 8 * it;
-    if (2 * p < cw)
-      dst_pair<R, T>(tile + 2 * p, tile + 2 * p + 1, pitch, 2 * p + 1 < cw, tw, l, one, one);
-  }
+  // forward DST along x, then Phi^{lmn} = delta^{lmn} 8/M^3 / (lambda_l + lambda_m + lambda_n)
+  auto sa = [&](int k, int j) { return norm / (ev[j - 1] + ly + lza[k]); };
+  auto sb = [&](int k, int j) { return norm / (ev[j - 1] + ly + lzb[k]); };
+  dst_pairs<R, 2, T>(la, lb, valid, hb, pitch, tw, l, sa, sb);
+  // the same half wavefront reads back only the lines it wrote
+  auto one = [](int, int) { return T(1); };
+  dst_pairs<R, 2, T>(la, lb, valid, hb, pitch, tw, l, one, one);
   __syncthreads();
 }
 
@@ -236,6 +291,7 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p2(MeshArgs<T> a, BlockMap m
   T* tile = reinterpret_cast<T*>(smem + 2 * kMaxM * sizeof(cx<T>));
   load_twiddles(tw, a, t);
   const int64_t base = t.g_off + (int64_t)y * n + z0;
+#pragma unroll 8
   for (int e = threadIdx.x; e < n * cw; e += blockDim.x) {
     const int x = e / cw, zc = e - (e / cw) * cw;
     tile[x * pitch + zc] = a.work[base + (int64_t)x * n * n + zc];
@@ -274,6 +330,7 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p3(MeshArgs<T> a, BlockMap m
   load_twiddles(tw, a, t);
   const int x = local;
   const int64_t base = t.g_off + (int64_t)x * n * n;
+#pragma unroll 8
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) plane[e] = a.work[base + e];
   __syncthreads();
   plane_dst<R, T>(plane, tw);

@@ -314,6 +314,7 @@ void build_layout(scola_plan* p) {
   l.n_particles = p->P;
   l.n_nodes = p->G;
   l.n_padded = p->H;
+  l.fixed_bits = p->is64 ? MeshFixed<double>::bits : MeshFixed<float>::bits;
 }
 
 Background background_of(const scola_cosmology& c) {

@@ -16,7 +16,6 @@ import synthetic
 
 pytestmark = pytest.mark.gpu
 
-FIX = 2.0 ** 40
 
 
 def say(*a):
@@ -51,6 +50,13 @@ def oracle_tile(sim, t):
     from oracle.tiling import Tile
     lo, n, b = sim.tiles[t]
     return Tile(tuple(lo), n, b)
+
+
+def dep_tol(precision):
+    """Deposit tolerance per node: FP64 plans form CiC weights in FP64 and quantise them to
+    2^-40; FP32 plans form them in FP32 (relative rounding 2^-24 per weight, a node collects
+    ~8-30 weights) and quantise to 2^-30."""
+    return 1e-9 if precision == "fp64" else 2e-6
 
 
 def box(arr, off, M):
@@ -121,11 +127,12 @@ def test_deposit_matches_oracle_and_conserves_mass(torch, precision):
     for t, (po, M, go, ho) in enumerate(sim.box_slices()):
         r = rho[go:go + (M - 1) ** 3]
         # every particle carries exactly 2^40 units, deposited or dropped (integer identity)
-        assert int(r.sum()) + int(dropped[t]) == M ** 3 * (1 << 40)
+        bits = sim.layout.fixed_bits
+        assert int(r.sum()) + int(dropped[t]) == M ** 3 * (1 << bits)
         u = box_positions(sim, g1, g2, xr, t, D1, D2)
         want, _ = box_deposit(u, M)
-        got = r.reshape((M - 1,) * 3).astype(np.float64) / FIX - 1.0
-        np.testing.assert_allclose(got, want, atol=1e-9)
+        got = r.reshape((M - 1,) * 3).astype(np.float64) / 2.0 ** bits - 1.0
+        np.testing.assert_allclose(got, want, atol=dep_tol(precision))
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
@@ -146,7 +153,7 @@ def test_poisson_matches_oracle(torch, precision):
     assert int(np.abs(sim.view("rho").cpu().numpy()).max()) == 0     # left zeroed
     tol = 1e-10 if precision == "fp64" else 3e-5
     for t, (po, M, go, ho) in enumerate(sim.box_slices()):
-        delta = rho[go:go + (M - 1) ** 3].reshape((M - 1,) * 3) / FIX - 1.0
+        delta = rho[go:go + (M - 1) ** 3].reshape((M - 1,) * 3) / 2.0 ** sim.layout.fixed_bits - 1.0
         want = dirichlet_potential(delta, D1 * bc[ho:ho + (M + 3) ** 3].reshape((M + 3,) * 3))
         got = phi[ho:ho + (M + 3) ** 3].reshape((M + 3,) * 3)
         err = np.abs(got - want).max() / np.abs(want).max()
@@ -191,8 +198,8 @@ def test_one_step_from_identical_state(torch, precision, M_buffer):
         assert perr < xtol / alpha * 2
         u2 = box_positions(sim, g1, g2, xr2, t, D1n, D2n)
         want, _ = box_deposit(u2, M)
-        got = rho[go:go + (M - 1) ** 3].reshape((M - 1,) * 3) / FIX - 1.0
-        np.testing.assert_allclose(got, want, atol=1e-9)
+        got = rho[go:go + (M - 1) ** 3].reshape((M - 1,) * 3) / 2.0 ** sim.layout.fixed_bits - 1.0
+        np.testing.assert_allclose(got, want, atol=dep_tol(precision))
 
 
 def test_fp64_run_matches_oracle_end_to_end(torch):
