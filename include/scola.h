@@ -98,7 +98,7 @@ typedef struct {
   int64_t n_particles;     /* P */
   int64_t n_nodes;         /* G */
   int64_t n_padded;        /* H */
-  int32_t fixed_bits;      /* one particle's mass in rho: 2^40 (FP64 plans) or 2^30 (FP32) */
+  int32_t fixed_bits;      /* one particle's mass in rho: 2^40 (FP64 plans) or 2^23 (FP32) */
 } scola_layout;
 
 #define SCOLA_FIXED_BITS 40  /* output-density CiC weights are accumulated as round(w 2^40) */

@@ -13,17 +13,21 @@ constexpr double kFixedOne = 1099511627776.0;        // 2^40
 constexpr double kFixedInv = 1.0 / 1099511627776.0;
 
 // Fixed-point unit of one particle's mass in the box meshes: 2^40 for FP64 plans (weights
-// formed in FP64), 2^30 for FP32 plans (weights formed in FP32 and converted with one
-// 32-bit instruction; the quantum 2^-30 is far below the FP32 weight rounding).
+// formed in FP64, block windows accumulated in 64-bit integers), 2^23 for FP32 plans
+// (weights formed in FP32 and converted with one 32-bit instruction; the quantum 2^-23 is
+// the FP32 weight rounding).  With 2^23 a 256-particle block window fits 32-bit integers
+// (at most 256 * 2^23 = 2^31 units on one node), which halves its LDS footprint.
 template <typename T>
 struct MeshFixed;
 template <>
 struct MeshFixed<double> {
   static constexpr int bits = 40;
+  using window_t = unsigned long long;
 };
 template <>
 struct MeshFixed<float> {
-  static constexpr int bits = 30;
+  static constexpr int bits = 23;
+  using window_t = unsigned int;
 };
 constexpr int kMaxM = 128;                            // boxes of 16..128 particles per side
 constexpr int kBlock = 256;                           // threads of every mesh/particle block

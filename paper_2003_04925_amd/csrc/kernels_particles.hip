@@ -54,7 +54,7 @@ __device__ __forceinline__ int wave_max(int v) {
              max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
-constexpr int kWindow = 4096;   // int64 LDS accumulators per block (32 KiB)
+constexpr int kWindow = 4096;   // LDS window entries per block (potential or mass)
 
 // Block-wide bounding box of per-thread integer ranges [lo, hi] (3 axes); threads with
 // any == false do not count.  Must be called by all threads of the block.
@@ -145,7 +145,8 @@ __device__ inline bool deposit_footprint(int M, double ux, double uy, double uz,
 template <typename T>
 __device__ inline long long deposit_block(unsigned long long* __restrict__ rho, int M,
                                           bool active, double ux, double uy, double uz,
-                                          unsigned long long* win, int* bounds) {
+                                          typename MeshFixed<T>::window_t* win, int* bounds) {
+  using W = typename MeshFixed<T>::window_t;
   const int n = M - 1;
   int j0[3] = {0, 0, 0};
   double f[3] = {0, 0, 0};
@@ -168,7 +169,7 @@ __device__ inline long long deposit_block(unsigned long long* __restrict__ rho, 
   const int vol = empty ? 0 : wx * wy * wz;
   const bool use_lds = !empty && vol <= kWindow;
   if (use_lds) {
-    for (int e = threadIdx.x; e < vol; e += blockDim.x) win[e] = 0ull;
+    for (int e = threadIdx.x; e < vol; e += blockDim.x) win[e] = W(0);
     __syncthreads();
   }
   long long dropped = 0;
@@ -181,7 +182,7 @@ __device__ inline long long deposit_block(unsigned long long* __restrict__ rho, 
         dropped += w[c];
       } else if (w[c] != 0) {
         if (use_lds)
-          atomicAdd(win + ((nx - lx) * wy + (ny - ly)) * wz + (nz - lz), (unsigned long long)w[c]);
+          atomicAdd(win + ((nx - lx) * wy + (ny - ly)) * wz + (nz - lz), (W)w[c]);
         else
           atomicAdd(rho + ((int64_t)(nx - 1) * n + (ny - 1)) * n + (nz - 1),
                     (unsigned long long)w[c]);
@@ -195,7 +196,7 @@ __device__ inline long long deposit_block(unsigned long long* __restrict__ rho, 
     const int wyz = wy * wz;
     const float inv_wz = 1.0f / (float)wz, inv_wyz = 1.0f / (float)wyz;
     for (int e = threadIdx.x; e < vol; e += blockDim.x) {
-      const unsigned long long v = win[e];
+      const unsigned long long v = (unsigned long long)win[e];
       if (v != 0ull) {
         int ex, ey, ez;
         window_coords(e, wz, wyz, inv_wz, inv_wyz, ex, ey, ez);
@@ -294,7 +295,8 @@ __device__ inline void block_force(const T* __restrict__ phi, int M, double ux, 
 }
 
 template <typename T, int MODE>
-__global__ void __launch_bounds__(kBlock) k_particles(ParticleArgs<T> a, BlockMap m) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6)))
+k_particles(ParticleArgs<T> a, BlockMap m) {
   const int L = logical_block(m);
   if (L >= m.count) return;
   const int b = m.base + L;
@@ -327,7 +329,9 @@ __global__ void __launch_bounds__(kBlock) k_particles(ParticleArgs<T> a, BlockMa
   double u[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) u[c] = q[c] - sc.D1 * s1[c] + sc.D2 * s2[c] + (double)xr[c];
-  __shared__ unsigned long long win[kWindow];
+  // one LDS window, first for the potential (kWindow T values), then for the block's mass
+  // (kWindow fixed-point accumulators)
+  __shared__ unsigned long long win[kWindow * sizeof(T) / 8];
   __shared__ int bounds[6];
   if (MODE != kDepositOnly && MODE != kInit) {
 #pragma unroll
@@ -355,7 +359,9 @@ __global__ void __launch_bounds__(kBlock) k_particles(ParticleArgs<T> a, BlockMa
   }
   __shared__ unsigned long long block_drop;
   if (threadIdx.x == 0) block_drop = 0ull;
-  const long long drop = deposit_block<T>(a.rho + t.g_off, M, true, u[0], u[1], u[2], win, bounds);
+  const long long drop = deposit_block<T>(a.rho + t.g_off, M, true, u[0], u[1], u[2],
+                                          reinterpret_cast<typename MeshFixed<T>::window_t*>(win),
+                                          bounds);
   if (drop != 0) atomicAdd(&block_drop, (unsigned long long)drop);
   __syncthreads();
   if (threadIdx.x == 0 && block_drop != 0ull) atomicAdd(a.dropped + ti, block_drop);
