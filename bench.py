@@ -119,6 +119,37 @@ def cpu_baseline(wl, budget_s=20.0):
                        f"included), FP64 NumPy, 1 thread, {platform.processor() or 'host CPU'}")
 
 
+def adjoint_timing(torch, S, synthetic, reps=3):
+    """Workload c4 (the c2 boxes, 20 steps FP32, checkpoints every 5 steps): forward with
+    checkpoints and the reverse pass (segment recompute + adjoint steps + FP64 set-up
+    adjoint), HIP-event timed on the current stream."""
+    wl = synthetic.WORKLOADS["c4"]
+    sim = S.Simulation(wl.L, wl.Np, S.uniform_tiling(wl.Np, wl.tiles_per_side, wl.buffer),
+                       wl.n_steps, precision="fp32", checkpoint_every=5)
+    w = torch.from_numpy(synthetic.white_noise(wl.Np, 42)).cuda()
+    t = torch.from_numpy(synthetic.loss_target(wl.Np, 43)).cuda().float()
+    sim.setup(w)
+    dens = torch.empty((wl.Np,) * 3, dtype=torch.float32, device="cuda")
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    fw, bw = [], []
+    for r in range(reps + 1):
+        a, b, c = ev(), ev(), ev()
+        a.record()
+        sim.evolve()
+        sim.output(density=dens)
+        b.record()
+        sim.backward(2.0 * (dens - t))
+        c.record()
+        torch.cuda.synchronize()
+        if r:
+            fw.append(a.elapsed_time(b))
+            bw.append(c.elapsed_time(b))
+    f, g = sum(fw) / reps, sum(bw) / reps
+    return {"workload": "c4: c2 boxes, 20 FP32 steps, density loss, checkpoint every 5",
+            "forward_ms": f, "backward_ms": g, "backward_over_forward": g / f,
+            "note": "backward = segment recomputation + adjoint steps + FP64 set-up adjoint"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +158,7 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--kernels-only", action="store_true",
                     help="set-up, then only the single-launch kernel timings and a "
                          "1 GiB device copy that calibrates the HBM byte counters")
@@ -237,6 +269,8 @@ def main():
         result["fp32_batched_same_workload"] = {
             "workload": "c1 in FP32 batched", "value": sim32.info()["n_particles"] *
             wl1.n_steps / (ms32 * 1e-3), "speedup_vs_fp64_per_tile": ms64 / ms32}
+    if not args.no_adjoint and args.workload == "c2":
+        result["adjoint"] = adjoint_timing(torch, S, synthetic)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(result), flush=True)

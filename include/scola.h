@@ -75,6 +75,9 @@ typedef struct {
   int32_t schedule;        /* SCOLA_BATCHED or SCOLA_PER_TILE */
   int32_t want_momenta;    /* nonzero: evaluate the last force and apply the final half
                               kick and L+ (App. B) so momenta are available */
+  int32_t checkpoint_every;/* 0: forward only.  c > 0: the forward stores (x_res, p_res)
+                              before steps 0, c, 2c, ... and scola_backward is available
+                              (it recomputes each segment of c steps) */
 } scola_config;
 
 typedef struct scola_plan scola_plan;
@@ -94,6 +97,16 @@ typedef struct {
   size_t phi1, phi2;       /* double [N^3]: Lagrangian potentials (Sec. 3.1, A.2) */
   size_t cbuf;             /* double2 [N^3]: FFT scratch */
   size_t outgrid;          /* int64 [N_out^3]: fixed-point output density */
+  /* reverse mode (all 0 when cfg.checkpoint_every == 0); c = checkpoint_every */
+  size_t ckpt;             /* R [ceil(n_steps/c)][6][P]: (x_res, p_res) before steps 0, c, ... */
+  size_t seg_x;            /* R [c][3][P]: x_res at each step of the segment being reversed */
+  size_t seg_phi;          /* R [c][H]: potential at each step of that segment */
+  size_t lam_x, lam_p;     /* R [3][P]: adjoints of x_res and p_res */
+  size_t lam_psi1, lam_psi2; /* double [3][P]: accumulated adjoints of Psi1, Psi2 */
+  size_t lam_G;            /* R [3][H]: transpose of the CiC interpolation on the nodes */
+  size_t lam_rho;          /* R [G]: adjoint of the deposited mass */
+  size_t lam_bc0;          /* double [H]: accumulated adjoint of Phi_BC^0 */
+  size_t adj_grid;         /* double [14][N^3]: set-up adjoint fields */
   size_t total;            /* workspace size in bytes */
   int64_t n_particles;     /* P */
   int64_t n_nodes;         /* G */
@@ -136,6 +149,20 @@ scola_status scola_workspace_layout(const scola_plan* plan, scola_layout* out);
 scola_status scola_forward(scola_plan* plan, const double* d_white_noise, void* d_pos,
                            void* d_mom, void* d_density, const int32_t* tile_subset,
                            int32_t n_subset, void* d_workspace, hipStream_t stream);
+
+/* Reverse mode of scola_forward for a loss on the output density: given d loss / d delta_out
+ * (R [N_out^3], device), writes d loss / d white noise (double [N_p^3], device).  Needs a
+ * plan with checkpoint_every > 0 and a preceding scola_forward over all tiles on the same
+ * workspace (else SCOLA_ESTATE).  Segments of checkpoint_every steps are recomputed from
+ * the checkpoints, then reversed step by step: transpose of the drift and kick, of the CiC
+ * interpolation (3-component scatter), of the gradient, the same Dirichlet DST solve (the
+ * FDA-2 Dirichlet Laplacian is symmetric) and of the deposit; finally the FP64 transposes
+ * of Phi_BC^0, Psi = D phi, the second-order source and the initial-condition filter.
+ * The particle state left in the workspace afterwards is that of the first segment;
+ * run scola_evolve again before scola_output. */
+scola_status scola_backward(scola_plan* plan, const void* d_grad_density,
+                            double* d_grad_white_noise, void* d_workspace,
+                            hipStream_t stream);
 
 /* Steps A.1-A.2 and C.1-C.3 (Sec. 3.1, 3.3) in FP64: white noise -> delta_i via the
  * Eisenstein-Hu spectrum (convolution approach), phi1 and phi2 with the FDA-2 kernel,

@@ -11,7 +11,8 @@ from . import _lib
 from ._lib import (SCOLA_BATCHED, SCOLA_FP32, SCOLA_FP64, SCOLA_PER_TILE, FIXED_BITS,
                    ScolaError)
 
-__all__ = ["Simulation", "CosmologyParams", "uniform_tiling", "particle_order", "schedule_table",
+__all__ = ["Simulation", "DensityFunction", "CosmologyParams", "uniform_tiling",
+           "particle_order", "schedule_table",
            "linear_power", "ScolaError", "SCOLA_FP32", "SCOLA_FP64", "SCOLA_BATCHED",
            "SCOLA_PER_TILE", "FIXED_BITS"]
 
@@ -52,11 +53,12 @@ def uniform_tiling(Np, tiles_per_side, buffer):
     return [(tuple(t.core_lo), t.core_n, t.buffer) for t in arr]
 
 
-def _config(L, Np, n_steps, a_i, a_f, precision, schedule, want_momenta, N_out):
+def _config(L, Np, n_steps, a_i, a_f, precision, schedule, want_momenta, N_out,
+            checkpoint_every=0):
     prec = {"fp32": SCOLA_FP32, "fp64": SCOLA_FP64}[precision]
     sch = {"batched": SCOLA_BATCHED, "per_tile": SCOLA_PER_TILE}[schedule]
     return _lib.Config(float(L), int(Np), int(N_out or 0), int(n_steps), float(a_i),
-                       float(a_f), prec, sch, 1 if want_momenta else 0)
+                       float(a_f), prec, sch, 1 if want_momenta else 0, int(checkpoint_every))
 
 
 def schedule_table(n_steps, a_i=0.05, a_f=1.0, cosmology=None):
@@ -93,7 +95,7 @@ class Simulation:
 
     def __init__(self, L, Np, tiles, n_steps, a_i=0.05, a_f=1.0, precision="fp32",
                  schedule="batched", want_momenta=False, N_out=None, cosmology=None,
-                 device=None):
+                 device=None, checkpoint_every=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("a HIP device is required (the engine has no CPU path)")
@@ -108,7 +110,9 @@ class Simulation:
         self.real = torch.float64 if precision == "fp64" else torch.float32
         self.want_momenta = bool(want_momenta)
         self.tiles = [(tuple(int(c) for c in lo), int(n), int(b)) for lo, n, b in tiles]
-        cfg = _config(L, Np, n_steps, a_i, a_f, precision, schedule, want_momenta, N_out)
+        self.checkpoint_every = int(checkpoint_every)
+        cfg = _config(L, Np, n_steps, a_i, a_f, precision, schedule, want_momenta, N_out,
+                      checkpoint_every)
         cosmo = (cosmology or CosmologyParams()).c()
         arr = (_lib.Tile * len(self.tiles))()
         for i, (lo, n, b) in enumerate(self.tiles):
@@ -195,6 +199,16 @@ class Simulation:
             sub, n, self._ws, self._stream()))
         return dict(pos=pos, mom=mom, density=dens)
 
+    def backward(self, grad_density):
+        """d loss / d white noise (float64, [Np]^3) for d loss / d density (plan dtype,
+        [N_out]^3); needs checkpoint_every > 0 and a preceding forward()."""
+        t = self.torch
+        grad_w = t.empty((self.Np,) * 3, dtype=t.float64, device=self.device)
+        _lib.check(_lib.lib().scola_backward(
+            self._plan, self._ptr(grad_density.contiguous(), self.real, (self.N_out,) * 3),
+            self._ptr(grad_w, t.float64, grad_w.shape), self._ws, self._stream()))
+        return grad_w
+
     def setup(self, white_noise):
         t = self.torch
         _lib.check(_lib.lib().scola_setup(
@@ -260,3 +274,36 @@ class Simulation:
             G += (M - 1) ** 3
             H += (M + 3) ** 3
         return out
+
+
+class DensityFunction:
+    """torch.autograd.Function: white noise (float64) -> output density (plan dtype).
+
+    backward() runs the library's reverse mode (scola_backward), i.e. the hand-written
+    adjoint of the whole chain, and returns d loss / d white noise."""
+
+    @staticmethod
+    def apply(sim, white_noise):
+        return _density_fn().apply(white_noise, sim)
+
+
+_FN = None
+
+
+def _density_fn():
+    global _FN
+    if _FN is None:
+        import torch
+
+        class _Density(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, w, sim):
+                ctx.sim = sim
+                return sim.forward(w, density=True)["density"]
+
+            @staticmethod
+            def backward(ctx, grad_out):
+                return ctx.sim.backward(grad_out.to(ctx.sim.real)), None
+
+        _FN = _Density
+    return _FN

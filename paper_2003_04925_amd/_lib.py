@@ -39,13 +39,16 @@ class Config(ctypes.Structure):
     _fields_ = [("L", ctypes.c_double), ("Np", ctypes.c_int32), ("N_out", ctypes.c_int32),
                 ("n_steps", ctypes.c_int32), ("a_i", ctypes.c_double),
                 ("a_f", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("want_momenta", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("want_momenta", ctypes.c_int32),
+                ("checkpoint_every", ctypes.c_int32)]
 
 
 class Layout(ctypes.Structure):
     _fields_ = [(n, ctypes.c_size_t) for n in
                 ("psi1", "psi2", "x_res", "p_res", "rho", "work", "phi", "bc0", "dropped",
-                 "phi1", "phi2", "cbuf", "outgrid", "total")] + \
+                 "phi1", "phi2", "cbuf", "outgrid", "ckpt", "seg_x", "seg_phi", "lam_x",
+                 "lam_p", "lam_psi1", "lam_psi2", "lam_G", "lam_rho", "lam_bc0", "adj_grid",
+                 "total")] + \
                [("n_particles", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
                 ("n_padded", ctypes.c_int64), ("fixed_bits", ctypes.c_int32)]
 
@@ -66,6 +69,7 @@ _SIGS = {
     "scola_workspace_layout": ([_P, ctypes.POINTER(Layout)], _I),
     "scola_forward": ([_P, _P, _P, _P, _P, ctypes.POINTER(_I), _I, _P, _P], _I),
     "scola_setup": ([_P, _P, _P, _P], _I),
+    "scola_backward": ([_P, _P, _P, _P, _P], _I),
     "scola_evolve": ([_P, ctypes.POINTER(_I), _I, _P, _P], _I),
     "scola_output": ([_P, _P, _P, _P, ctypes.POINTER(_I), _I, _P, _P], _I),
     "scola_op_deposit": ([_P, _D, _D, _P, _P], _I),

@@ -53,6 +53,10 @@ struct MeshArgs {
   const void* twiddles;     // complex T, per M: 2M entries W_{2M}^m
   const T* eigen;           // per M: lambda_l, l = 1..M-1 (FDA-2, unit spacing)
   double D1_bc;
+  // adjoint solve only: the source is read from `work`, the result written to lam_rho, and
+  // the boundary-source transpose accumulated into lam_bc0
+  T* lam_rho = nullptr;
+  double* lam_bc0 = nullptr;
 };
 
 template <typename T>
@@ -84,16 +88,37 @@ struct OutputArgs {
   double D1, D2, cell, L;
 };
 
+// Arrays and scalars of one reverse step (or of the output transpose).
+template <typename T>
+struct AdjointArgs {
+  const TileDesc* tiles;
+  const double* psi1;
+  const double* psi2;
+  const T* xk;              // x_res at the step's time, [3][P]
+  T* lam_x;                 // adjoint of x_res, [3][P]
+  T* lam_p;                 // adjoint of p_res, [3][P]
+  double* lam_psi1;         // accumulated adjoint of Psi1, [3][P]
+  double* lam_psi2;         // accumulated adjoint of Psi2, [3][P]
+  T* lam_G;                 // interpolation transpose on the padded nodes, [3][H]
+  const T* phi;             // potential at the step's time, [H]
+  const T* lam_rho;         // adjoint of the deposited mass, [G]
+  int64_t P, H;
+  double alpha, beta, D1, D2;
+};
+
 enum ParticleMode { kDepositOnly = 0, kStep = 1, kStepNoDeposit = 2, kFinalKick = 3, kInit = 4 };
 
 hipError_t launch_setup_potentials(const SetupArgs& a, hipStream_t s);
 template <typename T>
 hipError_t launch_setup_boxes(const BoxSetupArgs& a, T* xres, T* pres, hipStream_t s);
 
-// One size class (all blocks of the maps belong to boxes with this M).
+// One size class (all blocks of the maps belong to boxes with this M).  adjoint: solve
+// Delta lam = work with zero boundary values (the Dirichlet operator is symmetric), write
+// lam_rho, and add -D1_bc C^T lam to lam_bc0 (C maps face values onto the first interior
+// layer in delta' = delta - Delta Phi_BCs).
 template <typename T>
 hipError_t launch_poisson(const MeshArgs<T>& a, int M, const BlockMap& p1, const BlockMap& p2,
-                          const BlockMap& p3, hipStream_t s);
+                          const BlockMap& p3, hipStream_t s, bool adjoint = false);
 template <typename T>
 hipError_t launch_particles(const ParticleArgs<T>& a, int mode, const BlockMap& m,
                             hipStream_t s);
@@ -101,6 +126,29 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_output(const OutputArgs<T>& a, const BlockMap& m, bool density,
                          T* density_out, hipStream_t s);
+
+template <typename T>
+hipError_t launch_adj_output(const AdjointArgs<T>& a, const BlockMap& m, const T* lam_dens,
+                             int Np, int N_out, hipStream_t s);
+// stage 0: drift/kick transpose + interpolation scatter; 1: gradient transpose;
+// 2: gather of lam_u (run after the adjoint Poisson solve of stage 1's output)
+template <typename T>
+hipError_t launch_adj_step(const AdjointArgs<T>& a, const BlockMap& part, int stage, T* work,
+                           double* lam_bc0, int n_tiles, hipStream_t s);
+hipError_t launch_adj_setup_scatter(const BoxSetupArgs& b, const double* lam_psi1,
+                                    const double* lam_psi2, double* lam_psig,
+                                    const double* lam_bc0, double* lam_phi1, hipStream_t s);
+hipError_t launch_adj_phi_from_psi(const double* lam_psig, double* lam_phi1, double2* cbuf,
+                                   int N, hipStream_t s);
+hipError_t launch_adj_source(const double* phi1, const double* lam_s, double* f6,
+                             double* lam_phi1, int N, hipStream_t s);
+hipError_t launch_real_to_complex(const double* in, double2* out, int64_t n, hipStream_t s);
+// FP64 set-up pieces reused by the adjoint
+hipError_t fft3d_forward(double2* c, int N, hipStream_t s);
+hipError_t fft3d_inverse(double2* c, int N, hipStream_t s);
+hipError_t launch_ic_filter(const SetupArgs& a, hipStream_t s);
+hipError_t launch_inverse_laplacian(double2* c, int N, hipStream_t s);
+hipError_t launch_take_real(const double2* c, double* out, double scale, int64_t n, hipStream_t s);
 
 constexpr int kPencilChunk = 32;   // z-columns per block of the x-pencil pass
 

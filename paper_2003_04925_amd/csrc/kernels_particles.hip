@@ -18,61 +18,11 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "particle_common.h"
 
 namespace scola {
 
 namespace {
-
-__device__ inline int logical_block(const BlockMap& m) {
-  const int b = blockIdx.x;
-  if (!m.xcd_remap) return b;
-  const int per = gridDim.x >> 3;
-  return (b & 7) * per + (b >> 3);
-}
-
-inline unsigned padded_grid(const BlockMap& m) {
-  if (!m.xcd_remap) return (unsigned)m.count;
-  return (unsigned)(((m.count + 7) / 8) * 8);
-}
-
-// Wave-wide min / max: DPP exchanges inside 16-lane rows, then the four row results are
-// read into scalars; the result is uniform across the wave.
-__device__ __forceinline__ int wave_min(int v) {
-  v = min(v, lane_xor<1>(v));
-  v = min(v, lane_xor<2>(v));
-  v = min(v, lane_xor<4>(v));
-  v = min(v, lane_xor<8>(v));
-  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
-}
-__device__ __forceinline__ int wave_max(int v) {
-  v = max(v, lane_xor<1>(v));
-  v = max(v, lane_xor<2>(v));
-  v = max(v, lane_xor<4>(v));
-  v = max(v, lane_xor<8>(v));
-  return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-             max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
-}
-
-constexpr int kWindow = 4096;   // LDS window entries per block (potential or mass)
-
-// Block-wide bounding box of per-thread integer ranges [lo, hi] (3 axes); threads with
-// any == false do not count.  Must be called by all threads of the block.
-__device__ inline void block_bounds(bool any, const int (&lo)[3], const int (&hi)[3],
-                                    int* bounds) {
-  if (threadIdx.x < 6) bounds[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -0x7fffffff;
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const int a = wave_min(any ? lo[c] : 0x7fffffff);
-    const int b = wave_max(any ? hi[c] : -0x7fffffff);
-    if ((threadIdx.x & 63) == 0) {
-      atomicMin(bounds + c, a);
-      atomicMax(bounds + 3 + c, b);
-    }
-  }
-  __syncthreads();
-}
 
 // Fixed-point CiC weights of the 8 corners (offset bits x = 4, y = 2, z = 1); the eighth
 // corner gets the remainder so the eight sum to exactly one unit.
@@ -106,16 +56,6 @@ __device__ inline void mesh_weights(double fx, double fy, double fz, long long (
     }
     w[7] = (1 << MeshFixed<T>::bits) - sum;
   }
-}
-
-// Row-major decomposition e -> (ex, ey, ez) of a window with rows wy x wz, using FP32
-// reciprocals (exact for windows far below 2^20 entries) instead of integer division.
-__device__ inline void window_coords(int e, int wz, int wyz, float inv_wz, float inv_wyz,
-                                     int& ex, int& ey, int& ez) {
-  ex = (int)(((float)e + 0.5f) * inv_wyz);
-  const int r = e - ex * wyz;
-  ey = (int)(((float)r + 0.5f) * inv_wz);
-  ez = r - ey * wz;
 }
 
 // Corner range of one particle's CiC footprint restricted to interior nodes [1, n]:

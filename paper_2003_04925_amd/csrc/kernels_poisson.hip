@@ -200,7 +200,7 @@ __device__ inline void load_twiddles(cx<T>* tw, const MeshArgs<T>& a, const Tile
   for (int i = threadIdx.x; i < 2 * t.M; i += blockDim.x) tw[i] = src[i];
 }
 
-template <typename T, int R>
+template <typename T, int R, bool ADJ>
 __global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m) {
   const int L = logical_block(m);
   if (L >= m.count) return;
@@ -215,30 +215,35 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m
   const int64_t base = t.g_off + (int64_t)x * n * n;
   const double* bc = a.bc0 + t.h_off;
   const double D1 = a.D1_bc;
-  constexpr int kBatch = 8;   // independent loads in flight per thread
-  for (int e0 = 0; e0 < n * n; e0 += kBatch * kBlock) {
-    long long r[kBatch];
-#pragma unroll
-    for (int q = 0; q < kBatch; ++q) {
-      const int e = e0 + q * kBlock + threadIdx.x;
-      r[q] = e < n * n ? (long long)a.rho[base + e] : 0;
-    }
-#pragma unroll
-    for (int q = 0; q < kBatch; ++q) {
-      const int e = e0 + q * kBlock + threadIdx.x;
-      if (e >= n * n) continue;
-      a.rho[base + e] = 0ull;
-      const int y = e / n, z = e - (e / n) * n;
-      double d = (double)r[q] * (1.0 / (double)(1ll << MeshFixed<T>::bits)) - 1.0;
-      // delta' = delta - Delta Phi_BCs: face-layer neighbours of the first interior layer
-      // (padded index = node index + 1; interior node index = array index + 1)
-      if (x == 0) d -= D1 * bc[((int64_t)1 * Mp + y + 2) * Mp + z + 2];
-      if (x == n - 1) d -= D1 * bc[((int64_t)(M + 1) * Mp + y + 2) * Mp + z + 2];
-      if (y == 0) d -= D1 * bc[((int64_t)(x + 2) * Mp + 1) * Mp + z + 2];
-      if (y == n - 1) d -= D1 * bc[((int64_t)(x + 2) * Mp + M + 1) * Mp + z + 2];
-      if (z == 0) d -= D1 * bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + 1];
-      if (z == n - 1) d -= D1 * bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + M + 1];
-      plane[e] = (T)d;
+  if constexpr (ADJ) {
+#pragma unroll 8
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) plane[e] = a.work[base + e];
+  } else {
+    constexpr int kBatch = 8;   // independent loads in flight per thread
+    for (int e0 = 0; e0 < n * n; e0 += kBatch * kBlock) {
+      long long r[kBatch];
+  #pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        const int e = e0 + q * kBlock + threadIdx.x;
+        r[q] = e < n * n ? (long long)a.rho[base + e] : 0;
+      }
+  #pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        const int e = e0 + q * kBlock + threadIdx.x;
+        if (e >= n * n) continue;
+        a.rho[base + e] = 0ull;
+        const int y = e / n, z = e - (e / n) * n;
+        double d = (double)r[q] * (1.0 / (double)(1ll << MeshFixed<T>::bits)) - 1.0;
+        // delta' = delta - Delta Phi_BCs: face-layer neighbours of the first interior layer
+        // (padded index = node index + 1; interior node index = array index + 1)
+        if (x == 0) d -= D1 * bc[((int64_t)1 * Mp + y + 2) * Mp + z + 2];
+        if (x == n - 1) d -= D1 * bc[((int64_t)(M + 1) * Mp + y + 2) * Mp + z + 2];
+        if (y == 0) d -= D1 * bc[((int64_t)(x + 2) * Mp + 1) * Mp + z + 2];
+        if (y == n - 1) d -= D1 * bc[((int64_t)(x + 2) * Mp + M + 1) * Mp + z + 2];
+        if (z == 0) d -= D1 * bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + 1];
+        if (z == n - 1) d -= D1 * bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + M + 1];
+        plane[e] = (T)d;
+      }
     }
   }
   __syncthreads();
@@ -305,7 +310,7 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p2(MeshArgs<T> a, BlockMap m
   }
 }
 
-template <typename T, int R>
+template <typename T, int R, bool ADJ>
 __global__ void __launch_bounds__(kBlock) k_poisson_p3(MeshArgs<T> a, BlockMap m) {
   const int L = logical_block(m);
   if (L >= m.count) return;
@@ -317,6 +322,7 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p3(MeshArgs<T> a, BlockMap m
   T* phi = a.phi + t.h_off;
   const double D1 = a.D1_bc;
   if (local >= n) {
+    if (ADJ) return;
     // one of the four shell planes a = 0, 1, M+1, M+2 (node -1, 0, M, M+1)
     const int s = local - n;
     const int A = s < 2 ? s : M + s - 1;
@@ -335,6 +341,24 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p3(MeshArgs<T> a, BlockMap m
   __syncthreads();
   plane_dst<R, T>(plane, tw);
   const int A = x + 2;
+  if constexpr (ADJ) {
+    // lam_rho = lam_delta'; lam_bc0 -= D1 C^T lam_delta' (each face node has exactly one
+    // interior neighbour, so plain updates do not collide)
+    double* lb = a.lam_bc0 + t.h_off;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const T v = plane[e];
+      a.lam_rho[base + e] = v;
+      const int y = e / n, z = e - (e / n) * n;
+      const double d = -D1 * (double)v;
+      if (x == 0) lb[((int64_t)1 * Mp + y + 2) * Mp + z + 2] += d;
+      if (x == n - 1) lb[((int64_t)(M + 1) * Mp + y + 2) * Mp + z + 2] += d;
+      if (y == 0) lb[((int64_t)(x + 2) * Mp + 1) * Mp + z + 2] += d;
+      if (y == n - 1) lb[((int64_t)(x + 2) * Mp + M + 1) * Mp + z + 2] += d;
+      if (z == 0) lb[((int64_t)(x + 2) * Mp + y + 2) * Mp + 1] += d;
+      if (z == n - 1) lb[((int64_t)(x + 2) * Mp + y + 2) * Mp + M + 1] += d;
+    }
+    return;
+  }
   for (int e = threadIdx.x; e < Mp * Mp; e += blockDim.x) {
     const int B = e / Mp, C = e - (e / Mp) * Mp;
     const int64_t o = (int64_t)A * Mp * Mp + e;
@@ -363,54 +387,63 @@ size_t poisson_lds_bytes(int M) {
 
 namespace {
 
-template <typename T, int R>
+template <typename T, int R, bool ADJ>
 hipError_t launch_poisson_R(const MeshArgs<T>& a, const BlockMap& p1, const BlockMap& p2,
                             const BlockMap& p3, hipStream_t s) {
   const size_t lds = poisson_lds_bytes<T>(16 * R);
   if (lds > 65536) {
     static bool done = false;     // allow more than 64 KiB of dynamic LDS (160 KiB on gfx950)
     if (!done) {
-      hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p1<T, R>),
+      hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p1<T, R, ADJ>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p2<T, R>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p3<T, R>),
+      hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p3<T, R, ADJ>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       (void)hipGetLastError();
       done = true;
     }
   }
   if (p1.count > 0)
-    hipLaunchKernelGGL((k_poisson_p1<T, R>), dim3(padded_grid(p1)), dim3(kBlock), lds, s, a, p1);
+    hipLaunchKernelGGL((k_poisson_p1<T, R, ADJ>), dim3(padded_grid(p1)), dim3(kBlock), lds, s,
+                       a, p1);
   if (p2.count > 0)
     hipLaunchKernelGGL((k_poisson_p2<T, R>), dim3(padded_grid(p2)), dim3(kBlock), lds, s, a, p2);
   if (p3.count > 0)
-    hipLaunchKernelGGL((k_poisson_p3<T, R>), dim3(padded_grid(p3)), dim3(kBlock), lds, s, a, p3);
+    hipLaunchKernelGGL((k_poisson_p3<T, R, ADJ>), dim3(padded_grid(p3)), dim3(kBlock), lds, s,
+                       a, p3);
   return hipGetLastError();
+}
+
+template <typename T, int R>
+hipError_t launch_poisson_RA(const MeshArgs<T>& a, const BlockMap& p1, const BlockMap& p2,
+                             const BlockMap& p3, hipStream_t s, bool adjoint) {
+  return adjoint ? launch_poisson_R<T, R, true>(a, p1, p2, p3, s)
+                 : launch_poisson_R<T, R, false>(a, p1, p2, p3, s);
 }
 
 }  // namespace
 
 template <typename T>
 hipError_t launch_poisson(const MeshArgs<T>& a, int M, const BlockMap& p1, const BlockMap& p2,
-                          const BlockMap& p3, hipStream_t s) {
+                          const BlockMap& p3, hipStream_t s, bool adjoint) {
   switch (M) {
-    case 16: return launch_poisson_R<T, 1>(a, p1, p2, p3, s);
-    case 32: return launch_poisson_R<T, 2>(a, p1, p2, p3, s);
-    case 48: return launch_poisson_R<T, 3>(a, p1, p2, p3, s);
-    case 64: return launch_poisson_R<T, 4>(a, p1, p2, p3, s);
-    case 80: return launch_poisson_R<T, 5>(a, p1, p2, p3, s);
-    case 96: return launch_poisson_R<T, 6>(a, p1, p2, p3, s);
-    case 112: return launch_poisson_R<T, 7>(a, p1, p2, p3, s);
-    case 128: return launch_poisson_R<T, 8>(a, p1, p2, p3, s);
+    case 16: return launch_poisson_RA<T, 1>(a, p1, p2, p3, s, adjoint);
+    case 32: return launch_poisson_RA<T, 2>(a, p1, p2, p3, s, adjoint);
+    case 48: return launch_poisson_RA<T, 3>(a, p1, p2, p3, s, adjoint);
+    case 64: return launch_poisson_RA<T, 4>(a, p1, p2, p3, s, adjoint);
+    case 80: return launch_poisson_RA<T, 5>(a, p1, p2, p3, s, adjoint);
+    case 96: return launch_poisson_RA<T, 6>(a, p1, p2, p3, s, adjoint);
+    case 112: return launch_poisson_RA<T, 7>(a, p1, p2, p3, s, adjoint);
+    case 128: return launch_poisson_RA<T, 8>(a, p1, p2, p3, s, adjoint);
     default: return hipErrorInvalidValue;
   }
 }
 
 template hipError_t launch_poisson<float>(const MeshArgs<float>&, int, const BlockMap&,
-                                          const BlockMap&, const BlockMap&, hipStream_t);
+                                          const BlockMap&, const BlockMap&, hipStream_t, bool);
 template hipError_t launch_poisson<double>(const MeshArgs<double>&, int, const BlockMap&,
-                                           const BlockMap&, const BlockMap&, hipStream_t);
+                                           const BlockMap&, const BlockMap&, hipStream_t, bool);
 template size_t poisson_lds_bytes<float>(int);
 template size_t poisson_lds_bytes<double>(int);
 

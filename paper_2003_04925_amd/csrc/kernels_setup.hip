@@ -244,6 +244,28 @@ hipError_t fft3d(double2* c, int N, double sign, hipStream_t s) {
 
 }  // namespace
 
+hipError_t fft3d_forward(double2* c, int N, hipStream_t s) { return fft3d(c, N, -1.0, s); }
+hipError_t fft3d_inverse(double2* c, int N, hipStream_t s) { return fft3d(c, N, +1.0, s); }
+
+hipError_t launch_ic_filter(const SetupArgs& a, hipStream_t s) {
+  const int64_t n3 = (int64_t)a.N * a.N * a.N;
+  hipLaunchKernelGGL(k_ic_filter, dim3(grid1(n3)), dim3(kBlock), 0, s, a.cbuf, a.N, a.L,
+                     a.amplitude, a.ns, a.Om, a.Ob, a.h, a.Tcmb, a.growth2);
+  return hipGetLastError();
+}
+
+hipError_t launch_inverse_laplacian(double2* c, int N, hipStream_t s) {
+  const int64_t n3 = (int64_t)N * N * N;
+  hipLaunchKernelGGL(k_inverse_laplacian, dim3(grid1(n3)), dim3(kBlock), 0, s, c, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_take_real(const double2* c, double* out, double scale, int64_t n,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_take_real, dim3(grid1(n)), dim3(kBlock), 0, s, c, out, scale, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_setup_potentials(const SetupArgs& a, hipStream_t s) {
   const int N = a.N;
   const int64_t n3 = (int64_t)N * N * N;

@@ -89,6 +89,7 @@ struct scola_plan {
   bool is64 = false;
   // call-order state, keyed by the workspace it refers to
   const void* setup_ws = nullptr;
+  const void* forward_ws = nullptr;   // full forward with checkpoints done on this workspace
 };
 
 namespace {
@@ -173,6 +174,7 @@ void validate(const scola_config& c, const scola_cosmology& cs, const scola_tile
     fail(SCOLA_EINVAL, "precision must be SCOLA_FP32 or SCOLA_FP64");
   if (c.schedule != SCOLA_BATCHED && c.schedule != SCOLA_PER_TILE)
     fail(SCOLA_EINVAL, "schedule must be SCOLA_BATCHED or SCOLA_PER_TILE");
+  if (c.checkpoint_every < 0) fail(SCOLA_EINVAL, "checkpoint_every must be >= 0");
   if (!(cs.Omega_m > 0 && cs.Omega_m <= 1 && cs.Omega_b >= 0 && cs.Omega_b < cs.Omega_m &&
         cs.h > 0 && cs.sigma8 > 0 && cs.T_cmb > 0))
     fail(SCOLA_EINVAL, "cosmology out of range");
@@ -310,6 +312,21 @@ void build_layout(scola_plan* p) {
   l.phi2 = take((size_t)(N * N * N) * 8);
   l.cbuf = take((size_t)(N * N * N) * 16);
   l.outgrid = take((size_t)(No * No * No) * 8);
+  const int c = p->cfg.checkpoint_every;
+  if (c > 0) {
+    const size_t n_ckpt = (size_t)((p->cfg.n_steps + c - 1) / c);
+    l.ckpt = take(n_ckpt * 6 * (size_t)p->P * R);
+    l.seg_x = take((size_t)c * 3 * (size_t)p->P * R);
+    l.seg_phi = take((size_t)c * (size_t)p->H * R);
+    l.lam_x = take(3 * (size_t)p->P * R);
+    l.lam_p = take(3 * (size_t)p->P * R);
+    l.lam_psi1 = take(3 * (size_t)p->P * 8);
+    l.lam_psi2 = take(3 * (size_t)p->P * 8);
+    l.lam_G = take(3 * (size_t)p->H * R);
+    l.lam_rho = take((size_t)p->G * R);
+    l.lam_bc0 = take((size_t)p->H * 8);
+    l.adj_grid = take(14 * (size_t)(N * N * N) * 8);
+  }
   l.total = off;
   l.n_particles = p->P;
   l.n_nodes = p->G;
@@ -431,8 +448,7 @@ struct Runner {
   }
 };
 
-template <typename T>
-void do_setup(scola_plan* p, const double* w, void* ws, hipStream_t s) {
+SetupArgs setup_args(scola_plan* p, const double* w, void* ws) {
   SetupArgs a;
   a.white_noise = w;
   a.cbuf = reinterpret_cast<double2*>(ws_ptr(ws, p->lay.cbuf));
@@ -450,20 +466,31 @@ void do_setup(scola_plan* p, const double* w, void* ws, hipStream_t s) {
   std::vector<double> q = {p->cfg.a_i, 1.0}, D1, dD1, D2, dD2;
   p->bg.growth(q, D1, dD1, D2, dD2);
   a.growth2 = (D1[0] / D1[1]) * (D1[0] / D1[1]);
-  hip_check(launch_setup_potentials(a, s), "set-up potentials");
+  return a;
+}
+
+BoxSetupArgs box_setup_args(scola_plan* p, void* ws) {
   BoxSetupArgs b;
   b.tiles = p->d_tiles;
   b.n_tiles = (int)p->desc.size();
   b.blk_tile = p->part.d_tile;
   b.blk_first = p->part.d_local;
   b.n_blocks = (int)p->part.tile.size();
-  b.phi1 = a.phi1;
-  b.phi2 = a.phi2;
+  b.phi1 = reinterpret_cast<double*>(ws_ptr(ws, p->lay.phi1));
+  b.phi2 = reinterpret_cast<double*>(ws_ptr(ws, p->lay.phi2));
   b.psi1 = reinterpret_cast<double*>(ws_ptr(ws, p->lay.psi1));
   b.psi2 = reinterpret_cast<double*>(ws_ptr(ws, p->lay.psi2));
   b.bc0 = reinterpret_cast<double*>(ws_ptr(ws, p->lay.bc0));
   b.N = p->cfg.Np;
   b.P = p->P;
+  return b;
+}
+
+template <typename T>
+void do_setup(scola_plan* p, const double* w, void* ws, hipStream_t s) {
+  SetupArgs a = setup_args(p, w, ws);
+  hip_check(launch_setup_potentials(a, s), "set-up potentials");
+  BoxSetupArgs b = box_setup_args(p, ws);
   hip_check(launch_setup_boxes<T>(b, reinterpret_cast<T*>(ws_ptr(ws, p->lay.x_res)),
                                   reinterpret_cast<T*>(ws_ptr(ws, p->lay.p_res)), s),
             "set-up boxes");
@@ -483,6 +510,31 @@ StepScalars row_scalars(const scola_plan* p, int k) {
   return sc;
 }
 
+// (x_res, p_res) of the given tiles -> checkpoint slot (to_ckpt) or back.
+template <typename T>
+void copy_checkpoint(scola_plan* p, const std::vector<int>& tiles, int slot, bool to_ckpt,
+                     void* ws, hipStream_t s) {
+  const size_t R = sizeof(T);
+  char* ck = ws_ptr(ws, p->lay.ckpt) + (size_t)slot * 6 * p->P * R;
+  char* st[2] = {ws_ptr(ws, p->lay.x_res), ws_ptr(ws, p->lay.p_res)};
+  const bool all = tiles.size() == p->desc.size();
+  for (int a = 0; a < 2; ++a) {
+    char* c = ck + (size_t)a * 3 * p->P * R;
+    if (all) {
+      hip_check(hipMemcpyAsync(to_ckpt ? c : st[a], to_ckpt ? st[a] : c, 3 * p->P * R,
+                               hipMemcpyDeviceToDevice, s), "checkpoint copy");
+      continue;
+    }
+    for (int t : tiles)
+      for (int comp = 0; comp < 3; ++comp) {
+        const size_t o = ((size_t)comp * p->P + p->desc[t].p_off) * R;
+        const size_t nb = (size_t)p->desc[t].M * p->desc[t].M * p->desc[t].M * R;
+        hip_check(hipMemcpyAsync(to_ckpt ? c + o : st[a] + o, to_ckpt ? st[a] + o : c + o, nb,
+                                 hipMemcpyDeviceToDevice, s), "checkpoint copy");
+      }
+  }
+}
+
 template <typename T>
 void do_evolve(scola_plan* p, const std::vector<int>& tiles, void* ws, hipStream_t s) {
   const bool batched = p->cfg.schedule == SCOLA_BATCHED && tiles.size() == p->desc.size();
@@ -496,7 +548,9 @@ void do_evolve(scola_plan* p, const std::vector<int>& tiles, void* ws, hipStream
     init.D2 = p->D2[0];
     r.particles(kInit, init);               // L-: x_res = p_res = 0, deposit x_LPT(t_0)
     r.poisson(p->D1[0]);
+    const int ck = p->cfg.checkpoint_every;
     for (int k = 0; k < n; ++k) {
+      if (ck > 0 && k % ck == 0) copy_checkpoint<T>(p, set, k / ck, true, ws, s);
       const bool need_force = k < n - 1 || p->cfg.want_momenta;
       r.particles(need_force ? kStep : kStepNoDeposit, row_scalars(p, k));
       if (need_force) r.poisson(p->D1[k + 1]);
@@ -546,6 +600,130 @@ void do_output(scola_plan* p, void* pos, void* mom, void* dens, const std::vecto
     for (int t : tiles)
       hip_check(launch_output<T>(a, tile_map(p->part, t), false, nullptr, s), "output kernel");
   }
+}
+
+void zero_bytes(void* ptr, size_t bytes, hipStream_t s) {
+  // every region zeroed here is 8-byte aligned and a multiple of 4 bytes long
+  if (bytes % 8 == 0) {
+    hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ptr), (int64_t)(bytes / 8), s),
+              "zero");
+  } else {
+    hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ptr), (int64_t)(bytes / 8), s),
+              "zero");
+    hip_check(hipMemsetAsync(static_cast<char*>(ptr) + bytes - 4, 0, 4, s), "zero tail");
+  }
+}
+
+template <typename T>
+void do_backward(scola_plan* p, const T* lam_dens, double* grad_w, void* ws, hipStream_t s) {
+  const scola_layout& l = p->lay;
+  const int n = p->cfg.n_steps, c = p->cfg.checkpoint_every, N = p->cfg.Np;
+  const int nseg = (n + c - 1) / c;
+  const size_t R = sizeof(T);
+  const int n_tiles = (int)p->desc.size();
+  const int64_t N3 = (int64_t)N * N * N;
+  AdjointArgs<T> a;
+  a.tiles = p->d_tiles;
+  a.psi1 = reinterpret_cast<const double*>(ws_ptr(ws, l.psi1));
+  a.psi2 = reinterpret_cast<const double*>(ws_ptr(ws, l.psi2));
+  a.lam_x = reinterpret_cast<T*>(ws_ptr(ws, l.lam_x));
+  a.lam_p = reinterpret_cast<T*>(ws_ptr(ws, l.lam_p));
+  a.lam_psi1 = reinterpret_cast<double*>(ws_ptr(ws, l.lam_psi1));
+  a.lam_psi2 = reinterpret_cast<double*>(ws_ptr(ws, l.lam_psi2));
+  a.lam_G = reinterpret_cast<T*>(ws_ptr(ws, l.lam_G));
+  a.lam_rho = reinterpret_cast<const T*>(ws_ptr(ws, l.lam_rho));
+  a.P = p->P;
+  a.H = p->H;
+  double* lam_bc0 = reinterpret_cast<double*>(ws_ptr(ws, l.lam_bc0));
+  T* work = reinterpret_cast<T*>(ws_ptr(ws, l.work));
+  zero_bytes(a.lam_G, 3 * (size_t)p->H * R, s);
+  zero_bytes(lam_bc0, (size_t)p->H * 8, s);
+  // transpose of the output density at the final positions
+  a.xk = reinterpret_cast<const T*>(ws_ptr(ws, l.x_res));
+  a.D1 = p->D1[n];
+  a.D2 = p->D2[n];
+  a.phi = nullptr;
+  hip_check(launch_adj_output<T>(a, full_map(p->part), lam_dens, N, p->cfg.N_out, s),
+            "adjoint output");
+  std::vector<int> all = subset_list(p, nullptr, 0);
+  Runner<T> r{p, ws, s, all, true};
+  T* seg_x = reinterpret_cast<T*>(ws_ptr(ws, l.seg_x));
+  T* seg_phi = reinterpret_cast<T*>(ws_ptr(ws, l.seg_phi));
+  T* x_res = reinterpret_cast<T*>(ws_ptr(ws, l.x_res));
+  T* phi = reinterpret_cast<T*>(ws_ptr(ws, l.phi));
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int k0 = seg * c, k1 = std::min(k0 + c, n);
+    // recompute the segment forward from its checkpoint, keeping x_res and phi per step
+    copy_checkpoint<T>(p, all, seg, false, ws, s);
+    StepScalars d0{};
+    d0.D1 = p->D1[k0];
+    d0.D2 = p->D2[k0];
+    r.particles(kDepositOnly, d0);
+    r.poisson(p->D1[k0]);
+    for (int k = k0; k < k1; ++k) {
+      hip_check(hipMemcpyAsync(seg_x + (size_t)(k - k0) * 3 * p->P, x_res, 3 * p->P * R,
+                               hipMemcpyDeviceToDevice, s), "segment copy");
+      hip_check(hipMemcpyAsync(seg_phi + (size_t)(k - k0) * p->H, phi, p->H * R,
+                               hipMemcpyDeviceToDevice, s), "segment copy");
+      if (k < k1 - 1) {
+        r.particles(kStep, row_scalars(p, k));
+        r.poisson(p->D1[k + 1]);
+      }
+    }
+    // reverse the segment step by step
+    for (int k = k1 - 1; k >= k0; --k) {
+      const StepScalars sc = row_scalars(p, k);
+      a.xk = seg_x + (size_t)(k - k0) * 3 * p->P;
+      a.phi = seg_phi + (size_t)(k - k0) * p->H;
+      a.alpha = sc.alpha;
+      a.beta = sc.beta;
+      a.D1 = sc.D1;
+      a.D2 = sc.D2;
+      hip_check(launch_adj_step<T>(a, full_map(p->part), 0, work, lam_bc0, n_tiles, s),
+                "adjoint scatter");
+      hip_check(launch_adj_step<T>(a, full_map(p->part), 1, work, lam_bc0, n_tiles, s),
+                "adjoint divergence");
+      MeshArgs<T> m = mesh_args<T>(p, ws, sc.D1);
+      m.lam_rho = const_cast<T*>(a.lam_rho);
+      m.lam_bc0 = lam_bc0;
+      for (size_t cl = 0; cl < p->p1.class_M.size(); ++cl) {
+        auto cls = [&](const Maps& mm) {
+          BlockMap b = full_map(mm);
+          b.base = mm.class_first[cl];
+          b.count = mm.class_count[cl];
+          return b;
+        };
+        hip_check(launch_poisson<T>(m, p->p1.class_M[cl], cls(p->p1), cls(p->p2), cls(p->p3), s,
+                                    true), "adjoint poisson");
+      }
+      hip_check(launch_adj_step<T>(a, full_map(p->part), 2, work, lam_bc0, n_tiles, s),
+                "adjoint gather");
+    }
+  }
+  // FP64 set-up adjoint: Psi1, Psi2, Phi_BC^0 -> phi1, phi2 -> white noise
+  double* g = reinterpret_cast<double*>(ws_ptr(ws, l.adj_grid));
+  double* lam_psig = g;               // 6 N^3
+  double* lam_phi1 = g + 6 * N3;      // N^3
+  double* lam_s = g + 7 * N3;         // N^3
+  double* f6 = g + 8 * N3;            // 6 N^3
+  double2* cbuf = reinterpret_cast<double2*>(ws_ptr(ws, l.cbuf));
+  zero_bytes(g, 7 * (size_t)N3 * 8, s);
+  BoxSetupArgs b = box_setup_args(p, ws);
+  hip_check(launch_adj_setup_scatter(b, a.lam_psi1, a.lam_psi2, lam_psig, lam_bc0, lam_phi1, s),
+            "adjoint set-up scatter");
+  hip_check(launch_adj_phi_from_psi(lam_psig, lam_phi1, cbuf, N, s), "adjoint D^T");
+  hip_check(fft3d_forward(cbuf, N, s), "fft");
+  hip_check(launch_inverse_laplacian(cbuf, N, s), "adjoint Poisson (2LPT)");
+  hip_check(fft3d_inverse(cbuf, N, s), "fft");
+  hip_check(launch_take_real(cbuf, lam_s, 1.0 / (double)N3, N3, s), "take real");
+  hip_check(launch_adj_source(reinterpret_cast<const double*>(ws_ptr(ws, l.phi1)), lam_s, f6,
+                              lam_phi1, N, s), "adjoint second-order source");
+  hip_check(launch_real_to_complex(lam_phi1, cbuf, N3, s), "real to complex");
+  hip_check(fft3d_forward(cbuf, N, s), "fft");
+  SetupArgs sa = setup_args(p, nullptr, ws);
+  hip_check(launch_ic_filter(sa, s), "adjoint IC filter");
+  hip_check(fft3d_inverse(cbuf, N, s), "fft");
+  hip_check(launch_take_real(cbuf, grad_w, 1.0 / (double)N3, N3, s), "take real");
 }
 
 }  // namespace
@@ -685,6 +863,7 @@ scola_status scola_setup(scola_plan* p, const double* w, void* ws, hipStream_t s
     else
       do_setup<float>(p, w, ws, s);
     p->setup_ws = ws;
+    p->forward_ws = nullptr;
   });
 }
 
@@ -694,6 +873,7 @@ scola_status scola_evolve(scola_plan* p, const int32_t* subset, int32_t n_subset
     check_ws(p, ws);
     if (p->setup_ws != ws) fail(SCOLA_ESTATE, "scola_setup has not run on this workspace");
     const std::vector<int> tiles = subset_list(p, subset, n_subset);
+    p->forward_ws = (p->cfg.checkpoint_every > 0 && tiles.size() == p->desc.size()) ? ws : nullptr;
     if (p->is64)
       do_evolve<double>(p, tiles, ws, s);
     else
@@ -725,9 +905,27 @@ scola_status scola_forward(scola_plan* p, const double* w, void* pos, void* mom,
   return scola_output(p, pos, mom, dens, subset, n_subset, ws, s);
 }
 
+scola_status scola_backward(scola_plan* p, const void* grad_density, double* grad_w, void* ws,
+                            hipStream_t s) {
+  return guarded([&] {
+    check_ws(p, ws);
+    if (!grad_density || !grad_w) fail(SCOLA_EINVAL, "NULL gradient buffer");
+    if (p->cfg.checkpoint_every <= 0)
+      fail(SCOLA_ESTATE, "the plan was created with checkpoint_every = 0 (no reverse mode)");
+    if (p->forward_ws != ws)
+      fail(SCOLA_ESTATE, "scola_backward needs a full scola_forward on this workspace first");
+    if (p->is64)
+      do_backward<double>(p, reinterpret_cast<const double*>(grad_density), grad_w, ws, s);
+    else
+      do_backward<float>(p, reinterpret_cast<const float*>(grad_density), grad_w, ws, s);
+    p->forward_ws = nullptr;   // the particle state now belongs to the first segment
+  });
+}
+
 scola_status scola_op_deposit(scola_plan* p, double D1, double D2, void* ws, hipStream_t s) {
   return guarded([&] {
     check_ws(p, ws);
+    p->forward_ws = nullptr;
     hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.rho)),
                               p->G, s), "zero rho");
     hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped)),
@@ -748,6 +946,7 @@ scola_status scola_op_deposit(scola_plan* p, double D1, double D2, void* ws, hip
 scola_status scola_op_poisson(scola_plan* p, double D1_bc, void* ws, hipStream_t s) {
   return guarded([&] {
     check_ws(p, ws);
+    p->forward_ws = nullptr;
     if (p->is64) {
       Runner<double> r{p, ws, s, subset_list(p, nullptr, 0), true};
       r.poisson(D1_bc);
@@ -762,6 +961,7 @@ scola_status scola_op_step(scola_plan* p, double beta, double alpha, double D1, 
                            double D1n, double D2n, int32_t deposit, void* ws, hipStream_t s) {
   return guarded([&] {
     check_ws(p, ws);
+    p->forward_ws = nullptr;
     StepScalars sc{};
     sc.beta = beta;
     sc.alpha = alpha;
@@ -784,6 +984,7 @@ scola_status scola_op_final_kick(scola_plan* p, double beta, double D1, double D
                                  double c2, void* ws, hipStream_t s) {
   return guarded([&] {
     check_ws(p, ws);
+    p->forward_ws = nullptr;
     StepScalars sc{};
     sc.beta = beta;
     sc.D1 = D1;
