@@ -143,7 +143,7 @@ def adjoint_timing(torch, S, synthetic, reps=3):
         torch.cuda.synchronize()
         if r:
             fw.append(a.elapsed_time(b))
-            bw.append(c.elapsed_time(b))
+            bw.append(b.elapsed_time(c))
     f, g = sum(fw) / reps, sum(bw) / reps
     return {"workload": "c4: c2 boxes, 20 FP32 steps, density loss, checkpoint every 5",
             "forward_ms": f, "backward_ms": g, "backward_over_forward": g / f,
@@ -159,6 +159,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the forward + reverse timing of the adjoint workload")
     ap.add_argument("--kernels-only", action="store_true",
                     help="set-up, then only the single-launch kernel timings and a "
                          "1 GiB device copy that calibrates the HBM byte counters")
@@ -174,6 +176,10 @@ def main():
     import paper_2003_04925_amd as S
     import synthetic
     torch.cuda.set_device(0)
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_timing(torch, S, synthetic, reps=args.steps)}),
+              flush=True)
+        return
     wl = synthetic.WORKLOADS[args.workload]
     sim = build_sim(S, wl)
     info = sim.info()
