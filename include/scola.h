@@ -99,11 +99,11 @@ typedef struct {
   size_t outgrid;          /* int64 [N_out^3]: fixed-point output density */
   /* reverse mode (all 0 when cfg.checkpoint_every == 0); c = checkpoint_every */
   size_t ckpt;             /* R [ceil(n_steps/c)][6][P]: (x_res, p_res) before steps 0, c, ... */
-  size_t seg_x;            /* R [c][3][P]: x_res at each step of the segment being reversed */
-  size_t seg_phi;          /* R [c][H]: potential at each step of that segment */
+  size_t seg_x;            /* R [c+1][3][P]: ring of x_res per step (slot = step mod (c+1))
+                              for the segment being reversed and the first step after it */
+  size_t seg_phi;          /* R [c+1][H]: ring of the potentials of the same steps */
   size_t lam_x, lam_p;     /* R [3][P]: adjoints of x_res and p_res */
   size_t lam_psi1, lam_psi2; /* double [3][P]: accumulated adjoints of Psi1, Psi2 */
-  size_t lam_G;            /* R [3][H]: transpose of the CiC interpolation on the nodes */
   size_t lam_rho;          /* R [G]: adjoint of the deposited mass */
   size_t lam_bc0;          /* double [H]: accumulated adjoint of Phi_BC^0 */
   size_t adj_grid;         /* double [14][N^3]: set-up adjoint fields */

@@ -65,6 +65,7 @@ struct ParticleArgs {
   const double* psi1;
   const double* psi2;
   T* xres;
+  T* xout;                  // x_res after the drift: xres itself, or another buffer
   T* pres;
   const T* phi;
   unsigned long long* rho;
@@ -94,15 +95,22 @@ struct AdjointArgs {
   const TileDesc* tiles;
   const double* psi1;
   const double* psi2;
-  const T* xk;              // x_res at the step's time, [3][P]
   T* lam_x;                 // adjoint of x_res, [3][P]
   T* lam_p;                 // adjoint of p_res, [3][P]
   double* lam_psi1;         // accumulated adjoint of Psi1, [3][P]
   double* lam_psi2;         // accumulated adjoint of Psi2, [3][P]
-  T* lam_G;                 // interpolation transpose on the padded nodes, [3][H]
-  const T* phi;             // potential at the step's time, [H]
-  const T* lam_rho;         // adjoint of the deposited mass, [G]
   int64_t P, H;
+  // gather half: force positions of step g (x_res at that time), its potential and the
+  // adjoint of its deposited mass; lam_g = beta_g lam_p
+  const T* xg;
+  const T* phi;             // [H]
+  const T* lam_rho;         // [G]
+  double beta_g, D1g, D2g;
+  // scatter half: kick/drift coefficients of step k and its force positions; the
+  // transposed interpolation lands in `work` (interior nodes, zeroed) and lam_bc0 (shell)
+  const T* xs;
+  T* work;                  // [G]
+  double* lam_bc0;          // [H]
   double alpha, beta, D1, D2;
 };
 
@@ -130,11 +138,11 @@ hipError_t launch_output(const OutputArgs<T>& a, const BlockMap& m, bool density
 template <typename T>
 hipError_t launch_adj_output(const AdjointArgs<T>& a, const BlockMap& m, const T* lam_dens,
                              int Np, int N_out, hipStream_t s);
-// stage 0: drift/kick transpose + interpolation scatter; 1: gradient transpose;
-// 2: gather of lam_u (run after the adjoint Poisson solve of stage 1's output)
+// One fused particle pass of the reverse sweep: the gather half of step g (after that
+// step's adjoint Poisson solve) and/or the scatter half of step k = g - 1.
 template <typename T>
-hipError_t launch_adj_step(const AdjointArgs<T>& a, const BlockMap& part, int stage, T* work,
-                           double* lam_bc0, int n_tiles, hipStream_t s);
+hipError_t launch_adj_step(const AdjointArgs<T>& a, const BlockMap& part, bool gather,
+                           bool scatter, hipStream_t s);
 hipError_t launch_adj_setup_scatter(const BoxSetupArgs& b, const double* lam_psi1,
                                     const double* lam_psi2, double* lam_psig,
                                     const double* lam_bc0, double* lam_phi1, hipStream_t s);

@@ -4,9 +4,9 @@
 //   output CiC              -> W'-gather of the density adjoint at the final positions
 //   drift / kick (App. B)   -> linear updates of the particle adjoints (lam_x, lam_p) and
 //                              FP64 accumulation of lam_Psi1, lam_Psi2
-//   CiC interpolation       -> 3-component CiC scatter of beta lam_p onto the nodes, and a
-//                              W'-gather of lam_g . grad Phi at the particle
-//   central gradient        -> minus the central divergence; shell part -> lam Phi_BC
+//   CiC interpolation and   -> one scalar scatter of beta lam_p through the transposed
+//   central gradient           gradient stencil onto the padded nodes (shell part ->
+//                              lam Phi_BC), and a W'-gather of lam_g . grad Phi
 //   Dirichlet DST solve     -> the same solve (the FDA-2 Dirichlet Laplacian is symmetric)
 //   CiC deposit B^sCOLA     -> W'-gather of lam_rho at the particle
 //   Psi = D phi, Phi_BC^0, second-order source, IC filter -> their transposes (FP64)
@@ -27,202 +27,60 @@ __device__ inline int wrapn(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
-__device__ inline void atomic_add_real(float* p, float v) { unsafeAtomicAdd(p, v); }
-__device__ inline void atomic_add_real(double* p, double v) { unsafeAtomicAdd(p, v); }
-
-// Position at the step's time (FP64) of particle p with lattice site (i, j, k).
-template <typename T>
-__device__ inline void particle_position(const AdjointArgs<T>& a, int64_t p, int i, int j,
-                                         int k, double (&s1)[3], double (&s2)[3], double (&u)[3]) {
-  const int idx[3] = {i, j, k};
+// Position (FP64) of particle p with lattice site idx at a time with growth factors D1, D2
+// and residual displacement x.
+__device__ inline void lpt_position(const double (&s1)[3], const double (&s2)[3], const int (&idx)[3],
+                                    double D1, double D2, const double (&x)[3], double (&u)[3]) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    s1[c] = a.psi1[c * a.P + p];
-    s2[c] = a.psi2[c * a.P + p];
-    u[c] = idx[c] + 0.5 - a.D1 * s1[c] + a.D2 * s2[c] + (double)a.xk[c * a.P + p];
-  }
+  for (int c = 0; c < 3; ++c) u[c] = idx[c] + 0.5 - D1 * s1[c] + D2 * s2[c] + x[c];
 }
 
-// Pass A of one reverse step: through the drift (lam_p += alpha lam_x) and the kick (lam_g
-// = beta lam_p, Psi terms of K~), then the interpolation transpose: lam_G(n) += W(u - n)
-// lam_g for the corners n in [0, M]^3, privatised per block in an LDS window (one
-// component at a time), floating-point atomics to global memory.
+// Cell and CiC weights of the interpolation at u (corners outside [0, M]^3 weigh nothing);
+// returns false for a particle outside [-1, M+1)^3, which touches no node.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_adj_scatter(AdjointArgs<T> a, BlockMap m) {
-  const int L = logical_block(m);
-  if (L >= m.count) return;
-  const int b = m.base + L;
-  const TileDesc t = a.tiles[m.tile[b]];
-  const int M = t.M;
-  const int64_t pl = (int64_t)m.local[b] * kBlock + threadIdx.x;
-  const int64_t p = t.p_off + pl;
-  const int64_t P = a.P;
-  int i, j, k;
-  brick_site(pl, M, i, j, k);
-  double s1[3], s2[3], u[3];
-  particle_position(a, p, i, j, k, s1, s2, u);
-  T lg[3];
-  const double d2 = a.D2 - a.D1 * a.D1;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const T lt = a.lam_p[c * P + p] + (T)a.alpha * a.lam_x[c * P + p];
-    a.lam_p[c * P + p] = lt;
-    lg[c] = (T)a.beta * lt;
-    a.lam_psi1[c * P + p] += -a.beta * a.D1 * (double)lt;
-    a.lam_psi2[c * P + p] += a.beta * d2 * (double)lt;
-  }
-  // interpolation corners and weights (corners outside [0, M]^3 carry no weight)
+__device__ inline bool interp_cell(int M, const double (&u)[3], int (&j0)[3], T (&f)[3]) {
   const double hiu = (double)M + 1.0;
   const bool in = u[0] >= -1.0 && u[0] < hiu && u[1] >= -1.0 && u[1] < hiu && u[2] >= -1.0 &&
                   u[2] < hiu;
-  int j0[3] = {0, 0, 0};
-  T w[3][2];
-  int lo[3], hi[3];
-  bool any = in;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    T f = T(0);
-    if (in) {
-      const double fl = floor(u[c]);
-      j0[c] = (int)fl;
-      f = (T)(u[c] - fl);
-    }
-    w[c][0] = (j0[c] < 0 || j0[c] > M) ? T(0) : T(1) - f;
-    w[c][1] = (j0[c] + 1 < 0 || j0[c] + 1 > M) ? T(0) : f;
-    lo[c] = max(j0[c], 0);
-    hi[c] = min(j0[c] + 1, M);
-    any = any && lo[c] <= hi[c];
-  }
-  __shared__ T win[kWindow];
-  __shared__ int bounds[6];
-  block_bounds(any, lo, hi, bounds);
-  const int lx = bounds[0], ly = bounds[1], lz = bounds[2];
-  const int wx = bounds[3] - lx + 1, wy = bounds[4] - ly + 1, wz = bounds[5] - lz + 1;
-  const bool empty = wx <= 0 || wy <= 0 || wz <= 0;
-  const int vol = empty ? 0 : wx * wy * wz;
-  const bool use_lds = !empty && vol <= kWindow;
-  const int Mp = M + 3;
-  const int64_t Hs = a.H;
-  for (int comp = 0; comp < 3; ++comp) {
-    T* dst = a.lam_G + comp * Hs + t.h_off;
-    if (use_lds) {
-      for (int e = threadIdx.x; e < vol; e += blockDim.x) win[e] = T(0);
-      __syncthreads();
-    }
-    if (any) {
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
-        const T wc = w[0][dx] * w[1][dy] * w[2][dz];
-        if (wc == T(0)) continue;
-        const int nx = j0[0] + dx, ny = j0[1] + dy, nz = j0[2] + dz;
-        if (use_lds)
-          atomicAdd(win + ((nx - lx) * wy + (ny - ly)) * wz + (nz - lz), wc * lg[comp]);
-        else
-          atomic_add_real(dst + ((int64_t)(nx + 1) * Mp + (ny + 1)) * Mp + (nz + 1),
-                          wc * lg[comp]);
-      }
-    }
-    if (use_lds) {
-      __syncthreads();
-      const int wyz = wy * wz;
-      const float inv_wz = 1.0f / (float)wz, inv_wyz = 1.0f / (float)wyz;
-      for (int e = threadIdx.x; e < vol; e += blockDim.x) {
-        const T v = win[e];
-        if (v != T(0)) {
-          int ex, ey, ez;
-          window_coords(e, wz, wyz, inv_wz, inv_wyz, ex, ey, ez);
-          atomic_add_real(dst + ((int64_t)(lx + ex + 1) * Mp + (ly + ey + 1)) * Mp +
-                              (lz + ez + 1), v);
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// Transpose of the central gradient: lam_Phi(i) = 1/2 sum_a (lam_G_a(i - e_a) -
-// lam_G_a(i + e_a)) on [-1, M+1]^3 (lam_G vanishes outside [0, M]^3).  Interior nodes feed
-// the adjoint Poisson solve (written to `work`); shell nodes are the LEP boundary values
-// D1 Phi_BC^0, so lam_bc0 += D1 lam_Phi there.
-template <typename T>
-__global__ void k_adj_divergence(AdjointArgs<T> a, T* __restrict__ work, double* __restrict__ lam_bc0,
-                                 int n_tiles) {
-  const int ti = blockIdx.y;
-  if (ti >= n_tiles) return;
-  const TileDesc t = a.tiles[ti];
-  const int M = t.M, Mp = M + 3, n = M - 1;
-  const int64_t n3 = (int64_t)Mp * Mp * Mp;
-  const T* G0 = a.lam_G + t.h_off;
-  const T* G1 = G0 + a.H;
-  const T* G2 = G1 + a.H;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n3;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int A = (int)(e / ((int64_t)Mp * Mp)), B = (int)((e / Mp) % Mp), C = (int)(e % Mp);
-    T v = T(0);
-    const int64_t sx = (int64_t)Mp * Mp, sy = Mp;
-    if (A >= 1) v += G0[e - sx];
-    if (A + 1 < Mp) v -= G0[e + sx];
-    if (B >= 1) v += G1[e - sy];
-    if (B + 1 < Mp) v -= G1[e + sy];
-    if (C >= 1) v += G2[e - 1];
-    if (C + 1 < Mp) v -= G2[e + 1];
-    v *= T(0.5);
-    const int ix = A - 1, iy = B - 1, iz = C - 1;      // node coordinates
-    if (ix >= 1 && ix <= n && iy >= 1 && iy <= n && iz >= 1 && iz <= n)
-      work[t.g_off + ((int64_t)(ix - 1) * n + (iy - 1)) * n + (iz - 1)] = v;
-    else
-      lam_bc0[t.h_off + e] += a.D1 * (double)v;
-  }
-}
-
-// Pass B of one reverse step: lam_u = sum_c W'(u - n_c) [lam_g . grad Phi(n_c)] over the
-// interpolation corners plus sum_c W'(u - n_c) lam_rho(n_c) over the interior deposit
-// corners; then lam_x += lam_u and the Psi terms of u = q - D1 Psi1 + D2 Psi2 + x_res.
-// Also clears this block's slice of lam_G for the next reverse step.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_adj_gather(AdjointArgs<T> a, BlockMap m) {
-  const int L = logical_block(m);
-  if (L >= m.count) return;
-  const int b = m.base + L;
-  const TileDesc t = a.tiles[m.tile[b]];
-  const int M = t.M, Mp = M + 3, n = M - 1;
-  const int64_t pl = (int64_t)m.local[b] * kBlock + threadIdx.x;
-  const int64_t p = t.p_off + pl;
-  const int64_t P = a.P;
-  int i, j, k;
-  brick_site(pl, M, i, j, k);
-  double s1[3], s2[3], u[3];
-  particle_position(a, p, i, j, k, s1, s2, u);
-  T lg[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) lg[c] = (T)a.beta * a.lam_p[c * P + p];
-  const double hiu = (double)M + 1.0;
-  const bool in = u[0] >= -1.0 && u[0] < hiu && u[1] >= -1.0 && u[1] < hiu && u[2] >= -1.0 &&
-                  u[2] < hiu;
-  int j0[3] = {0, 0, 0};
-  T f[3] = {T(0), T(0), T(0)};
-  int lo[3], hi[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
+    j0[c] = 0;
+    f[c] = T(0);
     if (in) {
       const double fl = floor(u[c]);
       j0[c] = (int)fl;
       f[c] = (T)(u[c] - fl);
     }
+  }
+  return in;
+}
+
+// Gather half of a reverse step (transpose of deposit and interpolation at the force
+// positions u of step g):
+//   lam_u = sum_c grad W(u - n_c) [lam_g . grad Phi(n_c) + lam_rho(n_c)],
+// the first term over the interpolation corners in [0, M]^3, the second over the interior
+// deposit corners [1, M-1]^3.  The potential nodes of the block's stencils are staged in
+// LDS (global fallback).  Must be called by all threads of the block.
+template <typename T>
+__device__ inline void block_adjoint_gather(const T* __restrict__ phi, const T* __restrict__ lr,
+                                            int M, const double (&u)[3], const T (&lg)[3],
+                                            T* win, int* bounds, T (&lu)[3]) {
+  const int Mp = M + 3, n = M - 1;
+  int j0[3];
+  T f[3];
+  const bool in = interp_cell<T>(M, u, j0, f);
+  int lo[3], hi[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
     lo[c] = max(j0[c] - 1, -1);
     hi[c] = min(j0[c] + 2, M + 1);
   }
-  // stage the potential of the block's stencils in LDS (global fallback)
-  __shared__ T win[kWindow];
-  __shared__ int bounds[6];
   block_bounds(in, lo, hi, bounds);
   const int lx = bounds[0], ly = bounds[1], lz = bounds[2];
   const int wx = bounds[3] - lx + 1, wy = bounds[4] - ly + 1, wz = bounds[5] - lz + 1;
   const bool empty = wx <= 0 || wy <= 0 || wz <= 0;
   const int vol = empty ? 0 : wx * wy * wz;
   const bool use_lds = !empty && vol <= kWindow;
-  const T* phi = a.phi + t.h_off;
   if (use_lds) {
     const int wyz = wy * wz;
     const float inv_wz = 1.0f / (float)wz, inv_wyz = 1.0f / (float)wyz;
@@ -234,13 +92,12 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather(AdjointArgs<T> a, BlockMa
     }
   }
   __syncthreads();
-  T lu[3] = {T(0), T(0), T(0)};
+  lu[0] = lu[1] = lu[2] = T(0);
   if (in) {
     auto at = [&](int x, int y, int z) -> T {
       if (use_lds) return win[((x - lx) * wy + (y - ly)) * wz + (z - lz)];
       return phi[((int64_t)(x + 1) * Mp + (y + 1)) * Mp + (z + 1)];
     };
-    const T* lr = a.lam_rho + t.g_off;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int d[3] = {(c >> 2) & 1, (c >> 1) & 1, c & 1};
@@ -262,20 +119,201 @@ __global__ void __launch_bounds__(kBlock) k_adj_gather(AdjointArgs<T> a, BlockMa
       for (int q = 0; q < 3; ++q) lu[q] += dw[q] * s;
     }
   }
+  __syncthreads();   // the window and `bounds` are free again
+}
+
+// Scatter half of a reverse step: the transpose of "central gradient, then CiC
+// interpolation at u" applied to the particle's lam_g, i.e.
+//   lam_Phi(n) += sum_a lam_g_a sum_c W(u - n_c) (delta(n, n_c + e_a) - delta(n, n_c - e_a)) / 2
+// over the interpolation corners n_c in [0, M]^3.  Along axis a this is a 4-point stencil
+// {-w0, -w1, w0, w1} / 2 on nodes j0 - 1 .. j0 + 2, times the CiC weights across; the union
+// is the 2x2x2 corner block plus six 2x2 arms, 32 nodes in all, every one in [-1, M+1]^3.
+// Interior nodes [1, M-1]^3 feed the adjoint Poisson solve (`work`, zeroed beforehand);
+// shell nodes hold D1 Phi_BC^0, so D1 lam_Phi goes to lam_bc0.
+//
+// The block privatises its nodes in an LDS window of integers: LDS atomics on integers
+// run at full rate while floating-point LDS atomics serialise.  Each contribution is
+// rounded to a fixed-point grid of step 2^(e + 9 - Q) with 2^e above the block's largest
+// |lam_g| and Q = 30 (FP32 plans, int32) or 62 (FP64 plans, int64): a node receives at
+// most 256 particles x 1.5 |lam_g| < 2^(e + 9), so sums cannot overflow, and the rounding
+// error per contribution is below 2^(-Q + 8) of the block's largest |lam_g| (2^-22 for
+// FP32, 2^-54 for FP64).  The window is flushed with floating-point atomics to global
+// memory; blocks whose footprint exceeds the window add straight into global memory.
+// Must be called by all threads.
+template <typename T>
+__device__ inline void block_adjoint_scatter(T* __restrict__ work, double* __restrict__ lam_bc0,
+                                             double D1, int M, const double (&u)[3],
+                                             const T (&lg)[3], T* win_raw, int* bounds) {
+  using Q = typename std::conditional<std::is_same<T, float>::value, int, long long>::type;
+  constexpr int kQ = std::is_same<T, float>::value ? 30 : 62;
+  static_assert(sizeof(Q) == sizeof(T), "the integer window reuses the potential window");
+  Q* win = reinterpret_cast<Q*>(win_raw);
+  const int Mp = M + 3, n = M - 1;
+  int j0[3];
+  T f[3];
+  const bool in = interp_cell<T>(M, u, j0, f);
+  T w[3][2], h[3][4];
+  int lo[3], hi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    w[a][0] = (j0[a] < 0 || j0[a] > M) ? T(0) : T(1) - f[a];
+    w[a][1] = (j0[a] + 1 < 0 || j0[a] + 1 > M) ? T(0) : f[a];
+    h[a][0] = T(-0.5) * w[a][0];    // node j0 - 1
+    h[a][1] = T(-0.5) * w[a][1];    // node j0
+    h[a][2] = T(0.5) * w[a][0];     // node j0 + 1
+    h[a][3] = T(0.5) * w[a][1];     // node j0 + 2
+    lo[a] = max(j0[a] - 1, -1);
+    hi[a] = min(j0[a] + 2, M + 1);
+  }
+  constexpr int kNoExp = -900;
+  int ex = kNoExp;
+  if (in) {
+    const double mx = (double)fmax(fmax(fabs(lg[0]), fabs(lg[1])), fabs(lg[2]));
+    if (mx > 0.0) frexp(mx, &ex);
+  }
+  block_bounds_max(in, lo, hi, ex, bounds);
+  const int lx = bounds[0], ly = bounds[1], lz = bounds[2];
+  const int wx = bounds[3] - lx + 1, wy = bounds[4] - ly + 1, wz = bounds[5] - lz + 1;
+  const int emax = max(bounds[6], kNoExp);
+  const double qscale = ldexp(1.0, kQ - 9 - emax), qstep = ldexp(1.0, emax + 9 - kQ);
+  const bool empty = wx <= 0 || wy <= 0 || wz <= 0;
+  const int vol = empty ? 0 : wx * wy * wz;
+  const bool use_lds = !empty && vol <= kWindow;
+  if (use_lds) {
+    for (int e = threadIdx.x; e < vol; e += blockDim.x) win[e] = Q(0);
+    __syncthreads();
+  }
+  auto to_global = [&](int x, int y, int z, T v) {
+    if (x >= 1 && x <= n && y >= 1 && y <= n && z >= 1 && z <= n)
+      unsafeAtomicAdd(work + ((int64_t)(x - 1) * n + (y - 1)) * n + (z - 1), v);
+    else
+      unsafeAtomicAdd(lam_bc0 + ((int64_t)(x + 1) * Mp + (y + 1)) * Mp + (z + 1), D1 * (double)v);
+  };
+  if (in) {
+    // a node is touched only through a non-zero coefficient, which keeps it in [-1, M+1]^3
+    auto add = [&](int ox, int oy, int oz, T coef_zero_test, T v) {
+      if (coef_zero_test == T(0)) return;
+      const int x = j0[0] + ox, y = j0[1] + oy, z = j0[2] + oz;
+      if (use_lds) {
+        const Q qv = (Q)__double2ll_rn((double)v * qscale);
+        atomicAdd(reinterpret_cast<typename std::make_unsigned<Q>::type*>(win) +
+                      ((x - lx) * wy + (y - ly)) * wz + (z - lz),
+                  (typename std::make_unsigned<Q>::type)qv);
+      } else {
+        to_global(x, y, z, v);
+      }
+    };
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
+      const T kx = h[0][dx + 1] * w[1][dy] * w[2][dz];
+      const T ky = w[0][dx] * h[1][dy + 1] * w[2][dz];
+      const T kz = w[0][dx] * w[1][dy] * h[2][dz + 1];
+      const T nz_test = (kx != T(0) || ky != T(0) || kz != T(0)) ? T(1) : T(0);
+      add(dx, dy, dz, nz_test, lg[0] * kx + lg[1] * ky + lg[2] * kz);
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int o = e ? 2 : -1, hk = e ? 3 : 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = (q >> 1) & 1, s = q & 1;
+        const T kx = h[0][hk] * w[1][r] * w[2][s];
+        add(o, r, s, kx, lg[0] * kx);
+        const T ky = w[0][r] * h[1][hk] * w[2][s];
+        add(r, o, s, ky, lg[1] * ky);
+        const T kz = w[0][r] * w[1][s] * h[2][hk];
+        add(r, s, o, kz, lg[2] * kz);
+      }
+    }
+  }
+  if (use_lds) {
+    __syncthreads();
+    const int wyz = wy * wz;
+    const float inv_wz = 1.0f / (float)wz, inv_wyz = 1.0f / (float)wyz;
+    for (int e = threadIdx.x; e < vol; e += blockDim.x) {
+      const Q qv = win[e];
+      if (qv != Q(0)) {
+        int ex_, ey_, ez_;
+        window_coords(e, wz, wyz, inv_wz, inv_wyz, ex_, ey_, ez_);
+        to_global(lx + ex_, ly + ey_, lz + ez_, (T)((double)qv * qstep));
+      }
+    }
+  }
+}
+
+// One reverse step on the particles, two halves fused so each particle's adjoint state and
+// Psi are streamed once:
+//   GATHER  (force of step g = k+1): lam_x += lam_u(u_g) with lam_g = beta_g lam_p;
+//   SCATTER (kick and drift of step k, App. B): lam_p += alpha lam_x (drift transpose),
+//           lam_g = beta lam_p (kick transpose), then the interpolation/gradient transpose of
+//           lam_g at u_k into the nodes;
+// and the Psi terms: u = q - D1 Psi1 + D2 Psi2 + x_res gives lam_Psi1 -= D1 lam_u,
+// lam_Psi2 += D2 lam_u; the kick's -D1 Psi1 + (D2 - D1^2) Psi2 gives lam_Psi1 -= beta D1
+// lam_p, lam_Psi2 += beta (D2 - D1^2) lam_p.  Positions are formed in FP64 exactly as in the
+// forward pass, so every particle takes the cell it took there.
+template <typename T, bool GATHER, bool SCATTER>
+__global__ void __launch_bounds__(kBlock) k_adj_particles(AdjointArgs<T> a, BlockMap m) {
+  const int L = logical_block(m);
+  if (L >= m.count) return;
+  const int b = m.base + L;
+  const TileDesc t = a.tiles[m.tile[b]];
+  const int M = t.M;
+  const int64_t pl = (int64_t)m.local[b] * kBlock + threadIdx.x;
+  const int64_t p = t.p_off + pl;
+  const int64_t P = a.P;
+  int idx[3];
+  brick_site(pl, M, idx[0], idx[1], idx[2]);
+  double s1[3], s2[3], acc1[3], acc2[3];
+  T lx[3], lp[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    a.lam_x[c * P + p] += lu[c];
-    a.lam_psi1[c * P + p] += -a.D1 * (double)lu[c];
-    a.lam_psi2[c * P + p] += a.D2 * (double)lu[c];
+    s1[c] = a.psi1[c * P + p];
+    s2[c] = a.psi2[c * P + p];
+    lx[c] = a.lam_x[c * P + p];
+    lp[c] = a.lam_p[c * P + p];
+    acc1[c] = acc2[c] = 0.0;
   }
-  // clear this block's share of the box's lam_G (read by no kernel after pass A)
-  const int nblk = (M * M * M) / kBlock;
-  const int64_t len = (int64_t)Mp * Mp * Mp;
-  const int64_t chunk = (len + nblk - 1) / nblk;
-  const int64_t e0 = (int64_t)m.local[b] * chunk;
-  for (int comp = 0; comp < 3; ++comp) {
-    T* g = a.lam_G + comp * a.H + t.h_off;
-    for (int64_t e = e0 + threadIdx.x; e < e0 + chunk && e < len; e += blockDim.x) g[e] = T(0);
+  __shared__ T win[kWindow];
+  __shared__ int bounds[8];
+  if constexpr (GATHER) {
+    double x[3], u[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x[c] = (double)a.xg[c * P + p];
+    lpt_position(s1, s2, idx, a.D1g, a.D2g, x, u);
+    T lg[3], lu[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) lg[c] = (T)a.beta_g * lp[c];
+    block_adjoint_gather<T>(a.phi + t.h_off, a.lam_rho + t.g_off, M, u, lg, win, bounds, lu);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lx[c] += lu[c];
+      acc1[c] -= a.D1g * (double)lu[c];
+      acc2[c] += a.D2g * (double)lu[c];
+    }
+  }
+  if constexpr (SCATTER) {
+    const double d2 = a.D2 - a.D1 * a.D1;
+    T lg[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lp[c] += (T)a.alpha * lx[c];
+      lg[c] = (T)a.beta * lp[c];
+      acc1[c] -= a.beta * a.D1 * (double)lp[c];
+      acc2[c] += a.beta * d2 * (double)lp[c];
+    }
+    double x[3], u[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x[c] = (double)a.xs[c * P + p];
+    lpt_position(s1, s2, idx, a.D1, a.D2, x, u);
+    block_adjoint_scatter<T>(a.work + t.g_off, a.lam_bc0 + t.h_off, a.D1, M, u, lg, win, bounds);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (GATHER) a.lam_x[c * P + p] = lx[c];
+    if (SCATTER) a.lam_p[c * P + p] = lp[c];
+    a.lam_psi1[c * P + p] += acc1[c];
+    a.lam_psi2[c * P + p] += acc2[c];
   }
 }
 
@@ -301,8 +339,15 @@ __global__ void __launch_bounds__(kBlock) k_adj_output(AdjointArgs<T> a, BlockMa
   const bool core = i >= lo && i < hi && j >= lo && j < hi && k >= lo && k < hi;
   T lu[3] = {T(0), T(0), T(0)};
   if (core) {
-    double s1[3], s2[3], u[3];
-    particle_position(a, p, i, j, k, s1, s2, u);
+    double s1[3], s2[3], x[3], u[3];
+    const int idx[3] = {i, j, k};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      s1[c] = a.psi1[c * P + p];
+      s2[c] = a.psi2[c * P + p];
+      x[c] = (double)a.xg[c * P + p];
+    }
+    lpt_position(s1, s2, idx, a.D1g, a.D2g, x, u);
     const double s = (double)N_out / (double)Np;
     int j0[3];
     T f[3];
@@ -332,8 +377,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_output(AdjointArgs<T> a, BlockMa
   for (int c = 0; c < 3; ++c) {
     a.lam_x[c * P + p] = lu[c];
     a.lam_p[c * P + p] = T(0);
-    a.lam_psi1[c * P + p] = -a.D1 * (double)lu[c];
-    a.lam_psi2[c * P + p] = a.D2 * (double)lu[c];
+    a.lam_psi1[c * P + p] = -a.D1g * (double)lu[c];
+    a.lam_psi2[c * P + p] = a.D2g * (double)lu[c];
   }
 }
 
@@ -483,24 +528,16 @@ hipError_t launch_adj_output(const AdjointArgs<T>& a, const BlockMap& m, const T
 }
 
 template <typename T>
-hipError_t launch_adj_step(const AdjointArgs<T>& a, const BlockMap& part, int stage, T* work,
-                           double* lam_bc0, int n_tiles, hipStream_t s) {
-  switch (stage) {
-    case 0:
-      if (part.count > 0)
-        hipLaunchKernelGGL(k_adj_scatter<T>, dim3(padded_grid(part)), dim3(kBlock), 0, s, a, part);
-      break;
-    case 1:
-      hipLaunchKernelGGL(k_adj_divergence<T>, dim3(64, n_tiles), dim3(kBlock), 0, s, a, work,
-                         lam_bc0, n_tiles);
-      break;
-    case 2:
-      if (part.count > 0)
-        hipLaunchKernelGGL(k_adj_gather<T>, dim3(padded_grid(part)), dim3(kBlock), 0, s, a, part);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
+hipError_t launch_adj_step(const AdjointArgs<T>& a, const BlockMap& part, bool gather,
+                           bool scatter, hipStream_t s) {
+  if (part.count == 0) return hipSuccess;
+  const dim3 grid(padded_grid(part)), block(kBlock);
+  if (gather && scatter)
+    hipLaunchKernelGGL((k_adj_particles<T, true, true>), grid, block, 0, s, a, part);
+  else if (gather)
+    hipLaunchKernelGGL((k_adj_particles<T, true, false>), grid, block, 0, s, a, part);
+  else if (scatter)
+    hipLaunchKernelGGL((k_adj_particles<T, false, true>), grid, block, 0, s, a, part);
   return hipGetLastError();
 }
 
@@ -542,9 +579,9 @@ template hipError_t launch_adj_output<float>(const AdjointArgs<float>&, const Bl
                                              const float*, int, int, hipStream_t);
 template hipError_t launch_adj_output<double>(const AdjointArgs<double>&, const BlockMap&,
                                               const double*, int, int, hipStream_t);
-template hipError_t launch_adj_step<float>(const AdjointArgs<float>&, const BlockMap&, int,
-                                           float*, double*, int, hipStream_t);
-template hipError_t launch_adj_step<double>(const AdjointArgs<double>&, const BlockMap&, int,
-                                            double*, double*, int, hipStream_t);
+template hipError_t launch_adj_step<float>(const AdjointArgs<float>&, const BlockMap&, bool, bool,
+                                           hipStream_t);
+template hipError_t launch_adj_step<double>(const AdjointArgs<double>&, const BlockMap&, bool,
+                                            bool, hipStream_t);
 
 }  // namespace scola

@@ -290,7 +290,7 @@ k_particles(ParticleArgs<T> a, BlockMap m) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       xr[c] += (T)sc.alpha * pr[c];
-      a.xres[c * P + p] = xr[c];
+      a.xout[c * P + p] = xr[c];
       a.pres[c * P + p] = pr[c];
     }
     if (MODE == kStepNoDeposit) return;

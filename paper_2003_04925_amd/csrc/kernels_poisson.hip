@@ -343,11 +343,12 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p3(MeshArgs<T> a, BlockMap m
   const int A = x + 2;
   if constexpr (ADJ) {
     // lam_rho = lam_delta'; lam_bc0 -= D1 C^T lam_delta' (each face node has exactly one
-    // interior neighbour, so plain updates do not collide)
+    // interior neighbour, so plain updates do not collide); the plane of `work` is cleared
     double* lb = a.lam_bc0 + t.h_off;
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
       const T v = plane[e];
       a.lam_rho[base + e] = v;
+      a.work[base + e] = T(0);   // the next reverse step accumulates into a zeroed source
       const int y = e / n, z = e - (e / n) * n;
       const double d = -D1 * (double)v;
       if (x == 0) lb[((int64_t)1 * Mp + y + 2) * Mp + z + 2] += d;

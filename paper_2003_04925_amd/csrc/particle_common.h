@@ -64,6 +64,26 @@ __device__ inline void block_bounds(bool any, const int (&lo)[3], const int (&hi
   __syncthreads();
 }
 
+// block_bounds plus the block-wide maximum of one int per thread, left in bounds[6] (the
+// caller's array holds at least 7 entries).  Must be called by all threads of the block.
+__device__ inline void block_bounds_max(bool any, const int (&lo)[3], const int (&hi)[3], int v,
+                                        int* bounds) {
+  if (threadIdx.x < 7) bounds[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -0x7fffffff;
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int a = wave_min(any ? lo[c] : 0x7fffffff);
+    const int b = wave_max(any ? hi[c] : -0x7fffffff);
+    if ((threadIdx.x & 63) == 0) {
+      atomicMin(bounds + c, a);
+      atomicMax(bounds + 3 + c, b);
+    }
+  }
+  const int m = wave_max(v);
+  if ((threadIdx.x & 63) == 0) atomicMax(bounds + 6, m);
+  __syncthreads();
+}
+
 // Row-major decomposition e -> (ex, ey, ez) of a window with rows wy x wz, using FP32
 // reciprocals (exact for windows far below 2^20 entries) instead of integer division.
 __device__ inline void window_coords(int e, int wz, int wyz, float inv_wz, float inv_wyz,

@@ -316,13 +316,12 @@ void build_layout(scola_plan* p) {
   if (c > 0) {
     const size_t n_ckpt = (size_t)((p->cfg.n_steps + c - 1) / c);
     l.ckpt = take(n_ckpt * 6 * (size_t)p->P * R);
-    l.seg_x = take((size_t)c * 3 * (size_t)p->P * R);
-    l.seg_phi = take((size_t)c * (size_t)p->H * R);
+    l.seg_x = take((size_t)(c + 1) * 3 * (size_t)p->P * R);
+    l.seg_phi = take((size_t)(c + 1) * (size_t)p->H * R);
     l.lam_x = take(3 * (size_t)p->P * R);
     l.lam_p = take(3 * (size_t)p->P * R);
     l.lam_psi1 = take(3 * (size_t)p->P * 8);
     l.lam_psi2 = take(3 * (size_t)p->P * 8);
-    l.lam_G = take(3 * (size_t)p->H * R);
     l.lam_rho = take((size_t)p->G * R);
     l.lam_bc0 = take((size_t)p->H * 8);
     l.adj_grid = take(14 * (size_t)(N * N * N) * 8);
@@ -395,6 +394,7 @@ ParticleArgs<T> particle_args(scola_plan* p, void* ws, const StepScalars& sc) {
   a.psi1 = reinterpret_cast<const double*>(ws_ptr(ws, p->lay.psi1));
   a.psi2 = reinterpret_cast<const double*>(ws_ptr(ws, p->lay.psi2));
   a.xres = reinterpret_cast<T*>(ws_ptr(ws, p->lay.x_res));
+  a.xout = a.xres;
   a.pres = reinterpret_cast<T*>(ws_ptr(ws, p->lay.p_res));
   a.phi = reinterpret_cast<const T*>(ws_ptr(ws, p->lay.phi));
   a.rho = reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.rho));
@@ -413,6 +413,11 @@ struct Runner {
   hipStream_t s;
   std::vector<int> tiles;
   bool batched;
+  // optional redirections (segment recomputation of the reverse sweep): positions read from
+  // x_in and written to x_out, potential written and read at phi
+  T* x_in = nullptr;
+  T* x_out = nullptr;
+  T* phi = nullptr;
 
   std::vector<BlockMap> maps(const Maps& m) const {
     std::vector<BlockMap> out;
@@ -425,10 +430,14 @@ struct Runner {
   }
   void particles(int mode, const StepScalars& sc) {
     ParticleArgs<T> a = particle_args<T>(p, ws, sc);
+    if (x_in) a.xres = x_in;
+    a.xout = x_out ? x_out : a.xres;
+    if (phi) a.phi = phi;
     for (auto& m : maps(p->part)) hip_check(launch_particles<T>(a, mode, m, s), "particle kernel");
   }
   void poisson(double D1_bc) {
     MeshArgs<T> a = mesh_args<T>(p, ws, D1_bc);
+    if (phi) a.phi = phi;
     if (batched) {
       for (size_t c = 0; c < p->p1.class_M.size(); ++c) {
         auto cls = [&](const Maps& m) {
@@ -614,15 +623,27 @@ void zero_bytes(void* ptr, size_t bytes, hipStream_t s) {
   }
 }
 
+// Positions x_res and potentials of the steps of one segment, kept in a ring of c + 1 slots
+// indexed by step mod (c + 1): the segment [k0, k1] needs k1 - k0 + 1 <= c + 1 of them, and
+// the slot of step k1 still holds what the recomputation of the later segment left there.
+template <typename T>
+struct SegmentRing {
+  T* x;
+  T* phi;
+  int slots;
+  int64_t P, H;
+  T* xs(int k) const { return x + (size_t)(k % slots) * 3 * P; }
+  T* ph(int k) const { return phi + (size_t)(k % slots) * H; }
+};
+
 template <typename T>
 void do_backward(scola_plan* p, const T* lam_dens, double* grad_w, void* ws, hipStream_t s) {
   const scola_layout& l = p->lay;
   const int n = p->cfg.n_steps, c = p->cfg.checkpoint_every, N = p->cfg.Np;
   const int nseg = (n + c - 1) / c;
   const size_t R = sizeof(T);
-  const int n_tiles = (int)p->desc.size();
   const int64_t N3 = (int64_t)N * N * N;
-  AdjointArgs<T> a;
+  AdjointArgs<T> a{};
   a.tiles = p->d_tiles;
   a.psi1 = reinterpret_cast<const double*>(ws_ptr(ws, l.psi1));
   a.psi2 = reinterpret_cast<const double*>(ws_ptr(ws, l.psi2));
@@ -630,76 +651,87 @@ void do_backward(scola_plan* p, const T* lam_dens, double* grad_w, void* ws, hip
   a.lam_p = reinterpret_cast<T*>(ws_ptr(ws, l.lam_p));
   a.lam_psi1 = reinterpret_cast<double*>(ws_ptr(ws, l.lam_psi1));
   a.lam_psi2 = reinterpret_cast<double*>(ws_ptr(ws, l.lam_psi2));
-  a.lam_G = reinterpret_cast<T*>(ws_ptr(ws, l.lam_G));
   a.lam_rho = reinterpret_cast<const T*>(ws_ptr(ws, l.lam_rho));
+  a.work = reinterpret_cast<T*>(ws_ptr(ws, l.work));
+  a.lam_bc0 = reinterpret_cast<double*>(ws_ptr(ws, l.lam_bc0));
   a.P = p->P;
   a.H = p->H;
-  double* lam_bc0 = reinterpret_cast<double*>(ws_ptr(ws, l.lam_bc0));
-  T* work = reinterpret_cast<T*>(ws_ptr(ws, l.work));
-  zero_bytes(a.lam_G, 3 * (size_t)p->H * R, s);
-  zero_bytes(lam_bc0, (size_t)p->H * 8, s);
+  zero_bytes(a.lam_bc0, (size_t)p->H * 8, s);
   // transpose of the output density at the final positions
-  a.xk = reinterpret_cast<const T*>(ws_ptr(ws, l.x_res));
-  a.D1 = p->D1[n];
-  a.D2 = p->D2[n];
-  a.phi = nullptr;
+  a.xg = reinterpret_cast<const T*>(ws_ptr(ws, l.x_res));
+  a.D1g = p->D1[n];
+  a.D2g = p->D2[n];
   hip_check(launch_adj_output<T>(a, full_map(p->part), lam_dens, N, p->cfg.N_out, s),
             "adjoint output");
   std::vector<int> all = subset_list(p, nullptr, 0);
-  Runner<T> r{p, ws, s, all, true};
-  T* seg_x = reinterpret_cast<T*>(ws_ptr(ws, l.seg_x));
-  T* seg_phi = reinterpret_cast<T*>(ws_ptr(ws, l.seg_phi));
-  T* x_res = reinterpret_cast<T*>(ws_ptr(ws, l.x_res));
-  T* phi = reinterpret_cast<T*>(ws_ptr(ws, l.phi));
+  const SegmentRing<T> ring{reinterpret_cast<T*>(ws_ptr(ws, l.seg_x)),
+                            reinterpret_cast<T*>(ws_ptr(ws, l.seg_phi)), c + 1, p->P, p->H};
+  MeshArgs<T> m = mesh_args<T>(p, ws, 0.0);
+  m.lam_rho = const_cast<T*>(a.lam_rho);
+  m.lam_bc0 = a.lam_bc0;
+  auto adjoint_poisson = [&](double D1) {
+    m.D1_bc = D1;
+    for (size_t cl = 0; cl < p->p1.class_M.size(); ++cl) {
+      auto cls = [&](const Maps& mm) {
+        BlockMap b = full_map(mm);
+        b.base = mm.class_first[cl];
+        b.count = mm.class_count[cl];
+        return b;
+      };
+      hip_check(launch_poisson<T>(m, p->p1.class_M[cl], cls(p->p1), cls(p->p2), cls(p->p3), s,
+                                  true), "adjoint poisson");
+    }
+  };
+  auto set_gather = [&](int g) {       // force of step g
+    const StepScalars sg = row_scalars(p, g);
+    a.xg = ring.xs(g);
+    a.phi = ring.ph(g);
+    a.beta_g = sg.beta;
+    a.D1g = sg.D1;
+    a.D2g = sg.D2;
+  };
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int k0 = seg * c, k1 = std::min(k0 + c, n);
-    // recompute the segment forward from its checkpoint, keeping x_res and phi per step
-    copy_checkpoint<T>(p, all, seg, false, ws, s);
+    // recompute the segment from its checkpoint: x_res and the potential of steps k0 .. k1-1
+    // into the ring (step k1's entries are there from the later segment)
+    char* ck = ws_ptr(ws, l.ckpt) + (size_t)seg * 6 * p->P * R;
+    hip_check(hipMemcpyAsync(ring.xs(k0), ck, 3 * p->P * R, hipMemcpyDeviceToDevice, s),
+              "checkpoint restore");
+    hip_check(hipMemcpyAsync(ws_ptr(ws, l.p_res), ck + 3 * p->P * R, 3 * p->P * R,
+                             hipMemcpyDeviceToDevice, s), "checkpoint restore");
+    Runner<T> r{p, ws, s, all, true};
+    r.x_in = ring.xs(k0);
+    r.phi = ring.ph(k0);
     StepScalars d0{};
     d0.D1 = p->D1[k0];
     d0.D2 = p->D2[k0];
     r.particles(kDepositOnly, d0);
     r.poisson(p->D1[k0]);
-    for (int k = k0; k < k1; ++k) {
-      hip_check(hipMemcpyAsync(seg_x + (size_t)(k - k0) * 3 * p->P, x_res, 3 * p->P * R,
-                               hipMemcpyDeviceToDevice, s), "segment copy");
-      hip_check(hipMemcpyAsync(seg_phi + (size_t)(k - k0) * p->H, phi, p->H * R,
-                               hipMemcpyDeviceToDevice, s), "segment copy");
-      if (k < k1 - 1) {
-        r.particles(kStep, row_scalars(p, k));
-        r.poisson(p->D1[k + 1]);
-      }
+    for (int k = k0; k + 1 < k1; ++k) {
+      r.x_in = ring.xs(k);
+      r.x_out = ring.xs(k + 1);
+      r.phi = ring.ph(k);
+      r.particles(kStep, row_scalars(p, k));
+      r.phi = ring.ph(k + 1);
+      r.poisson(p->D1[k + 1]);
     }
-    // reverse the segment step by step
+    zero_bytes(a.work, (size_t)p->G * R, s);   // left over from the recomputation
+    // reverse the segment: gather of step k+1 fused with the scatter of step k
     for (int k = k1 - 1; k >= k0; --k) {
+      const bool gather = k + 1 < n;
+      if (gather) set_gather(k + 1);
       const StepScalars sc = row_scalars(p, k);
-      a.xk = seg_x + (size_t)(k - k0) * 3 * p->P;
-      a.phi = seg_phi + (size_t)(k - k0) * p->H;
+      a.xs = ring.xs(k);
       a.alpha = sc.alpha;
       a.beta = sc.beta;
       a.D1 = sc.D1;
       a.D2 = sc.D2;
-      hip_check(launch_adj_step<T>(a, full_map(p->part), 0, work, lam_bc0, n_tiles, s),
-                "adjoint scatter");
-      hip_check(launch_adj_step<T>(a, full_map(p->part), 1, work, lam_bc0, n_tiles, s),
-                "adjoint divergence");
-      MeshArgs<T> m = mesh_args<T>(p, ws, sc.D1);
-      m.lam_rho = const_cast<T*>(a.lam_rho);
-      m.lam_bc0 = lam_bc0;
-      for (size_t cl = 0; cl < p->p1.class_M.size(); ++cl) {
-        auto cls = [&](const Maps& mm) {
-          BlockMap b = full_map(mm);
-          b.base = mm.class_first[cl];
-          b.count = mm.class_count[cl];
-          return b;
-        };
-        hip_check(launch_poisson<T>(m, p->p1.class_M[cl], cls(p->p1), cls(p->p2), cls(p->p3), s,
-                                    true), "adjoint poisson");
-      }
-      hip_check(launch_adj_step<T>(a, full_map(p->part), 2, work, lam_bc0, n_tiles, s),
-                "adjoint gather");
+      hip_check(launch_adj_step<T>(a, full_map(p->part), gather, true, s), "adjoint particles");
+      adjoint_poisson(sc.D1);
     }
   }
+  set_gather(0);
+  hip_check(launch_adj_step<T>(a, full_map(p->part), true, false, s), "adjoint particles");
   // FP64 set-up adjoint: Psi1, Psi2, Phi_BC^0 -> phi1, phi2 -> white noise
   double* g = reinterpret_cast<double*>(ws_ptr(ws, l.adj_grid));
   double* lam_psig = g;               // 6 N^3
@@ -709,7 +741,7 @@ void do_backward(scola_plan* p, const T* lam_dens, double* grad_w, void* ws, hip
   double2* cbuf = reinterpret_cast<double2*>(ws_ptr(ws, l.cbuf));
   zero_bytes(g, 7 * (size_t)N3 * 8, s);
   BoxSetupArgs b = box_setup_args(p, ws);
-  hip_check(launch_adj_setup_scatter(b, a.lam_psi1, a.lam_psi2, lam_psig, lam_bc0, lam_phi1, s),
+  hip_check(launch_adj_setup_scatter(b, a.lam_psi1, a.lam_psi2, lam_psig, a.lam_bc0, lam_phi1, s),
             "adjoint set-up scatter");
   hip_check(launch_adj_phi_from_psi(lam_psig, lam_phi1, cbuf, N, s), "adjoint D^T");
   hip_check(fft3d_forward(cbuf, N, s), "fft");
