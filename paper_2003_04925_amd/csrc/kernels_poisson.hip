@@ -50,6 +50,10 @@ __device__ inline C c_mul(C a, C b) {
   return r;
 }
 
+// 1 / d: the hardware reciprocal (1 ulp) in FP32 plans, a correctly rounded division in FP64
+__device__ __forceinline__ float recip(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double recip(double d) { return 1.0 / d; }
+
 __device__ inline int bitrev5(int l) { return (int)(__brev((unsigned)l) >> 27); }
 
 // Logical block index: hardware dispatches consecutive workgroups round-robin over the 8
@@ -62,21 +66,66 @@ __device__ inline int logical_block(const BlockMap& m) {
   return (b & 7) * per + (b >> 3);
 }
 
+// exp(-2 pi i m / R) for R = 1..8 (row R - 1), m < R: the in-register DFT multiplies by
+// these compile-time constants, so the trivial ones (1, -1, +-i) cost no arithmetic.
+constexpr double kDftW[8][8][2] = {
+    {{1.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}},
+    {{1.0, 0.0}, {-1.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}},
+    {{1.0, 0.0}, {-0.5, -0.8660254037844386}, {-0.5, 0.8660254037844386}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}},
+    {{1.0, 0.0}, {0.0, -1.0}, {-1.0, 0.0}, {0.0, 1.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}},
+    {{1.0, 0.0}, {0.30901699437494745, -0.9510565162951535}, {-0.8090169943749473, -0.5877852522924732}, {-0.8090169943749473, 0.5877852522924732}, {0.30901699437494745, 0.9510565162951535}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}},
+    {{1.0, 0.0}, {0.5, -0.8660254037844386}, {-0.5, -0.8660254037844386}, {-1.0, 0.0}, {-0.5, 0.8660254037844386}, {0.5, 0.8660254037844386}, {0.0, 0.0}, {0.0, 0.0}},
+    {{1.0, 0.0}, {0.6234898018587336, -0.7818314824680298}, {-0.22252093395631434, -0.9749279121818236}, {-0.900968867902419, -0.43388373911755823}, {-0.900968867902419, 0.43388373911755823}, {-0.22252093395631434, 0.9749279121818236}, {0.6234898018587336, 0.7818314824680298}, {0.0, 0.0}},
+    {{1.0, 0.0}, {0.7071067811865476, -0.7071067811865476}, {0.0, -1.0}, {-0.7071067811865476, -0.7071067811865476}, {-1.0, 0.0}, {-0.7071067811865476, 0.7071067811865476}, {0.0, 1.0}, {0.7071067811865476, 0.7071067811865476}},
+};
+
+// a * W_R^m with W_R^m = exp(-2 pi i m / R); R and m are compile-time constants after
+// unrolling, and the branches on the table entries fold away.
+template <typename T>
+__device__ __forceinline__ cx<T> mul_wr(cx<T> a, int R, int m) {
+  const double c = kDftW[R - 1][m][0], s = kDftW[R - 1][m][1];
+  cx<T> r;
+  if (c == 1.0 && s == 0.0) return a;
+  if (c == -1.0 && s == 0.0) {
+    r.x = -a.x;
+    r.y = -a.y;
+  } else if (c == 0.0 && s == -1.0) {
+    r.x = a.y;
+    r.y = -a.x;
+  } else if (c == 0.0 && s == 1.0) {
+    r.x = -a.y;
+    r.y = a.x;
+  } else {
+    r.x = a.x * (T)c - a.y * (T)s;
+    r.y = a.x * (T)s + a.y * (T)c;
+  }
+  return r;
+}
+
 // One radix-2 decimation-in-frequency stage across lanes (partner lane l ^ S) of K x R
-// independent 32-point transforms.
+// independent 32-point transforms, without divergent branches: every lane forms
+// p + sign x (lower half: x + p; upper half: p - x) and multiplies by its twiddle, which
+// is 1 on the lower half; the last stage (S = 1) has only unit twiddles.
 template <int S, int R, int K, typename T>
 __device__ __forceinline__ void dif_stage(cx<T> (&x)[K][R], const cx<T>* __restrict__ tw,
                                           int l) {
   const bool upper = (l & S) != 0;
-  const cx<T> w = tw[(l & (S - 1)) * (16 / S) * R];                    // W_{2S}^(l mod S)
+  const T sg = upper ? T(-1) : T(1);
+  cx<T> w;
+  if constexpr (S > 1) w = tw[upper ? (l & (S - 1)) * (16 / S) * R : 0];   // W_{2S}^(l mod S)
 #pragma unroll
   for (int k = 0; k < K; ++k)
 #pragma unroll
     for (int k1 = 0; k1 < R; ++k1) {
-      cx<T> p;
-      p.x = lane_xor<S>(x[k][k1].x);
-      p.y = lane_xor<S>(x[k][k1].y);
-      x[k][k1] = upper ? c_mul(c_sub(p, x[k][k1]), w) : c_add(x[k][k1], p);
+      cx<T> v;
+      v.x = lane_xor<S>(x[k][k1].x) + sg * x[k][k1].x;
+      v.y = lane_xor<S>(x[k][k1].y) + sg * x[k][k1].y;
+      if constexpr (S > 1) {
+        x[k][k1].x = v.x * w.x - v.y * w.y;
+        x[k][k1].y = v.x * w.y + v.y * w.x;
+      } else {
+        x[k][k1] = v;
+      }
     }
 }
 
@@ -86,9 +135,6 @@ __device__ __forceinline__ void dif_stage(cx<T> (&x)[K][R], const cx<T>* __restr
 template <int R, int K, typename T>
 __device__ __forceinline__ void halfwave_fft(cx<T> (&x)[K][R], const cx<T>* __restrict__ tw, int l) {
   if constexpr (R > 1) {
-    cx<T> wr[R];
-#pragma unroll
-    for (int m = 0; m < R; ++m) wr[m] = tw[m * 32];       // W_R^m
     cx<T> tl[R];
 #pragma unroll
     for (int k1 = 1; k1 < R; ++k1) tl[k1] = tw[l * k1];    // W_N^(n1 k1)
@@ -99,7 +145,7 @@ __device__ __forceinline__ void halfwave_fft(cx<T> (&x)[K][R], const cx<T>* __re
       for (int k1 = 0; k1 < R; ++k1) {
         cx<T> acc = x[k][0];
 #pragma unroll
-        for (int n2 = 1; n2 < R; ++n2) acc = c_add(acc, c_mul(x[k][n2], wr[(n2 * k1) % R]));
+        for (int n2 = 1; n2 < R; ++n2) acc = c_add(acc, mul_wr<T>(x[k][n2], R, (n2 * k1) % R));
         y[k1] = k1 ? c_mul(acc, tl[k1]) : acc;
       }
 #pragma unroll
@@ -126,14 +172,16 @@ __device__ __forceinline__ void dst_pairs(T* const (&la)[K], T* const (&lb)[K], 
   for (int k = 0; k < K; ++k)
 #pragma unroll
     for (int n2 = 0; n2 < R; ++n2) {
+      // odd extension: position m holds a_m (m < M), 0 (m = 0, M), -a_{2M-m} (m > M); the
+      // zero positions read an in-line entry (finite data) and are masked by the sign factor
       const int m = 32 * n2 + l;
+      const bool lo = m < M;
+      const int idx = min(max(lo ? m - 1 : 2 * M - m - 1, 0), M - 2);
+      const T sg = (m == 0 || m == M) ? T(0) : (lo ? T(1) : T(-1));
       cx<T> v;
       v.x = T(0);
       v.y = T(0);
-      if (valid[k] && m != 0 && m != M) {
-        const bool lo = m < M;
-        const int idx = lo ? m - 1 : 2 * M - m - 1;
-        const T sg = lo ? T(1) : T(-1);
+      if (valid[k]) {
         v.x = sg * la[k][idx * stride];
         if (has_b[k]) v.y = sg * lb[k][idx * stride];
       }
@@ -271,8 +319,8 @@ __device__ __forceinline__ void pencil_solve(T* tile, int pitch, int cw, int y, 
     lzb[k] = hb[k] ? ev[z0 + 2 * p[k] + 1] : T(-1);
   }
   // forward DST along x, then Phi^{lmn} = delta^{lmn} 8/M^3 / (lambda_l + lambda_m + lambda_n)
-  auto sa = [&](int k, int j) { return norm / (ev[j - 1] + ly + lza[k]); };
-  auto sb = [&](int k, int j) { return norm / (ev[j - 1] + ly + lzb[k]); };
+  auto sa = [&](int k, int j) { return norm * recip(ev[j - 1] + ly + lza[k]); };
+  auto sb = [&](int k, int j) { return norm * recip(ev[j - 1] + ly + lzb[k]); };
   dst_pairs<R, 2, T>(la, lb, valid, hb, pitch, tw, l, sa, sb);
   // the same half wavefront reads back only the lines it wrote
   auto one = [](int, int) { return T(1); };
@@ -395,11 +443,11 @@ hipError_t launch_poisson_R(const MeshArgs<T>& a, const BlockMap& p1, const Bloc
   if (lds > 65536) {
     static bool done = false;     // allow more than 64 KiB of dynamic LDS (160 KiB on gfx950)
     if (!done) {
-      hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p1<T, R, ADJ>),
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p1<T, R, ADJ>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p2<T, R>),
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p2<T, R>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p3<T, R, ADJ>),
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p3<T, R, ADJ>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       (void)hipGetLastError();
       done = true;
