@@ -76,11 +76,10 @@ __device__ inline void block_adjoint_gather(const T* __restrict__ phi, const T* 
     hi[c] = min(j0[c] + 2, M + 1);
   }
   block_bounds(in, lo, hi, bounds);
-  const int lx = bounds[0], ly = bounds[1], lz = bounds[2];
-  const int wx = bounds[3] - lx + 1, wy = bounds[4] - ly + 1, wz = bounds[5] - lz + 1;
-  const bool empty = wx <= 0 || wy <= 0 || wz <= 0;
-  const int vol = empty ? 0 : wx * wy * wz;
-  const bool use_lds = !empty && vol <= kWindow;
+  const BlockWindow bw = block_window(bounds);
+  const int lx = bw.lx, ly = bw.ly, lz = bw.lz, wx = bw.wx, wy = bw.wy, wz = bw.wz;
+  const int vol = bw.vol;
+  const bool use_lds = bw.lds;
   if (use_lds) {
     const int wyz = wy * wz;
     const float inv_wz = 1.0f / (float)wz, inv_wyz = 1.0f / (float)wyz;
@@ -172,13 +171,12 @@ __device__ inline void block_adjoint_scatter(T* __restrict__ work, double* __res
     if (mx > 0.0) frexp(mx, &ex);
   }
   block_bounds_max(in, lo, hi, ex, bounds);
-  const int lx = bounds[0], ly = bounds[1], lz = bounds[2];
-  const int wx = bounds[3] - lx + 1, wy = bounds[4] - ly + 1, wz = bounds[5] - lz + 1;
+  const BlockWindow bw = block_window(bounds);
+  const int lx = bw.lx, ly = bw.ly, lz = bw.lz, wx = bw.wx, wy = bw.wy, wz = bw.wz;
   const int emax = max(bounds[6], kNoExp);
   const double qscale = ldexp(1.0, kQ - 9 - emax), qstep = ldexp(1.0, emax + 9 - kQ);
-  const bool empty = wx <= 0 || wy <= 0 || wz <= 0;
-  const int vol = empty ? 0 : wx * wy * wz;
-  const bool use_lds = !empty && vol <= kWindow;
+  const int vol = bw.vol;
+  const bool use_lds = bw.lds;
   if (use_lds) {
     for (int e = threadIdx.x; e < vol; e += blockDim.x) win[e] = Q(0);
     __syncthreads();

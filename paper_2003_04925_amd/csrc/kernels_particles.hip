@@ -103,11 +103,10 @@ __device__ inline long long deposit_block(unsigned long long* __restrict__ rho, 
     any = any && lo[c] <= hi[c];
   }
   block_bounds(any, lo, hi, bounds);
-  const int lx = bounds[0], ly = bounds[1], lz = bounds[2];
-  const int wx = bounds[3] - lx + 1, wy = bounds[4] - ly + 1, wz = bounds[5] - lz + 1;
-  const bool empty = wx <= 0 || wy <= 0 || wz <= 0;
-  const int vol = empty ? 0 : wx * wy * wz;
-  const bool use_lds = !empty && vol <= kWindow;
+  const BlockWindow bw = block_window(bounds);
+  const int lx = bw.lx, ly = bw.ly, lz = bw.lz, wx = bw.wx, wy = bw.wy, wz = bw.wz;
+  const int vol = bw.vol;
+  const bool use_lds = bw.lds;
   if (use_lds) {
     for (int e = threadIdx.x; e < vol; e += blockDim.x) win[e] = W(0);
     __syncthreads();
@@ -207,12 +206,11 @@ __device__ inline void block_force(const T* __restrict__ phi, int M, double ux, 
     hi[a] = min(j0[a] + 2, M + 1);
   }
   block_bounds(in, lo, hi, bounds);
-  const int lx = bounds[0], ly = bounds[1], lz = bounds[2];
-  const int wx = bounds[3] - lx + 1, wy = bounds[4] - ly + 1, wz = bounds[5] - lz + 1;
-  const bool empty = wx <= 0 || wy <= 0 || wz <= 0;
-  const int vol = empty ? 0 : wx * wy * wz;
+  const BlockWindow bw = block_window(bounds);
+  const int lx = bw.lx, ly = bw.ly, lz = bw.lz, wx = bw.wx, wy = bw.wy, wz = bw.wz;
+  const int vol = bw.vol;
   const int Mp = M + 3;
-  if (!empty && vol <= kWindow) {
+  if (bw.lds) {
     const int wyz = wy * wz;
     const float inv_wz = 1.0f / (float)wz, inv_wyz = 1.0f / (float)wyz;
 #pragma unroll 4

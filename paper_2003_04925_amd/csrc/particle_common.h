@@ -84,6 +84,29 @@ __device__ inline void block_bounds_max(bool any, const int (&lo)[3], const int 
   __syncthreads();
 }
 
+// The LDS window of a block from the bounds left by block_bounds: nodes [l, l + w) per
+// axis.  A block in which no thread contributed keeps the sentinels (lo > hi) and gets an
+// empty window; the widths are formed only for a non-empty window, where they are at most
+// M + 3, so the arithmetic cannot overflow.
+struct BlockWindow {
+  int lx, ly, lz, wx, wy, wz, vol;
+  bool lds;   // fits in kWindow entries
+};
+
+__device__ inline BlockWindow block_window(const int* bounds) {
+  BlockWindow w;
+  w.lx = bounds[0];
+  w.ly = bounds[1];
+  w.lz = bounds[2];
+  const bool empty = bounds[0] > bounds[3] || bounds[1] > bounds[4] || bounds[2] > bounds[5];
+  w.wx = empty ? 0 : bounds[3] - bounds[0] + 1;
+  w.wy = empty ? 0 : bounds[4] - bounds[1] + 1;
+  w.wz = empty ? 0 : bounds[5] - bounds[2] + 1;
+  w.vol = w.wx * w.wy * w.wz;
+  w.lds = !empty && w.vol <= kWindow;
+  return w;
+}
+
 // Row-major decomposition e -> (ex, ey, ez) of a window with rows wy x wz, using FP32
 // reciprocals (exact for windows far below 2^20 entries) instead of integer division.
 __device__ inline void window_coords(int e, int wz, int wyz, float inv_wz, float inv_wyz,

@@ -1,0 +1,65 @@
+"""GPU edge cases of the particle kernels, through the C ABI.
+
+Blocks whose particles all lie outside their box: the block-wide LDS window is empty (no
+thread contributes a node range) and must be treated as empty, not formed from the
+reduction's sentinels.  Such a block deposits nothing (every particle's unit of mass is
+counted as dropped, exactly) and its particles feel no mesh force (every interpolation
+corner lies outside [0, M]^3), so the kick reduces to its LPT terms.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_blocks_entirely_outside_their_box(torch, precision):
+    import paper_2003_04925_amd as S
+    Np, L = 32, 128.0
+    tiles = S.uniform_tiling(Np, 2, 8)
+    sim = S.Simulation(L, Np, tiles, 4, precision=precision)
+    say("all-outside blocks", precision)
+    sim.setup(torch.from_numpy(synthetic.white_noise(Np, 5)).cuda())
+    po, M, _, _ = sim.box_slices()[0]
+    n0 = M ** 3
+    x = sim.view("x_res")
+    x[:, po:po + n0] = 10.0 * M        # every particle of box 0 far outside its box
+    row = sim.step_table()[2]
+    beta, alpha, D1, D2, D1n, D2n = row[1], row[2], row[3], row[4], row[5], row[6]
+    sim.op_deposit(D1, D2)
+    torch.cuda.synchronize()
+    bits = sim.layout.fixed_bits
+    dropped = sim.view("dropped").cpu().numpy()
+    assert int(dropped[0]) == n0 * (1 << bits)            # exact: all of box 0's mass
+    assert all(0 <= int(d) < n0 * (1 << bits) for d in dropped[1:])
+    sim.op_poisson(D1)
+    p_before = sim.view("p_res").clone()
+    sim.op_step(beta, alpha, D1, D2, D1n, D2n, True)
+    torch.cuda.synchronize()
+    p = sim.view("p_res")[:, po:po + n0].double().cpu().numpy()
+    s1 = sim.view("psi1")[:, po:po + n0].double().cpu().numpy()
+    s2 = sim.view("psi2")[:, po:po + n0].double().cpu().numpy()
+    p0 = p_before[:, po:po + n0].double().cpu().numpy()
+    expect = p0 + beta * (-D1 * s1 + (D2 - D1 * D1) * s2)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    err = np.abs(p - expect).max() / max(np.abs(expect).max(), 1e-30)
+    say("  zero-force kick error", err)
+    assert np.isfinite(sim.view("p_res").double().cpu().numpy()).all()
+    assert err < tol
