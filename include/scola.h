@@ -154,10 +154,11 @@ scola_status scola_forward(scola_plan* plan, const double* d_white_noise, void* 
  * (R [N_out^3], device), writes d loss / d white noise (double [N_p^3], device).  Needs a
  * plan with checkpoint_every > 0 and a preceding scola_forward over all tiles on the same
  * workspace (else SCOLA_ESTATE).  Segments of checkpoint_every steps are recomputed from
- * the checkpoints, then reversed step by step: transpose of the drift and kick, of the CiC
- * interpolation (3-component scatter), of the gradient, the same Dirichlet DST solve (the
- * FDA-2 Dirichlet Laplacian is symmetric) and of the deposit; finally the FP64 transposes
- * of Phi_BC^0, Psi = D phi, the second-order source and the initial-condition filter.
+ * the checkpoints, then reversed step by step: transpose of the drift and kick, of the
+ * gradient-then-CiC-interpolation chain (one scalar scatter per particle onto the padded
+ * nodes), the same Dirichlet DST solve (the FDA-2 Dirichlet Laplacian is symmetric) and of
+ * the deposit; finally the FP64 transposes of Phi_BC^0, Psi = D phi, the second-order
+ * source and the initial-condition filter.
  * The particle state left in the workspace afterwards is that of the first segment;
  * run scola_evolve again before scola_output. */
 scola_status scola_backward(scola_plan* plan, const void* d_grad_density,
@@ -191,7 +192,7 @@ scola_status scola_output(scola_plan* plan, void* d_pos, void* d_mom, void* d_de
  * scola_op_deposit: B^sCOLA (Sec. 3.4.1) -- clears rho and deposits every box particle at
  *   u = q - D1 Psi1 + D2 Psi2 + x_res onto interior nodes [1, M-1]^3; mass that would land
  *   elsewhere is dropped and counted in `dropped`.
- * scola_op_poisson: App. C -- delta = rho / 2^40 - 1, delta' = delta - Delta Phi_BCs with
+ * scola_op_poisson: App. C -- delta = rho / 2^fixed_bits - 1, delta' = delta - Delta Phi_BCs with
  *   Phi_BCs = D1_bc Phi_BC^0, forward DST-I, division by the FDA-2 eigenvalues, inverse
  *   DST-I; writes phi on [-1, M+1]^3 with the shell set to D1_bc Phi_BC^0 (Sec. 3.4.2).
  *   rho is left zeroed for the next deposit.
