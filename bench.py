@@ -190,6 +190,7 @@ def main():
     sim.setup(w)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    block_schedule = sim.tune(reps=5)      # autotuned launch schedule, untimed
     if args.kernels_only:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
         dst = torch.empty_like(src)
@@ -248,7 +249,8 @@ def main():
                                f"{info['n_tiles']} boxes, {wl.n_steps} KDK steps, "
                                f"{sim.precision} {('per-tile' if sim.precision == 'fp64' else 'batched')}",
                    "box_particles": P, "n_tiles": info["n_tiles"],
-                   "oversimulation_r": info["r"], "n_steps": wl.n_steps},
+                   "oversimulation_r": info["r"], "n_steps": wl.n_steps,
+                   "launch_schedule": {str(k): v for k, v in block_schedule.items()}},
         "useful_particle_steps_per_s": wl.Np ** 3 * wl.n_steps / (ms * 1e-3),
         "end_to_end_s": e2e_s,
         "setup_s_first_call": setup_s,

@@ -179,6 +179,35 @@ scola_status scola_setup(scola_plan* plan, const double* d_white_noise, void* d_
 scola_status scola_evolve(scola_plan* plan, const int32_t* tile_subset, int32_t n_subset,
                           void* d_workspace, hipStream_t stream);
 
+/* Launch schedule (not a quantity of the paper; results are bitwise identical under every
+ * schedule).  Boxes are grouped by size M into classes (ascending M); every class has its
+ * own launches of the fused particle kernel and of the Poisson passes.  Per class:
+ *   waves_per_simd       4 or 6: register budget the fused particle kernel is compiled for
+ *                        (6 = 80 registers, 4 = 128);
+ *   xcd_remap_particles  1: blocks numbered so each of the 8 XCDs takes a contiguous run of
+ *                        whole boxes (their meshes stay in one L2); 0: hardware order;
+ *   xcd_remap_mesh       the same for the three Poisson passes.
+ * Defaults {6, 1, 1}.  scola_plan_tune times the choices per class on the workspace's
+ * particles (after scola_setup, else SCOLA_ESTATE) with `reps` launches each (1..1000) and
+ * keeps the fastest; it leaves the particle state unchanged, clears its deposits, and
+ * synchronises the stream (call it before scola_evolve, never inside a timed or captured
+ * region).  scola_plan_schedule copies the schedule of every class into out (capacity
+ * entries at least; out may be NULL to query *n_classes).  scola_plan_set_schedule sets it
+ * (same classes, same order). */
+typedef struct {
+  int32_t M;
+  int32_t waves_per_simd;
+  int32_t xcd_remap_particles;
+  int32_t xcd_remap_mesh;
+} scola_class_schedule;
+
+scola_status scola_plan_tune(scola_plan* plan, void* d_workspace, hipStream_t stream,
+                             int32_t reps);
+scola_status scola_plan_schedule(const scola_plan* plan, scola_class_schedule* out,
+                                 int32_t capacity, int32_t* n_classes);
+scola_status scola_plan_set_schedule(scola_plan* plan, const scola_class_schedule* in,
+                                     int32_t n_classes);
+
 /* Step B.2 (Sec. 3.2): core particles' positions/momenta to global lattice order, and the
  * periodic CiC density of the core particles on N_out^3 nodes (all tiles must have been
  * evolved for the density).  Any output pointer may be NULL. */

@@ -248,6 +248,31 @@ class Simulation:
             self._plan, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.n_steps + 1))
         return out
 
+    def tune(self, reps=5):
+        """Autotune the launch schedule on this workspace (after setup); returns it."""
+        _lib.check(_lib.lib().scola_plan_tune(self._plan, self._ws, self._stream(), reps))
+        return self.schedule()
+
+    def schedule(self):
+        """{M: {"waves_per_simd", "xcd_remap_particles", "xcd_remap_mesh"}} per box size."""
+        n = ctypes.c_int32()
+        _lib.check(_lib.lib().scola_plan_schedule(self._plan, None, 0, ctypes.byref(n)))
+        arr = (_lib.ClassSchedule * n.value)()
+        _lib.check(_lib.lib().scola_plan_schedule(self._plan, arr, n.value, ctypes.byref(n)))
+        return {int(c.M): {"waves_per_simd": int(c.waves_per_simd),
+                           "xcd_remap_particles": int(c.xcd_remap_particles),
+                           "xcd_remap_mesh": int(c.xcd_remap_mesh)} for c in arr}
+
+    def set_schedule(self, schedule):
+        """schedule: as returned by schedule(), for every box size of the plan."""
+        sizes = sorted(self.schedule())
+        arr = (_lib.ClassSchedule * len(sizes))()
+        for i, M in enumerate(sizes):
+            d = schedule[M]
+            arr[i] = _lib.ClassSchedule(M, d["waves_per_simd"], d["xcd_remap_particles"],
+                                        d["xcd_remap_mesh"])
+        _lib.check(_lib.lib().scola_plan_set_schedule(self._plan, arr, len(sizes)))
+
     def info(self):
         nt = ctypes.c_int32()
         np_ = ctypes.c_int64()

@@ -53,6 +53,11 @@ class Layout(ctypes.Structure):
                 ("n_padded", ctypes.c_int64), ("fixed_bits", ctypes.c_int32)]
 
 
+class ClassSchedule(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
+                ("xcd_remap_particles", ctypes.c_int32), ("xcd_remap_mesh", ctypes.c_int32)]
+
+
 _lib = None
 
 _P = ctypes.c_void_p
@@ -82,6 +87,9 @@ _SIGS = {
                               ctypes.POINTER(_D), _I], _I),
     "scola_linear_power": ([ctypes.POINTER(Cosmology), ctypes.POINTER(_D), ctypes.POINTER(_D),
                             _I], _I),
+    "scola_plan_tune": ([_P, _P, _P, _I], _I),
+    "scola_plan_schedule": ([_P, _P, _I, ctypes.POINTER(_I)], _I),
+    "scola_plan_set_schedule": ([_P, _P, _I], _I),
     "scola_plan_info": ([_P, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_int64),
                          ctypes.POINTER(_D), ctypes.POINTER(_D)], _I),
 }

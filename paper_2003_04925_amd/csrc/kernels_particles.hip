@@ -232,8 +232,9 @@ __device__ inline void block_force(const T* __restrict__ phi, int M, double ux, 
   __syncthreads();   // every thread is done with `bounds` and the window before reuse
 }
 
-template <typename T, int MODE>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6)))
+// OCC: waves per SIMD the register allocation is held to (4 or 6); a schedule choice.
+template <typename T, int MODE, int OCC>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OCC)))
 k_particles(ParticleArgs<T> a, BlockMap m) {
   const int L = logical_block(m);
   if (L >= m.count) return;
@@ -394,31 +395,41 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_particles(const ParticleArgs<T>& a, int mode, const BlockMap& m,
-                            hipStream_t s) {
+template <typename T, int OCC>
+hipError_t launch_particles_occ(const ParticleArgs<T>& a, int mode, const BlockMap& m,
+                                hipStream_t s) {
   if (m.count <= 0) return hipSuccess;
   const dim3 grid(padded_grid(m)), block(kBlock);
   switch (mode) {
     case kDepositOnly:
-      hipLaunchKernelGGL((k_particles<T, kDepositOnly>), grid, block, 0, s, a, m);
+      hipLaunchKernelGGL((k_particles<T, kDepositOnly, OCC>), grid, block, 0, s, a, m);
       break;
     case kStep:
-      hipLaunchKernelGGL((k_particles<T, kStep>), grid, block, 0, s, a, m);
+      hipLaunchKernelGGL((k_particles<T, kStep, OCC>), grid, block, 0, s, a, m);
       break;
     case kStepNoDeposit:
-      hipLaunchKernelGGL((k_particles<T, kStepNoDeposit>), grid, block, 0, s, a, m);
+      hipLaunchKernelGGL((k_particles<T, kStepNoDeposit, OCC>), grid, block, 0, s, a, m);
       break;
     case kFinalKick:
-      hipLaunchKernelGGL((k_particles<T, kFinalKick>), grid, block, 0, s, a, m);
+      hipLaunchKernelGGL((k_particles<T, kFinalKick, OCC>), grid, block, 0, s, a, m);
       break;
     case kInit:
-      hipLaunchKernelGGL((k_particles<T, kInit>), grid, block, 0, s, a, m);
+      hipLaunchKernelGGL((k_particles<T, kInit, OCC>), grid, block, 0, s, a, m);
       break;
     default:
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_particles(const ParticleArgs<T>& a, int mode, const BlockMap& m, int occ,
+                            hipStream_t s) {
+  switch (occ) {
+    case 4: return launch_particles_occ<T, 4>(a, mode, m, s);
+    case 6: return launch_particles_occ<T, 6>(a, mode, m, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename T>
@@ -442,10 +453,10 @@ hipError_t launch_output(const OutputArgs<T>& a, const BlockMap& m, bool density
   return hipGetLastError();
 }
 
-template hipError_t launch_particles<float>(const ParticleArgs<float>&, int, const BlockMap&,
+template hipError_t launch_particles<float>(const ParticleArgs<float>&, int, const BlockMap&, int,
                                             hipStream_t);
 template hipError_t launch_particles<double>(const ParticleArgs<double>&, int,
-                                             const BlockMap&, hipStream_t);
+                                             const BlockMap&, int, hipStream_t);
 template hipError_t launch_output<float>(const OutputArgs<float>&, const BlockMap&, bool,
                                          float*, hipStream_t);
 template hipError_t launch_output<double>(const OutputArgs<double>&, const BlockMap&, bool,

@@ -86,6 +86,8 @@ struct scola_plan {
   void* d_twiddles = nullptr;
   void* d_eigen = nullptr;
   Maps part, p1, p2, p3;
+  // launch schedule per size class (index as part.class_M), chosen by scola_plan_tune
+  std::vector<scola_class_schedule> sched;
   bool is64 = false;
   // call-order state, keyed by the workspace it refers to
   const void* setup_ws = nullptr;
@@ -404,6 +406,28 @@ ParticleArgs<T> particle_args(scola_plan* p, void* ws, const StepScalars& sc) {
   return a;
 }
 
+const scola_class_schedule& sched_of(const scola_plan* p, int M) {
+  for (size_t c = 0; c < p->part.class_M.size(); ++c)
+    if (p->part.class_M[c] == M) return p->sched[c];
+  return p->sched.front();
+}
+
+BlockMap class_map(const Maps& m, size_t c) {
+  BlockMap b = full_map(m);
+  b.base = m.class_first[c];
+  b.count = m.class_count[c];
+  return b;
+}
+
+// The three Poisson passes over every box of size class c (forward or adjoint solve).
+template <typename T>
+void poisson_class(const scola_plan* p, const MeshArgs<T>& a, size_t c, bool adjoint,
+                   hipStream_t s) {
+  BlockMap b1 = class_map(p->p1, c), b2 = class_map(p->p2, c), b3 = class_map(p->p3, c);
+  b1.xcd_remap = b2.xcd_remap = b3.xcd_remap = p->sched[c].xcd_remap_mesh;
+  hip_check(launch_poisson<T>(a, p->p1.class_M[c], b1, b2, b3, s, adjoint), "poisson kernels");
+}
+
 // One call of each kernel family over a set of tiles: all in one launch (batched) or one
 // launch per tile.
 template <typename T>
@@ -433,26 +457,35 @@ struct Runner {
     if (x_in) a.xres = x_in;
     a.xout = x_out ? x_out : a.xres;
     if (phi) a.phi = phi;
-    for (auto& m : maps(p->part)) hip_check(launch_particles<T>(a, mode, m, s), "particle kernel");
+    const Maps& pm = p->part;
+    if (batched) {
+      for (size_t c = 0; c < pm.class_M.size(); ++c) {
+        BlockMap b = class_map(pm, c);
+        b.xcd_remap = p->sched[c].xcd_remap_particles;
+        hip_check(launch_particles<T>(a, mode, b, p->sched[c].waves_per_simd, s),
+                  "particle kernel");
+      }
+    } else {
+      for (int t : tiles) {
+        const scola_class_schedule& cs = sched_of(p, p->desc[t].M);
+        BlockMap b = tile_map(pm, t);
+        b.xcd_remap = cs.xcd_remap_particles;
+        hip_check(launch_particles<T>(a, mode, b, cs.waves_per_simd, s), "particle kernel");
+      }
+    }
   }
   void poisson(double D1_bc) {
     MeshArgs<T> a = mesh_args<T>(p, ws, D1_bc);
     if (phi) a.phi = phi;
     if (batched) {
-      for (size_t c = 0; c < p->p1.class_M.size(); ++c) {
-        auto cls = [&](const Maps& m) {
-          BlockMap b = full_map(m);
-          b.base = m.class_first[c];
-          b.count = m.class_count[c];
-          return b;
-        };
-        hip_check(launch_poisson<T>(a, p->p1.class_M[c], cls(p->p1), cls(p->p2), cls(p->p3), s),
-                  "poisson kernels");
-      }
+      for (size_t c = 0; c < p->p1.class_M.size(); ++c) poisson_class(p, a, c, false, s);
     } else {
-      for (int t : tiles)
-        hip_check(launch_poisson<T>(a, p->desc[t].M, tile_map(p->p1, t), tile_map(p->p2, t),
-                                    tile_map(p->p3, t), s), "poisson kernels");
+      for (int t : tiles) {
+        const int r = sched_of(p, p->desc[t].M).xcd_remap_mesh;
+        BlockMap b1 = tile_map(p->p1, t), b2 = tile_map(p->p2, t), b3 = tile_map(p->p3, t);
+        b1.xcd_remap = b2.xcd_remap = b3.xcd_remap = r;
+        hip_check(launch_poisson<T>(a, p->desc[t].M, b1, b2, b3, s), "poisson kernels");
+      }
     }
   }
 };
@@ -671,16 +704,7 @@ void do_backward(scola_plan* p, const T* lam_dens, double* grad_w, void* ws, hip
   m.lam_bc0 = a.lam_bc0;
   auto adjoint_poisson = [&](double D1) {
     m.D1_bc = D1;
-    for (size_t cl = 0; cl < p->p1.class_M.size(); ++cl) {
-      auto cls = [&](const Maps& mm) {
-        BlockMap b = full_map(mm);
-        b.base = mm.class_first[cl];
-        b.count = mm.class_count[cl];
-        return b;
-      };
-      hip_check(launch_poisson<T>(m, p->p1.class_M[cl], cls(p->p1), cls(p->p2), cls(p->p3), s,
-                                  true), "adjoint poisson");
-    }
+    for (size_t cl = 0; cl < p->p1.class_M.size(); ++cl) poisson_class(p, m, cl, true, s);
   };
   auto set_gather = [&](int g) {       // force of step g
     const StepScalars sg = row_scalars(p, g);
@@ -756,6 +780,73 @@ void do_backward(scola_plan* p, const T* lam_dens, double* grad_w, void* ws, hip
   hip_check(launch_ic_filter(sa, s), "adjoint IC filter");
   hip_check(fft3d_inverse(cbuf, N, s), "fft");
   hip_check(launch_take_real(cbuf, grad_w, 1.0 / (double)N3, N3, s), "take real");
+}
+
+// Launch-schedule autotuner.  For every size class it times, on the workspace's own
+// particles at the positions of the last step (x_res as left by the set-up, i.e. on the
+// 2LPT trajectory) with zero kick and drift so the particle state is unchanged: the fused
+// step kernel compiled for 4 or 6 waves per SIMD, each with and without the XCD-aware block
+// numbering; then the three Poisson passes with and without it.  The fastest of each is
+// kept.  The deposits and potentials it leaves are cleared or overwritten by the next
+// scola_evolve (which starts from L-).
+template <typename T>
+void do_tune(scola_plan* p, void* ws, hipStream_t s, int reps) {
+  const int n = p->cfg.n_steps;
+  StepScalars sc = row_scalars(p, n - 1);
+  sc.beta = 0.0;
+  sc.alpha = 0.0;
+  ParticleArgs<T> a = particle_args<T>(p, ws, sc);
+  MeshArgs<T> ma = mesh_args<T>(p, ws, p->D1[n - 1]);
+  hipEvent_t e0, e1;
+  hip_check(hipEventCreate(&e0), "hipEventCreate");
+  hip_check(hipEventCreate(&e1), "hipEventCreate");
+  auto timed = [&](const std::function<void()>& f) {
+    f();                                               // warm-up
+    hip_check(hipEventRecord(e0, s), "hipEventRecord");
+    for (int r = 0; r < reps; ++r) f();
+    hip_check(hipEventRecord(e1, s), "hipEventRecord");
+    hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+    float ms = 0.0f;
+    hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    return ms;
+  };
+  const Maps& pm = p->part;
+  for (size_t c = 0; c < pm.class_M.size(); ++c) {
+    scola_class_schedule& cs = p->sched[c];
+    float best = 1e30f;
+    for (int occ : {6, 4})
+      for (int remap : {1, 0}) {
+        BlockMap b = class_map(pm, c);
+        b.xcd_remap = remap;
+        const float ms = timed([&] {
+          hip_check(launch_particles<T>(a, kStep, b, occ, s), "tuning launch");
+        });
+        if (ms < best) {
+          best = ms;
+          cs.waves_per_simd = occ;
+          cs.xcd_remap_particles = remap;
+        }
+      }
+    best = 1e30f;
+    const int keep = cs.xcd_remap_mesh;
+    int choice = keep;
+    for (int remap : {1, 0}) {
+      cs.xcd_remap_mesh = remap;
+      const float ms = timed([&] { poisson_class(p, ma, c, false, s); });
+      if (ms < best) {
+        best = ms;
+        choice = remap;
+      }
+    }
+    cs.xcd_remap_mesh = choice;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.rho)), p->G, s),
+            "zero rho");
+  hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped)),
+                            (int64_t)p->desc.size(), s), "zero dropped");
+  hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
 }  // namespace
@@ -841,6 +932,8 @@ scola_status scola_plan_create(const scola_config* cfg, const scola_cosmology* c
     else
       upload_tables<float>(p);
     build_maps(p->part, p->desc, [](const TileDesc& d) { return d.M * d.M * d.M / kBlock; });
+    p->sched.clear();
+    for (int M : p->part.class_M) p->sched.push_back(scola_class_schedule{M, 6, 1, 1});
     build_maps(p->p1, p->desc, [](const TileDesc& d) { return d.M - 1; });
     build_maps(p->p2, p->desc, [](const TileDesc& d) {
       return (d.M - 1) * ((d.M - 1 + kPencilChunk - 1) / kPencilChunk);
@@ -910,6 +1003,48 @@ scola_status scola_evolve(scola_plan* p, const int32_t* subset, int32_t n_subset
       do_evolve<double>(p, tiles, ws, s);
     else
       do_evolve<float>(p, tiles, ws, s);
+  });
+}
+
+scola_status scola_plan_tune(scola_plan* p, void* ws, hipStream_t s, int32_t reps) {
+  return guarded([&] {
+    check_ws(p, ws);
+    if (p->setup_ws != ws) fail(SCOLA_ESTATE, "scola_setup has not run on this workspace");
+    if (reps < 1 || reps > 1000) fail(SCOLA_EINVAL, "reps must be in [1, 1000]");
+    p->forward_ws = nullptr;
+    if (p->is64)
+      do_tune<double>(p, ws, s, reps);
+    else
+      do_tune<float>(p, ws, s, reps);
+  });
+}
+
+scola_status scola_plan_schedule(const scola_plan* p, scola_class_schedule* out,
+                                 int32_t capacity, int32_t* n_classes) {
+  return guarded([&] {
+    if (!p || !n_classes) fail(SCOLA_EINVAL, "null argument");
+    const int nc = (int)p->sched.size();
+    *n_classes = nc;
+    if (!out) return;
+    if (capacity < nc) fail(SCOLA_EINVAL, "capacity too small");
+    for (int c = 0; c < nc; ++c) out[c] = p->sched[c];
+  });
+}
+
+scola_status scola_plan_set_schedule(scola_plan* p, const scola_class_schedule* in,
+                                     int32_t n_classes) {
+  return guarded([&] {
+    if (!p || !in) fail(SCOLA_EINVAL, "null argument");
+    if (n_classes != (int)p->sched.size())
+      fail(SCOLA_EINVAL, "n_classes must equal the number of box sizes of the plan");
+    for (int c = 0; c < n_classes; ++c) {
+      if (in[c].M != p->sched[c].M) fail(SCOLA_EINVAL, "class order or M does not match");
+      if (in[c].waves_per_simd != 4 && in[c].waves_per_simd != 6)
+        fail(SCOLA_EINVAL, "waves_per_simd must be 4 or 6");
+      if ((in[c].xcd_remap_particles | in[c].xcd_remap_mesh) & ~1)
+        fail(SCOLA_EINVAL, "xcd_remap flags must be 0 or 1");
+    }
+    for (int c = 0; c < n_classes; ++c) p->sched[c] = in[c];
   });
 }
 

@@ -63,3 +63,44 @@ def test_blocks_entirely_outside_their_box(torch, precision):
     say("  zero-force kick error", err)
     assert np.isfinite(sim.view("p_res").double().cpu().numpy()).all()
     assert err < tol
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_launch_schedule_does_not_change_results(torch, precision):
+    """Occupancy variants and block numberings change only the launch; the fixed-point
+    deposit makes every schedule bitwise identical."""
+    import paper_2003_04925_amd as S
+    Np, L = 32, 128.0
+    w = torch.from_numpy(synthetic.white_noise(Np, 9)).cuda()
+    outs = []
+    for occ, rp, rm in ((6, 1, 1), (4, 0, 1), (6, 0, 0), (4, 1, 0)):
+        sim = S.Simulation(L, Np, S.uniform_tiling(Np, 2, 8), 4, precision=precision)
+        sim.set_schedule({M: {"waves_per_simd": occ, "xcd_remap_particles": rp,
+                              "xcd_remap_mesh": rm} for M in sim.schedule()})
+        say("schedule", precision, sim.schedule())
+        r = sim.forward(w)
+        outs.append((r["pos"].cpu().numpy(), r["density"].cpu().numpy()))
+    for pos, dens in outs[1:]:
+        assert np.array_equal(pos, outs[0][0])
+        assert np.array_equal(dens, outs[0][1])
+
+
+def test_tuner_picks_a_valid_schedule_and_keeps_the_state(torch):
+    import paper_2003_04925_amd as S
+    Np, L = 32, 128.0
+    w = torch.from_numpy(synthetic.white_noise(Np, 9)).cuda()
+    ref = S.Simulation(L, Np, S.uniform_tiling(Np, 2, 8), 4, precision="fp32").forward(w)
+    sim = S.Simulation(L, Np, S.uniform_tiling(Np, 2, 8), 4, precision="fp32")
+    with pytest.raises(S.ScolaError):
+        sim.tune()                                   # needs the set-up first
+    sim.setup(w)
+    sched = sim.tune(reps=2)
+    say("tuned schedule", sched)
+    assert list(sched) == [32]
+    assert sched[32]["waves_per_simd"] in (4, 6)
+    assert sched[32]["xcd_remap_particles"] in (0, 1) and sched[32]["xcd_remap_mesh"] in (0, 1)
+    sim.evolve()
+    pos = torch.empty_like(ref["pos"])
+    dens = torch.empty_like(ref["density"])
+    sim.output(pos=pos, density=dens)
+    assert torch.equal(pos, ref["pos"]) and torch.equal(dens, ref["density"])
