@@ -208,6 +208,13 @@ scola_status scola_plan_schedule(const scola_plan* plan, scola_class_schedule* o
 scola_status scola_plan_set_schedule(scola_plan* plan, const scola_class_schedule* in,
                                      int32_t n_classes);
 
+/* hipGraph replay of scola_evolve (enabled by default).  With the batched schedule over all
+ * tiles, the second call of scola_evolve on a workspace records the whole evolution (every
+ * kernel launch and checkpoint copy) as one graph on a plan-owned capture stream, and that
+ * and every later call launch the graph on `stream`.  The graph is rebuilt after a change
+ * of workspace or schedule.  enable = 0 drops it and runs every call eagerly. */
+scola_status scola_plan_set_graph(scola_plan* plan, int32_t enable);
+
 /* Step B.2 (Sec. 3.2): core particles' positions/momenta to global lattice order, and the
  * periodic CiC density of the core particles on N_out^3 nodes (all tiles must have been
  * evolved for the density).  Any output pointer may be NULL. */

@@ -248,6 +248,10 @@ class Simulation:
             self._plan, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.n_steps + 1))
         return out
 
+    def set_graph(self, enable):
+        """Replay the batched evolution as a captured hipGraph (default) or run it eagerly."""
+        _lib.check(_lib.lib().scola_plan_set_graph(self._plan, 1 if enable else 0))
+
     def tune(self, reps=5):
         """Autotune the launch schedule on this workspace (after setup); returns it."""
         _lib.check(_lib.lib().scola_plan_tune(self._plan, self._ws, self._stream(), reps))

@@ -88,6 +88,7 @@ _SIGS = {
     "scola_linear_power": ([ctypes.POINTER(Cosmology), ctypes.POINTER(_D), ctypes.POINTER(_D),
                             _I], _I),
     "scola_plan_tune": ([_P, _P, _P, _I], _I),
+    "scola_plan_set_graph": ([_P, _I], _I),
     "scola_plan_schedule": ([_P, _P, _I, ctypes.POINTER(_I)], _I),
     "scola_plan_set_schedule": ([_P, _P, _I], _I),
     "scola_plan_info": ([_P, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_int64),

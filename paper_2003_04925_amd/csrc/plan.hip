@@ -88,6 +88,16 @@ struct scola_plan {
   Maps part, p1, p2, p3;
   // launch schedule per size class (index as part.class_M), chosen by scola_plan_tune
   std::vector<scola_class_schedule> sched;
+  uint64_t sched_version = 0;         // bumped whenever the schedule changes
+  // the batched evolution over all tiles, captured once per workspace and schedule (from
+  // the second call on) and replayed as one hipGraph launch
+  bool use_graph = true;
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t evolve_graph = nullptr;
+  hipGraphExec_t evolve_exec = nullptr;
+  const void* graph_ws = nullptr;
+  uint64_t graph_version = 0;
+  int graph_eager_calls = 0;
   bool is64 = false;
   // call-order state, keyed by the workspace it refers to
   const void* setup_ws = nullptr;
@@ -782,6 +792,44 @@ void do_backward(scola_plan* p, const T* lam_dens, double* grad_w, void* ws, hip
   hip_check(launch_take_real(cbuf, grad_w, 1.0 / (double)N3, N3, s), "take real");
 }
 
+void drop_graph(scola_plan* p) {
+  if (p->evolve_exec) hipGraphExecDestroy(p->evolve_exec);
+  if (p->evolve_graph) hipGraphDestroy(p->evolve_graph);
+  p->evolve_exec = nullptr;
+  p->evolve_graph = nullptr;
+  p->graph_ws = nullptr;
+  p->graph_eager_calls = 0;
+}
+
+// Record the batched evolution (every kernel, checkpoint copy and counter reset of
+// do_evolve; no memset nodes) on the plan's capture stream and instantiate it.
+template <typename T>
+void capture_evolve(scola_plan* p, const std::vector<int>& tiles, void* ws) {
+  if (!p->capture_stream)
+    hip_check(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking),
+              "hipStreamCreateWithFlags");
+  hip_check(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal),
+            "hipStreamBeginCapture");
+  try {
+    do_evolve<T>(p, tiles, ws, p->capture_stream);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(p->capture_stream, &g);
+    if (g) hipGraphDestroy(g);
+    throw;
+  }
+  hipGraph_t g = nullptr;
+  hip_check(hipStreamEndCapture(p->capture_stream, &g), "hipStreamEndCapture");
+  hipGraphExec_t e = nullptr;
+  const hipError_t err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+  if (err != hipSuccess) {
+    hipGraphDestroy(g);
+    hip_check(err, "hipGraphInstantiate");
+  }
+  p->evolve_graph = g;
+  p->evolve_exec = e;
+}
+
 // Launch-schedule autotuner.  For every size class it times, on the workspace's own
 // particles at the positions of the last step (x_res as left by the set-up, i.e. on the
 // 2LPT trajectory) with zero kick and drift so the particle state is unchanged: the fused
@@ -958,6 +1006,8 @@ scola_status scola_plan_destroy(scola_plan* p) {
   free_maps(p->p1);
   free_maps(p->p2);
   free_maps(p->p3);
+  drop_graph(p);
+  if (p->capture_stream) hipStreamDestroy(p->capture_stream);
   if (p->d_tiles) hipFree(p->d_tiles);
   if (p->d_twiddles) hipFree(p->d_twiddles);
   if (p->d_eigen) hipFree(p->d_eigen);
@@ -999,6 +1049,26 @@ scola_status scola_evolve(scola_plan* p, const int32_t* subset, int32_t n_subset
     if (p->setup_ws != ws) fail(SCOLA_ESTATE, "scola_setup has not run on this workspace");
     const std::vector<int> tiles = subset_list(p, subset, n_subset);
     p->forward_ws = (p->cfg.checkpoint_every > 0 && tiles.size() == p->desc.size()) ? ws : nullptr;
+    const bool graphable = p->use_graph && p->cfg.schedule == SCOLA_BATCHED &&
+                           tiles.size() == p->desc.size();
+    if (graphable) {
+      if (p->graph_ws != ws || p->graph_version != p->sched_version) {
+        drop_graph(p);
+        p->graph_ws = ws;
+        p->graph_version = p->sched_version;
+      }
+      if (!p->evolve_exec && p->graph_eager_calls >= 1) {
+        if (p->is64)
+          capture_evolve<double>(p, tiles, ws);
+        else
+          capture_evolve<float>(p, tiles, ws);
+      }
+      if (p->evolve_exec) {
+        hip_check(hipGraphLaunch(p->evolve_exec, s), "hipGraphLaunch");
+        return;
+      }
+      ++p->graph_eager_calls;   // the first call runs eagerly (it also sets kernel attributes)
+    }
     if (p->is64)
       do_evolve<double>(p, tiles, ws, s);
     else
@@ -1016,6 +1086,15 @@ scola_status scola_plan_tune(scola_plan* p, void* ws, hipStream_t s, int32_t rep
       do_tune<double>(p, ws, s, reps);
     else
       do_tune<float>(p, ws, s, reps);
+    ++p->sched_version;
+  });
+}
+
+scola_status scola_plan_set_graph(scola_plan* p, int32_t enable) {
+  return guarded([&] {
+    if (!p) fail(SCOLA_EINVAL, "null plan");
+    p->use_graph = enable != 0;
+    if (!p->use_graph) drop_graph(p);
   });
 }
 
@@ -1045,6 +1124,7 @@ scola_status scola_plan_set_schedule(scola_plan* p, const scola_class_schedule* 
         fail(SCOLA_EINVAL, "xcd_remap flags must be 0 or 1");
     }
     for (int c = 0; c < n_classes; ++c) p->sched[c] = in[c];
+    ++p->sched_version;
   });
 }
 

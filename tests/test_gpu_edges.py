@@ -104,3 +104,45 @@ def test_tuner_picks_a_valid_schedule_and_keeps_the_state(torch):
     dens = torch.empty_like(ref["density"])
     sim.output(pos=pos, density=dens)
     assert torch.equal(pos, ref["pos"]) and torch.equal(dens, ref["density"])
+
+
+def test_graph_replay_matches_eager_runs(torch):
+    """The batched evolution replayed as a captured hipGraph gives bitwise the eager result on
+    every replay, with other eager GPU work (torch reductions, another plan) in between."""
+    import paper_2003_04925_amd as S
+    Np, L = 32, 128.0
+    w = torch.from_numpy(synthetic.white_noise(Np, 21)).cuda()
+    tiles = S.uniform_tiling(Np, 2, 8)
+    eager = S.Simulation(L, Np, tiles, 5, precision="fp32")
+    eager.set_graph(False)
+    ref = eager.forward(w)
+    sim = S.Simulation(L, Np, tiles, 5, precision="fp32")
+    sim.setup(w)
+    pos = torch.empty_like(ref["pos"])
+    dens = torch.empty_like(ref["density"])
+    for r in range(4):             # call 1 eager, call 2 records the graph, calls 2-4 replay it
+        sim.evolve()
+        sim.output(pos=pos, density=dens)
+        noise = float(torch.rand(1 << 20, device="cuda").sum())    # unrelated eager work
+        eager.evolve()
+        torch.cuda.synchronize()
+        say("replay", r, "extra work", round(noise))
+        assert torch.equal(pos, ref["pos"]) and torch.equal(dens, ref["density"])
+
+
+def test_backward_after_a_graph_replayed_forward(torch):
+    import paper_2003_04925_amd as S
+    Np, L = 16, 150.0
+    w = torch.from_numpy(synthetic.white_noise(Np, 3)).cuda()
+    t = torch.from_numpy(synthetic.loss_target(Np, 43)).cuda()
+    grads = []
+    for n_forward in (1, 3):
+        sim = S.Simulation(L, Np, S.uniform_tiling(Np, 2, 4), 3, precision="fp64",
+                           checkpoint_every=2)
+        for _ in range(n_forward):
+            dens = sim.forward(w)["density"]
+        grads.append(sim.backward(2.0 * (dens - t)).cpu().numpy())
+    # the reverse pass sums with floating-point atomics, so two runs agree to round-off only
+    err = np.abs(grads[0] - grads[1]).max() / np.abs(grads[0]).max()
+    say("graph-forward gradient max rel diff", err)
+    assert err < 1e-12
