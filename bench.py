@@ -41,7 +41,8 @@ def build_sim(S, wl, precision=None, schedule=None):
 
 
 def time_evolve(torch, sim, steps, warmup):
-    for _ in range(warmup):
+    # the second call records the evolution as a hipGraph; timed calls replay it
+    for _ in range(max(warmup, 2)):
         sim.evolve()
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -119,16 +120,17 @@ def cpu_baseline(wl, budget_s=20.0):
                        f"included), FP64 NumPy, 1 thread, {platform.processor() or 'host CPU'}")
 
 
-def adjoint_timing(torch, S, synthetic, reps=3):
-    """Workload c4 (the c2 boxes, 20 steps FP32, checkpoints every 5 steps): forward with
-    checkpoints and the reverse pass (segment recompute + adjoint steps + FP64 set-up
-    adjoint), HIP-event timed on the current stream."""
-    wl = synthetic.WORKLOADS["c4"]
+def adjoint_timing(torch, S, synthetic, name="c4", reps=3):
+    """Forward with checkpoints (every 5 steps) and the reverse pass (segment recomputation
+    + adjoint steps + FP64 set-up adjoint) of a density loss, HIP-event timed on the current
+    stream: c4 (the c2 boxes, 20 FP32 steps) or c5 (512 boxes of 96^3, 30 FP32 steps)."""
+    wl = synthetic.WORKLOADS[name]
     sim = S.Simulation(wl.L, wl.Np, S.uniform_tiling(wl.Np, wl.tiles_per_side, wl.buffer),
                        wl.n_steps, precision="fp32", checkpoint_every=5)
     w = torch.from_numpy(synthetic.white_noise(wl.Np, 42)).cuda()
     t = torch.from_numpy(synthetic.loss_target(wl.Np, 43)).cuda().float()
     sim.setup(w)
+    sched = sim.tune(reps=3)
     dens = torch.empty((wl.Np,) * 3, dtype=torch.float32, device="cuda")
     ev = lambda: torch.cuda.Event(enable_timing=True)
     fw, bw = [], []
@@ -145,9 +147,36 @@ def adjoint_timing(torch, S, synthetic, reps=3):
             fw.append(a.elapsed_time(b))
             bw.append(b.elapsed_time(c))
     f, g = sum(fw) / reps, sum(bw) / reps
-    return {"workload": "c4: c2 boxes, 20 FP32 steps, density loss, checkpoint every 5",
+    ws_gb = sim.layout.total / 1e9
+    del sim
+    torch.cuda.empty_cache()
+    return {"workload": f"{name}: {wl.Np}^3 particles, {wl.tiles_per_side ** 3} boxes of "
+                        f"{wl.Np // wl.tiles_per_side + 2 * wl.buffer}^3, {wl.n_steps} FP32 "
+                        f"steps, density loss, checkpoint every 5",
             "forward_ms": f, "backward_ms": g, "backward_over_forward": g / f,
-            "note": "backward = segment recomputation + adjoint steps + FP64 set-up adjoint"}
+            "workspace_GB": ws_gb, "launch_schedule": {str(k): v for k, v in sched.items()},
+            "note": "backward = segment recomputation (one forward's worth of steps) + adjoint "
+                    "steps + FP64 set-up adjoint"}
+
+
+def workload_rate(torch, S, synthetic, name, steps=3, warmup=2):
+    """Particle-steps/s of scola_evolve on one more workload (autotuned, graph replayed)."""
+    wl = synthetic.WORKLOADS[name]
+    sim = build_sim(S, wl)
+    w = torch.from_numpy(synthetic.white_noise(wl.Np, 42)).cuda()
+    sim.setup(w)
+    sched = sim.tune(reps=3)
+    ms, _ = time_evolve(torch, sim, steps, warmup)
+    info = sim.info()
+    out = {"workload": f"{name}: L={wl.L:g} Mpc/h, {wl.Np}^3 particles, {info['n_tiles']} "
+                       f"boxes, {wl.n_steps} steps, {sim.precision} batched",
+           "value": info["n_particles"] * wl.n_steps / (ms * 1e-3), "unit": "particle-steps/s",
+           "ms_per_evolve": ms, "box_particles": info["n_particles"],
+           "useful_particle_steps_per_s": wl.Np ** 3 * wl.n_steps / (ms * 1e-3),
+           "launch_schedule": {str(k): v for k, v in sched.items()}}
+    del sim
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -159,6 +188,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the mixed-size (c3) and large (c5) workload lines")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the forward + reverse timing of the adjoint workload")
     ap.add_argument("--kernels-only", action="store_true",
@@ -177,7 +208,7 @@ def main():
     import synthetic
     torch.cuda.set_device(0)
     if args.adjoint_only:
-        print(json.dumps({"adjoint": adjoint_timing(torch, S, synthetic, reps=args.steps)}),
+        print(json.dumps({"adjoint": adjoint_timing(torch, S, synthetic, "c4", reps=args.steps)}),
               flush=True)
         return
     wl = synthetic.WORKLOADS[args.workload]
@@ -266,19 +297,31 @@ def main():
         sim64 = build_sim(S, wl1)
         w1 = torch.from_numpy(synthetic.white_noise(wl1.Np, 42)).cuda()
         sim64.setup(w1)
-        ms64, _ = time_evolve(torch, sim64, 3, 1)
+        ms64, _ = time_evolve(torch, sim64, 3, 2)
         result["fp64_per_tile"] = {"workload": "c1: 64^3 particles, 8 boxes of 48^3, 10 "
                                                "steps, FP64 per-tile schedule",
                                    "value": sim64.info()["n_particles"] * wl1.n_steps /
                                    (ms64 * 1e-3), "unit": "particle-steps/s"}
         sim32 = build_sim(S, wl1, precision="fp32", schedule="batched")
         sim32.setup(w1)
-        ms32, _ = time_evolve(torch, sim32, 3, 1)
+        ms32, _ = time_evolve(torch, sim32, 3, 2)
         result["fp32_batched_same_workload"] = {
             "workload": "c1 in FP32 batched", "value": sim32.info()["n_particles"] *
             wl1.n_steps / (ms32 * 1e-3), "speedup_vs_fp64_per_tile": ms64 / ms32}
     if not args.no_adjoint and args.workload == "c2":
-        result["adjoint"] = adjoint_timing(torch, S, synthetic)
+        result["adjoint"] = adjoint_timing(torch, S, synthetic, "c4")
+    if not args.no_extra and args.workload == "c2":
+        # the other workloads: each guarded so that a failure is reported, not fatal
+        for key, fn in (("c3_mixed", lambda: workload_rate(torch, S, synthetic, "c3")),
+                        ("c5_large", lambda: workload_rate(torch, S, synthetic, "c5", 2, 2)),
+                        ("c5_adjoint", lambda: adjoint_timing(torch, S, synthetic, "c5", 1))):
+            if key == "c5_adjoint" and args.no_adjoint:
+                continue
+            try:
+                result[key] = fn()
+            except Exception as exc:          # noqa: BLE001 - reported in the JSON line
+                result[key] = {"error": f"{type(exc).__name__}: {exc}"}
+                torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(result), flush=True)

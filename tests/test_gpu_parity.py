@@ -162,6 +162,35 @@ def test_poisson_matches_oracle(torch, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("Np,buffer", [(16, 0), (32, 8), (32, 24), (32, 32), (32, 40), (32, 48)])
+def test_poisson_every_fft_radix(torch, precision, Np, buffer):
+    """One box of M = Np + 2 buffer = 16, 48, 80, 96, 112, 128 nodes per side: the DST-I runs
+    an FFT of length 2M = 32 R with an R-point register DFT, R = 1, 3, 5, 6, 7, 8 (R = 2, 4
+    are covered above).  Boxes larger than the lattice hold periodic images, as the oracle's
+    box extraction does."""
+    from oracle.poisson import dirichlet_potential
+    sim = make_sim(torch, precision, Np=Np, L=4.0 * Np, tps=1, buffer=buffer)
+    M = Np + 2 * buffer
+    say("poisson M", M, precision)
+    sim.setup(torch.from_numpy(synthetic.white_noise(Np, 17)).cuda())
+    seeded_state(sim, torch, 8, spread=2.0)
+    sim.op_deposit(2.0, -2.0)
+    torch.cuda.synchronize()
+    rho = sim.view("rho").cpu().numpy().copy()
+    D1 = 2.0
+    sim.op_poisson(D1)
+    torch.cuda.synchronize()
+    phi = sim.view("phi").double().cpu().numpy()
+    bc = sim.view("bc0").cpu().numpy()
+    delta = rho[:(M - 1) ** 3].reshape((M - 1,) * 3) / 2.0 ** sim.layout.fixed_bits - 1.0
+    want = dirichlet_potential(delta, D1 * bc[:(M + 3) ** 3].reshape((M + 3,) * 3))
+    got = phi[:(M + 3) ** 3].reshape((M + 3,) * 3)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    say("  rel err", err)
+    assert err < (1e-10 if precision == "fp64" else 3e-5)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("M_buffer", [(2, 8), (1, 24)])
 def test_one_step_from_identical_state(torch, precision, M_buffer):
     from oracle.scola import box_deposit, box_gradient, box_interpolate
