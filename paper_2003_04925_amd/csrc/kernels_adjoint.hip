@@ -87,15 +87,15 @@ __device__ inline void block_adjoint_gather(const T* __restrict__ phi, const T* 
     for (int e = threadIdx.x; e < vol; e += blockDim.x) {
       int ex, ey, ez;
       window_coords(e, wz, wyz, inv_wz, inv_wyz, ex, ey, ez);
-      win[e] = phi[((int64_t)(lx + ex + 1) * Mp + (ly + ey + 1)) * Mp + (lz + ez + 1)];
+      win[e] = phi[idx3(lx + ex + 1, ly + ey + 1, lz + ez + 1, Mp, Mp)];
     }
   }
   __syncthreads();
   lu[0] = lu[1] = lu[2] = T(0);
   if (in) {
     auto at = [&](int x, int y, int z) -> T {
-      if (use_lds) return win[((x - lx) * wy + (y - ly)) * wz + (z - lz)];
-      return phi[((int64_t)(x + 1) * Mp + (y + 1)) * Mp + (z + 1)];
+      if (use_lds) return win[idx3(x - lx, y - ly, z - lz, wy, wz)];
+      return phi[idx3(x + 1, y + 1, z + 1, Mp, Mp)];
     };
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
@@ -113,7 +113,7 @@ __device__ inline void block_adjoint_gather(const T* __restrict__ phi, const T* 
       const T gz = T(0.5) * (at(nx, ny, nz + 1) - at(nx, ny, nz - 1));
       T s = lg[0] * gx + lg[1] * gy + lg[2] * gz;
       if (nx >= 1 && nx <= n && ny >= 1 && ny <= n && nz >= 1 && nz <= n)
-        s += lr[((int64_t)(nx - 1) * n + (ny - 1)) * n + (nz - 1)];
+        s += lr[idx3(nx - 1, ny - 1, nz - 1, n, n)];
 #pragma unroll
       for (int q = 0; q < 3; ++q) lu[q] += dw[q] * s;
     }
@@ -183,9 +183,9 @@ __device__ inline void block_adjoint_scatter(T* __restrict__ work, double* __res
   }
   auto to_global = [&](int x, int y, int z, T v) {
     if (x >= 1 && x <= n && y >= 1 && y <= n && z >= 1 && z <= n)
-      unsafeAtomicAdd(work + ((int64_t)(x - 1) * n + (y - 1)) * n + (z - 1), v);
+      unsafeAtomicAdd(work + idx3(x - 1, y - 1, z - 1, n, n), v);
     else
-      unsafeAtomicAdd(lam_bc0 + ((int64_t)(x + 1) * Mp + (y + 1)) * Mp + (z + 1), D1 * (double)v);
+      unsafeAtomicAdd(lam_bc0 + idx3(x + 1, y + 1, z + 1, Mp, Mp), D1 * (double)v);
   };
   if (in) {
     // a node is touched only through a non-zero coefficient, which keeps it in [-1, M+1]^3
@@ -195,7 +195,7 @@ __device__ inline void block_adjoint_scatter(T* __restrict__ work, double* __res
       if (use_lds) {
         const Q qv = (Q)__double2ll_rn((double)v * qscale);
         atomicAdd(reinterpret_cast<typename std::make_unsigned<Q>::type*>(win) +
-                      ((x - lx) * wy + (y - ly)) * wz + (z - lz),
+                      idx3(x - lx, y - ly, z - lz, wy, wz),
                   (typename std::make_unsigned<Q>::type)qv);
       } else {
         to_global(x, y, z, v);

@@ -121,9 +121,9 @@ __device__ inline long long deposit_block(unsigned long long* __restrict__ rho, 
         dropped += w[c];
       } else if (w[c] != 0) {
         if (use_lds)
-          atomicAdd(win + ((nx - lx) * wy + (ny - ly)) * wz + (nz - lz), (W)w[c]);
+          atomicAdd(win + idx3(nx - lx, ny - ly, nz - lz, wy, wz), (W)w[c]);
         else
-          atomicAdd(rho + ((int64_t)(nx - 1) * n + (ny - 1)) * n + (nz - 1),
+          atomicAdd(rho + idx3(nx - 1, ny - 1, nz - 1, n, n),
                     (unsigned long long)w[c]);
       }
     }
@@ -139,7 +139,7 @@ __device__ inline long long deposit_block(unsigned long long* __restrict__ rho, 
       if (v != 0ull) {
         int ex, ey, ez;
         window_coords(e, wz, wyz, inv_wz, inv_wyz, ex, ey, ez);
-        atomicAdd(rho + ((int64_t)(lx + ex - 1) * n + (ly + ey - 1)) * n + (lz + ez - 1), v);
+        atomicAdd(rho + idx3(lx + ex - 1, ly + ey - 1, lz + ez - 1, n, n), v);
       }
     }
   }
@@ -217,16 +217,16 @@ __device__ inline void block_force(const T* __restrict__ phi, int M, double ux, 
     for (int e = threadIdx.x; e < vol; e += blockDim.x) {
       int ex, ey, ez;
       window_coords(e, wz, wyz, inv_wz, inv_wyz, ex, ey, ez);
-      win[e] = phi[((int64_t)(lx + ex + 1) * Mp + (ly + ey + 1)) * Mp + (lz + ez + 1)];
+      win[e] = phi[idx3(lx + ex + 1, ly + ey + 1, lz + ez + 1, Mp, Mp)];
     }
     __syncthreads();
     if (in)
       gather_force<T>(M, j0, fr,
-                      [&](int x, int y, int z) { return ((x - lx) * wy + (y - ly)) * wz + (z - lz); },
+                      [&](int x, int y, int z) { return (int)idx3(x - lx, y - ly, z - lz, wy, wz); },
                       wyz, wz, [&](int i) { return win[i]; }, g);
   } else if (in) {
     gather_force<T>(M, j0, fr,
-                    [&](int x, int y, int z) { return ((x + 1) * Mp + (y + 1)) * Mp + (z + 1); },
+                    [&](int x, int y, int z) { return (int)idx3(x + 1, y + 1, z + 1, Mp, Mp); },
                     Mp * Mp, Mp, [&](int i) { return phi[i]; }, g);
   }
   __syncthreads();   // every thread is done with `bounds` and the window before reuse

@@ -46,20 +46,46 @@ __device__ __forceinline__ int wave_max(int v) {
 
 constexpr int kWindow = 4096;   // LDS window entries per block (potential or mass)
 
-// Block-wide bounding box of per-thread integer ranges [lo, hi] (3 axes); threads with
-// any == false do not count.  Must be called by all threads of the block.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// Lane-wise minimum of two pairs of unsigned 16-bit values packed in 32 bits.
+__device__ __forceinline__ unsigned pk_min_u16(unsigned a, unsigned b) {
+  return __builtin_bit_cast(unsigned, __builtin_elementwise_min(__builtin_bit_cast(u16x2, a),
+                                                                __builtin_bit_cast(u16x2, b)));
+}
+
+// Wave-wide minimum of a packed pair of unsigned 16-bit values (one DPP exchange per step
+// moves both halves); the result is uniform across the wave.
+__device__ __forceinline__ unsigned wave_min_u16x2(unsigned v) {
+  v = pk_min_u16(v, (unsigned)lane_xor<1>((int)v));
+  v = pk_min_u16(v, (unsigned)lane_xor<2>((int)v));
+  v = pk_min_u16(v, (unsigned)lane_xor<4>((int)v));
+  v = pk_min_u16(v, (unsigned)lane_xor<8>((int)v));
+  return pk_min_u16(pk_min_u16(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+                    pk_min_u16(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
+// Block-wide bounding box of per-thread integer ranges [lo, hi] (3 axes, values in
+// [-16383, 16383]); threads with any == false do not count.  The six extrema are reduced
+// as three packed pairs of 16-bit minima: lo + 2^14 and 2^14 - hi (0xffff marks "none").
+// Must be called by all threads of the block.
 __device__ inline void block_bounds(bool any, const int (&lo)[3], const int (&hi)[3],
                                     int* bounds) {
+  constexpr int kOff = 1 << 14;
   if (threadIdx.x < 6) bounds[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -0x7fffffff;
   __syncthreads();
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const int a = wave_min(any ? lo[c] : 0x7fffffff);
-    const int b = wave_max(any ? hi[c] : -0x7fffffff);
-    if ((threadIdx.x & 63) == 0) {
-      atomicMin(bounds + c, a);
-      atomicMax(bounds + 3 + c, b);
-    }
+  const unsigned none = 0xffffffffu;
+  const unsigned p0 = any ? (unsigned)(lo[0] + kOff) | ((unsigned)(lo[1] + kOff) << 16) : none;
+  const unsigned p1 = any ? (unsigned)(lo[2] + kOff) | ((unsigned)(kOff - hi[0]) << 16) : none;
+  const unsigned p2 = any ? (unsigned)(kOff - hi[1]) | ((unsigned)(kOff - hi[2]) << 16) : none;
+  const unsigned r0 = wave_min_u16x2(p0), r1 = wave_min_u16x2(p1), r2 = wave_min_u16x2(p2);
+  if ((threadIdx.x & 63) == 0 && (r0 & 0xffffu) != 0xffffu) {   // the wave has a range
+    atomicMin(bounds + 0, (int)(r0 & 0xffffu) - kOff);
+    atomicMin(bounds + 1, (int)(r0 >> 16) - kOff);
+    atomicMin(bounds + 2, (int)(r1 & 0xffffu) - kOff);
+    atomicMax(bounds + 3, kOff - (int)(r1 >> 16));
+    atomicMax(bounds + 4, kOff - (int)(r2 & 0xffffu));
+    atomicMax(bounds + 5, kOff - (int)(r2 >> 16));
   }
   __syncthreads();
 }
@@ -105,6 +131,12 @@ __device__ inline BlockWindow block_window(const int* bounds) {
   w.vol = w.wx * w.wy * w.wz;
   w.lds = !empty && w.vol <= kWindow;
   return w;
+}
+
+// Row-major index (a * nb + b) * nc + c of a 3-D array with fewer than 2^24 entries and
+// non-negative coordinates, with full-rate 24-bit multiplies.
+__device__ __forceinline__ unsigned idx3(int a, int b, int c, int nb, int nc) {
+  return __umul24(__umul24((unsigned)a, (unsigned)nb) + (unsigned)b, (unsigned)nc) + (unsigned)c;
 }
 
 // Row-major decomposition e -> (ex, ey, ez) of a window with rows wy x wz, using FP32
