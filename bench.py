@@ -195,7 +195,8 @@ def workload_rate(torch, S, synthetic, name, steps=3, warmup=2):
            "value": info["n_particles"] * wl.n_steps / (ms * 1e-3), "unit": "particle-steps/s",
            "ms_per_evolve": ms, "box_particles": info["n_particles"],
            "useful_particle_steps_per_s": wl.Np ** 3 * wl.n_steps / (ms * 1e-3),
-           "launch_schedule": {str(k): v for k, v in sched.items()}}
+           "launch_schedule": {str(k): v for k, v in sched.items()},
+           "concurrent_box_groups": sim.groups}
     del sim
     torch.cuda.empty_cache()
     return out
@@ -304,7 +305,8 @@ def main():
                                f"{sim.precision} {('per-tile' if sim.precision == 'fp64' else 'batched')}",
                    "box_particles": P, "n_tiles": info["n_tiles"],
                    "oversimulation_r": info["r"], "n_steps": wl.n_steps,
-                   "launch_schedule": {str(k): v for k, v in block_schedule.items()}},
+                   "launch_schedule": {str(k): v for k, v in block_schedule.items()},
+                   "concurrent_box_groups": sim.groups},
         "useful_particle_steps_per_s": wl.Np ** 3 * wl.n_steps / (ms * 1e-3),
         "end_to_end_s": e2e_s,
         "setup_s_first_call": setup_s,

@@ -257,6 +257,17 @@ class Simulation:
         _lib.check(_lib.lib().scola_plan_tune(self._plan, self._ws, self._stream(), reps))
         return self.schedule()
 
+    @property
+    def groups(self):
+        """Concurrent box groups of the batched evolution (1 or 2)."""
+        g = ctypes.c_int32()
+        _lib.check(_lib.lib().scola_plan_concurrency(self._plan, ctypes.byref(g)))
+        return g.value
+
+    @groups.setter
+    def groups(self, value):
+        _lib.check(_lib.lib().scola_plan_set_concurrency(self._plan, int(value)))
+
     def schedule(self):
         """{M: {"waves_per_simd", "xcd_remap_particles", "xcd_remap_mesh"}} per box size."""
         n = ctypes.c_int32()

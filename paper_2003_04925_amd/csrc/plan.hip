@@ -88,6 +88,12 @@ struct scola_plan {
   Maps part, p1, p2, p3;
   // launch schedule per size class (index as part.class_M), chosen by scola_plan_tune
   std::vector<scola_class_schedule> sched;
+  std::vector<std::vector<int>> class_tiles;   // tiles of each size class, in map order
+  // concurrent box groups of the batched evolution: 1, or 2 (the tiles of every class split
+  // in halves, advanced on the caller's stream and on aux_stream at the same time)
+  int groups = 1;
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   uint64_t sched_version = 0;         // bumped whenever the schedule changes
   // the batched evolution over all tiles, captured once per workspace and schedule (from
   // the second call on) and replayed as one hipGraph launch
@@ -429,11 +435,48 @@ BlockMap class_map(const Maps& m, size_t c) {
   return b;
 }
 
-// The three Poisson passes over every box of size class c (forward or adjoint solve).
+// Tiles [i0, i1) of size class c's tile list for group g of G (halves when G = 2).
+void group_range(const scola_plan* p, size_t c, int g, int G, size_t& i0, size_t& i1) {
+  const size_t n = p->class_tiles[c].size();
+  i0 = n * (size_t)g / (size_t)G;
+  i1 = n * (size_t)(g + 1) / (size_t)G;
+}
+
+// Blocks of group g of G of size class c (the class's tiles are contiguous in every map).
+BlockMap class_group_map(const scola_plan* p, const Maps& m, size_t c, int g, int G) {
+  if (G == 1) return class_map(m, c);
+  size_t i0, i1;
+  group_range(p, c, g, G, i0, i1);
+  BlockMap b = full_map(m);
+  b.base = 0;
+  b.count = 0;
+  if (i0 < i1) {
+    b.base = m.first[p->class_tiles[c][i0]];
+    for (size_t i = i0; i < i1; ++i) b.count += m.count[p->class_tiles[c][i]];
+  }
+  return b;
+}
+
+// The tiles of group g of G over all classes.
+std::vector<int> group_tiles(const scola_plan* p, int g, int G) {
+  std::vector<int> out;
+  for (size_t c = 0; c < p->class_tiles.size(); ++c) {
+    size_t i0, i1;
+    group_range(p, c, g, G, i0, i1);
+    for (size_t i = i0; i < i1; ++i) out.push_back(p->class_tiles[c][i]);
+  }
+  std::sort(out.begin(), out.end());
+  return out;
+}
+
+// The three Poisson passes over the boxes of size class c (group g of G), forward or
+// adjoint solve.
 template <typename T>
 void poisson_class(const scola_plan* p, const MeshArgs<T>& a, size_t c, bool adjoint,
-                   hipStream_t s) {
-  BlockMap b1 = class_map(p->p1, c), b2 = class_map(p->p2, c), b3 = class_map(p->p3, c);
+                   hipStream_t s, int g = 0, int G = 1) {
+  BlockMap b1 = class_group_map(p, p->p1, c, g, G), b2 = class_group_map(p, p->p2, c, g, G),
+           b3 = class_group_map(p, p->p3, c, g, G);
+  if (b1.count == 0) return;
   b1.xcd_remap = b2.xcd_remap = b3.xcd_remap = p->sched[c].xcd_remap_mesh;
   hip_check(launch_poisson<T>(a, p->p1.class_M[c], b1, b2, b3, s, adjoint), "poisson kernels");
 }
@@ -452,6 +495,7 @@ struct Runner {
   T* x_in = nullptr;
   T* x_out = nullptr;
   T* phi = nullptr;
+  int group = 0, ngroups = 1;   // batched: this group's share of every class
 
   std::vector<BlockMap> maps(const Maps& m) const {
     std::vector<BlockMap> out;
@@ -470,7 +514,8 @@ struct Runner {
     const Maps& pm = p->part;
     if (batched) {
       for (size_t c = 0; c < pm.class_M.size(); ++c) {
-        BlockMap b = class_map(pm, c);
+        BlockMap b = class_group_map(p, pm, c, group, ngroups);
+        if (b.count == 0) continue;
         b.xcd_remap = p->sched[c].xcd_remap_particles;
         hip_check(launch_particles<T>(a, mode, b, p->sched[c].waves_per_simd, s),
                   "particle kernel");
@@ -488,7 +533,8 @@ struct Runner {
     MeshArgs<T> a = mesh_args<T>(p, ws, D1_bc);
     if (phi) a.phi = phi;
     if (batched) {
-      for (size_t c = 0; c < p->p1.class_M.size(); ++c) poisson_class(p, a, c, false, s);
+      for (size_t c = 0; c < p->p1.class_M.size(); ++c)
+        poisson_class(p, a, c, false, s, group, ngroups);
     } else {
       for (int t : tiles) {
         const int r = sched_of(p, p->desc[t].M).xcd_remap_mesh;
@@ -562,25 +608,30 @@ StepScalars row_scalars(const scola_plan* p, int k) {
   return sc;
 }
 
-// (x_res, p_res) of the given tiles -> checkpoint slot (to_ckpt) or back.
+// (x_res, p_res) of the given tiles -> checkpoint slot (to_ckpt) or back; tiles whose
+// particle ranges are adjacent are copied together.
 template <typename T>
 void copy_checkpoint(scola_plan* p, const std::vector<int>& tiles, int slot, bool to_ckpt,
                      void* ws, hipStream_t s) {
   const size_t R = sizeof(T);
   char* ck = ws_ptr(ws, p->lay.ckpt) + (size_t)slot * 6 * p->P * R;
   char* st[2] = {ws_ptr(ws, p->lay.x_res), ws_ptr(ws, p->lay.p_res)};
-  const bool all = tiles.size() == p->desc.size();
+  std::vector<int> sorted = tiles;
+  std::sort(sorted.begin(), sorted.end());
+  std::vector<std::pair<int64_t, int64_t>> runs;   // [first particle, count)
+  for (int t : sorted) {
+    const int64_t M = p->desc[t].M, off = p->desc[t].p_off, cnt = M * M * M;
+    if (!runs.empty() && runs.back().first + runs.back().second == off)
+      runs.back().second += cnt;
+    else
+      runs.push_back({off, cnt});
+  }
   for (int a = 0; a < 2; ++a) {
     char* c = ck + (size_t)a * 3 * p->P * R;
-    if (all) {
-      hip_check(hipMemcpyAsync(to_ckpt ? c : st[a], to_ckpt ? st[a] : c, 3 * p->P * R,
-                               hipMemcpyDeviceToDevice, s), "checkpoint copy");
-      continue;
-    }
-    for (int t : tiles)
-      for (int comp = 0; comp < 3; ++comp) {
-        const size_t o = ((size_t)comp * p->P + p->desc[t].p_off) * R;
-        const size_t nb = (size_t)p->desc[t].M * p->desc[t].M * p->desc[t].M * R;
+    for (int comp = 0; comp < 3; ++comp)
+      for (const auto& r : runs) {
+        const size_t o = ((size_t)comp * p->P + (size_t)r.first) * R;
+        const size_t nb = (size_t)r.second * R;
         hip_check(hipMemcpyAsync(to_ckpt ? c + o : st[a] + o, to_ckpt ? st[a] + o : c + o, nb,
                                  hipMemcpyDeviceToDevice, s), "checkpoint copy");
       }
@@ -593,8 +644,10 @@ void do_evolve(scola_plan* p, const std::vector<int>& tiles, void* ws, hipStream
   hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped)),
                             (int64_t)p->desc.size(), s), "zero dropped");
   const int n = p->cfg.n_steps;
-  auto run = [&](const std::vector<int>& set, bool b) {
+  auto run = [&](const std::vector<int>& set, bool b, hipStream_t s, int g, int G) {
     Runner<T> r{p, ws, s, set, b};
+    r.group = g;
+    r.ngroups = G;
     StepScalars init{};
     init.D1 = p->D1[0];
     init.D2 = p->D2[0];
@@ -618,10 +671,25 @@ void do_evolve(scola_plan* p, const std::vector<int>& tiles, void* ws, hipStream
       r.particles(kFinalKick, sc);
     }
   };
-  if (batched) {
-    run(tiles, true);
+  const int G = batched && tiles.size() >= 2 ? p->groups : 1;
+  if (batched && G == 2) {
+    // two halves of every size class advance concurrently on two streams, so one half's
+    // Poisson passes overlap the other half's particle kernel
+    if (!p->aux_stream)
+      hip_check(hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking),
+                "hipStreamCreateWithFlags");
+    if (!p->ev_fork) hip_check(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming), "event");
+    if (!p->ev_join) hip_check(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming), "event");
+    hip_check(hipEventRecord(p->ev_fork, s), "hipEventRecord");
+    hip_check(hipStreamWaitEvent(p->aux_stream, p->ev_fork, 0), "hipStreamWaitEvent");
+    run(group_tiles(p, 0, 2), true, s, 0, 2);
+    run(group_tiles(p, 1, 2), true, p->aux_stream, 1, 2);
+    hip_check(hipEventRecord(p->ev_join, p->aux_stream), "hipEventRecord");
+    hip_check(hipStreamWaitEvent(s, p->ev_join, 0), "hipStreamWaitEvent");
+  } else if (batched) {
+    run(tiles, true, s, 0, 1);
   } else {
-    for (int t : tiles) run(std::vector<int>{t}, false);   // plain per-tile schedule
+    for (int t : tiles) run(std::vector<int>{t}, false, s, 0, 1);   // plain per-tile schedule
   }
 }
 
@@ -888,6 +956,21 @@ void do_tune(scola_plan* p, void* ws, hipStream_t s, int reps) {
     }
     cs.xcd_remap_mesh = choice;
   }
+  // concurrent box groups: whole evolutions (eager), one or two groups
+  if (p->desc.size() >= 2 && p->cfg.schedule == SCOLA_BATCHED) {
+    const std::vector<int> all = subset_list(p, nullptr, 0);
+    float best = 1e30f;
+    int choice = p->groups;
+    for (int G : {1, 2}) {
+      p->groups = G;
+      const float ms = timed([&] { do_evolve<T>(p, all, ws, s); });
+      if (ms < best) {
+        best = ms;
+        choice = G;
+      }
+    }
+    p->groups = choice;
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.rho)), p->G, s),
@@ -982,6 +1065,10 @@ scola_status scola_plan_create(const scola_config* cfg, const scola_cosmology* c
     build_maps(p->part, p->desc, [](const TileDesc& d) { return d.M * d.M * d.M / kBlock; });
     p->sched.clear();
     for (int M : p->part.class_M) p->sched.push_back(scola_class_schedule{M, 6, 1, 1});
+    p->class_tiles.assign(p->part.class_M.size(), {});
+    for (size_t c = 0; c < p->part.class_M.size(); ++c)
+      for (size_t t = 0; t < p->desc.size(); ++t)
+        if (p->desc[t].M == p->part.class_M[c]) p->class_tiles[c].push_back((int)t);
     build_maps(p->p1, p->desc, [](const TileDesc& d) { return d.M - 1; });
     build_maps(p->p2, p->desc, [](const TileDesc& d) {
       return (d.M - 1) * ((d.M - 1 + kPencilChunk - 1) / kPencilChunk);
@@ -1008,6 +1095,9 @@ scola_status scola_plan_destroy(scola_plan* p) {
   free_maps(p->p3);
   drop_graph(p);
   if (p->capture_stream) hipStreamDestroy(p->capture_stream);
+  if (p->aux_stream) hipStreamDestroy(p->aux_stream);
+  if (p->ev_fork) hipEventDestroy(p->ev_fork);
+  if (p->ev_join) hipEventDestroy(p->ev_join);
   if (p->d_tiles) hipFree(p->d_tiles);
   if (p->d_twiddles) hipFree(p->d_twiddles);
   if (p->d_eigen) hipFree(p->d_eigen);
@@ -1095,6 +1185,22 @@ scola_status scola_plan_set_graph(scola_plan* p, int32_t enable) {
     if (!p) fail(SCOLA_EINVAL, "null plan");
     p->use_graph = enable != 0;
     if (!p->use_graph) drop_graph(p);
+  });
+}
+
+scola_status scola_plan_concurrency(const scola_plan* p, int32_t* groups) {
+  return guarded([&] {
+    if (!p || !groups) fail(SCOLA_EINVAL, "null argument");
+    *groups = p->groups;
+  });
+}
+
+scola_status scola_plan_set_concurrency(scola_plan* p, int32_t groups) {
+  return guarded([&] {
+    if (!p) fail(SCOLA_EINVAL, "null plan");
+    if (groups != 1 && groups != 2) fail(SCOLA_EINVAL, "groups must be 1 or 2");
+    p->groups = groups;
+    ++p->sched_version;
   });
 }
 
