@@ -203,11 +203,12 @@ typedef struct {
 
 scola_status scola_plan_tune(scola_plan* plan, void* d_workspace, hipStream_t stream,
                              int32_t reps);
-/* Concurrent box groups of the batched evolution (1 or 2, default 1): with 2, the tiles of
- * every size class are split in halves that advance at the same time, one on `stream` and
- * one on a plan-owned stream joined back to `stream` before the call's work ends, so one
- * half's Poisson passes overlap the other half's particle kernel.  scola_plan_tune also
- * chooses this (it times whole evolutions both ways). */
+/* Concurrent box groups of the batched evolution (1, 2 or 4, default 1): with G > 1, the
+ * tiles of every size class are split in G equal shares that advance at the same time, one
+ * on `stream` and the others on plan-owned streams that fork from and join back to `stream`
+ * with events, so one share's Poisson passes overlap another share's particle kernel.
+ * Results are bitwise independent of G.  scola_plan_tune also chooses G (it times whole
+ * evolutions each way). */
 scola_status scola_plan_concurrency(const scola_plan* plan, int32_t* groups);
 scola_status scola_plan_set_concurrency(scola_plan* plan, int32_t groups);
 scola_status scola_plan_schedule(const scola_plan* plan, scola_class_schedule* out,

@@ -259,7 +259,7 @@ class Simulation:
 
     @property
     def groups(self):
-        """Concurrent box groups of the batched evolution (1 or 2)."""
+        """Concurrent box groups of the batched evolution (1, 2 or 4)."""
         g = ctypes.c_int32()
         _lib.check(_lib.lib().scola_plan_concurrency(self._plan, ctypes.byref(g)))
         return g.value

@@ -89,11 +89,11 @@ struct scola_plan {
   // launch schedule per size class (index as part.class_M), chosen by scola_plan_tune
   std::vector<scola_class_schedule> sched;
   std::vector<std::vector<int>> class_tiles;   // tiles of each size class, in map order
-  // concurrent box groups of the batched evolution: 1, or 2 (the tiles of every class split
-  // in halves, advanced on the caller's stream and on aux_stream at the same time)
+  // concurrent box groups of the batched evolution: 1, 2 or 4 (the tiles of every class
+  // split in equal shares, advanced on the caller's stream and on aux streams at once)
   int groups = 1;
-  hipStream_t aux_stream = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t aux_stream[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
   uint64_t sched_version = 0;         // bumped whenever the schedule changes
   // the batched evolution over all tiles, captured once per workspace and schedule (from
   // the second call on) and replayed as one hipGraph launch
@@ -671,21 +671,26 @@ void do_evolve(scola_plan* p, const std::vector<int>& tiles, void* ws, hipStream
       r.particles(kFinalKick, sc);
     }
   };
-  const int G = batched && tiles.size() >= 2 ? p->groups : 1;
-  if (batched && G == 2) {
-    // two halves of every size class advance concurrently on two streams, so one half's
-    // Poisson passes overlap the other half's particle kernel
-    if (!p->aux_stream)
-      hip_check(hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking),
-                "hipStreamCreateWithFlags");
+  const int G = batched ? std::min<int>(p->groups, (int)tiles.size()) : 1;
+  if (batched && G > 1) {
+    // G shares of every size class advance concurrently on G streams, so one share's
+    // Poisson passes overlap another share's particle kernel
     if (!p->ev_fork) hip_check(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming), "event");
-    if (!p->ev_join) hip_check(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming), "event");
     hip_check(hipEventRecord(p->ev_fork, s), "hipEventRecord");
-    hip_check(hipStreamWaitEvent(p->aux_stream, p->ev_fork, 0), "hipStreamWaitEvent");
-    run(group_tiles(p, 0, 2), true, s, 0, 2);
-    run(group_tiles(p, 1, 2), true, p->aux_stream, 1, 2);
-    hip_check(hipEventRecord(p->ev_join, p->aux_stream), "hipEventRecord");
-    hip_check(hipStreamWaitEvent(s, p->ev_join, 0), "hipStreamWaitEvent");
+    for (int g = 1; g < G; ++g) {
+      if (!p->aux_stream[g - 1])
+        hip_check(hipStreamCreateWithFlags(&p->aux_stream[g - 1], hipStreamNonBlocking),
+                  "hipStreamCreateWithFlags");
+      if (!p->ev_join[g - 1])
+        hip_check(hipEventCreateWithFlags(&p->ev_join[g - 1], hipEventDisableTiming), "event");
+      hip_check(hipStreamWaitEvent(p->aux_stream[g - 1], p->ev_fork, 0), "hipStreamWaitEvent");
+    }
+    for (int g = 0; g < G; ++g)
+      run(group_tiles(p, g, G), true, g ? p->aux_stream[g - 1] : s, g, G);
+    for (int g = 1; g < G; ++g) {
+      hip_check(hipEventRecord(p->ev_join[g - 1], p->aux_stream[g - 1]), "hipEventRecord");
+      hip_check(hipStreamWaitEvent(s, p->ev_join[g - 1], 0), "hipStreamWaitEvent");
+    }
   } else if (batched) {
     run(tiles, true, s, 0, 1);
   } else {
@@ -961,7 +966,7 @@ void do_tune(scola_plan* p, void* ws, hipStream_t s, int reps) {
     const std::vector<int> all = subset_list(p, nullptr, 0);
     float best = 1e30f;
     int choice = p->groups;
-    for (int G : {1, 2}) {
+    for (int G : {1, 2, 4}) {
       p->groups = G;
       const float ms = timed([&] { do_evolve<T>(p, all, ws, s); });
       if (ms < best) {
@@ -1095,9 +1100,11 @@ scola_status scola_plan_destroy(scola_plan* p) {
   free_maps(p->p3);
   drop_graph(p);
   if (p->capture_stream) hipStreamDestroy(p->capture_stream);
-  if (p->aux_stream) hipStreamDestroy(p->aux_stream);
+  for (int i = 0; i < 3; ++i) {
+    if (p->aux_stream[i]) hipStreamDestroy(p->aux_stream[i]);
+    if (p->ev_join[i]) hipEventDestroy(p->ev_join[i]);
+  }
   if (p->ev_fork) hipEventDestroy(p->ev_fork);
-  if (p->ev_join) hipEventDestroy(p->ev_join);
   if (p->d_tiles) hipFree(p->d_tiles);
   if (p->d_twiddles) hipFree(p->d_twiddles);
   if (p->d_eigen) hipFree(p->d_eigen);
@@ -1198,7 +1205,7 @@ scola_status scola_plan_concurrency(const scola_plan* p, int32_t* groups) {
 scola_status scola_plan_set_concurrency(scola_plan* p, int32_t groups) {
   return guarded([&] {
     if (!p) fail(SCOLA_EINVAL, "null plan");
-    if (groups != 1 && groups != 2) fail(SCOLA_EINVAL, "groups must be 1 or 2");
+    if (groups != 1 && groups != 2 && groups != 4) fail(SCOLA_EINVAL, "groups must be 1, 2 or 4");
     p->groups = groups;
     ++p->sched_version;
   });

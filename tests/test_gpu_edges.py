@@ -149,16 +149,16 @@ def test_backward_after_a_graph_replayed_forward(torch):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_two_concurrent_box_groups_match_one(torch, precision):
-    """Two halves of the boxes advanced on two streams (eager and graph-replayed, with
-    checkpoints) give bitwise the single-stream result; the reverse pass after them agrees
-    to round-off."""
+def test_concurrent_box_groups_match_one(torch, precision):
+    """Two or four shares of the boxes advanced on as many streams (eager and
+    graph-replayed, with checkpoints) give bitwise the single-stream result; the reverse pass
+    after them agrees to round-off."""
     import paper_2003_04925_amd as S
     Np, L = 32, 128.0
     w = torch.from_numpy(synthetic.white_noise(Np, 23)).cuda()
     t = torch.from_numpy(synthetic.loss_target(Np, 43)).cuda()
     outs, grads = [], []
-    for groups in (1, 2):
+    for groups in (1, 2, 4):
         sim = S.Simulation(L, Np, S.uniform_tiling(Np, 2, 8), 4, precision=precision,
                            checkpoint_every=2)
         sim.groups = groups
@@ -167,7 +167,8 @@ def test_two_concurrent_box_groups_match_one(torch, precision):
             r = sim.forward(w)
         outs.append((r["pos"].cpu().numpy(), r["density"].cpu().numpy()))
         grads.append(sim.backward(2.0 * (r["density"] - t.to(sim.real))).cpu().numpy())
-    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
-    err = np.abs(grads[0] - grads[1]).max() / np.abs(grads[0]).max()
-    say("groups", precision, "gradient rel diff", err)
-    assert err < (1e-12 if precision == "fp64" else 1e-5)
+    for (pos, dens), g in zip(outs[1:], grads[1:]):
+        assert np.array_equal(outs[0][0], pos) and np.array_equal(outs[0][1], dens)
+        err = np.abs(grads[0] - g).max() / np.abs(grads[0]).max()
+        say("groups", precision, "gradient rel diff", err)
+        assert err < (1e-12 if precision == "fp64" else 1e-5)
