@@ -160,8 +160,12 @@ class Simulation:
         spec = {
             "psi1": (t.float64, (3, P)), "psi2": (t.float64, (3, P)),
             "x_res": (self.real, (3, P)), "p_res": (self.real, (3, P)),
-            "rho": (t.int64, (G,)), "work": (self.real, (G,)), "phi": (self.real, (H,)),
-            "bc0": (t.float64, (H,)), "dropped": (t.int64, (len(self.tiles),)),
+            # mass mesh: int64 (FP64 plans) or unsigned 32-bit held in an int32 view (FP32)
+            "rho": (t.int64 if self.precision == "fp64" else t.int32, (G,)),
+            "work": (self.real, (G,)), "phi": (self.real, (H,)),
+            "bc0": (t.float64, (H,)),
+            # per tile, then the FP32 mass alarm (nodes that held >= 2^31 units)
+            "dropped": (t.int64, (len(self.tiles) + 1,)),
             "phi1": (t.float64, (N, N, N)), "phi2": (t.float64, (N, N, N)),
             "outgrid": (t.int64, (self.N_out,) * 3),
         }[name]
@@ -169,7 +173,8 @@ class Simulation:
         nbytes = 1
         for s in shape:
             nbytes *= s
-        nbytes *= {t.float64: 8, t.float32: 4, t.int64: 8}[dtype] if dtype != self.real else rb
+        nbytes *= {t.float64: 8, t.float32: 4, t.int64: 8, t.int32: 4}[dtype] \
+            if dtype != self.real else rb
         off = self._ws_off + getattr(lay, name)
         return self.workspace[off:off + nbytes].view(dtype).view(shape)
 

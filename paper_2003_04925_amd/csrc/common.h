@@ -12,22 +12,25 @@ constexpr int kFixedBits = 40;                       // output-grid CiC weights,
 constexpr double kFixedOne = 1099511627776.0;        // 2^40
 constexpr double kFixedInv = 1.0 / 1099511627776.0;
 
-// Fixed-point unit of one particle's mass in the box meshes: 2^40 for FP64 plans (weights
-// formed in FP64, block windows accumulated in 64-bit integers), 2^23 for FP32 plans
-// (weights formed in FP32 and converted with one 32-bit instruction; the quantum 2^-23 is
-// the FP32 weight rounding).  With 2^23 a 256-particle block window fits 32-bit integers
-// (at most 256 * 2^23 = 2^31 units on one node), which halves its LDS footprint.
+// Fixed-point unit of one particle's mass in the box meshes.  FP64 plans: 2^40 (weights
+// formed in FP64), block windows and the mesh in 64-bit integers.  FP32 plans: 2^21 (weights
+// formed in FP32; the quantum 2^-21 is close to FP32 weight rounding), block windows and the
+// mesh in 32-bit unsigned integers: a node can hold 2^32 / 2^21 = 2048 particles (density
+// contrast below 2047; the workloads here peak far lower, and the Poisson pass flags any
+// node above 1023), and a 256-particle block window at most 2^29 units.
 template <typename T>
 struct MeshFixed;
 template <>
 struct MeshFixed<double> {
   static constexpr int bits = 40;
   using window_t = unsigned long long;
+  using rho_t = unsigned long long;
 };
 template <>
 struct MeshFixed<float> {
-  static constexpr int bits = 23;
+  static constexpr int bits = 21;
   using window_t = unsigned int;
+  using rho_t = unsigned int;
 };
 constexpr int kMaxM = 128;                            // boxes of 16..128 particles per side
 constexpr int kBlock = 256;                           // threads of every mesh/particle block

@@ -46,7 +46,8 @@ struct BoxSetupArgs {
 template <typename T>
 struct MeshArgs {
   const TileDesc* tiles;
-  unsigned long long* rho;  // fixed-point mass (int64 two's complement)
+  typename MeshFixed<T>::rho_t* rho;   // fixed-point mass
+  unsigned long long* alarm;           // count of FP32-plan nodes holding >= 2^31 units
   T* work;
   T* phi;
   const double* bc0;
@@ -68,7 +69,7 @@ struct ParticleArgs {
   T* xout;                  // x_res after the drift: xres itself, or another buffer
   T* pres;
   const T* phi;
-  unsigned long long* rho;
+  typename MeshFixed<T>::rho_t* rho;
   unsigned long long* dropped;
   int64_t P;
   StepScalars sc;

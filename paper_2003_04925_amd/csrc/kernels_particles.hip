@@ -83,7 +83,7 @@ __device__ inline bool deposit_footprint(int M, double ux, double uy, double uz,
 // paths give identical results.  Returns the fixed-point mass this thread dropped.
 // Must be called by all threads of the block.
 template <typename T>
-__device__ inline long long deposit_block(unsigned long long* __restrict__ rho, int M,
+__device__ inline long long deposit_block(typename MeshFixed<T>::rho_t* __restrict__ rho, int M,
                                           bool active, double ux, double uy, double uz,
                                           typename MeshFixed<T>::window_t* win, int* bounds) {
   using W = typename MeshFixed<T>::window_t;
@@ -124,7 +124,7 @@ __device__ inline long long deposit_block(unsigned long long* __restrict__ rho, 
           atomicAdd(win + idx3(nx - lx, ny - ly, nz - lz, wy, wz), (W)w[c]);
         else
           atomicAdd(rho + idx3(nx - 1, ny - 1, nz - 1, n, n),
-                    (unsigned long long)w[c]);
+                    (typename MeshFixed<T>::rho_t)w[c]);
       }
     }
   } else if (active) {
@@ -135,8 +135,8 @@ __device__ inline long long deposit_block(unsigned long long* __restrict__ rho, 
     const int wyz = wy * wz;
     const float inv_wz = 1.0f / (float)wz, inv_wyz = 1.0f / (float)wyz;
     for (int e = threadIdx.x; e < vol; e += blockDim.x) {
-      const unsigned long long v = (unsigned long long)win[e];
-      if (v != 0ull) {
+      const typename MeshFixed<T>::rho_t v = win[e];
+      if (v != 0) {
         int ex, ey, ez;
         window_coords(e, wz, wyz, inv_wz, inv_wyz, ex, ey, ez);
         atomicAdd(rho + idx3(lx + ex - 1, ly + ey - 1, lz + ez - 1, n, n), v);

@@ -279,7 +279,9 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m
       for (int q = 0; q < kBatch; ++q) {
         const int e = e0 + q * kBlock + threadIdx.x;
         if (e >= n * n) continue;
-        a.rho[base + e] = 0ull;
+        a.rho[base + e] = 0;
+        if constexpr (std::is_same<T, float>::value)
+          if (r[q] >= (1ll << 31)) atomicAdd(a.alarm, 1ull);   // within a factor 2 of wrapping
         const int y = e / n, z = e - (e / n) * n;
         double d = (double)r[q] * (1.0 / (double)(1ll << MeshFixed<T>::bits)) - 1.0;
         // delta' = delta - Delta Phi_BCs: face-layer neighbours of the first interior layer

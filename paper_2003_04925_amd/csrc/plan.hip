@@ -306,6 +306,13 @@ void compute_step_table(const scola_config& c, const Background& bg, std::vector
   r[5] = dD2[n] / (n1 * n1) * inv_drift;
 }
 
+// Bytes of the fixed-point mass mesh, rounded to 8 so it is cleared in 64-bit words.
+size_t rho_bytes(const scola_plan* p) {
+  const size_t b = (size_t)p->G * (p->is64 ? sizeof(MeshFixed<double>::rho_t)
+                                           : sizeof(MeshFixed<float>::rho_t));
+  return (b + 7) / 8 * 8;
+}
+
 void build_layout(scola_plan* p) {
   const size_t R = p->is64 ? 8 : 4;
   const int64_t N = p->cfg.Np;
@@ -321,11 +328,11 @@ void build_layout(scola_plan* p) {
   l.psi2 = take(3 * (size_t)p->P * 8);
   l.x_res = take(3 * (size_t)p->P * R);
   l.p_res = take(3 * (size_t)p->P * R);
-  l.rho = take((size_t)p->G * 8);
+  l.rho = take(rho_bytes(p));
   l.work = take((size_t)p->G * R);
   l.phi = take((size_t)p->H * R);
   l.bc0 = take((size_t)p->H * 8);
-  l.dropped = take(p->desc.size() * 8);
+  l.dropped = take((p->desc.size() + 1) * 8);   // per tile, then the mass alarm
   l.phi1 = take((size_t)(N * N * N) * 8);
   l.phi2 = take((size_t)(N * N * N) * 8);
   l.cbuf = take((size_t)(N * N * N) * 16);
@@ -395,7 +402,8 @@ template <typename T>
 MeshArgs<T> mesh_args(scola_plan* p, void* ws, double D1_bc) {
   MeshArgs<T> a;
   a.tiles = p->d_tiles;
-  a.rho = reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.rho));
+  a.rho = reinterpret_cast<typename MeshFixed<T>::rho_t*>(ws_ptr(ws, p->lay.rho));
+  a.alarm = reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped)) + p->desc.size();
   a.work = reinterpret_cast<T*>(ws_ptr(ws, p->lay.work));
   a.phi = reinterpret_cast<T*>(ws_ptr(ws, p->lay.phi));
   a.bc0 = reinterpret_cast<const double*>(ws_ptr(ws, p->lay.bc0));
@@ -415,7 +423,7 @@ ParticleArgs<T> particle_args(scola_plan* p, void* ws, const StepScalars& sc) {
   a.xout = a.xres;
   a.pres = reinterpret_cast<T*>(ws_ptr(ws, p->lay.p_res));
   a.phi = reinterpret_cast<const T*>(ws_ptr(ws, p->lay.phi));
-  a.rho = reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.rho));
+  a.rho = reinterpret_cast<typename MeshFixed<T>::rho_t*>(ws_ptr(ws, p->lay.rho));
   a.dropped = reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped));
   a.P = p->P;
   a.sc = sc;
@@ -593,7 +601,7 @@ void do_setup(scola_plan* p, const double* w, void* ws, hipStream_t s) {
                                   reinterpret_cast<T*>(ws_ptr(ws, p->lay.p_res)), s),
             "set-up boxes");
   hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.rho)),
-                            p->G, s), "zero rho");
+                            (int64_t)(rho_bytes(p) / 8), s), "zero rho");
 }
 
 StepScalars row_scalars(const scola_plan* p, int k) {
@@ -642,7 +650,7 @@ template <typename T>
 void do_evolve(scola_plan* p, const std::vector<int>& tiles, void* ws, hipStream_t s) {
   const bool batched = p->cfg.schedule == SCOLA_BATCHED && tiles.size() == p->desc.size();
   hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped)),
-                            (int64_t)p->desc.size(), s), "zero dropped");
+                            (int64_t)p->desc.size() + 1, s), "zero dropped");
   const int n = p->cfg.n_steps;
   auto run = [&](const std::vector<int>& set, bool b, hipStream_t s, int g, int G) {
     Runner<T> r{p, ws, s, set, b};
@@ -978,10 +986,10 @@ void do_tune(scola_plan* p, void* ws, hipStream_t s, int reps) {
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.rho)), p->G, s),
-            "zero rho");
+  hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.rho)),
+                            (int64_t)(rho_bytes(p) / 8), s), "zero rho");
   hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped)),
-                            (int64_t)p->desc.size(), s), "zero dropped");
+                            (int64_t)p->desc.size() + 1, s), "zero dropped");
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
@@ -1287,9 +1295,9 @@ scola_status scola_op_deposit(scola_plan* p, double D1, double D2, void* ws, hip
     check_ws(p, ws);
     p->forward_ws = nullptr;
     hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.rho)),
-                              p->G, s), "zero rho");
+                              (int64_t)(rho_bytes(p) / 8), s), "zero rho");
     hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped)),
-                              (int64_t)p->desc.size(), s), "zero dropped");
+                              (int64_t)p->desc.size() + 1, s), "zero dropped");
     StepScalars sc{};
     sc.D1 = D1;
     sc.D2 = D2;

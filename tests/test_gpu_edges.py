@@ -48,7 +48,8 @@ def test_blocks_entirely_outside_their_box(torch, precision):
     bits = sim.layout.fixed_bits
     dropped = sim.view("dropped").cpu().numpy()
     assert int(dropped[0]) == n0 * (1 << bits)            # exact: all of box 0's mass
-    assert all(0 <= int(d) < n0 * (1 << bits) for d in dropped[1:])
+    assert all(0 <= int(d) < n0 * (1 << bits) for d in dropped[1:len(tiles)])
+    assert int(dropped[len(tiles)]) == 0                   # no mass alarm
     sim.op_poisson(D1)
     p_before = sim.view("p_res").clone()
     sim.op_step(beta, alpha, D1, D2, D1n, D2n, True)
@@ -172,3 +173,29 @@ def test_concurrent_box_groups_match_one(torch, precision):
         err = np.abs(grads[0] - g).max() / np.abs(grads[0]).max()
         say("groups", precision, "gradient rel diff", err)
         assert err < (1e-12 if precision == "fp64" else 1e-5)
+
+
+def test_fp32_mass_alarm_flags_crowded_nodes(torch):
+    """FP32 plans hold node masses in 32-bit integers (2^21 units per particle): the Poisson
+    pass counts nodes that reach 2^31 units (1024 particles), within a factor 2 of wrapping."""
+    import paper_2003_04925_amd as S
+    Np, L = 32, 128.0
+    tiles = S.uniform_tiling(Np, 2, 8)
+    sim = S.Simulation(L, Np, tiles, 4, precision="fp32")
+    sim.setup(torch.from_numpy(synthetic.white_noise(Np, 5)).cuda())
+    po, M, _, _ = sim.box_slices()[0]
+    order = torch.from_numpy(S.particle_order(M)).cuda()
+    i = torch.arange(M ** 3, device="cuda")
+    site = torch.stack([i // (M * M), (i // M) % M, i % M]).double()     # lattice order
+    x = sim.view("x_res")
+    for crowd, expect in ((1000, 0), (1500, 1)):
+        x.zero_()
+        # the first `crowd` sites of box 0 moved exactly onto node (10, 10, 10): u = q + x_res
+        # with D1 = D2 = 0, and 10 - (i + 1/2) is exact in FP32
+        x[:, po + order[:crowd]] = (10.0 - (site[:, :crowd] + 0.5)).float()
+        sim.op_deposit(0.0, 0.0)
+        sim.op_poisson(1.0)
+        torch.cuda.synchronize()
+        alarm = int(sim.view("dropped")[len(tiles)].cpu())
+        say("crowd", crowd, "alarm", alarm)
+        assert alarm == expect
