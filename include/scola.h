@@ -88,12 +88,17 @@ typedef struct scola_plan scola_plan;
 typedef struct {
   size_t psi1, psi2;       /* double [3][P]: Psi1 = grad phi1, Psi2 = grad phi2 (cells) */
   size_t x_res, p_res;     /* R [3][P]: COLA residual position and momentum (cells) */
-  size_t rho;              /* int64 [G]: fixed-point CiC mass, 2^fixed_bits per particle */
+  size_t rho;              /* fixed-point CiC mass, 2^fixed_bits units per particle: int64 [G]
+                              (FP64 plans) or uint32 [G] (FP32 plans; a node holds at most
+                              2048 particles, see `dropped`); size rounded up to 8 bytes */
   size_t work;             /* R [G]: sine-space scratch of the Poisson solve */
   size_t phi;              /* R [H]: potential on the padded node grid [-1, M+1]^3 */
   size_t bc0;              /* double [H]: Phi_BC^0 (LEP boundary potential at D1 = 1) */
-  size_t dropped;          /* int64 [n_tiles]: fixed-point mass dropped by the deposits since
-                              the last reset (scola_evolve and scola_op_deposit reset it) */
+  size_t dropped;          /* int64 [n_tiles + 1]: fixed-point mass dropped by the deposits
+                              since the last reset, per tile; then the mass alarm: the number
+                              of node visits by the Poisson pass that found >= 2^31 units on
+                              an FP32-plan node (1024 particles, within a factor 2 of the
+                              32-bit range).  scola_evolve and scola_op_deposit reset all. */
   size_t phi1, phi2;       /* double [N^3]: Lagrangian potentials (Sec. 3.1, A.2) */
   size_t cbuf;             /* double2 [N^3]: FFT scratch */
   size_t outgrid;          /* int64 [N_out^3]: fixed-point output density */
@@ -111,7 +116,7 @@ typedef struct {
   int64_t n_particles;     /* P */
   int64_t n_nodes;         /* G */
   int64_t n_padded;        /* H */
-  int32_t fixed_bits;      /* one particle's mass in rho: 2^40 (FP64 plans) or 2^23 (FP32) */
+  int32_t fixed_bits;      /* one particle's mass in rho: 2^40 (FP64 plans) or 2^21 (FP32) */
 } scola_layout;
 
 #define SCOLA_FIXED_BITS 40  /* output-density CiC weights are accumulated as round(w 2^40) */
