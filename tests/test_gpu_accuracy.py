@@ -1,0 +1,75 @@
+"""Per-result accuracy of the GPU plans against the FP64 oracle on the 64^3 workload
+(L = 200 Mpc/h, 2^3 boxes of 32^3 core + 8 buffer, 10 steps): final positions (max and
+99.9th percentile of the displacement error in cells, and cell indices), the output
+density, and its power spectrum (max over bins of |P_gpu / P_oracle - 1|, 100 log bins from
+2 pi / L to the Nyquist wavenumber).  The statements are printed; the bounds asserted are
+FP64: positions 1e-8 cell, P(k) 1e-9; FP32 batched: positions 1e-2 cell max and 1e-3 at
+the 99.9th percentile, P(k) 1e-4.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def oracle_c1():
+    from oracle.run import run_scola
+    from oracle.tiling import uniform_tiling
+    wl = synthetic.WORKLOADS["c1"]
+    w = synthetic.white_noise(wl.Np, 42)
+    ora = run_scola(w, wl.L, uniform_tiling(wl.Np, wl.tiles_per_side, wl.buffer),
+                    n_steps=wl.n_steps)
+    return wl, w, ora
+
+
+@pytest.mark.parametrize("precision,schedule", [("fp64", "per_tile"), ("fp32", "batched")])
+def test_accuracy_statement(torch, oracle_c1, precision, schedule):
+    import paper_2003_04925_amd as S
+    from oracle.run import power_spectrum
+    wl, w, ora = oracle_c1
+    sim = S.Simulation(wl.L, wl.Np, S.uniform_tiling(wl.Np, wl.tiles_per_side, wl.buffer),
+                       wl.n_steps, precision=precision, schedule=schedule)
+    out = sim.forward(torch.from_numpy(w).cuda())
+    torch.cuda.synchronize()
+    cell = wl.L / wl.Np
+    u_gpu = out["pos"].double().cpu().numpy() / cell
+    u_ora = ora["pos"] / cell
+    d = (u_gpu - u_ora + wl.Np / 2) % wl.Np - wl.Np / 2
+    dmax, d999 = float(np.abs(d).max()), float(np.quantile(np.abs(d), 0.999))
+    # cell indices: equal for every particle whose oracle position is more than 1e-4 cell
+    # from a cell face (where rounding may legitimately pick the other cell)
+    frac = u_ora - np.floor(u_ora)
+    far = (np.minimum(frac, 1 - frac) > 1e-4).all(axis=0)
+    same = (np.floor(u_gpu) == np.floor(u_ora)).all(axis=0)
+    idx_mismatch = int((far & ~same).sum())
+    dens_err = float(np.abs(out["density"].double().cpu().numpy() - ora["density"]).max())
+    kny = np.pi * wl.Np / wl.L
+    pg = power_spectrum(out["density"].double().cpu().numpy(), wl.L, k_max=kny)
+    po = power_spectrum(ora["density"], wl.L, k_max=kny)
+    ok = po["count"] > 0
+    pk_err = float(np.abs(pg["P"][ok] / po["P"][ok] - 1).max())
+    say(f"accuracy {precision} {schedule}: positions max {dmax:.3e} cell, p99.9 {d999:.3e} "
+        f"cell; cell-index mismatches (away from faces) {idx_mismatch} of {far.sum()}; "
+        f"density max {dens_err:.3e}; P(k) max |ratio-1| {pk_err:.3e}")
+    if precision == "fp64":
+        assert dmax < 1e-8 and pk_err < 1e-9 and idx_mismatch == 0
+    else:
+        assert dmax < 1e-2 and d999 < 1e-3 and pk_err < 1e-4
