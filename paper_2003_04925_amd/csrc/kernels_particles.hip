@@ -80,27 +80,32 @@ __device__ inline bool deposit_footprint(int M, double ux, double uy, double uz,
 // onto interior nodes [1, M-1]^3 of its box, privatised in an LDS window that covers the
 // block's Eulerian footprint, then one global atomic per touched node.  Blocks whose
 // footprint exceeds the window add straight into global memory.  Integer sums make both
-// paths give identical results.  Returns the fixed-point mass this thread dropped.
-// Must be called by all threads of the block.
+// paths give identical results.  Returns the fixed-point mass this thread dropped (the
+// eight weights sum to exactly one unit, so dropped = unit - deposited).  Must be called by
+// all threads of the block.
 template <typename T>
 __device__ inline long long deposit_block(typename MeshFixed<T>::rho_t* __restrict__ rho, int M,
                                           bool active, double ux, double uy, double uz,
                                           typename MeshFixed<T>::window_t* win, int* bounds) {
   using W = typename MeshFixed<T>::window_t;
+  using Rho = typename MeshFixed<T>::rho_t;
   const int n = M - 1;
   int j0[3] = {0, 0, 0};
   double f[3] = {0, 0, 0};
   const bool in = active && deposit_footprint(M, ux, uy, uz, j0, f);
   long long w[8];
   if (in) mesh_weights<T>(f[0], f[1], f[2], w);
-  // interior corner range of this particle (empty when lo > hi)
+  // interior corner range of this particle (empty when lo > hi), and which of the two
+  // corner planes along each axis are interior nodes
   int lo[3], hi[3];
-  bool any = in;
+  bool any = in, inner[3][2];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     lo[c] = max(j0[c], 1);
     hi[c] = min(j0[c] + 1, n);
     any = any && lo[c] <= hi[c];
+    inner[c][0] = j0[c] >= 1 && j0[c] <= n;
+    inner[c][1] = j0[c] + 1 >= 1 && j0[c] + 1 <= n;
   }
   block_bounds(any, lo, hi, bounds);
   const BlockWindow bw = block_window(bounds);
@@ -111,35 +116,38 @@ __device__ inline long long deposit_block(typename MeshFixed<T>::rho_t* __restri
     for (int e = threadIdx.x; e < vol; e += blockDim.x) win[e] = W(0);
     __syncthreads();
   }
-  long long dropped = 0;
+  long long kept = 0;
   if (in) {
+    const int wyz = wy * wz;
+    // window index of corner (0, 0, 0); corners add dx wyz + dy wz + dz (only interior
+    // corners are used, and those lie inside the window)
+    const int base = ((j0[0] - lx) * wy + (j0[1] - ly)) * wz + (j0[2] - lz);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      const int nx = j0[0] + ((c >> 2) & 1), ny = j0[1] + ((c >> 1) & 1), nz = j0[2] + (c & 1);
-      const bool inside = nx >= 1 && nx <= n && ny >= 1 && ny <= n && nz >= 1 && nz <= n;
-      if (!inside) {
-        dropped += w[c];
-      } else if (w[c] != 0) {
+      const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
+      if (inner[0][dx] && inner[1][dy] && inner[2][dz] && w[c] != 0) {
+        kept += w[c];
         if (use_lds)
-          atomicAdd(win + idx3(nx - lx, ny - ly, nz - lz, wy, wz), (W)w[c]);
+          atomicAdd(win + (base + dx * wyz + dy * wz + dz), (W)w[c]);
         else
-          atomicAdd(rho + idx3(nx - 1, ny - 1, nz - 1, n, n),
-                    (typename MeshFixed<T>::rho_t)w[c]);
+          atomicAdd(rho + idx3(j0[0] + dx - 1, j0[1] + dy - 1, j0[2] + dz - 1, n, n), (Rho)w[c]);
       }
     }
-  } else if (active) {
-    dropped = 1ll << MeshFixed<T>::bits;       // the whole particle lies outside
   }
+  const long long dropped = active ? (1ll << MeshFixed<T>::bits) - kept : 0;
   if (use_lds) {
     __syncthreads();
+    // flush: each thread takes a (y, z) column of the window and walks it along x
     const int wyz = wy * wz;
-    const float inv_wz = 1.0f / (float)wz, inv_wyz = 1.0f / (float)wyz;
-    for (int e = threadIdx.x; e < vol; e += blockDim.x) {
-      const typename MeshFixed<T>::rho_t v = win[e];
-      if (v != 0) {
-        int ex, ey, ez;
-        window_coords(e, wz, wyz, inv_wz, inv_wyz, ex, ey, ez);
-        atomicAdd(rho + idx3(lx + ex - 1, ly + ey - 1, lz + ez - 1, n, n), v);
+    const float inv_wz = 1.0f / (float)wz;
+    const unsigned gstep = (unsigned)(n * n);
+    for (int pos = threadIdx.x; pos < wyz; pos += blockDim.x) {
+      const int ey = (int)(((float)pos + 0.5f) * inv_wz), ez = pos - ey * wz;
+      unsigned widx = (unsigned)pos;
+      unsigned gidx = idx3(lx - 1, ly + ey - 1, lz + ez - 1, n, n);
+      for (int ex = 0; ex < wx; ++ex, widx += (unsigned)wyz, gidx += gstep) {
+        const Rho v = win[widx];
+        if (v != 0) atomicAdd(rho + gidx, v);
       }
     }
   }
@@ -212,12 +220,16 @@ __device__ inline void block_force(const T* __restrict__ phi, int M, double ux, 
   const int Mp = M + 3;
   if (bw.lds) {
     const int wyz = wy * wz;
-    const float inv_wz = 1.0f / (float)wz, inv_wyz = 1.0f / (float)wyz;
+    // staging: each thread takes a (y, z) column of the window and walks it along x
+    const float inv_wz = 1.0f / (float)wz;
+    const unsigned gstep = (unsigned)(Mp * Mp);
+    for (int pos = threadIdx.x; pos < wyz; pos += blockDim.x) {
+      const int ey = (int)(((float)pos + 0.5f) * inv_wz), ez = pos - ey * wz;
+      unsigned widx = (unsigned)pos;
+      unsigned gidx = idx3(lx + 1, ly + ey + 1, lz + ez + 1, Mp, Mp);
 #pragma unroll 4
-    for (int e = threadIdx.x; e < vol; e += blockDim.x) {
-      int ex, ey, ez;
-      window_coords(e, wz, wyz, inv_wz, inv_wyz, ex, ey, ez);
-      win[e] = phi[idx3(lx + ex + 1, ly + ey + 1, lz + ez + 1, Mp, Mp)];
+      for (int ex = 0; ex < bw.wx; ++ex, widx += (unsigned)wyz, gidx += gstep)
+        win[widx] = phi[gidx];
     }
     __syncthreads();
     if (in)
