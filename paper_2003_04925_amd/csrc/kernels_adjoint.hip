@@ -81,13 +81,17 @@ __device__ inline void block_adjoint_gather(const T* __restrict__ phi, const T* 
   const int vol = bw.vol;
   const bool use_lds = bw.lds;
   if (use_lds) {
+    // staging: each thread takes a (y, z) column of the window and walks it along x
     const int wyz = wy * wz;
-    const float inv_wz = 1.0f / (float)wz, inv_wyz = 1.0f / (float)wyz;
+    const float inv_wz = 1.0f / (float)wz;
+    const unsigned gstep = (unsigned)(Mp * Mp);
+    for (int pos = threadIdx.x; pos < wyz; pos += blockDim.x) {
+      const int ey = (int)(((float)pos + 0.5f) * inv_wz), ez = pos - ey * wz;
+      unsigned widx = (unsigned)pos;
+      unsigned gidx = idx3(lx + 1, ly + ey + 1, lz + ez + 1, Mp, Mp);
 #pragma unroll 4
-    for (int e = threadIdx.x; e < vol; e += blockDim.x) {
-      int ex, ey, ez;
-      window_coords(e, wz, wyz, inv_wz, inv_wyz, ex, ey, ez);
-      win[e] = phi[idx3(lx + ex + 1, ly + ey + 1, lz + ez + 1, Mp, Mp)];
+      for (int ex = 0; ex < bw.wx; ++ex, widx += (unsigned)wyz, gidx += gstep)
+        win[widx] = phi[gidx];
     }
   }
   __syncthreads();
@@ -227,14 +231,15 @@ __device__ inline void block_adjoint_scatter(T* __restrict__ work, double* __res
   }
   if (use_lds) {
     __syncthreads();
+    // flush: each thread takes a (y, z) column of the window and walks it along x
     const int wyz = wy * wz;
-    const float inv_wz = 1.0f / (float)wz, inv_wyz = 1.0f / (float)wyz;
-    for (int e = threadIdx.x; e < vol; e += blockDim.x) {
-      const Q qv = win[e];
-      if (qv != Q(0)) {
-        int ex_, ey_, ez_;
-        window_coords(e, wz, wyz, inv_wz, inv_wyz, ex_, ey_, ez_);
-        to_global(lx + ex_, ly + ey_, lz + ez_, (T)((double)qv * qstep));
+    const float inv_wz = 1.0f / (float)wz;
+    for (int pos = threadIdx.x; pos < wyz; pos += blockDim.x) {
+      const int ey = (int)(((float)pos + 0.5f) * inv_wz), ez = pos - ey * wz;
+      unsigned widx = (unsigned)pos;
+      for (int ex = 0; ex < bw.wx; ++ex, widx += (unsigned)wyz) {
+        const Q qv = win[widx];
+        if (qv != Q(0)) to_global(lx + ex, ly + ey, lz + ez, (T)((double)qv * qstep));
       }
     }
   }
