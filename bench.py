@@ -170,6 +170,7 @@ def adjoint_timing(torch, S, synthetic, name="c4", reps=3):
             bw.append(b.elapsed_time(c))
     f, g = sum(fw) / reps, sum(bw) / reps
     ws_gb = sim.layout.total / 1e9
+    groups = sim.groups
     del sim
     torch.cuda.empty_cache()
     return {"workload": f"{name}: {wl.Np}^3 particles, {wl.tiles_per_side ** 3} boxes of "
@@ -177,6 +178,7 @@ def adjoint_timing(torch, S, synthetic, name="c4", reps=3):
                         f"steps, density loss, checkpoint every 5",
             "forward_ms": f, "backward_ms": g, "backward_over_forward": g / f,
             "workspace_GB": ws_gb, "launch_schedule": {str(k): v for k, v in sched.items()},
+            "concurrent_box_groups": groups,
             "note": "backward = segment recomputation (one forward's worth of steps) + adjoint "
                     "steps + FP64 set-up adjoint"}
 

@@ -133,6 +133,7 @@ template <typename T>
 hipError_t launch_particles(const ParticleArgs<T>& a, int mode, const BlockMap& m, int occ,
                             hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
+hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t s);
 template <typename T>
 hipError_t launch_output(const OutputArgs<T>& a, const BlockMap& m, bool density,
                          T* density_out, hipStream_t s);

@@ -318,6 +318,12 @@ k_particles(ParticleArgs<T> a, BlockMap m) {
   if (threadIdx.x == 0 && block_drop != 0ull) atomicAdd(a.dropped + ti, block_drop);
 }
 
+__global__ void k_zero_u32(unsigned* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
 __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -398,6 +404,14 @@ __global__ void k_density_convert(const unsigned long long* __restrict__ grid, T
 }
 
 }  // namespace
+
+hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)(blocks < 65536 ? blocks : 65536)),
+                     dim3(kBlock), 0, s, p, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;

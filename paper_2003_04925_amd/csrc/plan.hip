@@ -646,6 +646,66 @@ void copy_checkpoint(scola_plan* p, const std::vector<int>& tiles, int slot, boo
   }
 }
 
+// Fork G - 1 plan-owned streams from s (after everything enqueued on s so far) and join
+// them back into s.
+void fork_streams(scola_plan* p, int G, hipStream_t s) {
+  if (!p->ev_fork) hip_check(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming), "event");
+  hip_check(hipEventRecord(p->ev_fork, s), "hipEventRecord");
+  for (int g = 1; g < G; ++g) {
+    if (!p->aux_stream[g - 1])
+      hip_check(hipStreamCreateWithFlags(&p->aux_stream[g - 1], hipStreamNonBlocking),
+                "hipStreamCreateWithFlags");
+    if (!p->ev_join[g - 1])
+      hip_check(hipEventCreateWithFlags(&p->ev_join[g - 1], hipEventDisableTiming), "event");
+    hip_check(hipStreamWaitEvent(p->aux_stream[g - 1], p->ev_fork, 0), "hipStreamWaitEvent");
+  }
+}
+
+void join_streams(scola_plan* p, int G, hipStream_t s) {
+  for (int g = 1; g < G; ++g) {
+    hip_check(hipEventRecord(p->ev_join[g - 1], p->aux_stream[g - 1]), "hipEventRecord");
+    hip_check(hipStreamWaitEvent(s, p->ev_join[g - 1], 0), "hipStreamWaitEvent");
+  }
+}
+
+// Runs of adjacent tiles: [first, count) in particle (or node) units.
+std::vector<std::pair<int64_t, int64_t>> tile_runs(const scola_plan* p, const std::vector<int>& tiles,
+                                                   bool nodes) {
+  std::vector<int> sorted = tiles;
+  std::sort(sorted.begin(), sorted.end());
+  std::vector<std::pair<int64_t, int64_t>> runs;
+  for (int t : sorted) {
+    const int64_t M = p->desc[t].M;
+    const int64_t off = nodes ? p->desc[t].g_off : p->desc[t].p_off;
+    const int64_t cnt = nodes ? (M - 1) * (M - 1) * (M - 1) : M * M * M;
+    if (!runs.empty() && runs.back().first + runs.back().second == off)
+      runs.back().second += cnt;
+    else
+      runs.push_back({off, cnt});
+  }
+  return runs;
+}
+
+// dst[3][P] <- src[3][P] for the particles of the given tiles.
+template <typename T>
+void copy_particle_ranges(const scola_plan* p, const std::vector<int>& tiles, T* dst,
+                          const T* src, hipStream_t s) {
+  for (const auto& r : tile_runs(p, tiles, false))
+    for (int comp = 0; comp < 3; ++comp) {
+      const size_t o = (size_t)comp * p->P + (size_t)r.first;
+      hip_check(hipMemcpyAsync(dst + o, src + o, (size_t)r.second * sizeof(T),
+                               hipMemcpyDeviceToDevice, s), "checkpoint restore");
+    }
+}
+
+// Clear the interior-node array entries [G] of the given tiles.
+template <typename T>
+void zero_node_ranges(const scola_plan* p, const std::vector<int>& tiles, T* arr, hipStream_t s) {
+  for (const auto& r : tile_runs(p, tiles, true))
+    hip_check(launch_zero_u32(reinterpret_cast<unsigned*>(arr + r.first),
+                              r.second * (int64_t)(sizeof(T) / 4), s), "zero");
+}
+
 template <typename T>
 void do_evolve(scola_plan* p, const std::vector<int>& tiles, void* ws, hipStream_t s) {
   const bool batched = p->cfg.schedule == SCOLA_BATCHED && tiles.size() == p->desc.size();
@@ -683,22 +743,10 @@ void do_evolve(scola_plan* p, const std::vector<int>& tiles, void* ws, hipStream
   if (batched && G > 1) {
     // G shares of every size class advance concurrently on G streams, so one share's
     // Poisson passes overlap another share's particle kernel
-    if (!p->ev_fork) hip_check(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming), "event");
-    hip_check(hipEventRecord(p->ev_fork, s), "hipEventRecord");
-    for (int g = 1; g < G; ++g) {
-      if (!p->aux_stream[g - 1])
-        hip_check(hipStreamCreateWithFlags(&p->aux_stream[g - 1], hipStreamNonBlocking),
-                  "hipStreamCreateWithFlags");
-      if (!p->ev_join[g - 1])
-        hip_check(hipEventCreateWithFlags(&p->ev_join[g - 1], hipEventDisableTiming), "event");
-      hip_check(hipStreamWaitEvent(p->aux_stream[g - 1], p->ev_fork, 0), "hipStreamWaitEvent");
-    }
+    fork_streams(p, G, s);
     for (int g = 0; g < G; ++g)
       run(group_tiles(p, g, G), true, g ? p->aux_stream[g - 1] : s, g, G);
-    for (int g = 1; g < G; ++g) {
-      hip_check(hipEventRecord(p->ev_join[g - 1], p->aux_stream[g - 1]), "hipEventRecord");
-      hip_check(hipStreamWaitEvent(s, p->ev_join[g - 1], 0), "hipStreamWaitEvent");
-    }
+    join_streams(p, G, s);
   } else if (batched) {
     run(tiles, true, s, 0, 1);
   } else {
@@ -793,60 +841,85 @@ void do_backward(scola_plan* p, const T* lam_dens, double* grad_w, void* ws, hip
   MeshArgs<T> m = mesh_args<T>(p, ws, 0.0);
   m.lam_rho = const_cast<T*>(a.lam_rho);
   m.lam_bc0 = a.lam_bc0;
-  auto adjoint_poisson = [&](double D1) {
-    m.D1_bc = D1;
-    for (size_t cl = 0; cl < p->p1.class_M.size(); ++cl) poisson_class(p, m, cl, true, s);
-  };
-  auto set_gather = [&](int g) {       // force of step g
-    const StepScalars sg = row_scalars(p, g);
-    a.xg = ring.xs(g);
-    a.phi = ring.ph(g);
-    a.beta_g = sg.beta;
-    a.D1g = sg.D1;
-    a.D2g = sg.D2;
-  };
-  for (int seg = nseg - 1; seg >= 0; --seg) {
-    const int k0 = seg * c, k1 = std::min(k0 + c, n);
-    // recompute the segment from its checkpoint: x_res and the potential of steps k0 .. k1-1
-    // into the ring (step k1's entries are there from the later segment)
-    char* ck = ws_ptr(ws, l.ckpt) + (size_t)seg * 6 * p->P * R;
-    hip_check(hipMemcpyAsync(ring.xs(k0), ck, 3 * p->P * R, hipMemcpyDeviceToDevice, s),
-              "checkpoint restore");
-    hip_check(hipMemcpyAsync(ws_ptr(ws, l.p_res), ck + 3 * p->P * R, 3 * p->P * R,
-                             hipMemcpyDeviceToDevice, s), "checkpoint restore");
-    Runner<T> r{p, ws, s, all, true};
-    r.x_in = ring.xs(k0);
-    r.phi = ring.ph(k0);
-    StepScalars d0{};
-    d0.D1 = p->D1[k0];
-    d0.D2 = p->D2[k0];
-    r.particles(kDepositOnly, d0);
-    r.poisson(p->D1[k0]);
-    for (int k = k0; k + 1 < k1; ++k) {
-      r.x_in = ring.xs(k);
-      r.x_out = ring.xs(k + 1);
-      r.phi = ring.ph(k);
-      r.particles(kStep, row_scalars(p, k));
-      r.phi = ring.ph(k + 1);
-      r.poisson(p->D1[k + 1]);
+  // The boxes are independent until the set-up adjoint: G groups of them (the tuned
+  // concurrency) run their whole reverse sweep on G streams.
+  auto reverse = [&](int grp, int G, hipStream_t st) {
+    AdjointArgs<T> ga = a;
+    MeshArgs<T> gm = m;
+    const std::vector<int> mine = G == 1 ? all : group_tiles(p, grp, G);
+    auto particle_maps = [&]() {
+      std::vector<BlockMap> out;
+      for (size_t cl = 0; cl < p->part.class_M.size(); ++cl) {
+        BlockMap b = class_group_map(p, p->part, cl, grp, G);
+        if (b.count > 0) out.push_back(b);
+      }
+      return out;
+    };
+    const std::vector<BlockMap> pmaps = particle_maps();
+    auto set_gather = [&](int gs) {       // force of step gs
+      const StepScalars sg = row_scalars(p, gs);
+      ga.xg = ring.xs(gs);
+      ga.phi = ring.ph(gs);
+      ga.beta_g = sg.beta;
+      ga.D1g = sg.D1;
+      ga.D2g = sg.D2;
+    };
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+      const int k0 = seg * c, k1 = std::min(k0 + c, n);
+      // recompute the segment from its checkpoint: x_res and the potential of steps
+      // k0 .. k1-1 into the ring (step k1's entries are there from the later segment)
+      const T* ck = reinterpret_cast<const T*>(ws_ptr(ws, l.ckpt) + (size_t)seg * 6 * p->P * R);
+      copy_particle_ranges<T>(p, mine, ring.xs(k0), ck, st);
+      copy_particle_ranges<T>(p, mine, reinterpret_cast<T*>(ws_ptr(ws, l.p_res)), ck + 3 * p->P,
+                              st);
+      Runner<T> r{p, ws, st, mine, true};
+      r.group = grp;
+      r.ngroups = G;
+      r.x_in = ring.xs(k0);
+      r.phi = ring.ph(k0);
+      StepScalars d0{};
+      d0.D1 = p->D1[k0];
+      d0.D2 = p->D2[k0];
+      r.particles(kDepositOnly, d0);
+      r.poisson(p->D1[k0]);
+      for (int k = k0; k + 1 < k1; ++k) {
+        r.x_in = ring.xs(k);
+        r.x_out = ring.xs(k + 1);
+        r.phi = ring.ph(k);
+        r.particles(kStep, row_scalars(p, k));
+        r.phi = ring.ph(k + 1);
+        r.poisson(p->D1[k + 1]);
+      }
+      zero_node_ranges<T>(p, mine, ga.work, st);   // left over from the recomputation
+      // reverse the segment: gather of step k+1 fused with the scatter of step k
+      for (int k = k1 - 1; k >= k0; --k) {
+        const bool gather = k + 1 < n;
+        if (gather) set_gather(k + 1);
+        const StepScalars sc = row_scalars(p, k);
+        ga.xs = ring.xs(k);
+        ga.alpha = sc.alpha;
+        ga.beta = sc.beta;
+        ga.D1 = sc.D1;
+        ga.D2 = sc.D2;
+        for (const BlockMap& b : pmaps)
+          hip_check(launch_adj_step<T>(ga, b, gather, true, st), "adjoint particles");
+        gm.D1_bc = sc.D1;
+        for (size_t cl = 0; cl < p->p1.class_M.size(); ++cl)
+          poisson_class(p, gm, cl, true, st, grp, G);
+      }
     }
-    zero_bytes(a.work, (size_t)p->G * R, s);   // left over from the recomputation
-    // reverse the segment: gather of step k+1 fused with the scatter of step k
-    for (int k = k1 - 1; k >= k0; --k) {
-      const bool gather = k + 1 < n;
-      if (gather) set_gather(k + 1);
-      const StepScalars sc = row_scalars(p, k);
-      a.xs = ring.xs(k);
-      a.alpha = sc.alpha;
-      a.beta = sc.beta;
-      a.D1 = sc.D1;
-      a.D2 = sc.D2;
-      hip_check(launch_adj_step<T>(a, full_map(p->part), gather, true, s), "adjoint particles");
-      adjoint_poisson(sc.D1);
-    }
+    set_gather(0);
+    for (const BlockMap& b : pmaps)
+      hip_check(launch_adj_step<T>(ga, b, true, false, st), "adjoint particles");
+  };
+  const int G = std::min<int>(p->groups, (int)p->desc.size());
+  if (G > 1) {
+    fork_streams(p, G, s);
+    for (int grp = 0; grp < G; ++grp) reverse(grp, G, grp ? p->aux_stream[grp - 1] : s);
+    join_streams(p, G, s);
+  } else {
+    reverse(0, 1, s);
   }
-  set_gather(0);
-  hip_check(launch_adj_step<T>(a, full_map(p->part), true, false, s), "adjoint particles");
   // FP64 set-up adjoint: Psi1, Psi2, Phi_BC^0 -> phi1, phi2 -> white noise
   double* g = reinterpret_cast<double*>(ws_ptr(ws, l.adj_grid));
   double* lam_psig = g;               // 6 N^3
