@@ -108,7 +108,7 @@ typedef struct {
                               for the segment being reversed and the first step after it */
   size_t seg_phi;          /* R [c+1][H]: ring of the potentials of the same steps */
   size_t lam_x, lam_p;     /* R [3][P]: adjoints of x_res and p_res */
-  size_t lam_psi1, lam_psi2; /* double [3][P]: accumulated adjoints of Psi1, Psi2 */
+  size_t lam_psi1, lam_psi2; /* R [3][P]: accumulated adjoints of Psi1, Psi2 */
   size_t lam_rho;          /* R [G]: adjoint of the deposited mass */
   size_t lam_bc0;          /* double [H]: accumulated adjoint of Phi_BC^0 */
   size_t adj_grid;         /* double [14][N^3]: set-up adjoint fields */

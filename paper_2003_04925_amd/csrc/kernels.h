@@ -98,8 +98,8 @@ struct AdjointArgs {
   const double* psi2;
   T* lam_x;                 // adjoint of x_res, [3][P]
   T* lam_p;                 // adjoint of p_res, [3][P]
-  double* lam_psi1;         // accumulated adjoint of Psi1, [3][P]
-  double* lam_psi2;         // accumulated adjoint of Psi2, [3][P]
+  T* lam_psi1;              // accumulated adjoint of Psi1, [3][P] (plan precision)
+  T* lam_psi2;              // accumulated adjoint of Psi2, [3][P]
   int64_t P, H;
   // gather half: force positions of step g (x_res at that time), its potential and the
   // adjoint of its deposited mass; lam_g = beta_g lam_p
@@ -146,8 +146,9 @@ hipError_t launch_adj_output(const AdjointArgs<T>& a, const BlockMap& m, const T
 template <typename T>
 hipError_t launch_adj_step(const AdjointArgs<T>& a, const BlockMap& part, bool gather,
                            bool scatter, hipStream_t s);
-hipError_t launch_adj_setup_scatter(const BoxSetupArgs& b, const double* lam_psi1,
-                                    const double* lam_psi2, double* lam_psig,
+template <typename T>
+hipError_t launch_adj_setup_scatter(const BoxSetupArgs& b, const T* lam_psi1,
+                                    const T* lam_psi2, double* lam_psig,
                                     const double* lam_bc0, double* lam_phi1, hipStream_t s);
 hipError_t launch_adj_phi_from_psi(const double* lam_psig, double* lam_phi1, double2* cbuf,
                                    int N, hipStream_t s);

@@ -315,8 +315,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(AdjointArgs<T> a, Bloc
   for (int c = 0; c < 3; ++c) {
     if (GATHER) a.lam_x[c * P + p] = lx[c];
     if (SCATTER) a.lam_p[c * P + p] = lp[c];
-    a.lam_psi1[c * P + p] += acc1[c];
-    a.lam_psi2[c * P + p] += acc2[c];
+    a.lam_psi1[c * P + p] += (T)acc1[c];
+    a.lam_psi2[c * P + p] += (T)acc2[c];
   }
 }
 
@@ -380,8 +380,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_output(AdjointArgs<T> a, BlockMa
   for (int c = 0; c < 3; ++c) {
     a.lam_x[c * P + p] = lu[c];
     a.lam_p[c * P + p] = T(0);
-    a.lam_psi1[c * P + p] = -a.D1g * (double)lu[c];
-    a.lam_psi2[c * P + p] = a.D2g * (double)lu[c];
+    a.lam_psi1[c * P + p] = (T)(-a.D1g * (double)lu[c]);
+    a.lam_psi2[c * P + p] = (T)(a.D2g * (double)lu[c]);
   }
 }
 
@@ -389,11 +389,12 @@ __global__ void __launch_bounds__(kBlock) k_adj_output(AdjointArgs<T> a, BlockMa
 
 // Box particles -> global lattice sites: lam_Psi_global += lam_Psi (boxes overlap in their
 // buffers, hence the atomics).
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_adj_psi_scatter(const TileDesc* __restrict__ tiles,
                                                             const int* __restrict__ blk_tile,
                                                             const int* __restrict__ blk_first,
-                                                            const double* __restrict__ lp1,
-                                                            const double* __restrict__ lp2,
+                                                            const T* __restrict__ lp1,
+                                                            const T* __restrict__ lp2,
                                                             double* __restrict__ g, int N,
                                                             int64_t P) {
   const TileDesc t = tiles[blk_tile[blockIdx.x]];
@@ -407,7 +408,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_psi_scatter(const TileDesc* __re
                      wrapn(t.origin[2] + k, N);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double v1 = lp1[c * P + p], v2 = lp2[c * P + p];
+    const double v1 = (double)lp1[c * P + p], v2 = (double)lp2[c * P + p];
     if (v1 != 0.0) unsafeAtomicAdd(g + c * N3 + gs, v1);
     if (v2 != 0.0) unsafeAtomicAdd(g + (3 + c) * N3 + gs, v2);
   }
@@ -544,11 +545,12 @@ hipError_t launch_adj_step(const AdjointArgs<T>& a, const BlockMap& part, bool g
   return hipGetLastError();
 }
 
-hipError_t launch_adj_setup_scatter(const BoxSetupArgs& b, const double* lam_psi1,
-                                    const double* lam_psi2, double* lam_psig,
+template <typename T>
+hipError_t launch_adj_setup_scatter(const BoxSetupArgs& b, const T* lam_psi1,
+                                    const T* lam_psi2, double* lam_psig,
                                     const double* lam_bc0, double* lam_phi1, hipStream_t s) {
   if (b.n_blocks > 0)
-    hipLaunchKernelGGL(k_adj_psi_scatter, dim3(b.n_blocks), dim3(kBlock), 0, s, b.tiles,
+    hipLaunchKernelGGL(k_adj_psi_scatter<T>, dim3(b.n_blocks), dim3(kBlock), 0, s, b.tiles,
                        b.blk_tile, b.blk_first, lam_psi1, lam_psi2, lam_psig, b.N, b.P);
   hipLaunchKernelGGL(k_adj_boundary, dim3(64, b.n_tiles), dim3(kBlock), 0, s, b.tiles, b.n_tiles,
                      lam_bc0, lam_phi1, b.N);
@@ -582,6 +584,12 @@ template hipError_t launch_adj_output<float>(const AdjointArgs<float>&, const Bl
                                              const float*, int, int, hipStream_t);
 template hipError_t launch_adj_output<double>(const AdjointArgs<double>&, const BlockMap&,
                                               const double*, int, int, hipStream_t);
+template hipError_t launch_adj_setup_scatter<float>(const BoxSetupArgs&, const float*,
+                                                    const float*, double*, const double*, double*,
+                                                    hipStream_t);
+template hipError_t launch_adj_setup_scatter<double>(const BoxSetupArgs&, const double*,
+                                                     const double*, double*, const double*,
+                                                     double*, hipStream_t);
 template hipError_t launch_adj_step<float>(const AdjointArgs<float>&, const BlockMap&, bool, bool,
                                            hipStream_t);
 template hipError_t launch_adj_step<double>(const AdjointArgs<double>&, const BlockMap&, bool,

@@ -345,8 +345,8 @@ void build_layout(scola_plan* p) {
     l.seg_phi = take((size_t)(c + 1) * (size_t)p->H * R);
     l.lam_x = take(3 * (size_t)p->P * R);
     l.lam_p = take(3 * (size_t)p->P * R);
-    l.lam_psi1 = take(3 * (size_t)p->P * 8);
-    l.lam_psi2 = take(3 * (size_t)p->P * 8);
+    l.lam_psi1 = take(3 * (size_t)p->P * R);
+    l.lam_psi2 = take(3 * (size_t)p->P * R);
     l.lam_rho = take((size_t)p->G * R);
     l.lam_bc0 = take((size_t)p->H * 8);
     l.adj_grid = take(14 * (size_t)(N * N * N) * 8);
@@ -821,8 +821,8 @@ void do_backward(scola_plan* p, const T* lam_dens, double* grad_w, void* ws, hip
   a.psi2 = reinterpret_cast<const double*>(ws_ptr(ws, l.psi2));
   a.lam_x = reinterpret_cast<T*>(ws_ptr(ws, l.lam_x));
   a.lam_p = reinterpret_cast<T*>(ws_ptr(ws, l.lam_p));
-  a.lam_psi1 = reinterpret_cast<double*>(ws_ptr(ws, l.lam_psi1));
-  a.lam_psi2 = reinterpret_cast<double*>(ws_ptr(ws, l.lam_psi2));
+  a.lam_psi1 = reinterpret_cast<T*>(ws_ptr(ws, l.lam_psi1));
+  a.lam_psi2 = reinterpret_cast<T*>(ws_ptr(ws, l.lam_psi2));
   a.lam_rho = reinterpret_cast<const T*>(ws_ptr(ws, l.lam_rho));
   a.work = reinterpret_cast<T*>(ws_ptr(ws, l.work));
   a.lam_bc0 = reinterpret_cast<double*>(ws_ptr(ws, l.lam_bc0));
@@ -929,7 +929,7 @@ void do_backward(scola_plan* p, const T* lam_dens, double* grad_w, void* ws, hip
   double2* cbuf = reinterpret_cast<double2*>(ws_ptr(ws, l.cbuf));
   zero_bytes(g, 7 * (size_t)N3 * 8, s);
   BoxSetupArgs b = box_setup_args(p, ws);
-  hip_check(launch_adj_setup_scatter(b, a.lam_psi1, a.lam_psi2, lam_psig, a.lam_bc0, lam_phi1, s),
+  hip_check(launch_adj_setup_scatter<T>(b, a.lam_psi1, a.lam_psi2, lam_psig, a.lam_bc0, lam_phi1, s),
             "adjoint set-up scatter");
   hip_check(launch_adj_phi_from_psi(lam_psig, lam_phi1, cbuf, N, s), "adjoint D^T");
   hip_check(fft3d_forward(cbuf, N, s), "fft");
