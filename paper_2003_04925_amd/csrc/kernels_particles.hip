@@ -76,15 +76,53 @@ __device__ inline bool deposit_footprint(int M, double ux, double uy, double uz,
 }
 
 
+// LDS windows of a block.  The fast form has a fixed geometry of kFw^3 nodes with
+// compile-time pitches (x: kFw^2, y: kFw, z: 1): every stencil read and every deposit of a
+// particle is one base address plus an immediate offset, and thread t owns the window
+// column (y, z) = (t / kFw, t % kFw) when staging, clearing and flushing.  A block whose
+// extent exceeds kFw nodes along some axis takes a window sized to its extent (runtime
+// pitches, at most kWindow entries), and beyond that works on global memory.  All forms
+// perform the same arithmetic, so they give identical results.
+constexpr int kFw = 16, kFwY = kFw, kFwX = kFw * kFw;
+
+// base + a byte offset below 2^32: a wave-uniform base and a 32-bit per-lane offset map to
+// the scalar-base form of the global memory instructions
+template <typename P>
+__device__ __forceinline__ P* byte_offset(P* base, unsigned bytes) {
+  using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+  return reinterpret_cast<P*>(reinterpret_cast<C*>(base) + bytes);
+}
+static_assert(kFw * kFw * kFw == kWindow, "fixed window = LDS window");
+static_assert(kFw * kFw == kBlock, "one window column per thread");
+
+// Block-wide extent of the cells j0 of the particles with in == true: lo (minima) and hi
+// (maxima) per axis, as wave-uniform scalars; any is false when no particle of the block is
+// in.  Must be called by all threads of the block.
+struct CellRange {
+  int lo[3], hi[3];
+  bool any;
+};
+
+__device__ __forceinline__ CellRange block_cells(bool in, const int (&j0)[3], int* bounds) {
+  block_bounds(in, j0, j0, bounds);
+  CellRange r;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r.lo[a] = __builtin_amdgcn_readfirstlane(bounds[a]);
+    r.hi[a] = __builtin_amdgcn_readfirstlane(bounds[3 + a]);
+  }
+  r.any = r.lo[0] <= r.hi[0] && r.lo[1] <= r.hi[1] && r.lo[2] <= r.hi[2];
+  return r;
+}
+
 // B^sCOLA for the 256 particles of one block (one Lagrangian brick): CiC of every particle
 // onto interior nodes [1, M-1]^3 of its box, privatised in an LDS window that covers the
-// block's Eulerian footprint, then one global atomic per touched node.  Blocks whose
-// footprint exceeds the window add straight into global memory.  Integer sums make both
-// paths give identical results.  Returns the fixed-point mass this thread dropped (the
-// eight weights sum to exactly one unit, so dropped = unit - deposited).  Must be called by
-// all threads of the block.
+// block's Eulerian footprint, then one global atomic per touched interior node.  Integer
+// sums make every window form give identical results.  Returns the fixed-point mass this
+// thread dropped (the eight weights sum to exactly one unit, so dropped = unit - kept).
+// Must be called by all threads of the block.
 template <typename T>
-__device__ inline long long deposit_block(typename MeshFixed<T>::rho_t* __restrict__ rho, int M,
+__device__ __forceinline__ long long deposit_block(typename MeshFixed<T>::rho_t* __restrict__ rho, int M,
                                           bool active, double ux, double uy, double uz,
                                           typename MeshFixed<T>::window_t* win, int* bounds) {
   using W = typename MeshFixed<T>::window_t;
@@ -95,38 +133,70 @@ __device__ inline long long deposit_block(typename MeshFixed<T>::rho_t* __restri
   const bool in = active && deposit_footprint(M, ux, uy, uz, j0, f);
   long long w[8];
   if (in) mesh_weights<T>(f[0], f[1], f[2], w);
-  // interior corner range of this particle (empty when lo > hi), and which of the two
-  // corner planes along each axis are interior nodes
-  int lo[3], hi[3];
-  bool any = in, inner[3][2];
+  // which of the two corner planes along each axis are interior nodes
+  bool inner[3][2];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    lo[c] = max(j0[c], 1);
-    hi[c] = min(j0[c] + 1, n);
-    any = any && lo[c] <= hi[c];
     inner[c][0] = j0[c] >= 1 && j0[c] <= n;
-    inner[c][1] = j0[c] + 1 >= 1 && j0[c] + 1 <= n;
+    inner[c][1] = j0[c] >= 0 && j0[c] <= n - 1;
   }
-  block_bounds(any, lo, hi, bounds);
-  const BlockWindow bw = block_window(bounds);
-  const int lx = bw.lx, ly = bw.ly, lz = bw.lz, wx = bw.wx, wy = bw.wy, wz = bw.wz;
-  const int vol = bw.vol;
-  const bool use_lds = bw.lds;
+  long long kept = 0;
+  if (in) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if (inner[0][(c >> 2) & 1] && inner[1][(c >> 1) & 1] && inner[2][c & 1]) kept += w[c];
+  }
+  const long long dropped = active ? (1ll << MeshFixed<T>::bits) - kept : 0;
+  const CellRange cr = block_cells(in, j0, bounds);
+  if (!cr.any) return dropped;
+  // the corners of the block's particles span [min j0, max j0 + 1] per axis
+  const int ox = cr.lo[0], oy = cr.lo[1], oz = cr.lo[2];
+  const int ex = cr.hi[0] - ox + 2, ey = cr.hi[1] - oy + 2, ez = cr.hi[2] - oz + 2;
+  if (ex <= kFw && ey <= kFw && ez <= kFw) {
+    const int t = threadIdx.x, ty = t / kFw, tz = t % kFw;
+#pragma unroll
+    for (int xi = 0; xi < kFw; ++xi)
+      if (xi < ex) win[t + kFwX * xi] = W(0);
+    __syncthreads();
+    if (in) {
+      // all eight corners go to the window; only interior nodes are flushed
+      W* wp = win + (j0[0] - ox) * kFwX + (j0[1] - oy) * kFwY + (j0[2] - oz);
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        atomicAdd(wp + ((c >> 2) & 1) * kFwX + ((c >> 1) & 1) * kFwY + (c & 1), (W)w[c]);
+    }
+    __syncthreads();
+    const int ny = oy + ty, nz = oz + tz;
+    if (ty < ey && tz < ez && ny >= 1 && ny <= n && nz >= 1 && nz <= n) {
+      const int xa = max(1 - ox, 0), xb = min(n + 1 - ox, ex);   // interior x planes
+      const unsigned gcol = (unsigned)(((ny - 1) * n + (nz - 1)) * (int)sizeof(Rho));
+      Rho v[kFw];
+#pragma unroll
+      for (int xi = 0; xi < kFw; ++xi) v[xi] = (xi >= xa && xi < xb) ? win[t + kFwX * xi] : Rho(0);
+#pragma unroll
+      for (int xi = 0; xi < kFw; ++xi)
+        if (v[xi] != 0) atomicAdd(byte_offset(rho + (int64_t)(ox - 1 + xi) * (n * n), gcol), v[xi]);
+    }
+    return dropped;
+  }
+  // sized window over the interior nodes the block touches
+  const int lx = max(ox, 1), ly = max(oy, 1), lz = max(oz, 1);
+  const int hx = min(cr.hi[0] + 1, n), hy = min(cr.hi[1] + 1, n), hz = min(cr.hi[2] + 1, n);
+  if (lx > hx || ly > hy || lz > hz) return dropped;   // no interior corner at all
+  const int wx = hx - lx + 1, wy = hy - ly + 1, wz = hz - lz + 1;
+  const int wyz = wy * wz, vol = wx * wyz;
+  const bool use_lds = vol <= kWindow;
   if (use_lds) {
     for (int e = threadIdx.x; e < vol; e += blockDim.x) win[e] = W(0);
     __syncthreads();
   }
-  long long kept = 0;
   if (in) {
-    const int wyz = wy * wz;
-    // window index of corner (0, 0, 0); corners add dx wyz + dy wz + dz (only interior
-    // corners are used, and those lie inside the window)
+    // window index of corner (0, 0, 0); interior corners add dx wyz + dy wz + dz
     const int base = ((j0[0] - lx) * wy + (j0[1] - ly)) * wz + (j0[2] - lz);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
       if (inner[0][dx] && inner[1][dy] && inner[2][dz] && w[c] != 0) {
-        kept += w[c];
         if (use_lds)
           atomicAdd(win + (base + dx * wyz + dy * wz + dz), (W)w[c]);
         else
@@ -134,18 +204,16 @@ __device__ inline long long deposit_block(typename MeshFixed<T>::rho_t* __restri
       }
     }
   }
-  const long long dropped = active ? (1ll << MeshFixed<T>::bits) - kept : 0;
   if (use_lds) {
     __syncthreads();
     // flush: each thread takes a (y, z) column of the window and walks it along x
-    const int wyz = wy * wz;
     const float inv_wz = 1.0f / (float)wz;
     const unsigned gstep = (unsigned)(n * n);
     for (int pos = threadIdx.x; pos < wyz; pos += blockDim.x) {
-      const int ey = (int)(((float)pos + 0.5f) * inv_wz), ez = pos - ey * wz;
+      const int ey2 = (int)(((float)pos + 0.5f) * inv_wz), ez2 = pos - ey2 * wz;
       unsigned widx = (unsigned)pos;
-      unsigned gidx = idx3(lx - 1, ly + ey - 1, lz + ez - 1, n, n);
-      for (int ex = 0; ex < wx; ++ex, widx += (unsigned)wyz, gidx += gstep) {
+      unsigned gidx = idx3(lx - 1, ly + ey2 - 1, lz + ez2 - 1, n, n);
+      for (int x = 0; x < wx; ++x, widx += (unsigned)wyz, gidx += gstep) {
         const Rho v = win[widx];
         if (v != 0) atomicAdd(rho + gidx, v);
       }
@@ -154,47 +222,47 @@ __device__ inline long long deposit_block(typename MeshFixed<T>::rho_t* __restri
   return dropped;
 }
 
-// grad^sCOLA + B-bar^sCOLA: central-difference gradient of the padded potential on nodes
-// [0, M]^3, CiC-interpolated at u; corners outside [0, M]^3 contribute nothing.  `at(x, y,
-// z)` reads the potential at node (x, y, z) in [-1, M+1]^3.
-template <typename T, typename Idx, typename Ld>
-__device__ inline void gather_force(int M, const int (&j0)[3], const T (&fr)[3], Idx idx,
-                                    int sx, int sy, Ld ld, T (&g)[3]) {
-  // idx(x, y, z): storage index of node (x, y, z) in [-1, M+1]^3; neighbours along x, y, z
-  // are at +-sx, +-sy, +-1; ld(i) loads entry i.
+// grad^sCOLA + B-bar^sCOLA at one particle: the central-difference gradient of the padded
+// potential at the CiC corners j0 + {0, 1} that lie in [0, M] (others carry zero weight),
+// interpolated with the weights fr.  `at(kx, ky, kz)` returns the potential at node
+// j0 - 1 + k (k in 0..3 per axis; a finite stand-in where only zero weights use it).
+// Along each axis, corner j0 differences nodes j0 + 1 and j0 - 1, corner j0 + 1 nodes
+// j0 + 2 and j0: 32 distinct nodes for the three components.
+template <typename T, typename At>
+__device__ __forceinline__ void gather_force(int M, const int (&j0)[3], const T (&fr)[3], At at,
+                                    T (&g)[3]) {
   T w[3][2];
-  int nc[3][2];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-#pragma unroll
-    for (int d = 0; d < 2; ++d) {
-      const int n = j0[a] + d;
-      w[a][d] = (n < 0 || n > M) ? T(0) : (d ? fr[a] : T(1) - fr[a]);
-      // clamped corners have zero weight; clamping keeps every read inside [-1, M+1]
-      nc[a][d] = min(max(n, 0), M);
-    }
+    w[a][0] = j0[a] >= 0 ? T(1) - fr[a] : T(0);
+    w[a][1] = j0[a] + 1 <= M ? fr[a] : T(0);
   }
   T gx = 0, gy = 0, gz = 0;
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
-    const T wc = w[0][dx] * w[1][dy] * w[2][dz];
-    const int o = idx(nc[0][dx], nc[1][dy], nc[2][dz]);
-    gx += wc * (ld(o + sx) - ld(o - sx));
-    gy += wc * (ld(o + sy) - ld(o - sy));
-    gz += wc * (ld(o + 1) - ld(o - 1));
-  }
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      gx += w[1][p] * w[2][q] *
+            (w[0][0] * (at(2, 1 + p, 1 + q) - at(0, 1 + p, 1 + q)) +
+             w[0][1] * (at(3, 1 + p, 1 + q) - at(1, 1 + p, 1 + q)));
+      gy += w[0][p] * w[2][q] *
+            (w[1][0] * (at(1 + p, 2, 1 + q) - at(1 + p, 0, 1 + q)) +
+             w[1][1] * (at(1 + p, 3, 1 + q) - at(1 + p, 1, 1 + q)));
+      gz += w[0][p] * w[1][q] *
+            (w[2][0] * (at(1 + p, 1 + q, 2) - at(1 + p, 1 + q, 0)) +
+             w[2][1] * (at(1 + p, 1 + q, 3) - at(1 + p, 1 + q, 1)));
+    }
   g[0] = T(0.5) * gx;
   g[1] = T(0.5) * gy;
   g[2] = T(0.5) * gz;
 }
 
 // Force at u for the 256 particles of a block: the potential nodes the block's stencils
-// touch are staged once in LDS (coalesced rows along z) and gathered from there; a block
-// whose footprint exceeds the window gathers from global memory.  Must be called by all
-// threads of the block.
+// touch are staged once in LDS (each thread loads window columns along x) and gathered
+// from there; a block whose footprint exceeds the sized window gathers from global
+// memory.  Must be called by all threads of the block.
 template <typename T>
-__device__ inline void block_force(const T* __restrict__ phi, int M, double ux, double uy,
+__device__ __forceinline__ void block_force(const T* __restrict__ phi, int M, double ux, double uy,
                                    double uz, T* win, int* bounds, T (&g)[3]) {
   g[0] = g[1] = g[2] = T(0);
   const double hiu = (double)M + 1.0;
@@ -202,44 +270,77 @@ __device__ inline void block_force(const T* __restrict__ phi, int M, double ux, 
   const double u[3] = {ux, uy, uz};
   int j0[3] = {0, 0, 0};
   T fr[3] = {T(0), T(0), T(0)};
-  int lo[3], hi[3];
+  if (in) {
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    if (in) {
+    for (int a = 0; a < 3; ++a) {
       const double fl = floor(u[a]);
       j0[a] = (int)fl;
       fr[a] = (T)(u[a] - fl);
     }
-    lo[a] = max(j0[a] - 1, -1);
-    hi[a] = min(j0[a] + 2, M + 1);
   }
-  block_bounds(in, lo, hi, bounds);
-  const BlockWindow bw = block_window(bounds);
-  const int lx = bw.lx, ly = bw.ly, lz = bw.lz, wx = bw.wx, wy = bw.wy, wz = bw.wz;
-  const int vol = bw.vol;
-  const int Mp = M + 3;
-  if (bw.lds) {
-    const int wyz = wy * wz;
-    // staging: each thread takes a (y, z) column of the window and walks it along x
-    const float inv_wz = 1.0f / (float)wz;
-    const unsigned gstep = (unsigned)(Mp * Mp);
-    for (int pos = threadIdx.x; pos < wyz; pos += blockDim.x) {
-      const int ey = (int)(((float)pos + 0.5f) * inv_wz), ez = pos - ey * wz;
-      unsigned widx = (unsigned)pos;
-      unsigned gidx = idx3(lx + 1, ly + ey + 1, lz + ez + 1, Mp, Mp);
+  const int Mp = M + 3, Mp2 = Mp * Mp;
+  const CellRange cr = block_cells(in, j0, bounds);
+  if (cr.any) {
+    // the stencils of the block's particles span [min j0 - 1, max j0 + 2] per axis
+    const int ox = cr.lo[0] - 1, oy = cr.lo[1] - 1, oz = cr.lo[2] - 1;
+    const int ex = cr.hi[0] - ox + 3, ey = cr.hi[1] - oy + 3, ez = cr.hi[2] - oz + 3;
+    if (ex <= kFw && ey <= kFw && ez <= kFw) {
+      const int t = threadIdx.x, ty = t / kFw, tz = t % kFw;
+      const int ny = oy + ty, nz = oz + tz;
+      // window nodes outside the padded grid [-1, M+1] (one layer at most) are zero; only
+      // zero-weight corners read them
+      const bool col = ty < ey && tz < ez && ny >= -1 && ny <= M + 1 && nz >= -1 && nz <= M + 1;
+      const int xa = max(-1 - ox, 0), xb = min(M + 2 - ox, ex);
+      // all loads of the column are issued before the first LDS store
+      const unsigned gcol = col ? (unsigned)(((ny + 1) * Mp + (nz + 1)) * (int)sizeof(T)) : 0u;
+      T v[kFw];
+#pragma unroll
+      for (int xi = 0; xi < kFw; ++xi) v[xi] = T(0);
+      if (col) {
+#pragma unroll
+        for (int xi = 0; xi < kFw; ++xi)
+          if (xi >= xa && xi < xb) v[xi] = *byte_offset(phi + (int64_t)(ox + 1 + xi) * Mp2, gcol);
+      }
+#pragma unroll
+      for (int xi = 0; xi < kFw; ++xi)
+        if (xi < ex) win[t + kFwX * xi] = v[xi];
+      __syncthreads();
+      if (in) {
+        const T* wp = win + (j0[0] - 1 - ox) * kFwX + (j0[1] - 1 - oy) * kFwY + (j0[2] - 1 - oz);
+        gather_force<T>(M, j0, fr,
+                        [&](int kx, int ky, int kz) { return wp[kx * kFwX + ky * kFwY + kz]; }, g);
+      }
+    } else {
+      // sized window over the padded grid; stencil coordinates are clamped into
+      // [-1, M+1], which changes only reads that carry zero weight
+      const int lx = max(ox, -1), ly = max(oy, -1), lz = max(oz, -1);
+      const int wx = min(cr.hi[0] + 2, M + 1) - lx + 1, wy = min(cr.hi[1] + 2, M + 1) - ly + 1,
+                wz = min(cr.hi[2] + 2, M + 1) - lz + 1;
+      const int wyz = wy * wz;
+      auto cl = [&](int v) { return min(max(v, -1), M + 1); };
+      if (wx * wyz <= kWindow) {
+        const float inv_wz = 1.0f / (float)wz;
+        const unsigned gstep = (unsigned)Mp2;
+        for (int pos = threadIdx.x; pos < wyz; pos += blockDim.x) {
+          const int ey2 = (int)(((float)pos + 0.5f) * inv_wz), ez2 = pos - ey2 * wz;
+          unsigned widx = (unsigned)pos;
+          unsigned gidx = idx3(lx + 1, ly + ey2 + 1, lz + ez2 + 1, Mp, Mp);
 #pragma unroll 4
-      for (int ex = 0; ex < bw.wx; ++ex, widx += (unsigned)wyz, gidx += gstep)
-        win[widx] = phi[gidx];
+          for (int x = 0; x < wx; ++x, widx += (unsigned)wyz, gidx += gstep) win[widx] = phi[gidx];
+        }
+        __syncthreads();
+        if (in)
+          gather_force<T>(M, j0, fr, [&](int kx, int ky, int kz) {
+            return win[idx3(cl(j0[0] - 1 + kx) - lx, cl(j0[1] - 1 + ky) - ly,
+                            cl(j0[2] - 1 + kz) - lz, wy, wz)];
+          }, g);
+      } else if (in) {
+        gather_force<T>(M, j0, fr, [&](int kx, int ky, int kz) {
+          return phi[idx3(cl(j0[0] - 1 + kx) + 1, cl(j0[1] - 1 + ky) + 1,
+                          cl(j0[2] - 1 + kz) + 1, Mp, Mp)];
+        }, g);
+      }
     }
-    __syncthreads();
-    if (in)
-      gather_force<T>(M, j0, fr,
-                      [&](int x, int y, int z) { return (int)idx3(x - lx, y - ly, z - lz, wy, wz); },
-                      wyz, wz, [&](int i) { return win[i]; }, g);
-  } else if (in) {
-    gather_force<T>(M, j0, fr,
-                    [&](int x, int y, int z) { return (int)idx3(x + 1, y + 1, z + 1, Mp, Mp); },
-                    Mp * Mp, Mp, [&](int i) { return phi[i]; }, g);
   }
   __syncthreads();   // every thread is done with `bounds` and the window before reuse
 }
@@ -287,12 +388,20 @@ k_particles(ParticleArgs<T> a, BlockMap m) {
   if (MODE != kDepositOnly && MODE != kInit) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) pr[c] = a.pres[c * P + p];
+    // the LPT terms of the kick and of the next position are formed before the force, so
+    // Psi1 and Psi2 are not held across it
+    const double d2 = sc.D2 - sc.D1 * sc.D1;
+    T lpt[3];
+    double un[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lpt[c] = (T)(sc.D1 * s1[c] - d2 * s2[c]);
+      un[c] = q[c] - sc.D1n * s1[c] + sc.D2n * s2[c];
+    }
     T g[3];
     block_force<T>(a.phi + t.h_off, M, u[0], u[1], u[2], reinterpret_cast<T*>(win), bounds, g);
-    const double d2 = sc.D2 - sc.D1 * sc.D1;
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      pr[c] += (T)sc.beta * (g[c] - (T)(sc.D1 * s1[c] - d2 * s2[c]));
+    for (int c = 0; c < 3; ++c) pr[c] += (T)sc.beta * (g[c] - lpt[c]);
     if (MODE == kFinalKick) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) a.pres[c * P + p] = pr[c] + (T)(sc.c1 * s1[c] + sc.c2 * s2[c]);
@@ -306,7 +415,7 @@ k_particles(ParticleArgs<T> a, BlockMap m) {
     }
     if (MODE == kStepNoDeposit) return;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) u[c] = q[c] - sc.D1n * s1[c] + sc.D2n * s2[c] + (double)xr[c];
+    for (int c = 0; c < 3; ++c) u[c] = un[c] + (double)xr[c];
   }
   __shared__ unsigned long long block_drop;
   if (threadIdx.x == 0) block_drop = 0ull;
