@@ -160,86 +160,113 @@ __device__ __forceinline__ void halfwave_fft(cx<T> (&x)[K][R], const cx<T>* __re
 }
 
 // In-place DST-I (unnormalised, eq. DST_delta) of K pairs of lines (a_k, b_k), each n =
-// 16R - 1 values at stride `stride` in LDS; output j (1..n) of pair k is multiplied by
-// sa(k, j) / sb(k, j).  Pairs with valid[k] false are neither read nor written.
-template <int R, int K, typename T, typename SA, typename SB>
-__device__ __forceinline__ void dst_pairs(T* const (&la)[K], T* const (&lb)[K], const bool (&valid)[K],
-                                 const bool (&has_b)[K], int stride, const cx<T>* tw, int l,
-                                 SA sa, SB sb) {
+// 16R - 1 values at the compile-time stride S in LDS; output j (1..n) of pair k is
+// multiplied by sa(k, j) / sb(k, j).  Pairs with valid[k] false are neither read nor
+// written.  Lane l loads positions m = 32 n2 + l of the odd extension; the register n2
+// decides at compile time whether m lies in the lower half (a_m at index m - 1), the upper
+// half (-a_{2M-m} at index 2M - m - 1) or straddles m = M (odd R), so addresses are one
+// per-lane base plus immediate offsets.  The zero positions m = 0 and m = M read an
+// in-line entry (finite data) and are masked.
+template <int R, int K, int S, typename T, typename SA, typename SB>
+__device__ __forceinline__ void dst_pairs(T* const (&la)[K], T* const (&lb)[K],
+                                          const bool (&valid)[K], const bool (&has_b)[K],
+                                          const cx<T>* tw, int l, SA sa, SB sb) {
   constexpr int M = 16 * R;
   cx<T> x[K][R];
 #pragma unroll
   for (int k = 0; k < K; ++k)
 #pragma unroll
     for (int n2 = 0; n2 < R; ++n2) {
-      // odd extension: position m holds a_m (m < M), 0 (m = 0, M), -a_{2M-m} (m > M); the
-      // zero positions read an in-line entry (finite data) and are masked by the sign factor
-      const int m = 32 * n2 + l;
-      const bool lo = m < M;
-      const int idx = min(max(lo ? m - 1 : 2 * M - m - 1, 0), M - 2);
-      const T sg = (m == 0 || m == M) ? T(0) : (lo ? T(1) : T(-1));
+      const int m0 = 32 * n2;
+      int idx;
+      T sg;
+      if (m0 + 32 <= M) {
+        idx = m0 + l - 1;
+        sg = T(1);
+        if (m0 == 0) {
+          idx = max(idx, 0);
+          sg = l == 0 ? T(0) : T(1);
+        }
+      } else if (m0 >= M) {
+        idx = 2 * M - 1 - m0 - l;
+        sg = T(-1);
+        if (m0 == M) {
+          idx = min(idx, M - 2);
+          sg = l == 0 ? T(0) : T(-1);
+        }
+      } else {
+        const int m = m0 + l;
+        const bool lo = m < M;
+        idx = min(max(lo ? m - 1 : 2 * M - m - 1, 0), M - 2);
+        sg = (m == 0 || m == M) ? T(0) : (lo ? T(1) : T(-1));
+      }
       cx<T> v;
       v.x = T(0);
       v.y = T(0);
       if (valid[k]) {
-        v.x = sg * la[k][idx * stride];
-        if (has_b[k]) v.y = sg * lb[k][idx * stride];
+        v.x = sg * la[k][idx * S];
+        if (has_b[k]) v.y = sg * lb[k][idx * S];
       }
       x[k][n2] = v;
     }
   halfwave_fft<R, K, T>(x, tw, l);
+  // lane l holds Z at positions k1 + R bitrev5(l); the sine coefficients j = 1..M-1 sit on
+  // the even lanes (bitrev5(l) < 16)
   const int br = bitrev5(l);
+  if ((l & 1) == 0) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    if (!valid[k]) continue;
+    for (int k = 0; k < K; ++k) {
+      if (!valid[k]) continue;
 #pragma unroll
-    for (int k1 = 0; k1 < R; ++k1) {
-      const int j = k1 + R * br;
-      if (j >= 1 && j <= M - 1) {
-        la[k][(j - 1) * stride] = T(-0.5) * x[k][k1].y * sa(k, j);
-        if (has_b[k]) lb[k][(j - 1) * stride] = T(0.5) * x[k][k1].x * sb(k, j);
+      for (int k1 = 0; k1 < R; ++k1) {
+        const int j = k1 + R * br;
+        if (k1 == 0 && br == 0) continue;
+        la[k][(j - 1) * S] = T(-0.5) * x[k][k1].y * sa(k, j);
+        if (has_b[k]) lb[k][(j - 1) * S] = T(0.5) * x[k][k1].x * sb(k, j);
       }
     }
   }
 }
 
-// DST-I along z (rows) then y (columns) of an n x n plane in LDS (row pitch n): 8R line
-// pairs per direction, R per half wavefront, two at a time.
+// DST-I of all lines of an n x n plane in LDS along one direction: lines at distance STEP,
+// entries at stride S; 8R line pairs, R per half wavefront, two at a time while registers
+// allow (R <= 4).
+template <int R, int S, int STEP, typename T>
+__device__ __forceinline__ void plane_lines(T* plane, const cx<T>* tw, int hw, int l) {
+  constexpr int n = 16 * R - 1;
+  auto one = [](int, int) { return T(1); };
+  if constexpr (R <= 4) {
+#pragma unroll
+    for (int i = 0; i < R; i += 2) {
+      const int p0 = hw + 8 * i, p1 = hw + 8 * (i + 1);
+      T* const la[2] = {plane + 2 * p0 * STEP, plane + 2 * p1 * STEP};
+      T* const lb[2] = {plane + (2 * p0 + 1) * STEP, plane + (2 * p1 + 1) * STEP};
+      const bool valid[2] = {true, i + 1 < R};
+      const bool hb[2] = {2 * p0 + 1 < n, i + 1 < R && 2 * p1 + 1 < n};
+      dst_pairs<R, 2, S, T>(la, lb, valid, hb, tw, l, one, one);
+    }
+  } else {
+#pragma unroll 1
+    for (int i = 0; i < R; ++i) {
+      const int p0 = hw + 8 * i;
+      T* const la[1] = {plane + 2 * p0 * STEP};
+      T* const lb[1] = {plane + (2 * p0 + 1) * STEP};
+      const bool valid[1] = {true};
+      const bool hb[1] = {2 * p0 + 1 < n};
+      dst_pairs<R, 1, S, T>(la, lb, valid, hb, tw, l, one, one);
+    }
+  }
+}
+
+// DST-I along z (rows, stride 1) then y (columns, stride n) of an n x n plane in LDS.
 template <int R, typename T>
 __device__ __forceinline__ void plane_dst(T* plane, const cx<T>* tw) {
   constexpr int n = 16 * R - 1;
   const int hw = threadIdx.x >> 5, l = threadIdx.x & 31;
-  auto one = [](int, int) { return T(1); };
-  // two line pairs in flight per half wavefront while registers allow (R <= 4)
-  constexpr int K = R <= 4 ? 2 : 1;
-#pragma unroll 1
-  for (int dir = 0; dir < 2; ++dir) {
-    // dir 0: rows (z lines, stride 1); dir 1: columns (y lines, stride n)
-    const int stride = dir ? n : 1;
-    const int step = dir ? 1 : n;   // distance between consecutive lines
-    if constexpr (K == 2) {
-#pragma unroll
-      for (int i = 0; i < R; i += 2) {
-        const int p0 = hw + 8 * i, p1 = hw + 8 * (i + 1);
-        T* const la[2] = {plane + 2 * p0 * step, plane + 2 * p1 * step};
-        T* const lb[2] = {plane + (2 * p0 + 1) * step, plane + (2 * p1 + 1) * step};
-        const bool valid[2] = {true, i + 1 < R};
-        const bool hb[2] = {2 * p0 + 1 < n, i + 1 < R && 2 * p1 + 1 < n};
-        dst_pairs<R, 2, T>(la, lb, valid, hb, stride, tw, l, one, one);
-      }
-    } else {
-#pragma unroll 1
-      for (int i = 0; i < R; ++i) {
-        const int p0 = hw + 8 * i;
-        T* const la[1] = {plane + 2 * p0 * step};
-        T* const lb[1] = {plane + (2 * p0 + 1) * step};
-        const bool valid[1] = {true};
-        const bool hb[1] = {2 * p0 + 1 < n};
-        dst_pairs<R, 1, T>(la, lb, valid, hb, stride, tw, l, one, one);
-      }
-    }
-    __syncthreads();
-  }
+  plane_lines<R, 1, n, T>(plane, tw, hw, l);
+  __syncthreads();
+  plane_lines<R, n, 1, T>(plane, tw, hw, l);
+  __syncthreads();
 }
 
 template <typename T>
@@ -258,7 +285,7 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m
   constexpr int M = 16 * R, n = M - 1, Mp = M + 3;
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
-  T* plane = reinterpret_cast<T*>(smem + 2 * kMaxM * sizeof(cx<T>));
+  T* plane = reinterpret_cast<T*>(smem + 2 * kMaxM * sizeof(cx<T>)) + kMaxM;
   load_twiddles(tw, a, t);
   const int64_t base = t.g_off + (int64_t)x * n * n;
   const double* bc = a.bc0 + t.h_off;
@@ -267,33 +294,59 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m
 #pragma unroll 8
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) plane[e] = a.work[base + e];
   } else {
+    using Rho = typename MeshFixed<T>::rho_t;
     constexpr int kBatch = 8;   // independent loads in flight per thread
+    constexpr double kUnit = 1.0 / (double)(1ll << MeshFixed<T>::bits);
+    // the plane's first and last rows and columns, and the whole plane when it touches an
+    // x face, also receive the boundary source; they are converted in the second loop
+    const bool xface = x == 0 || x == n - 1;
     for (int e0 = 0; e0 < n * n; e0 += kBatch * kBlock) {
-      long long r[kBatch];
-  #pragma unroll
+      Rho r[kBatch];
+#pragma unroll
       for (int q = 0; q < kBatch; ++q) {
         const int e = e0 + q * kBlock + threadIdx.x;
-        r[q] = e < n * n ? (long long)a.rho[base + e] : 0;
+        r[q] = e < n * n ? a.rho[base + e] : Rho(0);
       }
-  #pragma unroll
+#pragma unroll
       for (int q = 0; q < kBatch; ++q) {
         const int e = e0 + q * kBlock + threadIdx.x;
         if (e >= n * n) continue;
-        a.rho[base + e] = 0;
-        if constexpr (std::is_same<T, float>::value)
-          if (r[q] >= (1ll << 31)) atomicAdd(a.alarm, 1ull);   // within a factor 2 of wrapping
         const int y = e / n, z = e - (e / n) * n;
-        double d = (double)r[q] * (1.0 / (double)(1ll << MeshFixed<T>::bits)) - 1.0;
-        // delta' = delta - Delta Phi_BCs: face-layer neighbours of the first interior layer
-        // (padded index = node index + 1; interior node index = array index + 1)
-        if (x == 0) d -= D1 * bc[((int64_t)1 * Mp + y + 2) * Mp + z + 2];
-        if (x == n - 1) d -= D1 * bc[((int64_t)(M + 1) * Mp + y + 2) * Mp + z + 2];
-        if (y == 0) d -= D1 * bc[((int64_t)(x + 2) * Mp + 1) * Mp + z + 2];
-        if (y == n - 1) d -= D1 * bc[((int64_t)(x + 2) * Mp + M + 1) * Mp + z + 2];
-        if (z == 0) d -= D1 * bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + 1];
-        if (z == n - 1) d -= D1 * bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + M + 1];
-        plane[e] = (T)d;
+        if (xface || y == 0 || y == n - 1 || z == 0 || z == n - 1) continue;
+        a.rho[base + e] = Rho(0);
+        if constexpr (std::is_same<T, float>::value)
+          if (r[q] >= (1u << 31)) atomicAdd(a.alarm, 1ull);   // within a factor 2 of wrapping
+        plane[e] = (T)((double)r[q] * kUnit - 1.0);
       }
+    }
+    // delta' = delta - Delta Phi_BCs (App. C.1): each face-layer neighbour of an interior
+    // node adds D1 Phi_BC^0 there (padded index = node index + 1; interior node index =
+    // array index + 1)
+    const int nb = xface ? n * n : 4 * (n - 1);
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+      int y, z;
+      if (xface) {
+        y = i / n;
+        z = i - y * n;
+      } else {
+        // perimeter of the plane: i < n - 1 first row, then last column, last row, first column
+        const int side = i / (n - 1), o = i - side * (n - 1);
+        y = side == 0 ? 0 : side == 1 ? o : side == 2 ? n - 1 : n - 1 - o;
+        z = side == 0 ? o : side == 1 ? n - 1 : side == 2 ? n - 1 - o : 0;
+      }
+      const int e = y * n + z;
+      const Rho rv = a.rho[base + e];
+      a.rho[base + e] = Rho(0);
+      if constexpr (std::is_same<T, float>::value)
+        if (rv >= (1u << 31)) atomicAdd(a.alarm, 1ull);
+      double d = (double)rv * kUnit - 1.0;
+      if (x == 0) d -= D1 * bc[((int64_t)1 * Mp + y + 2) * Mp + z + 2];
+      if (x == n - 1) d -= D1 * bc[((int64_t)(M + 1) * Mp + y + 2) * Mp + z + 2];
+      if (y == 0) d -= D1 * bc[((int64_t)(x + 2) * Mp + 1) * Mp + z + 2];
+      if (y == n - 1) d -= D1 * bc[((int64_t)(x + 2) * Mp + M + 1) * Mp + z + 2];
+      if (z == 0) d -= D1 * bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + 1];
+      if (z == n - 1) d -= D1 * bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + M + 1];
+      plane[e] = (T)d;
     }
   }
   __syncthreads();
@@ -302,9 +355,9 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m
 }
 
 template <int R, typename T>
-__device__ __forceinline__ void pencil_solve(T* tile, int pitch, int cw, int y, int z0, const T* ev,
-                                    const cx<T>* tw) {
-  constexpr int M = 16 * R;
+__device__ __forceinline__ void pencil_solve(T* tile, int cw, int y, int z0, const T* ev,
+                                             const cx<T>* tw) {
+  constexpr int M = 16 * R, pitch = kPencilChunk + 1;
   const int hw = threadIdx.x >> 5, l = threadIdx.x & 31;
   const T norm = T(8.0 / ((double)M * M * M));
   const T ly = ev[y];
@@ -323,10 +376,10 @@ __device__ __forceinline__ void pencil_solve(T* tile, int pitch, int cw, int y, 
   // forward DST along x, then Phi^{lmn} = delta^{lmn} 8/M^3 / (lambda_l + lambda_m + lambda_n)
   auto sa = [&](int k, int j) { return norm * recip(ev[j - 1] + ly + lza[k]); };
   auto sb = [&](int k, int j) { return norm * recip(ev[j - 1] + ly + lzb[k]); };
-  dst_pairs<R, 2, T>(la, lb, valid, hb, pitch, tw, l, sa, sb);
+  dst_pairs<R, 2, pitch, T>(la, lb, valid, hb, tw, l, sa, sb);
   // the same half wavefront reads back only the lines it wrote
   auto one = [](int, int) { return T(1); };
-  dst_pairs<R, 2, T>(la, lb, valid, hb, pitch, tw, l, one, one);
+  dst_pairs<R, 2, pitch, T>(la, lb, valid, hb, tw, l, one, one);
   __syncthreads();
 }
 
@@ -343,20 +396,26 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p2(MeshArgs<T> a, BlockMap m
   constexpr int pitch = kPencilChunk + 1;
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
-  T* tile = reinterpret_cast<T*>(smem + 2 * kMaxM * sizeof(cx<T>));
+  T* ev = reinterpret_cast<T*>(smem + 2 * kMaxM * sizeof(cx<T>));
+  T* tile = ev + kMaxM;
   load_twiddles(tw, a, t);
-  const int64_t base = t.g_off + (int64_t)y * n + z0;
-#pragma unroll 8
-  for (int e = threadIdx.x; e < n * cw; e += blockDim.x) {
-    const int x = e / cw, zc = e - (e / cw) * cw;
-    tile[x * pitch + zc] = a.work[base + (int64_t)x * n * n + zc];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) ev[i] = a.eigen[t.ev_off + i];
+  // thread -> (x row x0 + 8 i, z column zc): rows of 32 consecutive z, coalesced
+  static_assert(kPencilChunk == 32 && kBlock == 256, "eight rows of 32 columns per sweep");
+  const int zc = threadIdx.x & 31, x0 = threadIdx.x >> 5;
+  const bool zin = zc < cw;
+  T* col = a.work + t.g_off + (int64_t)y * n + z0 + zc;
+#pragma unroll
+  for (int i = 0; i < (n + 7) / 8; ++i) {
+    const int x = x0 + 8 * i;
+    if (zin && x < n) tile[x * pitch + zc] = col[(int64_t)x * n * n];
   }
   __syncthreads();
-  const T* ev = a.eigen + t.ev_off;
-  pencil_solve<R, T>(tile, pitch, cw, y, z0, ev, tw);
-  for (int e = threadIdx.x; e < n * cw; e += blockDim.x) {
-    const int x = e / cw, zc = e - (e / cw) * cw;
-    a.work[base + (int64_t)x * n * n + zc] = tile[x * pitch + zc];
+  pencil_solve<R, T>(tile, cw, y, z0, ev, tw);
+#pragma unroll
+  for (int i = 0; i < (n + 7) / 8; ++i) {
+    const int x = x0 + 8 * i;
+    if (zin && x < n) col[(int64_t)x * n * n] = tile[x * pitch + zc];
   }
 }
 
@@ -382,7 +441,7 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p3(MeshArgs<T> a, BlockMap m
   }
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
-  T* plane = reinterpret_cast<T*>(smem + 2 * kMaxM * sizeof(cx<T>));
+  T* plane = reinterpret_cast<T*>(smem + 2 * kMaxM * sizeof(cx<T>)) + kMaxM;
   load_twiddles(tw, a, t);
   const int x = local;
   const int64_t base = t.g_off + (int64_t)x * n * n;
@@ -430,7 +489,7 @@ inline unsigned padded_grid(const BlockMap& m) {
 template <typename T>
 size_t poisson_lds_bytes(int M) {
   const int n = M - 1;
-  const size_t tw = 2 * kMaxM * sizeof(cx<T>);
+  const size_t tw = 2 * kMaxM * sizeof(cx<T>) + kMaxM * sizeof(T);   // twiddles, eigenvalues
   const size_t plane = (size_t)n * n * sizeof(T);
   const size_t pencil = (size_t)n * (kPencilChunk + 1) * sizeof(T);
   return tw + (plane > pencil ? plane : pencil);
