@@ -257,6 +257,39 @@ __device__ __forceinline__ void gather_force(int M, const int (&j0)[3], const T 
   g[2] = T(0.5) * gz;
 }
 
+// gather_force with the four (p, q) lines of the stencil in a rolled loop: the same
+// arithmetic in the same order, for the rarely taken sized-window and global-memory forms,
+// which then hold few values in registers and do not set the kernel's register budget.
+template <typename T, typename At>
+__device__ __forceinline__ void gather_force_rolled(int M, const int (&j0)[3], const T (&fr)[3],
+                                                 At at, T (&g)[3]) {
+  T w[3][2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    w[a][0] = j0[a] >= 0 ? T(1) - fr[a] : T(0);
+    w[a][1] = j0[a] + 1 <= M ? fr[a] : T(0);
+  }
+  T gx = 0, gy = 0, gz = 0;
+#pragma unroll 1
+  for (int pq = 0; pq < 4; ++pq) {
+    const int p = pq >> 1, q = pq & 1;
+    const T wxp = p ? w[0][1] : w[0][0], wyp = p ? w[1][1] : w[1][0];
+    const T wyq = q ? w[1][1] : w[1][0], wzq = q ? w[2][1] : w[2][0];
+    gx += wyp * wzq *
+          (w[0][0] * (at(2, 1 + p, 1 + q) - at(0, 1 + p, 1 + q)) +
+           w[0][1] * (at(3, 1 + p, 1 + q) - at(1, 1 + p, 1 + q)));
+    gy += wxp * wzq *
+          (w[1][0] * (at(1 + p, 2, 1 + q) - at(1 + p, 0, 1 + q)) +
+           w[1][1] * (at(1 + p, 3, 1 + q) - at(1 + p, 1, 1 + q)));
+    gz += wxp * wyq *
+          (w[2][0] * (at(1 + p, 1 + q, 2) - at(1 + p, 1 + q, 0)) +
+           w[2][1] * (at(1 + p, 1 + q, 3) - at(1 + p, 1 + q, 1)));
+  }
+  g[0] = T(0.5) * gx;
+  g[1] = T(0.5) * gy;
+  g[2] = T(0.5) * gz;
+}
+
 // Force at u for the 256 particles of a block: the potential nodes the block's stencils
 // touch are staged once in LDS (each thread loads window columns along x) and gathered
 // from there; a block whose footprint exceeds the sized window gathers from global
@@ -330,12 +363,12 @@ __device__ __forceinline__ void block_force(const T* __restrict__ phi, int M, do
         }
         __syncthreads();
         if (in)
-          gather_force<T>(M, j0, fr, [&](int kx, int ky, int kz) {
+          gather_force_rolled<T>(M, j0, fr, [&](int kx, int ky, int kz) {
             return win[idx3(cl(j0[0] - 1 + kx) - lx, cl(j0[1] - 1 + ky) - ly,
                             cl(j0[2] - 1 + kz) - lz, wy, wz)];
           }, g);
       } else if (in) {
-        gather_force<T>(M, j0, fr, [&](int kx, int ky, int kz) {
+        gather_force_rolled<T>(M, j0, fr, [&](int kx, int ky, int kz) {
           return phi[idx3(cl(j0[0] - 1 + kx) + 1, cl(j0[1] - 1 + ky) + 1,
                           cl(j0[2] - 1 + kz) + 1, Mp, Mp)];
         }, g);
