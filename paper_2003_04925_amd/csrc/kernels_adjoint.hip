@@ -59,70 +59,128 @@ __device__ inline bool interp_cell(int M, const double (&u)[3], int (&j0)[3], T 
 // positions u of step g):
 //   lam_u = sum_c grad W(u - n_c) [lam_g . grad Phi(n_c) + lam_rho(n_c)],
 // the first term over the interpolation corners in [0, M]^3, the second over the interior
-// deposit corners [1, M-1]^3.  The potential nodes of the block's stencils are staged in
-// LDS (global fallback).  Must be called by all threads of the block.
+// deposit corners [1, M-1]^3.  The potential and lam_rho on the nodes of the block's
+// stencils are staged in LDS: in the fixed kFw^3 windows when the block's extent fits
+// (lam_rho zero off the interior, potential zero off the padded grid, where only
+// zero-weight terms read it), else in a window sized to the extent (potential only), else
+// read from global memory.  Every form sums the same terms in the same order.  Must be
+// called by all threads of the block.
 template <typename T>
-__device__ inline void block_adjoint_gather(const T* __restrict__ phi, const T* __restrict__ lr,
-                                            int M, const double (&u)[3], const T (&lg)[3],
-                                            T* win, int* bounds, T (&lu)[3]) {
+__device__ __forceinline__ void block_adjoint_gather(const T* __restrict__ phi,
+                                                     const T* __restrict__ lr, int M,
+                                                     const double (&u)[3], const T (&lg)[3],
+                                                     T* win, T* win2, int* bounds, T (&lu)[3]) {
   const int Mp = M + 3, n = M - 1;
   int j0[3];
   T f[3];
   const bool in = interp_cell<T>(M, u, j0, f);
-  int lo[3], hi[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    lo[c] = max(j0[c] - 1, -1);
-    hi[c] = min(j0[c] + 2, M + 1);
-  }
-  block_bounds(in, lo, hi, bounds);
-  const BlockWindow bw = block_window(bounds);
-  const int lx = bw.lx, ly = bw.ly, lz = bw.lz, wx = bw.wx, wy = bw.wy, wz = bw.wz;
-  const int vol = bw.vol;
-  const bool use_lds = bw.lds;
-  if (use_lds) {
-    // staging: each thread takes a (y, z) column of the window and walks it along x
-    const int wyz = wy * wz;
-    const float inv_wz = 1.0f / (float)wz;
-    const unsigned gstep = (unsigned)(Mp * Mp);
-    for (int pos = threadIdx.x; pos < wyz; pos += blockDim.x) {
-      const int ey = (int)(((float)pos + 0.5f) * inv_wz), ez = pos - ey * wz;
-      unsigned widx = (unsigned)pos;
-      unsigned gidx = idx3(lx + 1, ly + ey + 1, lz + ez + 1, Mp, Mp);
-#pragma unroll 4
-      for (int ex = 0; ex < bw.wx; ++ex, widx += (unsigned)wyz, gidx += gstep)
-        win[widx] = phi[gidx];
-    }
-  }
-  __syncthreads();
   lu[0] = lu[1] = lu[2] = T(0);
-  if (in) {
-    auto at = [&](int x, int y, int z) -> T {
-      if (use_lds) return win[idx3(x - lx, y - ly, z - lz, wy, wz)];
-      return phi[idx3(x + 1, y + 1, z + 1, Mp, Mp)];
-    };
+  // the corner term with node values at(kx, ky, kz) = potential at j0 - 1 + k and
+  // rho(dx, dy, dz) = lam_rho at corner j0 + d (zero off the interior)
+  auto corners = [&](auto at, auto rho) {
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int d[3] = {(c >> 2) & 1, (c >> 1) & 1, c & 1};
       const int nx = j0[0] + d[0], ny = j0[1] + d[1], nz = j0[2] + d[2];
-      if (nx < 0 || nx > M || ny < 0 || ny > M || nz < 0 || nz > M) continue;
+      const bool inr = nx >= 0 && nx <= M && ny >= 0 && ny <= M && nz >= 0 && nz <= M;
       T wa[3], dw[3];
 #pragma unroll
       for (int q = 0; q < 3; ++q) wa[q] = d[q] ? f[q] : T(1) - f[q];
       dw[0] = (d[0] ? T(1) : T(-1)) * wa[1] * wa[2];
       dw[1] = (d[1] ? T(1) : T(-1)) * wa[0] * wa[2];
       dw[2] = (d[2] ? T(1) : T(-1)) * wa[0] * wa[1];
-      const T gx = T(0.5) * (at(nx + 1, ny, nz) - at(nx - 1, ny, nz));
-      const T gy = T(0.5) * (at(nx, ny + 1, nz) - at(nx, ny - 1, nz));
-      const T gz = T(0.5) * (at(nx, ny, nz + 1) - at(nx, ny, nz - 1));
-      T s = lg[0] * gx + lg[1] * gy + lg[2] * gz;
-      if (nx >= 1 && nx <= n && ny >= 1 && ny <= n && nz >= 1 && nz <= n)
-        s += lr[idx3(nx - 1, ny - 1, nz - 1, n, n)];
+      const T gx = T(0.5) * (at(2 + d[0], 1 + d[1], 1 + d[2]) - at(d[0], 1 + d[1], 1 + d[2]));
+      const T gy = T(0.5) * (at(1 + d[0], 2 + d[1], 1 + d[2]) - at(1 + d[0], d[1], 1 + d[2]));
+      const T gz = T(0.5) * (at(1 + d[0], 1 + d[1], 2 + d[2]) - at(1 + d[0], 1 + d[1], d[2]));
+      T s = inr ? lg[0] * gx + lg[1] * gy + lg[2] * gz : T(0);
+      s += rho(d[0], d[1], d[2]);
 #pragma unroll
       for (int q = 0; q < 3; ++q) lu[q] += dw[q] * s;
     }
+  };
+  const CellRange cr = block_cells(in, j0, bounds);
+  if (cr.any) {
+    // the stencils of the block's particles span [min j0 - 1, max j0 + 2] per axis
+    const int ox = cr.lo[0] - 1, oy = cr.lo[1] - 1, oz = cr.lo[2] - 1;
+    const int ex = cr.hi[0] - ox + 3, ey = cr.hi[1] - oy + 3, ez = cr.hi[2] - oz + 3;
+    if (ex <= kFw && ey <= kFw && ez <= kFw) {
+      const int t = threadIdx.x, ty = t / kFw, tz = t % kFw;
+      const int ny = oy + ty, nz = oz + tz;
+      const bool cin = ty < ey && tz < ez;
+      const bool colp = cin && ny >= -1 && ny <= M + 1 && nz >= -1 && nz <= M + 1;
+      const bool colr = cin && ny >= 1 && ny <= n && nz >= 1 && nz <= n;
+      const int xa = max(-1 - ox, 0), xb = min(M + 2 - ox, ex);     // padded-grid planes
+      const int ra = max(1 - ox, 0), rb = min(n + 1 - ox, ex);      // interior planes
+      const unsigned gp = colp ? (unsigned)(((ny + 1) * Mp + (nz + 1)) * (int)sizeof(T)) : 0u;
+      const unsigned gr = colr ? (unsigned)(((ny - 1) * n + (nz - 1)) * (int)sizeof(T)) : 0u;
+      T v[kFw], r[kFw];
+#pragma unroll
+      for (int xi = 0; xi < kFw; ++xi) v[xi] = r[xi] = T(0);
+      if (colp) {
+#pragma unroll
+        for (int xi = 0; xi < kFw; ++xi)
+          if (xi >= xa && xi < xb) v[xi] = *byte_offset(phi + (int64_t)(ox + 1 + xi) * (Mp * Mp), gp);
+      }
+      if (colr) {
+#pragma unroll
+        for (int xi = 0; xi < kFw; ++xi)
+          if (xi >= ra && xi < rb) r[xi] = *byte_offset(lr + (int64_t)(ox - 1 + xi) * (n * n), gr);
+      }
+#pragma unroll
+      for (int xi = 0; xi < kFw; ++xi)
+        if (xi < ex) {
+          win[t + kFwX * xi] = v[xi];
+          win2[t + kFwX * xi] = r[xi];
+        }
+      __syncthreads();
+      if (in) {
+        const int base = (j0[0] - 1 - ox) * kFwX + (j0[1] - 1 - oy) * kFwY + (j0[2] - 1 - oz);
+        const T* wp = win + base;
+        const T* rp = win2 + base + kFwX + kFwY + 1;   // node j0
+        corners([&](int kx, int ky, int kz) { return wp[kx * kFwX + ky * kFwY + kz]; },
+                [&](int dx, int dy, int dz) { return rp[dx * kFwX + dy * kFwY + dz]; });
+      }
+    } else {
+      // sized window over the padded grid, potential only
+      const int lx = max(ox, -1), ly = max(oy, -1), lz = max(oz, -1);
+      const int wx = min(cr.hi[0] + 2, M + 1) - lx + 1, wy = min(cr.hi[1] + 2, M + 1) - ly + 1,
+                wz = min(cr.hi[2] + 2, M + 1) - lz + 1;
+      const int wyz = wy * wz;
+      const bool use_lds = wx * wyz <= kWindow;
+      if (use_lds) {
+        const float inv_wz = 1.0f / (float)wz;
+        const unsigned gstep = (unsigned)(Mp * Mp);
+        for (int pos = threadIdx.x; pos < wyz; pos += blockDim.x) {
+          const int ey2 = (int)(((float)pos + 0.5f) * inv_wz), ez2 = pos - ey2 * wz;
+          unsigned widx = (unsigned)pos;
+          unsigned gidx = idx3(lx + 1, ly + ey2 + 1, lz + ez2 + 1, Mp, Mp);
+#pragma unroll 4
+          for (int x = 0; x < wx; ++x, widx += (unsigned)wyz, gidx += gstep) win[widx] = phi[gidx];
+        }
+      }
+      __syncthreads();
+      if (in) {
+        auto cl = [&](int v) { return min(max(v, -1), M + 1); };
+        auto rho = [&](int dx, int dy, int dz) -> T {
+          const int x = j0[0] + dx, y = j0[1] + dy, z = j0[2] + dz;
+          if (x >= 1 && x <= n && y >= 1 && y <= n && z >= 1 && z <= n)
+            return lr[idx3(x - 1, y - 1, z - 1, n, n)];
+          return T(0);
+        };
+        if (use_lds)
+          corners([&](int kx, int ky, int kz) {
+            return win[idx3(cl(j0[0] - 1 + kx) - lx, cl(j0[1] - 1 + ky) - ly,
+                            cl(j0[2] - 1 + kz) - lz, wy, wz)];
+          }, rho);
+        else
+          corners([&](int kx, int ky, int kz) {
+            return phi[idx3(cl(j0[0] - 1 + kx) + 1, cl(j0[1] - 1 + ky) + 1,
+                            cl(j0[2] - 1 + kz) + 1, Mp, Mp)];
+          }, rho);
+      }
+    }
   }
-  __syncthreads();   // the window and `bounds` are free again
+  __syncthreads();   // the windows and `bounds` are free again
 }
 
 // Scatter half of a reverse step: the transpose of "central gradient, then CiC
@@ -130,9 +188,10 @@ __device__ inline void block_adjoint_gather(const T* __restrict__ phi, const T* 
 //   lam_Phi(n) += sum_a lam_g_a sum_c W(u - n_c) (delta(n, n_c + e_a) - delta(n, n_c - e_a)) / 2
 // over the interpolation corners n_c in [0, M]^3.  Along axis a this is a 4-point stencil
 // {-w0, -w1, w0, w1} / 2 on nodes j0 - 1 .. j0 + 2, times the CiC weights across; the union
-// is the 2x2x2 corner block plus six 2x2 arms, 32 nodes in all, every one in [-1, M+1]^3.
-// Interior nodes [1, M-1]^3 feed the adjoint Poisson solve (`work`, zeroed beforehand);
-// shell nodes hold D1 Phi_BC^0, so D1 lam_Phi goes to lam_bc0.
+// is the 2x2x2 corner block plus six 2x2 arms, 32 nodes in all.  Every node with a non-zero
+// coefficient lies in [-1, M+1]^3.  Interior nodes [1, M-1]^3 feed the adjoint Poisson
+// solve (`work`, zeroed beforehand); shell nodes hold D1 Phi_BC^0, so D1 lam_Phi goes to
+// lam_bc0.
 //
 // The block privatises its nodes in an LDS window of integers: LDS atomics on integers
 // run at full rate while floating-point LDS atomics serialise.  Each contribution is
@@ -140,14 +199,17 @@ __device__ inline void block_adjoint_gather(const T* __restrict__ phi, const T* 
 // |lam_g| and Q = 30 (FP32 plans, int32) or 62 (FP64 plans, int64): a node receives at
 // most 256 particles x 1.5 |lam_g| < 2^(e + 9), so sums cannot overflow, and the rounding
 // error per contribution is below 2^(-Q + 8) of the block's largest |lam_g| (2^-22 for
-// FP32, 2^-54 for FP64).  The window is flushed with floating-point atomics to global
-// memory; blocks whose footprint exceeds the window add straight into global memory.
-// Must be called by all threads.
+// FP32, 2^-54 for FP64).  The window (fixed kFw^3 geometry when the block's extent fits,
+// else sized to it) is flushed with floating-point atomics to global memory; blocks whose
+// footprint exceeds both add straight into global memory.  Must be called by all threads.
 template <typename T>
-__device__ inline void block_adjoint_scatter(T* __restrict__ work, double* __restrict__ lam_bc0,
-                                             double D1, int M, const double (&u)[3],
-                                             const T (&lg)[3], T* win_raw, int* bounds) {
+__device__ __forceinline__ void block_adjoint_scatter(T* __restrict__ work,
+                                                      double* __restrict__ lam_bc0, double D1,
+                                                      int M, const double (&u)[3],
+                                                      const T (&lg)[3], T* win_raw,
+                                                      int* bounds) {
   using Q = typename std::conditional<std::is_same<T, float>::value, int, long long>::type;
+  using UQ = typename std::make_unsigned<Q>::type;
   constexpr int kQ = std::is_same<T, float>::value ? 30 : 62;
   static_assert(sizeof(Q) == sizeof(T), "the integer window reuses the potential window");
   Q* win = reinterpret_cast<Q*>(win_raw);
@@ -156,7 +218,6 @@ __device__ inline void block_adjoint_scatter(T* __restrict__ work, double* __res
   T f[3];
   const bool in = interp_cell<T>(M, u, j0, f);
   T w[3][2], h[3][4];
-  int lo[3], hi[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     w[a][0] = (j0[a] < 0 || j0[a] > M) ? T(0) : T(1) - f[a];
@@ -165,81 +226,112 @@ __device__ inline void block_adjoint_scatter(T* __restrict__ work, double* __res
     h[a][1] = T(-0.5) * w[a][1];    // node j0
     h[a][2] = T(0.5) * w[a][0];     // node j0 + 1
     h[a][3] = T(0.5) * w[a][1];     // node j0 + 2
-    lo[a] = max(j0[a] - 1, -1);
-    hi[a] = min(j0[a] + 2, M + 1);
   }
   constexpr int kNoExp = -900;
-  int ex = kNoExp;
+  int ex_l = kNoExp;
   if (in) {
     const double mx = (double)fmax(fmax(fabs(lg[0]), fabs(lg[1])), fabs(lg[2]));
-    if (mx > 0.0) frexp(mx, &ex);
+    if (mx > 0.0) frexp(mx, &ex_l);
   }
-  block_bounds_max(in, lo, hi, ex, bounds);
-  const BlockWindow bw = block_window(bounds);
-  const int lx = bw.lx, ly = bw.ly, lz = bw.lz, wx = bw.wx, wy = bw.wy, wz = bw.wz;
-  const int emax = max(bounds[6], kNoExp);
+  int emax_b;
+  const CellRange cr = block_cells_max(in, j0, ex_l, bounds, emax_b);
+  if (!cr.any) return;
+  const int emax = max(emax_b, kNoExp);
   const double qscale = ldexp(1.0, kQ - 9 - emax), qstep = ldexp(1.0, emax + 9 - kQ);
-  const int vol = bw.vol;
-  const bool use_lds = bw.lds;
-  if (use_lds) {
-    for (int e = threadIdx.x; e < vol; e += blockDim.x) win[e] = Q(0);
-    __syncthreads();
-  }
   auto to_global = [&](int x, int y, int z, T v) {
     if (x >= 1 && x <= n && y >= 1 && y <= n && z >= 1 && z <= n)
       unsafeAtomicAdd(work + idx3(x - 1, y - 1, z - 1, n, n), v);
     else
       unsafeAtomicAdd(lam_bc0 + idx3(x + 1, y + 1, z + 1, Mp, Mp), D1 * (double)v);
   };
-  if (in) {
-    // a node is touched only through a non-zero coefficient, which keeps it in [-1, M+1]^3
-    auto add = [&](int ox, int oy, int oz, T coef_zero_test, T v) {
-      if (coef_zero_test == T(0)) return;
-      const int x = j0[0] + ox, y = j0[1] + oy, z = j0[2] + oz;
-      if (use_lds) {
-        const Q qv = (Q)__double2ll_rn((double)v * qscale);
-        atomicAdd(reinterpret_cast<typename std::make_unsigned<Q>::type*>(win) +
-                      idx3(x - lx, y - ly, z - lz, wy, wz),
-                  (typename std::make_unsigned<Q>::type)qv);
-      } else {
-        to_global(x, y, z, v);
-      }
-    };
+  // the 32 contributions: node offset k = 0..3 from j0 - 1 per axis and value
+  auto contributions = [&](auto add) {
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
       const T kx = h[0][dx + 1] * w[1][dy] * w[2][dz];
       const T ky = w[0][dx] * h[1][dy + 1] * w[2][dz];
       const T kz = w[0][dx] * w[1][dy] * h[2][dz + 1];
-      const T nz_test = (kx != T(0) || ky != T(0) || kz != T(0)) ? T(1) : T(0);
-      add(dx, dy, dz, nz_test, lg[0] * kx + lg[1] * ky + lg[2] * kz);
+      add(1 + dx, 1 + dy, 1 + dz, (kx != T(0) || ky != T(0) || kz != T(0)),
+          lg[0] * kx + lg[1] * ky + lg[2] * kz);
     }
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      const int o = e ? 2 : -1, hk = e ? 3 : 0;
+      const int o = e ? 3 : 0, hk = e ? 3 : 0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int r = (q >> 1) & 1, s = q & 1;
         const T kx = h[0][hk] * w[1][r] * w[2][s];
-        add(o, r, s, kx, lg[0] * kx);
+        add(o, 1 + r, 1 + s, kx != T(0), lg[0] * kx);
         const T ky = w[0][r] * h[1][hk] * w[2][s];
-        add(r, o, s, ky, lg[1] * ky);
+        add(1 + r, o, 1 + s, ky != T(0), lg[1] * ky);
         const T kz = w[0][r] * w[1][s] * h[2][hk];
-        add(r, s, o, kz, lg[2] * kz);
+        add(1 + r, 1 + s, o, kz != T(0), lg[2] * kz);
       }
     }
+  };
+  // stencil nodes of the block span [min j0 - 1, max j0 + 2] per axis
+  const int ox = cr.lo[0] - 1, oy = cr.lo[1] - 1, oz = cr.lo[2] - 1;
+  const int ex = cr.hi[0] - ox + 3, ey = cr.hi[1] - oy + 3, ez = cr.hi[2] - oz + 3;
+  if (ex <= kFw && ey <= kFw && ez <= kFw) {
+    const int t = threadIdx.x, ty = t / kFw, tz = t % kFw;
+#pragma unroll
+    for (int xi = 0; xi < kFw; ++xi)
+      if (xi < ex) win[t + kFwX * xi] = Q(0);
+    __syncthreads();
+    if (in) {
+      // zero contributions add nothing, so every node is added unconditionally
+      UQ* qp = reinterpret_cast<UQ*>(win) + (j0[0] - 1 - ox) * kFwX + (j0[1] - 1 - oy) * kFwY +
+               (j0[2] - 1 - oz);
+      contributions([&](int kx, int ky, int kz, bool, T v) {
+        atomicAdd(qp + kx * kFwX + ky * kFwY + kz, (UQ)(Q)__double2ll_rn((double)v * qscale));
+      });
+    }
+    __syncthreads();
+    const int ny = oy + ty, nz = oz + tz;
+    if (ty < ey && tz < ez && ny >= -1 && ny <= M + 1 && nz >= -1 && nz <= M + 1) {
+      const int xa = max(-1 - ox, 0), xb = min(M + 2 - ox, ex);
+      Q qv[kFw];
+#pragma unroll
+      for (int xi = 0; xi < kFw; ++xi) qv[xi] = (xi >= xa && xi < xb) ? win[t + kFwX * xi] : Q(0);
+#pragma unroll
+      for (int xi = 0; xi < kFw; ++xi)
+        if (qv[xi] != Q(0)) to_global(ox + xi, ny, nz, (T)((double)qv[xi] * qstep));
+    }
+    return;
+  }
+  // sized window over the padded grid
+  const int lx = max(ox, -1), ly = max(oy, -1), lz = max(oz, -1);
+  const int wx = min(cr.hi[0] + 2, M + 1) - lx + 1, wy = min(cr.hi[1] + 2, M + 1) - ly + 1,
+            wz = min(cr.hi[2] + 2, M + 1) - lz + 1;
+  const int wyz = wy * wz;
+  const bool use_lds = wx * wyz <= kWindow;
+  if (use_lds) {
+    for (int e = threadIdx.x; e < wx * wyz; e += blockDim.x) win[e] = Q(0);
+    __syncthreads();
+  }
+  if (in) {
+    // a node is touched only through a non-zero coefficient, which keeps it in [-1, M+1]^3
+    contributions([&](int kx, int ky, int kz, bool nonzero, T v) {
+      if (!nonzero) return;
+      const int x = j0[0] - 1 + kx, y = j0[1] - 1 + ky, z = j0[2] - 1 + kz;
+      if (use_lds)
+        atomicAdd(reinterpret_cast<UQ*>(win) + idx3(x - lx, y - ly, z - lz, wy, wz),
+                  (UQ)(Q)__double2ll_rn((double)v * qscale));
+      else
+        to_global(x, y, z, v);
+    });
   }
   if (use_lds) {
     __syncthreads();
     // flush: each thread takes a (y, z) column of the window and walks it along x
-    const int wyz = wy * wz;
     const float inv_wz = 1.0f / (float)wz;
     for (int pos = threadIdx.x; pos < wyz; pos += blockDim.x) {
-      const int ey = (int)(((float)pos + 0.5f) * inv_wz), ez = pos - ey * wz;
+      const int ey2 = (int)(((float)pos + 0.5f) * inv_wz), ez2 = pos - ey2 * wz;
       unsigned widx = (unsigned)pos;
-      for (int ex = 0; ex < bw.wx; ++ex, widx += (unsigned)wyz) {
-        const Q qv = win[widx];
-        if (qv != Q(0)) to_global(lx + ex, ly + ey, lz + ez, (T)((double)qv * qstep));
+      for (int x = 0; x < wx; ++x, widx += (unsigned)wyz) {
+        const Q q = win[widx];
+        if (q != Q(0)) to_global(lx + x, ly + ey2, lz + ez2, (T)((double)q * qstep));
       }
     }
   }
@@ -278,6 +370,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(AdjointArgs<T> a, Bloc
     acc1[c] = acc2[c] = 0.0;
   }
   __shared__ T win[kWindow];
+  __shared__ T win2[GATHER ? kWindow : 1];   // lam_rho window of the gather half
   __shared__ int bounds[8];
   if constexpr (GATHER) {
     double x[3], u[3];
@@ -287,7 +380,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(AdjointArgs<T> a, Bloc
     T lg[3], lu[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) lg[c] = (T)a.beta_g * lp[c];
-    block_adjoint_gather<T>(a.phi + t.h_off, a.lam_rho + t.g_off, M, u, lg, win, bounds, lu);
+    block_adjoint_gather<T>(a.phi + t.h_off, a.lam_rho + t.g_off, M, u, lg, win, win2, bounds,
+                            lu);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       lx[c] += lu[c];

@@ -2,6 +2,8 @@
 // XCD-aware block numbering, wave and block reductions, and LDS window indexing.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -147,6 +149,62 @@ __device__ inline void window_coords(int e, int wz, int wyz, float inv_wz, float
   const int r = e - ex * wyz;
   ey = (int)(((float)r + 0.5f) * inv_wz);
   ez = r - ey * wz;
+}
+
+// LDS windows of a block.  The fast form has a fixed geometry of kFw^3 nodes with
+// compile-time pitches (x: kFw^2, y: kFw, z: 1): every stencil read and every deposit of a
+// particle is one base address plus an immediate offset, and thread t owns the window
+// column (y, z) = (t / kFw, t % kFw) when staging, clearing and flushing.  A block whose
+// extent exceeds kFw nodes along some axis takes a window sized to its extent (runtime
+// pitches, at most kWindow entries), and beyond that works on global memory.  All forms
+// perform the same arithmetic, so they give identical results.
+constexpr int kFw = 16, kFwY = kFw, kFwX = kFw * kFw;
+
+// base + a byte offset below 2^32: a wave-uniform base and a 32-bit per-lane offset map to
+// the scalar-base form of the global memory instructions
+template <typename P>
+__device__ __forceinline__ P* byte_offset(P* base, unsigned bytes) {
+  using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+  return reinterpret_cast<P*>(reinterpret_cast<C*>(base) + bytes);
+}
+static_assert(kFw * kFw * kFw == kWindow, "fixed window = LDS window");
+static_assert(kFw * kFw == kBlock, "one window column per thread");
+
+// Block-wide extent of the cells j0 of the particles with in == true: lo (minima) and hi
+// (maxima) per axis, as wave-uniform scalars; any is false when no particle of the block is
+// in.  Must be called by all threads of the block.
+struct CellRange {
+  int lo[3], hi[3];
+  bool any;
+};
+
+__device__ __forceinline__ CellRange block_cells(bool in, const int (&j0)[3], int* bounds) {
+  block_bounds(in, j0, j0, bounds);
+  CellRange r;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r.lo[a] = __builtin_amdgcn_readfirstlane(bounds[a]);
+    r.hi[a] = __builtin_amdgcn_readfirstlane(bounds[3 + a]);
+  }
+  r.any = r.lo[0] <= r.hi[0] && r.lo[1] <= r.hi[1] && r.lo[2] <= r.hi[2];
+  return r;
+}
+
+
+// Block-wide extent of the cells j0 (as block_cells) and the block-wide maximum of one int
+// per thread (v), all wave-uniform.  Must be called by all threads of the block.
+__device__ __forceinline__ CellRange block_cells_max(bool in, const int (&j0)[3], int v,
+                                                     int* bounds, int& vmax) {
+  block_bounds_max(in, j0, j0, v, bounds);
+  CellRange r;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r.lo[a] = __builtin_amdgcn_readfirstlane(bounds[a]);
+    r.hi[a] = __builtin_amdgcn_readfirstlane(bounds[3 + a]);
+  }
+  vmax = __builtin_amdgcn_readfirstlane(bounds[6]);
+  r.any = r.lo[0] <= r.hi[0] && r.lo[1] <= r.hi[1] && r.lo[2] <= r.hi[2];
+  return r;
 }
 
 }  // namespace
