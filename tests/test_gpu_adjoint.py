@@ -66,6 +66,54 @@ def test_fp64_gradient_matches_oracle_reference(torch, ckpt):
     assert err < 1e-7
 
 
+def test_fp64_gradient_with_wide_windows_and_coarse_output(torch):
+    """A small, strongly clustered volume (L = 16 Mpc/h, sigma_8 = 2) sends most blocks of
+    the late steps to the sized and global-memory window forms of the reverse pass, and the
+    loss is taken on an output grid coarser than the lattice (N_out = 8 for N_p = 16); the
+    gradient must still match the oracle's reverse-mode reference."""
+    import paper_2003_04925_amd as S
+    from oracle.adjoint import _box, _boundary_potential0, _roll_diff, evolve_box, potentials
+    from oracle.adjoint import loss_and_gradient
+    from oracle.cosmology import Cosmology, cola_schedule
+    from oracle.tiling import uniform_tiling
+    from test_gpu_parity import window_forms
+    Np, L, tps, buf, n, N_out, s8 = 16, 16.0, 2, 4, 3, 8, 2.0
+    say("fp64 adjoint, wide windows, N_out", N_out)
+    cosmo = Cosmology(sigma8=s8)
+    wn = synthetic.white_noise(Np, 3)
+    otiles = uniform_tiling(Np, tps, buf)
+    # premise: the final positions put blocks in every window form
+    w64 = torch.tensor(wn)
+    phi1, phi2 = potentials(w64, L, cosmo, 0.05)
+    psi1 = torch.stack([_roll_diff(phi1, a) for a in range(3)])
+    psi2 = torch.stack([_roll_diff(phi2, a) for a in range(3)])
+    steps, _ = cola_schedule(cosmo, 0.05, 1.0, n)
+    forms = set()
+    for t in otiles:
+        u = evolve_box(_box(psi1, t), _box(psi2, t), _boundary_potential0(phi1, t), steps)
+        forms |= set(window_forms(u.detach().numpy().reshape(3, -1), t.M).tolist())
+    say("  window forms at the final step", sorted(forms))
+    assert {0, 1, 2} <= forms
+    target = 0.5 * synthetic.normal((N_out,) * 3, 1.0, 43)
+    sim = S.Simulation(L, Np, S.uniform_tiling(Np, tps, buf), n, precision="fp64",
+                       N_out=N_out, cosmology=S.CosmologyParams(sigma8=s8), checkpoint_every=2)
+    w = torch.from_numpy(wn).cuda()
+    t = torch.from_numpy(target).cuda()
+    dens = sim.forward(w)["density"]
+    loss = float(((dens - t) ** 2).sum())
+    g = sim.backward(2.0 * (dens - t)).cpu().numpy()
+    torch.cuda.synchronize()
+    oloss, og, odens = loss_and_gradient(wn, L, otiles, target, cosmo=cosmo, n_steps=n,
+                                         N_out=N_out)
+    derr = np.abs(dens.cpu().numpy() - odens).max()
+    say("  output density max err", derr, "loss", loss, oloss)
+    assert derr < 1e-9
+    assert loss == pytest.approx(oloss, rel=1e-9)
+    err = np.abs(g - og).max() / np.abs(og).max()
+    say("  max rel err", err)
+    assert err < 1e-7
+
+
 def test_fp32_gradient_close_to_oracle_reference(torch):
     Np, L, tps, buf, n = 32, 200.0, 2, 8, 6
     say("fp32 adjoint vs oracle")

@@ -232,6 +232,89 @@ def test_one_step_from_identical_state(torch, precision, M_buffer):
         np.testing.assert_allclose(got, want, atol=dep_tol(precision))
 
 
+def window_forms(u, M):
+    """Which LDS window form each 4 x 8 x 8 brick of a box takes for its force stencils, from
+    positions u (3, M^3) in lattice order: 0 = fixed 16^3 window, 1 = window sized to the
+    block's extent (at most 4096 nodes), 2 = global memory; -1 = no particle inside."""
+    M4, M8 = M // 4, M // 8
+    j0 = np.floor(u).reshape(3, M4, 4, M8, 8, M8, 8).transpose(0, 1, 3, 5, 2, 4, 6)
+    j0 = j0.reshape(3, -1, 256)
+    uu = u.reshape(3, M4, 4, M8, 8, M8, 8).transpose(0, 1, 3, 5, 2, 4, 6).reshape(3, -1, 256)
+    inside = ((uu >= -1) & (uu < M + 1)).all(axis=0)
+    forms = []
+    for b in range(j0.shape[1]):
+        if not inside[b].any():
+            forms.append(-1)
+            continue
+        lo = j0[:, b, inside[b]].min(axis=1)
+        hi = j0[:, b, inside[b]].max(axis=1)
+        if (hi - lo + 4 <= 16).all():
+            forms.append(0)
+            continue
+        vol = np.prod(np.minimum(hi + 2, M + 1) - np.maximum(lo - 1, -1) + 1)
+        forms.append(1 if vol <= 4096 else 2)
+    return np.array(forms)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_one_step_every_window_form(torch, precision):
+    """Bricks given small, elongated and wide residual displacements take the fixed, the
+    sized and the global-memory window forms; every form must match the oracle."""
+    from oracle.scola import box_deposit, box_gradient, box_interpolate
+    say("one-step parity over the window forms", precision)
+    Np = 32
+    sim = make_sim(torch, precision, Np=Np, tps=2, buffer=8)
+    sim.setup(torch.from_numpy(synthetic.white_noise(Np, 21)).cuda())
+    P = sim.layout.n_particles
+    xr = synthetic.uniform((3, P), -0.5, 0.5, 31)
+    wide = synthetic.uniform((3, P), -8.0, 8.0, 32)
+    for po, M, _, _ in sim.box_slices():
+        for b in range(M ** 3 // 256):
+            sl = slice(po + 256 * b, po + 256 * (b + 1))
+            if b % 3 == 1:
+                xr[0, sl] = 0.9 * wide[0, sl]          # elongated along x: sized window
+            elif b % 3 == 2:
+                xr[:, sl] = wide[:, sl]                # wide: global memory
+    sim.view("x_res").copy_(torch.from_numpy(xr).to(sim.real))
+    sim.view("p_res").copy_(torch.from_numpy(synthetic.normal((3, P), 0.5, 33)).to(sim.real))
+    torch.cuda.synchronize()
+    xr = sim.view("x_res").double().cpu().numpy()
+    pr = sim.view("p_res").double().cpu().numpy()
+    D1, D2, D1n, D2n = 3.0, -4.0, 3.5, -5.3
+    beta, alpha = -0.05, 1.7
+    sim.op_deposit(D1, D2)
+    sim.op_poisson(D1)
+    torch.cuda.synchronize()
+    phi = sim.view("phi").double().cpu().numpy()
+    g1 = sim.view("psi1").cpu().numpy()
+    g2 = sim.view("psi2").cpu().numpy()
+    seen = set()
+    for t in range(len(sim.tiles)):
+        M = sim.box_slices()[t][1]
+        seen |= set(window_forms(box_positions(sim, g1, g2, xr, t, D1, D2), M).tolist())
+    say("  window forms present", sorted(seen))
+    assert {0, 1, 2} <= seen
+    sim.op_step(beta, alpha, D1, D2, D1n, D2n, deposit=True)
+    torch.cuda.synchronize()
+    xr2 = sim.view("x_res").double().cpu().numpy()
+    pr2 = sim.view("p_res").double().cpu().numpy()
+    rho = sim.view("rho").cpu().numpy()
+    xtol = 1e-10 if precision == "fp64" else 1e-5
+    for t, (po, M, go, ho) in enumerate(sim.box_slices()):
+        b = lambda a: box(a, po, M).reshape(3, -1)
+        u = box_positions(sim, g1, g2, xr, t, D1, D2)
+        g = box_interpolate(box_gradient(phi[ho:ho + (M + 3) ** 3].reshape((M + 3,) * 3)), u)
+        p_want = b(pr) + beta * (g - D1 * b(g1) + (D2 - D1 ** 2) * b(g2))
+        x_want = b(xr) + alpha * p_want
+        xerr = np.abs(b(xr2) - x_want).max()
+        say("  tile", t, "max |dx| cells", xerr)
+        assert xerr < xtol
+        u2 = box_positions(sim, g1, g2, xr2, t, D1n, D2n)
+        want, _ = box_deposit(u2, M)
+        got = rho[go:go + (M - 1) ** 3].reshape((M - 1,) * 3) / 2.0 ** sim.layout.fixed_bits - 1.0
+        np.testing.assert_allclose(got, want, atol=dep_tol(precision))
+
+
 def test_fp64_run_matches_oracle_end_to_end(torch):
     from oracle.run import run_scola
     from oracle.tiling import uniform_tiling as otiling
