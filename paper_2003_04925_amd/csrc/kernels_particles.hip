@@ -9,11 +9,13 @@
 // formed in FP64 (u = q - D1 Psi1 + D2 Psi2 + x_res) before its cell index is taken, so
 // cell indices do not depend on the state precision.
 //
-// The deposit accumulates round(w * 2^40) in 64-bit integers: sums are exact and
+// The deposit accumulates rounded fixed-point weights in integers (2^40 units per
+// particle in 64 bits for FP64 plans, 2^21 in 32 bits for FP32 plans): sums are exact and
 // independent of the order of the atomics, which makes every run bitwise reproducible and
-// a box computed alone bitwise equal to the same box in a batch.  The eighth corner gets
-// 2^40 minus the other seven, so every particle carries exactly one unit of mass, split
-// between deposited and dropped (outside the interior nodes).
+// a box computed alone bitwise equal to the same box in a batch.  The corner with the
+// largest weight takes the rounding remainder, so every particle carries exactly one unit
+// of mass, split between deposited and dropped (outside the interior nodes), and no weight
+// is negative.
 #include <type_traits>
 
 #include "common.h"
@@ -24,19 +26,28 @@ namespace scola {
 
 namespace {
 
-// Fixed-point CiC weights of the 8 corners (offset bits x = 4, y = 2, z = 1); the eighth
-// corner gets the remainder so the eight sum to exactly one unit.
+// Fixed-point CiC weights of the 8 corners (offset bits x = 4, y = 2, z = 1).  Every weight
+// is rounded to the nearest unit, and the corner with the largest weight (the one nearest
+// the particle, weight at least 1/8) takes the remainder, so the eight sum to exactly one
+// unit and none is negative: no node total can fall below zero through rounding.
+__device__ inline int largest_corner(double fx, double fy, double fz) {
+  return (fx >= 0.5 ? 4 : 0) | (fy >= 0.5 ? 2 : 0) | (fz >= 0.5 ? 1 : 0);
+}
+
 __device__ inline void fixed_weights(double fx, double fy, double fz, long long (&w)[8]) {
   long long sum = 0;
 #pragma unroll
-  for (int c = 0; c < 7; ++c) {
+  for (int c = 0; c < 8; ++c) {
     const double wx = (c & 4) ? fx : 1.0 - fx;
     const double wy = (c & 2) ? fy : 1.0 - fy;
     const double wz = (c & 1) ? fz : 1.0 - fz;
     w[c] = __double2ll_rn(wx * wy * wz * kFixedOne);
     sum += w[c];
   }
-  w[7] = (long long)kFixedOne - sum;
+  const long long adj = (long long)kFixedOne - sum;
+  const int cl = largest_corner(fx, fy, fz);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) w[c] += c == cl ? adj : 0ll;
 }
 
 template <typename T>
@@ -48,13 +59,16 @@ __device__ inline void mesh_weights(double fx, double fy, double fz, long long (
     const float ax[2] = {1.0f - (float)fx, (float)fx}, ay[2] = {1.0f - (float)fy, (float)fy},
                 az[2] = {1.0f - (float)fz, (float)fz};
     int sum = 0;
+    int v[8];
 #pragma unroll
-    for (int c = 0; c < 7; ++c) {
-      const int v = __float2int_rn(ax[(c >> 2) & 1] * ay[(c >> 1) & 1] * az[c & 1] * one);
-      w[c] = v;
-      sum += v;
+    for (int c = 0; c < 8; ++c) {
+      v[c] = __float2int_rn(ax[(c >> 2) & 1] * ay[(c >> 1) & 1] * az[c & 1] * one);
+      sum += v[c];
     }
-    w[7] = (1 << MeshFixed<T>::bits) - sum;
+    const int adj = (1 << MeshFixed<T>::bits) - sum;
+    const int cl = largest_corner(fx, fy, fz);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) w[c] = v[c] + (c == cl ? adj : 0);
   }
 }
 

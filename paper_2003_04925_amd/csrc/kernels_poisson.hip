@@ -102,24 +102,61 @@ __device__ __forceinline__ cx<T> mul_wr(cx<T> a, int R, int m) {
   return r;
 }
 
-// One radix-2 decimation-in-frequency stage across lanes (partner lane l ^ S) of K x R
-// independent 32-point transforms, without divergent branches: every lane forms
-// p + sign x (lower half: x + p; upper half: p - x) and multiplies by its twiddle, which
-// is 1 on the lower half; the last stage (S = 1) has only unit twiddles.
-template <int S, int R, int K, typename T>
+// Lane l of a half wavefront holds data index n(l) of the 32-point transforms across lanes.
+// The lane bits are a GF(2)-linear relabelling of the data bits chosen so that the partner
+// of every radix-2 stage is a single DPP move away: data bit 0 -> lane xor 1, bit 1 -> xor 2
+// (quad permutations), bit 2 -> xor 7 (half-row mirror), bit 3 -> xor 15 (row mirror), bit
+// 4 -> xor 16 (ds_swizzle across the two 16-lane rows).  n(0) = 0.
+__device__ __forceinline__ int fft_index(int l) {
+  const int l0 = l & 1, l1 = (l >> 1) & 1, l2 = (l >> 2) & 1, l3 = (l >> 3) & 1;
+  return (l0 ^ l2) | ((l1 ^ l2) << 1) | ((l2 ^ l3) << 2) | (l & 0x18);
+}
+
+template <int B>
+__device__ __forceinline__ int stage_partner(int v) {
+  static_assert(B >= 0 && B <= 4, "data bit");
+  if constexpr (B == 0) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);   // xor 1
+  if constexpr (B == 1) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);   // xor 2
+  if constexpr (B == 2) return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);  // xor 7
+  if constexpr (B == 3) return __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true);  // xor 15
+  if constexpr (B == 4) return __builtin_amdgcn_ds_swizzle(v, 0x401F);              // xor 16
+  return v;
+}
+template <int B>
+__device__ __forceinline__ float stage_partner(float v) {
+  return __int_as_float(stage_partner<B>(__float_as_int(v)));
+}
+template <int B>
+__device__ __forceinline__ double stage_partner(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = stage_partner<B>((int)(b & 0xffffffffll));
+  const int hi = stage_partner<B>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One radix-2 decimation-in-frequency stage on data bit B (distance S = 2^B) of K x R
+// independent 32-point transforms across lanes, without divergent branches: every lane
+// forms v = own + s * partner with s = +1 where its data bit B is clear and -1 where it is
+// set, i.e. a + b on the lower and -(a - b) on the upper element of each pair; the upper
+// element's twiddle is taken negated, -W_{2S}^(n mod S) = W_{32R}^(((n mod S) 16/S + 16) R),
+// which restores (a - b) W_{2S}^(n mod S).  The last stage (S = 1) has no twiddle and leaves
+// the upper elements negated; those hold the outputs 16..31 of each transform, which the
+// sine transform never uses.
+template <int B, int R, int K, typename T>
 __device__ __forceinline__ void dif_stage(cx<T> (&x)[K][R], const cx<T>* __restrict__ tw,
-                                          int l) {
-  const bool upper = (l & S) != 0;
-  const T sg = upper ? T(-1) : T(1);
+                                          int n) {
+  constexpr int S = 1 << B;
+  const bool upper = ((n >> B) & 1) != 0;
+  const T s = upper ? T(-1) : T(1);
   cx<T> w;
-  if constexpr (S > 1) w = tw[upper ? (l & (S - 1)) * (16 / S) * R : 0];   // W_{2S}^(l mod S)
+  if constexpr (S > 1) w = tw[upper ? ((n & (S - 1)) * (16 / S) + 16) * R : 0];
 #pragma unroll
   for (int k = 0; k < K; ++k)
 #pragma unroll
     for (int k1 = 0; k1 < R; ++k1) {
       cx<T> v;
-      v.x = lane_xor<S>(x[k][k1].x) + sg * x[k][k1].x;
-      v.y = lane_xor<S>(x[k][k1].y) + sg * x[k][k1].y;
+      v.x = fma(stage_partner<B>(x[k][k1].x), s, x[k][k1].x);
+      v.y = fma(stage_partner<B>(x[k][k1].y), s, x[k][k1].y);
       if constexpr (S > 1) {
         x[k][k1].x = v.x * w.x - v.y * w.y;
         x[k][k1].y = v.x * w.y + v.y * w.x;
@@ -129,40 +166,76 @@ __device__ __forceinline__ void dif_stage(cx<T> (&x)[K][R], const cx<T>* __restr
     }
 }
 
-// K independent FFTs of length 32R on one half wavefront (interleaved for ILP); lane l holds
-// x[k][n2] = input k at position 32 n2 + l, n2 < R.  On return lane l holds Z_k at
-// position k1 + R bitrev5(l) in x[k][k1].  tw = W_{32R}^m, m < 32R (in LDS).
+// In-register DFT of R points (forward, W_R = exp(-2 pi i / R)): radix-2 and radix-4
+// butterflies for R = 2, 4, 8, the direct sum with compile-time twiddles otherwise.
+template <int R, typename T>
+__device__ __forceinline__ void small_dft(cx<T> (&x)[R]) {
+  if constexpr (R == 2) {
+    const cx<T> a = x[0], b = x[1];
+    x[0] = c_add(a, b);
+    x[1] = c_sub(a, b);
+  } else if constexpr (R == 4) {
+    const cx<T> t0 = c_add(x[0], x[2]), t1 = c_sub(x[0], x[2]);
+    const cx<T> t2 = c_add(x[1], x[3]), t3 = c_sub(x[1], x[3]);
+    x[0] = c_add(t0, t2);
+    x[2] = c_sub(t0, t2);
+    x[1].x = t1.x + t3.y;   // t1 - i t3
+    x[1].y = t1.y - t3.x;
+    x[3].x = t1.x - t3.y;   // t1 + i t3
+    x[3].y = t1.y + t3.x;
+  } else if constexpr (R == 8) {
+    cx<T> e[4] = {x[0], x[2], x[4], x[6]}, o[4] = {x[1], x[3], x[5], x[7]};
+    small_dft<4, T>(e);
+    small_dft<4, T>(o);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const cx<T> t = mul_wr<T>(o[k], 8, k);
+      x[k] = c_add(e[k], t);
+      x[k + 4] = c_sub(e[k], t);
+    }
+  } else if constexpr (R > 1) {
+    cx<T> y[R];
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) {
+      cx<T> acc = x[0];
+#pragma unroll
+      for (int n2 = 1; n2 < R; ++n2) acc = c_add(acc, mul_wr<T>(x[n2], R, (n2 * k1) % R));
+      y[k1] = acc;
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) x[k1] = y[k1];
+  }
+}
+
+// K independent FFTs of length 32R on one half wavefront (interleaved for ILP); lane l
+// holds x[k][n2] = input k at position 32 n2 + n with n = fft_index(l).  On return lane l
+// holds Z_k at position k1 + R bitrev5(n) in x[k][k1] (negated where n is odd).
+// tw = W_{32R}^m, m < 32R (in LDS).
 template <int R, int K, typename T>
-__device__ __forceinline__ void halfwave_fft(cx<T> (&x)[K][R], const cx<T>* __restrict__ tw, int l) {
+__device__ __forceinline__ void halfwave_fft(cx<T> (&x)[K][R], const cx<T>* __restrict__ tw,
+                                             int n) {
   if constexpr (R > 1) {
     cx<T> tl[R];
 #pragma unroll
-    for (int k1 = 1; k1 < R; ++k1) tl[k1] = tw[l * k1];    // W_N^(n1 k1)
+    for (int k1 = 1; k1 < R; ++k1) tl[k1] = tw[n * k1];    // W_N^(n k1)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      cx<T> y[R];
+      small_dft<R, T>(x[k]);
 #pragma unroll
-      for (int k1 = 0; k1 < R; ++k1) {
-        cx<T> acc = x[k][0];
-#pragma unroll
-        for (int n2 = 1; n2 < R; ++n2) acc = c_add(acc, mul_wr<T>(x[k][n2], R, (n2 * k1) % R));
-        y[k1] = k1 ? c_mul(acc, tl[k1]) : acc;
-      }
-#pragma unroll
-      for (int k1 = 0; k1 < R; ++k1) x[k][k1] = y[k1];
+      for (int k1 = 1; k1 < R; ++k1) x[k][k1] = c_mul(x[k][k1], tl[k1]);
     }
   }
-  dif_stage<16, R, K, T>(x, tw, l);
-  dif_stage<8, R, K, T>(x, tw, l);
-  dif_stage<4, R, K, T>(x, tw, l);
-  dif_stage<2, R, K, T>(x, tw, l);
-  dif_stage<1, R, K, T>(x, tw, l);
+  dif_stage<4, R, K, T>(x, tw, n);
+  dif_stage<3, R, K, T>(x, tw, n);
+  dif_stage<2, R, K, T>(x, tw, n);
+  dif_stage<1, R, K, T>(x, tw, n);
+  dif_stage<0, R, K, T>(x, tw, n);
 }
 
 // In-place DST-I (unnormalised, eq. DST_delta) of K pairs of lines (a_k, b_k), each n =
 // 16R - 1 values at the compile-time stride S in LDS; output j (1..n) of pair k is
 // multiplied by sa(k, j) / sb(k, j).  Pairs with valid[k] false are neither read nor
-// written.  Lane l loads positions m = 32 n2 + l of the odd extension; the register n2
+// written.  Lane l loads positions m = 32 n2 + n(l) of the odd extension; the register n2
 // decides at compile time whether m lies in the lower half (a_m at index m - 1), the upper
 // half (-a_{2M-m} at index 2M - m - 1) or straddles m = M (odd R), so addresses are one
 // per-lane base plus immediate offsets.  The zero positions m = 0 and m = M read an
@@ -172,6 +245,7 @@ __device__ __forceinline__ void dst_pairs(T* const (&la)[K], T* const (&lb)[K],
                                           const bool (&valid)[K], const bool (&has_b)[K],
                                           const cx<T>* tw, int l, SA sa, SB sb) {
   constexpr int M = 16 * R;
+  const int nl = fft_index(l);   // this lane's data index within each 32-point transform
   cx<T> x[K][R];
 #pragma unroll
   for (int k = 0; k < K; ++k)
@@ -181,21 +255,21 @@ __device__ __forceinline__ void dst_pairs(T* const (&la)[K], T* const (&lb)[K],
       int idx;
       T sg;
       if (m0 + 32 <= M) {
-        idx = m0 + l - 1;
+        idx = m0 + nl - 1;
         sg = T(1);
         if (m0 == 0) {
           idx = max(idx, 0);
-          sg = l == 0 ? T(0) : T(1);
+          sg = nl == 0 ? T(0) : T(1);
         }
       } else if (m0 >= M) {
-        idx = 2 * M - 1 - m0 - l;
+        idx = 2 * M - 1 - m0 - nl;
         sg = T(-1);
         if (m0 == M) {
           idx = min(idx, M - 2);
-          sg = l == 0 ? T(0) : T(-1);
+          sg = nl == 0 ? T(0) : T(-1);
         }
       } else {
-        const int m = m0 + l;
+        const int m = m0 + nl;
         const bool lo = m < M;
         idx = min(max(lo ? m - 1 : 2 * M - m - 1, 0), M - 2);
         sg = (m == 0 || m == M) ? T(0) : (lo ? T(1) : T(-1));
@@ -209,11 +283,11 @@ __device__ __forceinline__ void dst_pairs(T* const (&la)[K], T* const (&lb)[K],
       }
       x[k][n2] = v;
     }
-  halfwave_fft<R, K, T>(x, tw, l);
-  // lane l holds Z at positions k1 + R bitrev5(l); the sine coefficients j = 1..M-1 sit on
-  // the even lanes (bitrev5(l) < 16)
-  const int br = bitrev5(l);
-  if ((l & 1) == 0) {
+  halfwave_fft<R, K, T>(x, tw, nl);
+  // lane l holds Z at positions k1 + R bitrev5(n); the sine coefficients j = 1..M-1 sit on
+  // the lanes with even n (bitrev5(n) < 16)
+  const int br = bitrev5(nl);
+  if ((nl & 1) == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (!valid[k]) continue;
@@ -269,6 +343,12 @@ __device__ __forceinline__ void plane_dst(T* plane, const cx<T>* tw) {
   __syncthreads();
 }
 
+// Fixed-point mass of a node in units: 64-bit words are read as signed (a total can only be
+// non-negative, and the signed reading keeps a rounding below zero harmless), 32-bit words
+// as unsigned (2^21 units per particle: up to 2048 particles per node).
+__device__ __forceinline__ double mass_units(unsigned long long r) { return (double)(long long)r; }
+__device__ __forceinline__ double mass_units(unsigned int r) { return (double)r; }
+
 template <typename T>
 __device__ inline void load_twiddles(cx<T>* tw, const MeshArgs<T>& a, const TileDesc& t) {
   const cx<T>* src = reinterpret_cast<const cx<T>*>(a.twiddles) + t.tw_off;
@@ -316,7 +396,7 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m
         a.rho[base + e] = Rho(0);
         if constexpr (std::is_same<T, float>::value)
           if (r[q] >= (1u << 31)) atomicAdd(a.alarm, 1ull);   // within a factor 2 of wrapping
-        plane[e] = (T)((double)r[q] * kUnit - 1.0);
+        plane[e] = (T)(mass_units(r[q]) * kUnit - 1.0);
       }
     }
     // delta' = delta - Delta Phi_BCs (App. C.1): each face-layer neighbour of an interior
@@ -339,7 +419,7 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m
       a.rho[base + e] = Rho(0);
       if constexpr (std::is_same<T, float>::value)
         if (rv >= (1u << 31)) atomicAdd(a.alarm, 1ull);
-      double d = (double)rv * kUnit - 1.0;
+      double d = mass_units(rv) * kUnit - 1.0;
       if (x == 0) d -= D1 * bc[((int64_t)1 * Mp + y + 2) * Mp + z + 2];
       if (x == n - 1) d -= D1 * bc[((int64_t)(M + 1) * Mp + y + 2) * Mp + z + 2];
       if (y == 0) d -= D1 * bc[((int64_t)(x + 2) * Mp + 1) * Mp + z + 2];
