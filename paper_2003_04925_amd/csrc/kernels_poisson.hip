@@ -375,11 +375,32 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) plane[e] = a.work[base + e];
   } else {
     using Rho = typename MeshFixed<T>::rho_t;
-    constexpr int kBatch = 8;   // independent loads in flight per thread
+    constexpr int kBatch = 16;   // independent loads in flight per thread
     constexpr double kUnit = 1.0 / (double)(1ll << MeshFixed<T>::bits);
-    // the plane's first and last rows and columns, and the whole plane when it touches an
-    // x face, also receive the boundary source; they are converted in the second loop
+    // delta' = delta - Delta Phi_BCs (App. C.1): an interior node next to a face takes
+    // D1 Phi_BC^0 of its face-layer neighbour (padded index = node index + 1; interior node
+    // index = array index + 1).  Interior x planes need it on their perimeter only (one
+    // element per thread, its face values fetched before the mass so that the latencies
+    // overlap); the two x-face planes need it everywhere.
     const bool xface = x == 0 || x == n - 1;
+    auto yz_term = [&](int y, int z) {
+      double s = 0.0;
+      if (y == 0) s += bc[((int64_t)(x + 2) * Mp + 1) * Mp + z + 2];
+      if (y == n - 1) s += bc[((int64_t)(x + 2) * Mp + M + 1) * Mp + z + 2];
+      if (z == 0) s += bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + 1];
+      if (z == n - 1) s += bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + M + 1];
+      return s;
+    };
+    int pe = -1;
+    double pterm = 0.0;
+    if (!xface && (int)threadIdx.x < 4 * (n - 1)) {
+      // perimeter of the plane: i < n - 1 first row, then last column, last row, first column
+      const int i = threadIdx.x, side = i / (n - 1), o = i - side * (n - 1);
+      const int y = side == 0 ? 0 : side == 1 ? o : side == 2 ? n - 1 : n - 1 - o;
+      const int z = side == 0 ? o : side == 1 ? n - 1 : side == 2 ? n - 1 - o : 0;
+      pe = y * n + z;
+      pterm = yz_term(y, z);
+    }
     for (int e0 = 0; e0 < n * n; e0 += kBatch * kBlock) {
       Rho r[kBatch];
 #pragma unroll
@@ -391,42 +412,29 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m
       for (int q = 0; q < kBatch; ++q) {
         const int e = e0 + q * kBlock + threadIdx.x;
         if (e >= n * n) continue;
-        const int y = e / n, z = e - (e / n) * n;
-        if (xface || y == 0 || y == n - 1 || z == 0 || z == n - 1) continue;
         a.rho[base + e] = Rho(0);
         if constexpr (std::is_same<T, float>::value)
           if (r[q] >= (1u << 31)) atomicAdd(a.alarm, 1ull);   // within a factor 2 of wrapping
         plane[e] = (T)(mass_units(r[q]) * kUnit - 1.0);
       }
     }
-    // delta' = delta - Delta Phi_BCs (App. C.1): each face-layer neighbour of an interior
-    // node adds D1 Phi_BC^0 there (padded index = node index + 1; interior node index =
-    // array index + 1)
-    const int nb = xface ? n * n : 4 * (n - 1);
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-      int y, z;
-      if (xface) {
-        y = i / n;
-        z = i - y * n;
-      } else {
-        // perimeter of the plane: i < n - 1 first row, then last column, last row, first column
-        const int side = i / (n - 1), o = i - side * (n - 1);
-        y = side == 0 ? 0 : side == 1 ? o : side == 2 ? n - 1 : n - 1 - o;
-        z = side == 0 ? o : side == 1 ? n - 1 : side == 2 ? n - 1 - o : 0;
+    __syncthreads();
+    if (xface) {
+      const int A = x == 0 ? 1 : M + 1;   // padded x index of the face layer
+      for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int y = e / n, z = e - (e / n) * n;
+        const double s = bc[((int64_t)A * Mp + y + 2) * Mp + z + 2] + yz_term(y, z);
+        plane[e] = (T)((double)plane[e] - D1 * s);
       }
-      const int e = y * n + z;
-      const Rho rv = a.rho[base + e];
-      a.rho[base + e] = Rho(0);
-      if constexpr (std::is_same<T, float>::value)
-        if (rv >= (1u << 31)) atomicAdd(a.alarm, 1ull);
-      double d = mass_units(rv) * kUnit - 1.0;
-      if (x == 0) d -= D1 * bc[((int64_t)1 * Mp + y + 2) * Mp + z + 2];
-      if (x == n - 1) d -= D1 * bc[((int64_t)(M + 1) * Mp + y + 2) * Mp + z + 2];
-      if (y == 0) d -= D1 * bc[((int64_t)(x + 2) * Mp + 1) * Mp + z + 2];
-      if (y == n - 1) d -= D1 * bc[((int64_t)(x + 2) * Mp + M + 1) * Mp + z + 2];
-      if (z == 0) d -= D1 * bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + 1];
-      if (z == n - 1) d -= D1 * bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + M + 1];
-      plane[e] = (T)d;
+    } else {
+      // the remaining perimeter elements of planes wider than the block
+      for (int i = threadIdx.x + blockDim.x; i < 4 * (n - 1); i += blockDim.x) {
+        const int side = i / (n - 1), o = i - side * (n - 1);
+        const int y = side == 0 ? 0 : side == 1 ? o : side == 2 ? n - 1 : n - 1 - o;
+        const int z = side == 0 ? o : side == 1 ? n - 1 : side == 2 ? n - 1 - o : 0;
+        plane[y * n + z] = (T)((double)plane[y * n + z] - D1 * yz_term(y, z));
+      }
+      if (pe >= 0) plane[pe] = (T)((double)plane[pe] - D1 * pterm);
     }
   }
   __syncthreads();
@@ -525,11 +533,45 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p3(MeshArgs<T> a, BlockMap m
   load_twiddles(tw, a, t);
   const int x = local;
   const int64_t base = t.g_off + (int64_t)x * n * n;
+  const int A = x + 2;
+  // the padded plane's border (two layers on each side) takes D1 Phi_BC^0: those values
+  // are fetched first so that their latency overlaps the load of the plane.  Border
+  // element i: rows 0, 1, M+1, M+2 whole, then columns 0, 1, M+1, M+2 of rows 2..M.
+  constexpr int kBorder = Mp * Mp - n * n;
+  constexpr int kPerThread = (kBorder + kBlock - 1) / kBlock;
+  T* border = plane + n * n;   // the border values, staged in LDS behind the plane
+  auto border_offset = [](int i) {
+    int B, C;
+    if (i < 4 * Mp) {
+      const int r = i / Mp;
+      B = r < 2 ? r : M - 1 + r;
+      C = i - r * Mp;
+    } else {
+      const int j = i - 4 * Mp, c = j & 3;
+      B = 2 + (j >> 2);
+      C = c < 2 ? c : M - 1 + c;
+    }
+    return B * Mp + C;
+  };
+  double bval[kPerThread];
+  if constexpr (!ADJ) {
+#pragma unroll
+    for (int q = 0; q < kPerThread; ++q) {
+      const int i = q * kBlock + threadIdx.x;
+      bval[q] = i < kBorder ? bc[(int64_t)A * Mp * Mp + border_offset(i)] : 0.0;
+    }
+  }
 #pragma unroll 8
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) plane[e] = a.work[base + e];
+  if constexpr (!ADJ) {
+#pragma unroll
+    for (int q = 0; q < kPerThread; ++q) {
+      const int i = q * kBlock + threadIdx.x;
+      if (i < kBorder) border[i] = (T)(D1 * bval[q]);
+    }
+  }
   __syncthreads();
   plane_dst<R, T>(plane, tw);
-  const int A = x + 2;
   if constexpr (ADJ) {
     // lam_rho = lam_delta'; lam_bc0 -= D1 C^T lam_delta' (each face node has exactly one
     // interior neighbour, so plain updates do not collide); the plane of `work` is cleared
@@ -549,14 +591,12 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p3(MeshArgs<T> a, BlockMap m
     }
     return;
   }
-  for (int e = threadIdx.x; e < Mp * Mp; e += blockDim.x) {
-    const int B = e / Mp, C = e - (e / Mp) * Mp;
-    const int64_t o = (int64_t)A * Mp * Mp + e;
-    if (B >= 2 && B <= M && C >= 2 && C <= M)
-      phi[o] = plane[(B - 2) * n + (C - 2)];
-    else
-      phi[o] = (T)(D1 * bc[o]);
+  T* out = phi + (int64_t)A * Mp * Mp;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int y = e / n, z = e - (e / n) * n;
+    out[(y + 2) * Mp + z + 2] = plane[e];
   }
+  for (int i = threadIdx.x; i < kBorder; i += blockDim.x) out[border_offset(i)] = border[i];
 }
 
 inline unsigned padded_grid(const BlockMap& m) {
@@ -570,7 +610,7 @@ template <typename T>
 size_t poisson_lds_bytes(int M) {
   const int n = M - 1;
   const size_t tw = 2 * kMaxM * sizeof(cx<T>) + kMaxM * sizeof(T);   // twiddles, eigenvalues
-  const size_t plane = (size_t)n * n * sizeof(T);
+  const size_t plane = (size_t)(M + 3) * (M + 3) * sizeof(T);   // plane and its padded border
   const size_t pencil = (size_t)n * (kPencilChunk + 1) * sizeof(T);
   return tw + (plane > pencil ? plane : pencil);
 }
