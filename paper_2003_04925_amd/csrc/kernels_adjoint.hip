@@ -360,13 +360,18 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(AdjointArgs<T> a, Bloc
   int idx[3];
   brick_site(pl, M, idx[0], idx[1], idx[2]);
   double s1[3], s2[3], acc1[3], acc2[3];
-  T lx[3], lp[3];
+  T lx[3], lp[3], xsc[3], lq1[3], lq2[3];
+  // every particle stream of the pass is loaded up front, so the block waits on global
+  // memory once before its windows are staged
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     s1[c] = a.psi1[c * P + p];
     s2[c] = a.psi2[c * P + p];
     lx[c] = a.lam_x[c * P + p];
     lp[c] = a.lam_p[c * P + p];
+    if (SCATTER) xsc[c] = a.xs[c * P + p];
+    lq1[c] = a.lam_psi1[c * P + p];
+    lq2[c] = a.lam_psi2[c * P + p];
     acc1[c] = acc2[c] = 0.0;
   }
   __shared__ T win[kWindow];
@@ -401,7 +406,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(AdjointArgs<T> a, Bloc
     }
     double x[3], u[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) x[c] = (double)a.xs[c * P + p];
+    for (int c = 0; c < 3; ++c) x[c] = (double)xsc[c];
     lpt_position(s1, s2, idx, a.D1, a.D2, x, u);
     block_adjoint_scatter<T>(a.work + t.g_off, a.lam_bc0 + t.h_off, a.D1, M, u, lg, win, bounds);
   }
@@ -409,8 +414,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(AdjointArgs<T> a, Bloc
   for (int c = 0; c < 3; ++c) {
     if (GATHER) a.lam_x[c * P + p] = lx[c];
     if (SCATTER) a.lam_p[c * P + p] = lp[c];
-    a.lam_psi1[c * P + p] += (T)acc1[c];
-    a.lam_psi2[c * P + p] += (T)acc2[c];
+    a.lam_psi1[c * P + p] = lq1[c] + (T)acc1[c];
+    a.lam_psi2[c * P + p] = lq2[c] + (T)acc2[c];
   }
 }
 
