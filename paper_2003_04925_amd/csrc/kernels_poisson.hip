@@ -561,6 +561,28 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p3(MeshArgs<T> a, BlockMap m
       bval[q] = i < kBorder ? bc[(int64_t)A * Mp * Mp + border_offset(i)] : 0.0;
     }
   }
+  // adjoint: lam_bc0 -= D1 C^T lam_delta' on the face layer.  Each face node has exactly
+  // one interior neighbour, so plain updates do not collide.  On an interior x plane only
+  // the perimeter touches a face (one element per thread): the old values of its face nodes
+  // are fetched here, so that their latency overlaps the load of the plane.
+  double* lb = a.lam_bc0 + t.h_off;
+  const bool xface = x == 0 || x == n - 1;
+  int pe = -1, iy = -1, iz = -1;   // indices into the box's padded grid (< 2^31)
+  double oy = 0.0, oz = 0.0;
+  if constexpr (ADJ) {
+    if (!xface && (int)threadIdx.x < 4 * (n - 1)) {
+      const int i = threadIdx.x, side = i / (n - 1), o = i - side * (n - 1);
+      const int y = side == 0 ? 0 : side == 1 ? o : side == 2 ? n - 1 : n - 1 - o;
+      const int z = side == 0 ? o : side == 1 ? n - 1 : side == 2 ? n - 1 - o : 0;
+      pe = y * n + z;
+      if (y == 0) iy = ((x + 2) * Mp + 1) * Mp + z + 2;
+      if (y == n - 1) iy = ((x + 2) * Mp + M + 1) * Mp + z + 2;
+      if (z == 0) iz = ((x + 2) * Mp + y + 2) * Mp + 1;
+      if (z == n - 1) iz = ((x + 2) * Mp + y + 2) * Mp + M + 1;
+      if (iy >= 0) oy = lb[iy];
+      if (iz >= 0) oz = lb[iz];
+    }
+  }
 #pragma unroll 8
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) plane[e] = a.work[base + e];
   if constexpr (!ADJ) {
@@ -573,21 +595,40 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p3(MeshArgs<T> a, BlockMap m
   __syncthreads();
   plane_dst<R, T>(plane, tw);
   if constexpr (ADJ) {
-    // lam_rho = lam_delta'; lam_bc0 -= D1 C^T lam_delta' (each face node has exactly one
-    // interior neighbour, so plain updates do not collide); the plane of `work` is cleared
-    double* lb = a.lam_bc0 + t.h_off;
+    // lam_rho = lam_delta', and the plane of `work` is cleared (the next reverse step
+    // accumulates into a zeroed source)
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-      const T v = plane[e];
-      a.lam_rho[base + e] = v;
-      a.work[base + e] = T(0);   // the next reverse step accumulates into a zeroed source
-      const int y = e / n, z = e - (e / n) * n;
-      const double d = -D1 * (double)v;
-      if (x == 0) lb[((int64_t)1 * Mp + y + 2) * Mp + z + 2] += d;
-      if (x == n - 1) lb[((int64_t)(M + 1) * Mp + y + 2) * Mp + z + 2] += d;
-      if (y == 0) lb[((int64_t)(x + 2) * Mp + 1) * Mp + z + 2] += d;
-      if (y == n - 1) lb[((int64_t)(x + 2) * Mp + M + 1) * Mp + z + 2] += d;
-      if (z == 0) lb[((int64_t)(x + 2) * Mp + y + 2) * Mp + 1] += d;
-      if (z == n - 1) lb[((int64_t)(x + 2) * Mp + y + 2) * Mp + M + 1] += d;
+      a.lam_rho[base + e] = plane[e];
+      a.work[base + e] = T(0);
+    }
+    if (xface) {
+      for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int y = e / n, z = e - (e / n) * n;
+        const double d = -D1 * (double)plane[e];
+        if (x == 0) lb[((int64_t)1 * Mp + y + 2) * Mp + z + 2] += d;
+        if (x == n - 1) lb[((int64_t)(M + 1) * Mp + y + 2) * Mp + z + 2] += d;
+        if (y == 0) lb[((int64_t)(x + 2) * Mp + 1) * Mp + z + 2] += d;
+        if (y == n - 1) lb[((int64_t)(x + 2) * Mp + M + 1) * Mp + z + 2] += d;
+        if (z == 0) lb[((int64_t)(x + 2) * Mp + y + 2) * Mp + 1] += d;
+        if (z == n - 1) lb[((int64_t)(x + 2) * Mp + y + 2) * Mp + M + 1] += d;
+      }
+    } else {
+      // perimeter elements beyond the first blockDim.x (planes wider than the block)
+      for (int i = threadIdx.x + blockDim.x; i < 4 * (n - 1); i += blockDim.x) {
+        const int side = i / (n - 1), o = i - side * (n - 1);
+        const int y = side == 0 ? 0 : side == 1 ? o : side == 2 ? n - 1 : n - 1 - o;
+        const int z = side == 0 ? o : side == 1 ? n - 1 : side == 2 ? n - 1 - o : 0;
+        const double d = -D1 * (double)plane[y * n + z];
+        if (y == 0) lb[((int64_t)(x + 2) * Mp + 1) * Mp + z + 2] += d;
+        if (y == n - 1) lb[((int64_t)(x + 2) * Mp + M + 1) * Mp + z + 2] += d;
+        if (z == 0) lb[((int64_t)(x + 2) * Mp + y + 2) * Mp + 1] += d;
+        if (z == n - 1) lb[((int64_t)(x + 2) * Mp + y + 2) * Mp + M + 1] += d;
+      }
+      if (pe >= 0) {
+        const double d = -D1 * (double)plane[pe];
+        if (iy >= 0) lb[iy] = oy + d;
+        if (iz >= 0) lb[iz] = oz + d;
+      }
     }
     return;
   }
