@@ -222,7 +222,7 @@ def main():
                          "1 GiB device copy that calibrates the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the boxes are independent and this build has "
+        print("bench.py runs on one GPU only: the boxes are independent and the library has "
               "no multi-GPU path (see the design notes for how it would shard).",
               file=sys.stderr)
         sys.exit(2)

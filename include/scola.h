@@ -44,7 +44,7 @@ typedef enum {
   SCOLA_ENOMEM = -2,       /* host or plan-owned device allocation failed */
   SCOLA_EDEVICE = -3,      /* a HIP call failed (launch, copy, event) */
   SCOLA_ESTATE = -4,       /* call order violated (e.g. evolve before setup) */
-  SCOLA_EUNSUPPORTED = -5  /* valid request outside what this build implements */
+  SCOLA_EUNSUPPORTED = -5  /* valid request outside what the library implements */
 } scola_status;
 
 enum { SCOLA_FP32 = 0, SCOLA_FP64 = 1 };           /* particle/mesh arithmetic */
