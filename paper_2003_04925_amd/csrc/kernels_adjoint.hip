@@ -376,7 +376,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(AdjointArgs<T> a, Bloc
   }
   __shared__ T win[kWindow];
   __shared__ T win2[GATHER ? kWindow : 1];   // lam_rho window of the gather half
-  __shared__ int bounds[8];
+  __shared__ int bounds[kCellScratch];
   if constexpr (GATHER) {
     double x[3], u[3];
 #pragma unroll

@@ -50,19 +50,29 @@ __device__ inline void fixed_weights(double fx, double fy, double fz, long long 
   for (int c = 0; c < 8; ++c) w[c] += c == cl ? adj : 0ll;
 }
 
+// Integer type of one particle's fixed-point corner weights: 64-bit for the 2^40 units of
+// FP64 plans, 32-bit for the 2^21 units of FP32 plans.
 template <typename T>
-__device__ inline void mesh_weights(double fx, double fy, double fz, long long (&w)[8]) {
+using WeightT = typename std::conditional<MeshFixed<T>::bits == 40, long long, int>::type;
+
+template <typename T>
+__device__ inline void mesh_weights(double fx, double fy, double fz, WeightT<T> (&w)[8]) {
   if constexpr (MeshFixed<T>::bits == 40) {
     fixed_weights(fx, fy, fz, w);
   } else {
+    // the unit scale rides on the x factor; weights are non-negative, so adding one half
+    // before truncation rounds them to the nearest unit
     const float one = (float)(1 << MeshFixed<T>::bits);
-    const float ax[2] = {1.0f - (float)fx, (float)fx}, ay[2] = {1.0f - (float)fy, (float)fy},
-                az[2] = {1.0f - (float)fz, (float)fz};
+    const float ax[2] = {(1.0f - (float)fx) * one, (float)fx * one};
+    const float ay[2] = {1.0f - (float)fy, (float)fy}, az[2] = {1.0f - (float)fz, (float)fz};
+    float ayz[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ayz[q] = ay[q >> 1] * az[q & 1];
     int sum = 0;
     int v[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      v[c] = __float2int_rn(ax[(c >> 2) & 1] * ay[(c >> 1) & 1] * az[c & 1] * one);
+      v[c] = (int)fmaf(ax[(c >> 2) & 1], ayz[c & 3], 0.5f);
       sum += v[c];
     }
     const int adj = (1 << MeshFixed<T>::bits) - sum;
@@ -106,7 +116,7 @@ __device__ __forceinline__ long long deposit_block(typename MeshFixed<T>::rho_t*
   int j0[3] = {0, 0, 0};
   double f[3] = {0, 0, 0};
   const bool in = active && deposit_footprint(M, ux, uy, uz, j0, f);
-  long long w[8];
+  WeightT<T> w[8];
   if (in) mesh_weights<T>(f[0], f[1], f[2], w);
   // which of the two corner planes along each axis are interior nodes
   bool inner[3][2];
@@ -115,13 +125,13 @@ __device__ __forceinline__ long long deposit_block(typename MeshFixed<T>::rho_t*
     inner[c][0] = j0[c] >= 1 && j0[c] <= n;
     inner[c][1] = j0[c] >= 0 && j0[c] <= n - 1;
   }
-  long long kept = 0;
+  WeightT<T> kept = 0;
   if (in) {
 #pragma unroll
     for (int c = 0; c < 8; ++c)
       if (inner[0][(c >> 2) & 1] && inner[1][(c >> 1) & 1] && inner[2][c & 1]) kept += w[c];
   }
-  const long long dropped = active ? (1ll << MeshFixed<T>::bits) - kept : 0;
+  const long long dropped = active ? (1ll << MeshFixed<T>::bits) - (long long)kept : 0;
   const CellRange cr = block_cells(in, j0, bounds);
   if (!cr.any) return dropped;
   // the corners of the block's particles span [min j0, max j0 + 1] per axis
@@ -392,7 +402,7 @@ k_particles(ParticleArgs<T> a, BlockMap m) {
   // one LDS window, first for the potential (kWindow T values), then for the block's mass
   // (kWindow fixed-point accumulators)
   __shared__ unsigned long long win[kWindow * sizeof(T) / 8];
-  __shared__ int bounds[6];
+  __shared__ int bounds[kCellScratch];
   if (MODE != kDepositOnly && MODE != kInit) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) pr[c] = a.pres[c * P + p];

@@ -67,88 +67,10 @@ __device__ __forceinline__ unsigned wave_min_u16x2(unsigned v) {
                     pk_min_u16(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
-// Block-wide bounding box of per-thread integer ranges [lo, hi] (3 axes, values in
-// [-16383, 16383]); threads with any == false do not count.  The six extrema are reduced
-// as three packed pairs of 16-bit minima: lo + 2^14 and 2^14 - hi (0xffff marks "none").
-// Must be called by all threads of the block.
-__device__ inline void block_bounds(bool any, const int (&lo)[3], const int (&hi)[3],
-                                    int* bounds) {
-  constexpr int kOff = 1 << 14;
-  if (threadIdx.x < 6) bounds[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -0x7fffffff;
-  __syncthreads();
-  const unsigned none = 0xffffffffu;
-  const unsigned p0 = any ? (unsigned)(lo[0] + kOff) | ((unsigned)(lo[1] + kOff) << 16) : none;
-  const unsigned p1 = any ? (unsigned)(lo[2] + kOff) | ((unsigned)(kOff - hi[0]) << 16) : none;
-  const unsigned p2 = any ? (unsigned)(kOff - hi[1]) | ((unsigned)(kOff - hi[2]) << 16) : none;
-  const unsigned r0 = wave_min_u16x2(p0), r1 = wave_min_u16x2(p1), r2 = wave_min_u16x2(p2);
-  if ((threadIdx.x & 63) == 0 && (r0 & 0xffffu) != 0xffffu) {   // the wave has a range
-    atomicMin(bounds + 0, (int)(r0 & 0xffffu) - kOff);
-    atomicMin(bounds + 1, (int)(r0 >> 16) - kOff);
-    atomicMin(bounds + 2, (int)(r1 & 0xffffu) - kOff);
-    atomicMax(bounds + 3, kOff - (int)(r1 >> 16));
-    atomicMax(bounds + 4, kOff - (int)(r2 & 0xffffu));
-    atomicMax(bounds + 5, kOff - (int)(r2 >> 16));
-  }
-  __syncthreads();
-}
-
-// block_bounds plus the block-wide maximum of one int per thread, left in bounds[6] (the
-// caller's array holds at least 7 entries).  Must be called by all threads of the block.
-__device__ inline void block_bounds_max(bool any, const int (&lo)[3], const int (&hi)[3], int v,
-                                        int* bounds) {
-  if (threadIdx.x < 7) bounds[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -0x7fffffff;
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const int a = wave_min(any ? lo[c] : 0x7fffffff);
-    const int b = wave_max(any ? hi[c] : -0x7fffffff);
-    if ((threadIdx.x & 63) == 0) {
-      atomicMin(bounds + c, a);
-      atomicMax(bounds + 3 + c, b);
-    }
-  }
-  const int m = wave_max(v);
-  if ((threadIdx.x & 63) == 0) atomicMax(bounds + 6, m);
-  __syncthreads();
-}
-
-// The LDS window of a block from the bounds left by block_bounds: nodes [l, l + w) per
-// axis.  A block in which no thread contributed keeps the sentinels (lo > hi) and gets an
-// empty window; the widths are formed only for a non-empty window, where they are at most
-// M + 3, so the arithmetic cannot overflow.
-struct BlockWindow {
-  int lx, ly, lz, wx, wy, wz, vol;
-  bool lds;   // fits in kWindow entries
-};
-
-__device__ inline BlockWindow block_window(const int* bounds) {
-  BlockWindow w;
-  w.lx = bounds[0];
-  w.ly = bounds[1];
-  w.lz = bounds[2];
-  const bool empty = bounds[0] > bounds[3] || bounds[1] > bounds[4] || bounds[2] > bounds[5];
-  w.wx = empty ? 0 : bounds[3] - bounds[0] + 1;
-  w.wy = empty ? 0 : bounds[4] - bounds[1] + 1;
-  w.wz = empty ? 0 : bounds[5] - bounds[2] + 1;
-  w.vol = w.wx * w.wy * w.wz;
-  w.lds = !empty && w.vol <= kWindow;
-  return w;
-}
-
 // Row-major index (a * nb + b) * nc + c of a 3-D array with fewer than 2^24 entries and
 // non-negative coordinates, with full-rate 24-bit multiplies.
 __device__ __forceinline__ unsigned idx3(int a, int b, int c, int nb, int nc) {
   return __umul24(__umul24((unsigned)a, (unsigned)nb) + (unsigned)b, (unsigned)nc) + (unsigned)c;
-}
-
-// Row-major decomposition e -> (ex, ey, ez) of a window with rows wy x wz, using FP32
-// reciprocals (exact for windows far below 2^20 entries) instead of integer division.
-__device__ inline void window_coords(int e, int wz, int wyz, float inv_wz, float inv_wyz,
-                                     int& ex, int& ey, int& ez) {
-  ex = (int)(((float)e + 0.5f) * inv_wyz);
-  const int r = e - ex * wyz;
-  ey = (int)(((float)r + 0.5f) * inv_wz);
-  ez = r - ey * wz;
 }
 
 // LDS windows of a block.  The fast form has a fixed geometry of kFw^3 nodes with
@@ -172,39 +94,77 @@ static_assert(kFw * kFw == kBlock, "one window column per thread");
 
 // Block-wide extent of the cells j0 of the particles with in == true: lo (minima) and hi
 // (maxima) per axis, as wave-uniform scalars; any is false when no particle of the block is
-// in.  Must be called by all threads of the block.
+// in.  The six extrema travel as three packed pairs of 16-bit minima, j0 + 2^14 and
+// 2^14 - j0 (cells lie in [-16383, 16383]; 0xffff marks "none"): each wave reduces its
+// lanes with DPP exchanges and stores its three words in its own slot of `scratch`, and
+// after one barrier every thread combines the slots of all waves.  No LDS atomics and no
+// initialisation pass are needed.  Must be called by all threads of the block; `scratch`
+// holds kCellScratch ints, and its previous contents must have been read before a barrier
+// that precedes this call.
+constexpr int kWaves = kBlock / 64;
+constexpr int kCellScratch = 4 * kWaves;
+
 struct CellRange {
   int lo[3], hi[3];
   bool any;
 };
 
-__device__ __forceinline__ CellRange block_cells(bool in, const int (&j0)[3], int* bounds) {
-  block_bounds(in, j0, j0, bounds);
-  CellRange r;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    r.lo[a] = __builtin_amdgcn_readfirstlane(bounds[a]);
-    r.hi[a] = __builtin_amdgcn_readfirstlane(bounds[3 + a]);
+__device__ __forceinline__ void cells_to_slots(bool in, const int (&j0)[3], unsigned* s) {
+  constexpr int kOff = 1 << 14;
+  const unsigned none = 0xffffffffu;
+  const unsigned p0 = in ? (unsigned)(j0[0] + kOff) | ((unsigned)(j0[1] + kOff) << 16) : none;
+  const unsigned p1 = in ? (unsigned)(j0[2] + kOff) | ((unsigned)(kOff - j0[0]) << 16) : none;
+  const unsigned p2 = in ? (unsigned)(kOff - j0[1]) | ((unsigned)(kOff - j0[2]) << 16) : none;
+  const unsigned r0 = wave_min_u16x2(p0), r1 = wave_min_u16x2(p1), r2 = wave_min_u16x2(p2);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s[wv] = r0;
+    s[kWaves + wv] = r1;
+    s[2 * kWaves + wv] = r2;
   }
+}
+
+__device__ __forceinline__ CellRange cells_from_slots(const unsigned* s) {
+  constexpr int kOff = 1 << 14;
+  unsigned q[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    unsigned m = s[i * kWaves];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) m = pk_min_u16(m, s[i * kWaves + w]);
+    q[i] = __builtin_amdgcn_readfirstlane(m);
+  }
+  CellRange r;
+  r.lo[0] = (int)(q[0] & 0xffffu) - kOff;
+  r.lo[1] = (int)(q[0] >> 16) - kOff;
+  r.lo[2] = (int)(q[1] & 0xffffu) - kOff;
+  r.hi[0] = kOff - (int)(q[1] >> 16);
+  r.hi[1] = kOff - (int)(q[2] & 0xffffu);
+  r.hi[2] = kOff - (int)(q[2] >> 16);
   r.any = r.lo[0] <= r.hi[0] && r.lo[1] <= r.hi[1] && r.lo[2] <= r.hi[2];
   return r;
 }
 
+__device__ __forceinline__ CellRange block_cells(bool in, const int (&j0)[3], int* scratch) {
+  unsigned* s = reinterpret_cast<unsigned*>(scratch);
+  cells_to_slots(in, j0, s);
+  __syncthreads();
+  return cells_from_slots(s);
+}
 
-// Block-wide extent of the cells j0 (as block_cells) and the block-wide maximum of one int
-// per thread (v), all wave-uniform.  Must be called by all threads of the block.
+// block_cells and the block-wide maximum of one int per thread (v), wave-uniform.
 __device__ __forceinline__ CellRange block_cells_max(bool in, const int (&j0)[3], int v,
-                                                     int* bounds, int& vmax) {
-  block_bounds_max(in, j0, j0, v, bounds);
-  CellRange r;
+                                                     int* scratch, int& vmax) {
+  unsigned* s = reinterpret_cast<unsigned*>(scratch);
+  cells_to_slots(in, j0, s);
+  const int m = wave_max(v);
+  if ((threadIdx.x & 63) == 0) scratch[3 * kWaves + (threadIdx.x >> 6)] = m;
+  __syncthreads();
+  int mm = scratch[3 * kWaves];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    r.lo[a] = __builtin_amdgcn_readfirstlane(bounds[a]);
-    r.hi[a] = __builtin_amdgcn_readfirstlane(bounds[3 + a]);
-  }
-  vmax = __builtin_amdgcn_readfirstlane(bounds[6]);
-  r.any = r.lo[0] <= r.hi[0] && r.lo[1] <= r.hi[1] && r.lo[2] <= r.hi[2];
-  return r;
+  for (int w = 1; w < kWaves; ++w) mm = max(mm, scratch[3 * kWaves + w]);
+  vmax = __builtin_amdgcn_readfirstlane(mm);
+  return cells_from_slots(s);
 }
 
 }  // namespace
