@@ -99,6 +99,11 @@ typedef struct {
                               of node visits by the Poisson pass that found >= 2^31 units on
                               an FP32-plan node (1024 particles, within a factor 2 of the
                               32-bit range).  scola_evolve and scola_op_deposit reset all. */
+  size_t cells;            /* uint32 [P / 256][4]: per brick of 256 particles (lattice order
+                              within a box), the block cell extent of its last deposit, packed;
+                              the force pass of the next step tries it before reducing the
+                              extent itself.  Any content is valid: a stale entry costs time
+                              and changes no result. */
   size_t phi1, phi2;       /* double [N^3]: Lagrangian potentials (Sec. 3.1, A.2) */
   size_t cbuf;             /* double2 [N^3]: FFT scratch */
   size_t outgrid;          /* int64 [N_out^3]: fixed-point output density */

@@ -166,6 +166,8 @@ class Simulation:
             "bc0": (t.float64, (H,)),
             # per tile, then the FP32 mass alarm (nodes that held >= 2^31 units)
             "dropped": (t.int64, (len(self.tiles) + 1,)),
+            # per brick of 256 particles: packed cell extent of its last deposit
+            "cells": (t.int32, (P // 256, 4)),
             "phi1": (t.float64, (N, N, N)), "phi2": (t.float64, (N, N, N)),
             "outgrid": (t.int64, (self.N_out,) * 3),
         }[name]

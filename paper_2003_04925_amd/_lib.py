@@ -46,7 +46,7 @@ class Config(ctypes.Structure):
 class Layout(ctypes.Structure):
     _fields_ = [(n, ctypes.c_size_t) for n in
                 ("psi1", "psi2", "x_res", "p_res", "rho", "work", "phi", "bc0", "dropped",
-                 "phi1", "phi2", "cbuf", "outgrid", "ckpt", "seg_x", "seg_phi", "lam_x",
+                 "cells", "phi1", "phi2", "cbuf", "outgrid", "ckpt", "seg_x", "seg_phi", "lam_x",
                  "lam_p", "lam_psi1", "lam_psi2", "lam_rho", "lam_bc0", "adj_grid",
                  "total")] + \
                [("n_particles", ctypes.c_int64), ("n_nodes", ctypes.c_int64),

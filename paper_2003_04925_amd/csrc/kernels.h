@@ -71,6 +71,11 @@ struct ParticleArgs {
   const T* phi;
   typename MeshFixed<T>::rho_t* rho;
   unsigned long long* dropped;
+  // per brick of 256 particles: the packed cell extent of its last deposit, written by
+  // every depositing launch and, with use_hints, tried by the force pass before it
+  // reduces the extent itself (a stale entry costs time, never a result)
+  uint4* cells;
+  int use_hints;
   int64_t P;
   StepScalars sc;
 };

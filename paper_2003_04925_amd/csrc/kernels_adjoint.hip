@@ -32,7 +32,7 @@ __device__ inline int wrapn(int i, int n) {
 __device__ inline void lpt_position(const double (&s1)[3], const double (&s2)[3], const int (&idx)[3],
                                     double D1, double D2, const double (&x)[3], double (&u)[3]) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) u[c] = idx[c] + 0.5 - D1 * s1[c] + D2 * s2[c] + x[c];
+  for (int c = 0; c < 3; ++c) u[c] = lpt_base(idx[c] + 0.5, D1, s1[c], D2, s2[c]) + x[c];
 }
 
 // Cell and CiC weights of the interpolation at u (corners outside [0, M]^3 weigh nothing);

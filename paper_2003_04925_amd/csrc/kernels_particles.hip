@@ -105,11 +105,13 @@ __device__ inline bool deposit_footprint(int M, double ux, double uy, double uz,
 // block's Eulerian footprint, then one global atomic per touched interior node.  Integer
 // sums make every window form give identical results.  Returns the fixed-point mass this
 // thread dropped (the eight weights sum to exactly one unit, so dropped = unit - kept).
-// Must be called by all threads of the block.
+// When hint_out is not null, the block's packed cell extent is stored there for the force
+// pass at the same positions.  Must be called by all threads of the block.
 template <typename T>
 __device__ __forceinline__ long long deposit_block(typename MeshFixed<T>::rho_t* __restrict__ rho, int M,
                                           bool active, double ux, double uy, double uz,
-                                          typename MeshFixed<T>::window_t* win, int* bounds) {
+                                          typename MeshFixed<T>::window_t* win, int* bounds,
+                                          uint4* hint_out) {
   using W = typename MeshFixed<T>::window_t;
   using Rho = typename MeshFixed<T>::rho_t;
   const int n = M - 1;
@@ -132,7 +134,9 @@ __device__ __forceinline__ long long deposit_block(typename MeshFixed<T>::rho_t*
       if (inner[0][(c >> 2) & 1] && inner[1][(c >> 1) & 1] && inner[2][c & 1]) kept += w[c];
   }
   const long long dropped = active ? (1ll << MeshFixed<T>::bits) - (long long)kept : 0;
-  const CellRange cr = block_cells(in, j0, bounds);
+  unsigned q[3];
+  const CellRange cr = block_cells(in, j0, bounds, q);
+  if (hint_out != nullptr && threadIdx.x == 0) *hint_out = make_uint4(q[0], q[1], q[2], 0u);
   if (!cr.any) return dropped;
   // the corners of the block's particles span [min j0, max j0 + 1] per axis
   const int ox = cr.lo[0], oy = cr.lo[1], oz = cr.lo[2];
@@ -278,10 +282,16 @@ __device__ __forceinline__ void gather_force_rolled(int M, const int (&j0)[3], c
 // Force at u for the 256 particles of a block: the potential nodes the block's stencils
 // touch are staged once in LDS (each thread loads window columns along x) and gathered
 // from there; a block whose footprint exceeds the sized window gathers from global
-// memory.  Must be called by all threads of the block.
+// memory.  The window is placed from the block's cell extent.  With `hinted`, the packed
+// extent hq kept by the deposit of the same positions is checked (every particle's cell
+// inside it, one vote per wave) and used in place of the reduction; a stale hint fails
+// the check and the block reduces its extent as usual.  Any window that covers every
+// stencil gives the same force, so the hint changes no result.  Must be called by all
+// threads of the block.
 template <typename T>
 __device__ __forceinline__ void block_force(const T* __restrict__ phi, int M, double ux, double uy,
-                                   double uz, T* win, int* bounds, T (&g)[3]) {
+                                   double uz, T* win, int* bounds, bool hinted,
+                                   const unsigned (&hq)[3], T (&g)[3]) {
   g[0] = g[1] = g[2] = T(0);
   const double hiu = (double)M + 1.0;
   const bool in = ux >= -1.0 && ux < hiu && uy >= -1.0 && uy < hiu && uz >= -1.0 && uz < hiu;
@@ -297,7 +307,14 @@ __device__ __forceinline__ void block_force(const T* __restrict__ phi, int M, do
     }
   }
   const int Mp = M + 3, Mp2 = Mp * Mp;
-  const CellRange cr = block_cells(in, j0, bounds);
+  CellRange cr = cells_decode(hq);
+  bool held = false;
+  if (hinted) {
+    hint_to_slots(in, j0, cr, bounds);
+    __syncthreads();
+    held = hint_holds(bounds);
+  }
+  if (!held) cr = block_cells(in, j0, bounds);
   if (cr.any) {
     // the stencils of the block's particles span [min j0 - 1, max j0 + 2] per axis
     const int ox = cr.lo[0] - 1, oy = cr.lo[1] - 1, oz = cr.lo[2] - 1;
@@ -376,6 +393,11 @@ k_particles(ParticleArgs<T> a, BlockMap m) {
   const int64_t pl = (int64_t)m.local[b] * kBlock + threadIdx.x;   // one brick per block
   const int64_t p = t.p_off + pl;
   const int64_t P = a.P;
+  // the block's cell extent as the previous deposit of these positions left it
+  uint4* const hint = a.cells + (t.p_off / kBlock + m.local[b]);
+  constexpr bool kForce = MODE != kDepositOnly && MODE != kInit;
+  uint4 h = make_uint4(0u, 0u, 0u, 0u);
+  if (kForce && a.use_hints) h = *hint;
   int i, j, k;
   brick_site(pl, M, i, j, k);
   const double q[3] = {i + 0.5, j + 0.5, k + 0.5};
@@ -398,12 +420,12 @@ k_particles(ParticleArgs<T> a, BlockMap m) {
   const StepScalars sc = a.sc;
   double u[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) u[c] = q[c] - sc.D1 * s1[c] + sc.D2 * s2[c] + (double)xr[c];
+  for (int c = 0; c < 3; ++c) u[c] = lpt_base(q[c], sc.D1, s1[c], sc.D2, s2[c]) + (double)xr[c];
   // one LDS window, first for the potential (kWindow T values), then for the block's mass
   // (kWindow fixed-point accumulators)
   __shared__ unsigned long long win[kWindow * sizeof(T) / 8];
   __shared__ int bounds[kCellScratch];
-  if (MODE != kDepositOnly && MODE != kInit) {
+  if (kForce) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) pr[c] = a.pres[c * P + p];
     // the LPT terms of the kick and of the next position are formed before the force, so
@@ -414,10 +436,17 @@ k_particles(ParticleArgs<T> a, BlockMap m) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       lpt[c] = (T)(sc.D1 * s1[c] - d2 * s2[c]);
-      un[c] = q[c] - sc.D1n * s1[c] + sc.D2n * s2[c];
+      un[c] = lpt_base(q[c], sc.D1n, s1[c], sc.D2n, s2[c]);
+      // formed here: the compiler would otherwise sink them past the force and keep
+      // Psi1, Psi2 and q alive across it
+      asm volatile("" : "+v"(lpt[c]), "+v"(un[c]));
     }
     T g[3];
-    block_force<T>(a.phi + t.h_off, M, u[0], u[1], u[2], reinterpret_cast<T*>(win), bounds, g);
+    const unsigned hq[3] = {(unsigned)__builtin_amdgcn_readfirstlane(h.x),
+                            (unsigned)__builtin_amdgcn_readfirstlane(h.y),
+                            (unsigned)__builtin_amdgcn_readfirstlane(h.z)};
+    block_force<T>(a.phi + t.h_off, M, u[0], u[1], u[2], reinterpret_cast<T*>(win), bounds,
+                   a.use_hints != 0, hq, g);
 #pragma unroll
     for (int c = 0; c < 3; ++c) pr[c] += (T)sc.beta * (g[c] - lpt[c]);
     if (MODE == kFinalKick) {
@@ -439,7 +468,7 @@ k_particles(ParticleArgs<T> a, BlockMap m) {
   if (threadIdx.x == 0) block_drop = 0ull;
   const long long drop = deposit_block<T>(a.rho + t.g_off, M, true, u[0], u[1], u[2],
                                           reinterpret_cast<typename MeshFixed<T>::window_t*>(win),
-                                          bounds);
+                                          bounds, hint);
   if (drop != 0) atomicAdd(&block_drop, (unsigned long long)drop);
   __syncthreads();
   if (threadIdx.x == 0 && block_drop != 0ull) atomicAdd(a.dropped + ti, block_drop);
@@ -486,7 +515,7 @@ __global__ void __launch_bounds__(kBlock) k_output(OutputArgs<T> a, BlockMap m, 
   double ug[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double u = idx[c] + 0.5 - a.D1 * a.psi1[c * P + p] + a.D2 * a.psi2[c * P + p] +
+    const double u = lpt_base(idx[c] + 0.5, a.D1, a.psi1[c * P + p], a.D2, a.psi2[c * P + p]) +
                      (double)a.xres[c * P + p];
     ug[c] = t.origin[c] + u;
     if (a.pos) {

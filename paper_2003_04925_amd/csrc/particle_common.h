@@ -67,6 +67,14 @@ __device__ __forceinline__ unsigned wave_min_u16x2(unsigned v) {
                     pk_min_u16(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
+// LPT part of a particle's FP64 box coordinate (App. B): q - D1 Psi1 + D2 Psi2 for the
+// lattice coordinate q; the residual displacement is added to the result.  The two fused
+// multiply-adds are written out, so every kernel that forms the position of a particle at
+// the same growth factors gets the same bits, and hence the same cell.
+__device__ __forceinline__ double lpt_base(double q, double D1, double s1, double D2, double s2) {
+  return fma(D2, s2, fma(-D1, s1, q));
+}
+
 // Row-major index (a * nb + b) * nc + c of a 3-D array with fewer than 2^24 entries and
 // non-negative coordinates, with full-rate 24-bit multiplies.
 __device__ __forceinline__ unsigned idx3(int a, int b, int c, int nb, int nc) {
@@ -124,16 +132,10 @@ __device__ __forceinline__ void cells_to_slots(bool in, const int (&j0)[3], unsi
   }
 }
 
-__device__ __forceinline__ CellRange cells_from_slots(const unsigned* s) {
+// Decodes the three packed words of cells_to_slots (after the block-wide minimum) into a
+// CellRange; words 0xffffffff (no particle) give any == false.
+__device__ __forceinline__ CellRange cells_decode(const unsigned (&q)[3]) {
   constexpr int kOff = 1 << 14;
-  unsigned q[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    unsigned m = s[i * kWaves];
-#pragma unroll
-    for (int w = 1; w < kWaves; ++w) m = pk_min_u16(m, s[i * kWaves + w]);
-    q[i] = __builtin_amdgcn_readfirstlane(m);
-  }
   CellRange r;
   r.lo[0] = (int)(q[0] & 0xffffu) - kOff;
   r.lo[1] = (int)(q[0] >> 16) - kOff;
@@ -145,11 +147,48 @@ __device__ __forceinline__ CellRange cells_from_slots(const unsigned* s) {
   return r;
 }
 
-__device__ __forceinline__ CellRange block_cells(bool in, const int (&j0)[3], int* scratch) {
+// Block-wide packed words from the wave slots, uniform across the block.
+__device__ __forceinline__ void cells_from_slots(const unsigned* s, unsigned (&q)[3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    unsigned m = s[i * kWaves];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) m = pk_min_u16(m, s[i * kWaves + w]);
+    q[i] = __builtin_amdgcn_readfirstlane(m);
+  }
+}
+
+// q receives the packed words of the extent, the form in which it is kept between launches.
+__device__ __forceinline__ CellRange block_cells(bool in, const int (&j0)[3], int* scratch,
+                                                 unsigned (&q)[3]) {
   unsigned* s = reinterpret_cast<unsigned*>(scratch);
   cells_to_slots(in, j0, s);
   __syncthreads();
-  return cells_from_slots(s);
+  cells_from_slots(s, q);
+  return cells_decode(q);
+}
+
+__device__ __forceinline__ CellRange block_cells(bool in, const int (&j0)[3], int* scratch) {
+  unsigned q[3];
+  return block_cells(in, j0, scratch, q);
+}
+
+// A block extent kept from an earlier launch and used in place of block_cells: each wave
+// stores in slot 3 kWaves + wave whether every in-particle of the wave has its cell inside
+// `cr`; after a barrier, hint_holds() tells every thread whether all waves agreed.
+__device__ __forceinline__ void hint_to_slots(bool in, const int (&j0)[3], const CellRange& cr,
+                                              int* scratch) {
+  const bool ok = !in || (j0[0] >= cr.lo[0] && j0[0] <= cr.hi[0] && j0[1] >= cr.lo[1] &&
+                          j0[1] <= cr.hi[1] && j0[2] >= cr.lo[2] && j0[2] <= cr.hi[2]);
+  const int all = __all(ok);
+  if ((threadIdx.x & 63) == 0) scratch[3 * kWaves + (threadIdx.x >> 6)] = all;
+}
+
+__device__ __forceinline__ bool hint_holds(const int* scratch) {
+  int a = scratch[3 * kWaves];
+#pragma unroll
+  for (int w = 1; w < kWaves; ++w) a &= scratch[3 * kWaves + w];
+  return __builtin_amdgcn_readfirstlane(a) != 0;
 }
 
 // block_cells and the block-wide maximum of one int per thread (v), wave-uniform.
@@ -164,7 +203,9 @@ __device__ __forceinline__ CellRange block_cells_max(bool in, const int (&j0)[3]
 #pragma unroll
   for (int w = 1; w < kWaves; ++w) mm = max(mm, scratch[3 * kWaves + w]);
   vmax = __builtin_amdgcn_readfirstlane(mm);
-  return cells_from_slots(s);
+  unsigned q[3];
+  cells_from_slots(s, q);
+  return cells_decode(q);
 }
 
 }  // namespace

@@ -333,6 +333,7 @@ void build_layout(scola_plan* p) {
   l.phi = take((size_t)p->H * R);
   l.bc0 = take((size_t)p->H * 8);
   l.dropped = take((p->desc.size() + 1) * 8);   // per tile, then the mass alarm
+  l.cells = take((size_t)(p->P / kBlock) * 16);   // per brick: packed cell extent
   l.phi1 = take((size_t)(N * N * N) * 8);
   l.phi2 = take((size_t)(N * N * N) * 8);
   l.cbuf = take((size_t)(N * N * N) * 16);
@@ -425,6 +426,8 @@ ParticleArgs<T> particle_args(scola_plan* p, void* ws, const StepScalars& sc) {
   a.phi = reinterpret_cast<const T*>(ws_ptr(ws, p->lay.phi));
   a.rho = reinterpret_cast<typename MeshFixed<T>::rho_t*>(ws_ptr(ws, p->lay.rho));
   a.dropped = reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped));
+  a.cells = reinterpret_cast<uint4*>(ws_ptr(ws, p->lay.cells));
+  a.use_hints = 1;
   a.P = p->P;
   a.sc = sc;
   return a;
@@ -602,6 +605,10 @@ void do_setup(scola_plan* p, const double* w, void* ws, hipStream_t s) {
             "set-up boxes");
   hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.rho)),
                             (int64_t)(rho_bytes(p) / 8), s), "zero rho");
+  // zero words decode to an extent wider than any window: the first force pass reduces
+  // its own
+  hip_check(launch_zero_u32(reinterpret_cast<unsigned*>(ws_ptr(ws, p->lay.cells)),
+                            (p->P / kBlock) * 4, s), "zero cell hints");
 }
 
 StepScalars row_scalars(const scola_plan* p, int k) {

@@ -315,6 +315,85 @@ def test_one_step_every_window_form(torch, precision):
         np.testing.assert_allclose(got, want, atol=dep_tol(precision))
 
 
+def decode_cells(h):
+    """Packed block cell extents (rows of uint32 words, as int64) -> lo, hi (n, 3): words 0
+    and 1 hold 2^14 + min j0 for x, y, z in 16-bit halves, words 1 (high half) and 2 hold
+    2^14 - max j0."""
+    off = 1 << 14
+    lo = np.stack([(h[:, 0] & 0xffff) - off, (h[:, 0] >> 16) - off, (h[:, 1] & 0xffff) - off], 1)
+    hi = np.stack([off - (h[:, 1] >> 16), off - (h[:, 2] & 0xffff), off - (h[:, 2] >> 16)], 1)
+    return lo, hi
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_cell_hints_exact_and_step_independent_of_them(torch, precision):
+    """Each deposit keeps the cell extent of every block of 256 particles for the force pass
+    of the next step, which checks it against its particles and uses it in place of its own
+    reduction.  The kept extents equal min / max of floor(u) over the block's particles
+    inside [-1, M+1)^3, exactly; and valid, widened (other window origins and forms),
+    narrowed (fails the check), zeroed and random hints give bitwise the same step."""
+    from paper_2003_04925_amd import particle_order
+    say("cell hints", precision)
+    sim = make_sim(torch, precision)
+    sim.setup(torch.from_numpy(synthetic.white_noise(32, 23)).cuda())
+    xr, _ = seeded_state(sim, torch, 24, spread=1.0, pscale=0.5)
+    x0, p0 = sim.view("x_res").clone(), sim.view("p_res").clone()
+    D1, D2, D1n, D2n = 3.0, -4.0, 3.5, -5.3
+    beta, alpha = -0.05, 1.7
+    g1 = sim.view("psi1").cpu().numpy()
+    g2 = sim.view("psi2").cpu().numpy()
+    cells = sim.view("cells")
+    rng = np.random.default_rng(25)
+    names = ("x_res", "p_res", "rho", "dropped", "cells")
+    ref = None
+    for kind in ("valid", "widened", "narrowed", "zero", "random"):
+        sim.view("x_res").copy_(x0)
+        sim.view("p_res").copy_(p0)
+        sim.op_deposit(D1, D2)
+        sim.op_poisson(D1)
+        torch.cuda.synchronize()
+        h = cells.cpu().numpy().astype(np.int64) & 0xffffffff
+        if kind == "valid":
+            lo, hi = decode_cells(h)
+            n_checked = 0
+            for t, (po, M, go, ho) in enumerate(sim.box_slices()):
+                u = box_positions(sim, g1, g2, xr, t, D1, D2)
+                order = particle_order(M)
+                j0 = np.empty((3, M ** 3), dtype=np.int64)
+                j0[:, order] = np.floor(u).astype(np.int64)
+                inside = np.empty(M ** 3, dtype=bool)
+                inside[order] = ((u >= -1) & (u < M + 1)).all(axis=0)
+                j0 = j0.reshape(3, -1, 256)
+                inside = inside.reshape(-1, 256)
+                b0, nb = po // 256, M ** 3 // 256
+                for b in range(nb):
+                    if inside[b].any():
+                        np.testing.assert_array_equal(lo[b0 + b], j0[:, b, inside[b]].min(axis=1))
+                        np.testing.assert_array_equal(hi[b0 + b], j0[:, b, inside[b]].max(axis=1))
+                        n_checked += 1
+                    else:
+                        assert (h[b0 + b, :3] == 0xffffffff).all()
+            say("  extents of", n_checked, "blocks exact")
+        elif kind == "widened":
+            h[:, :3] -= 0x00010001    # lo - 1 and hi + 1 along every axis
+        elif kind == "narrowed":
+            h[:, :3] += 0x00010001    # lo + 1 and hi - 1: some particle falls outside
+        elif kind == "zero":
+            h[:] = 0
+        else:
+            h = rng.integers(0, 1 << 32, size=h.shape, dtype=np.int64)
+        h &= 0xffffffff
+        cells.copy_(torch.from_numpy(h.astype(np.uint32).view(np.int32)))
+        sim.op_step(beta, alpha, D1, D2, D1n, D2n, deposit=True)
+        torch.cuda.synchronize()
+        out = [sim.view(n).cpu().clone() for n in names]
+        if ref is None:
+            ref = out
+        for n, a, b in zip(names, ref, out):
+            assert torch.equal(a, b), (kind, n)
+        say("  hints", kind, "bitwise equal")
+
+
 def test_fp64_run_matches_oracle_end_to_end(torch):
     from oracle.run import run_scola
     from oracle.tiling import uniform_tiling as otiling
