@@ -279,19 +279,56 @@ __device__ __forceinline__ void gather_force_rolled(int M, const int (&j0)[3], c
   g[2] = T(0.5) * gz;
 }
 
+// Direct-to-LDS staging of the fixed potential window placed from a kept extent cr (FP32
+// plans): for each of the window's x planes, every lane of a wave loads the potential at
+// its window column (y, z) = (t / kFw, t % kFw), coordinates clamped into the padded grid,
+// and the load itself writes the value to win[t + kFwX x] (the 64 lanes of a wave fill 64
+// consecutive words, which is the window's layout).  No registers hold the values, so the
+// loads can be issued before the block's particles arrive.  Nodes outside the padded grid
+// (one layer at most) get finite stand-ins that only zero-weight corners read.  Returns
+// false, having issued nothing, for FP64 plans and for extents beyond the fixed window.
+template <typename T>
+__device__ __forceinline__ bool stage_window_direct(const T* __restrict__ phi, int M,
+                                                    const CellRange& cr, T* win) {
+  if constexpr (sizeof(T) != 4) {
+    return false;
+  } else {
+    const int ox = cr.lo[0] - 1, oy = cr.lo[1] - 1, oz = cr.lo[2] - 1;
+    const int ex = cr.hi[0] - ox + 3, ey = cr.hi[1] - oy + 3, ez = cr.hi[2] - oz + 3;
+    if (!(cr.any && ex <= kFw && ey <= kFw && ez <= kFw)) return false;
+    const int Mp = M + 3, Mp2 = Mp * Mp;
+    const int t = threadIdx.x, ty = t / kFw, tz = t % kFw;
+    if (ty < ey && tz < ez) {
+      const int ny = min(max(oy + ty, -1), M + 1), nz = min(max(oz + tz, -1), M + 1);
+      const unsigned gcol = (unsigned)(((ny + 1) * Mp + (nz + 1)) * (int)sizeof(T));
+      T* const wave_base = win + (t & ~63);
+#pragma unroll
+      for (int xi = 0; xi < kFw; ++xi)
+        if (xi < ex) {
+          const int nx = min(max(ox + xi, -1), M + 1);
+          __builtin_amdgcn_global_load_lds(
+              (const void*)byte_offset(phi + (int64_t)(nx + 1) * Mp2, gcol),
+              (__attribute__((address_space(3))) void*)(wave_base + kFwX * xi), 4, 0, 0);
+        }
+    }
+    return true;
+  }
+}
+
 // Force at u for the 256 particles of a block: the potential nodes the block's stencils
 // touch are staged once in LDS (each thread loads window columns along x) and gathered
 // from there; a block whose footprint exceeds the sized window gathers from global
-// memory.  The window is placed from the block's cell extent.  With `hinted`, the packed
-// extent hq kept by the deposit of the same positions is checked (every particle's cell
-// inside it, one vote per wave) and used in place of the reduction; a stale hint fails
-// the check and the block reduces its extent as usual.  Any window that covers every
-// stencil gives the same force, so the hint changes no result.  Must be called by all
-// threads of the block.
+// memory.  The window is placed from the block's cell extent.  With `hinted`, the extent
+// hc kept by the deposit of the same positions is checked (every particle's cell inside
+// it, one vote per wave) and used in place of the reduction; `staged` says that the fixed
+// window placed from hc is already on its way into LDS (stage_window_direct).  A stale
+// hint fails the check, and the block reduces its extent and stages as usual.  Any window
+// that covers every stencil gives the same force, so the hint changes no result.  Must be
+// called by all threads of the block.
 template <typename T>
 __device__ __forceinline__ void block_force(const T* __restrict__ phi, int M, double ux, double uy,
                                    double uz, T* win, int* bounds, bool hinted,
-                                   const unsigned (&hq)[3], T (&g)[3]) {
+                                   const CellRange& hc, bool staged, T (&g)[3]) {
   g[0] = g[1] = g[2] = T(0);
   const double hiu = (double)M + 1.0;
   const bool in = ux >= -1.0 && ux < hiu && uy >= -1.0 && uy < hiu && uz >= -1.0 && uz < hiu;
@@ -307,11 +344,11 @@ __device__ __forceinline__ void block_force(const T* __restrict__ phi, int M, do
     }
   }
   const int Mp = M + 3, Mp2 = Mp * Mp;
-  CellRange cr = cells_decode(hq);
+  CellRange cr = hc;
   bool held = false;
   if (hinted) {
     hint_to_slots(in, j0, cr, bounds);
-    __syncthreads();
+    __syncthreads();   // also completes the direct staging
     held = hint_holds(bounds);
   }
   if (!held) cr = block_cells(in, j0, bounds);
@@ -320,26 +357,29 @@ __device__ __forceinline__ void block_force(const T* __restrict__ phi, int M, do
     const int ox = cr.lo[0] - 1, oy = cr.lo[1] - 1, oz = cr.lo[2] - 1;
     const int ex = cr.hi[0] - ox + 3, ey = cr.hi[1] - oy + 3, ez = cr.hi[2] - oz + 3;
     if (ex <= kFw && ey <= kFw && ez <= kFw) {
-      const int t = threadIdx.x, ty = t / kFw, tz = t % kFw;
-      const int ny = oy + ty, nz = oz + tz;
-      // window nodes outside the padded grid [-1, M+1] (one layer at most) are zero; only
-      // zero-weight corners read them
-      const bool col = ty < ey && tz < ez && ny >= -1 && ny <= M + 1 && nz >= -1 && nz <= M + 1;
-      const int xa = max(-1 - ox, 0), xb = min(M + 2 - ox, ex);
-      // all loads of the column are issued before the first LDS store
-      const unsigned gcol = col ? (unsigned)(((ny + 1) * Mp + (nz + 1)) * (int)sizeof(T)) : 0u;
-      T v[kFw];
+      if (!(held && staged)) {
+        const int t = threadIdx.x, ty = t / kFw, tz = t % kFw;
+        const int ny = oy + ty, nz = oz + tz;
+        // window nodes outside the padded grid [-1, M+1] (one layer at most) are zero; only
+        // zero-weight corners read them
+        const bool col =
+            ty < ey && tz < ez && ny >= -1 && ny <= M + 1 && nz >= -1 && nz <= M + 1;
+        const int xa = max(-1 - ox, 0), xb = min(M + 2 - ox, ex);
+        // all loads of the column are issued before the first LDS store
+        const unsigned gcol = col ? (unsigned)(((ny + 1) * Mp + (nz + 1)) * (int)sizeof(T)) : 0u;
+        T v[kFw];
 #pragma unroll
-      for (int xi = 0; xi < kFw; ++xi) v[xi] = T(0);
-      if (col) {
+        for (int xi = 0; xi < kFw; ++xi) v[xi] = T(0);
+        if (col) {
+#pragma unroll
+          for (int xi = 0; xi < kFw; ++xi)
+            if (xi >= xa && xi < xb) v[xi] = *byte_offset(phi + (int64_t)(ox + 1 + xi) * Mp2, gcol);
+        }
 #pragma unroll
         for (int xi = 0; xi < kFw; ++xi)
-          if (xi >= xa && xi < xb) v[xi] = *byte_offset(phi + (int64_t)(ox + 1 + xi) * Mp2, gcol);
+          if (xi < ex) win[t + kFwX * xi] = v[xi];
+        __syncthreads();
       }
-#pragma unroll
-      for (int xi = 0; xi < kFw; ++xi)
-        if (xi < ex) win[t + kFwX * xi] = v[xi];
-      __syncthreads();
       if (in) {
         const T* wp = win + (j0[0] - 1 - ox) * kFwX + (j0[1] - 1 - oy) * kFwY + (j0[2] - 1 - oz);
         gather_force<T>(M, j0, fr,
@@ -417,14 +457,26 @@ k_particles(ParticleArgs<T> a, BlockMap m) {
       xr[c] = a.xres[c * P + p];
     }
   }
-  const StepScalars sc = a.sc;
-  double u[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) u[c] = lpt_base(q[c], sc.D1, s1[c], sc.D2, s2[c]) + (double)xr[c];
   // one LDS window, first for the potential (kWindow T values), then for the block's mass
   // (kWindow fixed-point accumulators)
   __shared__ unsigned long long win[kWindow * sizeof(T) / 8];
   __shared__ int bounds[kCellScratch];
+  // the potential window placed from the kept extent is requested while the particle
+  // streams are still in flight
+  const bool hinted = kForce && a.use_hints != 0;
+  CellRange hc;
+  bool staged = false;
+  if (hinted) {
+    const unsigned hq[3] = {(unsigned)__builtin_amdgcn_readfirstlane(h.x),
+                            (unsigned)__builtin_amdgcn_readfirstlane(h.y),
+                            (unsigned)__builtin_amdgcn_readfirstlane(h.z)};
+    hc = cells_decode(hq);
+    staged = stage_window_direct<T>(a.phi + t.h_off, M, hc, reinterpret_cast<T*>(win));
+  }
+  const StepScalars sc = a.sc;
+  double u[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) u[c] = lpt_base(q[c], sc.D1, s1[c], sc.D2, s2[c]) + (double)xr[c];
   if (kForce) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) pr[c] = a.pres[c * P + p];
@@ -442,11 +494,8 @@ k_particles(ParticleArgs<T> a, BlockMap m) {
       asm volatile("" : "+v"(lpt[c]), "+v"(un[c]));
     }
     T g[3];
-    const unsigned hq[3] = {(unsigned)__builtin_amdgcn_readfirstlane(h.x),
-                            (unsigned)__builtin_amdgcn_readfirstlane(h.y),
-                            (unsigned)__builtin_amdgcn_readfirstlane(h.z)};
     block_force<T>(a.phi + t.h_off, M, u[0], u[1], u[2], reinterpret_cast<T*>(win), bounds,
-                   a.use_hints != 0, hq, g);
+                   hinted, hc, staged, g);
 #pragma unroll
     for (int c = 0; c < 3; ++c) pr[c] += (T)sc.beta * (g[c] - lpt[c]);
     if (MODE == kFinalKick) {
