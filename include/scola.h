@@ -192,16 +192,19 @@ scola_status scola_evolve(scola_plan* plan, const int32_t* tile_subset, int32_t 
 /* Launch schedule (not a quantity of the paper; results are bitwise identical under every
  * schedule).  Boxes are grouped by size M into classes (ascending M); every class has its
  * own launches of the fused particle kernel and of the Poisson passes.  Per class:
- *   waves_per_simd       4 or 6: register budget the fused particle kernel is compiled for
- *                        (6 = 80 registers, 4 = 128);
+ *   waves_per_simd       6 or 8: register budget the fused particle kernel is compiled for
+ *                        (6 = 80 registers, 8 = 64; FP64 plans need more than 64 and run
+ *                        at the occupancy their registers allow);
  *   xcd_remap_particles  1: blocks numbered so each of the 8 XCDs takes a contiguous run of
  *                        whole boxes (their meshes stay in one L2); 0: hardware order;
  *   xcd_remap_mesh       the same for the three Poisson passes.
  * Defaults {6, 1, 1}.  scola_plan_tune times the choices per class on the workspace's
  * particles (after scola_setup, else SCOLA_ESTATE) with `reps` launches each (1..1000) and
- * keeps the fastest; it leaves the particle state unchanged, clears its deposits, and
- * synchronises the stream (call it before scola_evolve, never inside a timed or captured
- * region).  scola_plan_schedule copies the schedule of every class into out (capacity
+ * keeps the fastest; it leaves the set-up fields (Psi, Phi_BC^0) untouched, clears its
+ * deposits, and synchronises the stream (call it before scola_evolve, never inside a timed
+ * or captured region).  Its timed evolutions leave x_res and p_res at the end of an
+ * evolution; scola_evolve starts from L- whatever they hold, so runs after tuning are
+ * bitwise those without it.  scola_plan_schedule copies the schedule of every class into out (capacity
  * entries at least; out may be NULL to query *n_classes).  scola_plan_set_schedule sets it
  * (same classes, same order). */
 typedef struct {
@@ -217,8 +220,10 @@ scola_status scola_plan_tune(scola_plan* plan, void* d_workspace, hipStream_t st
  * tiles of every size class are split in G equal shares that advance at the same time, one
  * on `stream` and the others on plan-owned streams that fork from and join back to `stream`
  * with events, so one share's Poisson passes overlap another share's particle kernel.
- * Results are bitwise independent of G.  scola_plan_tune also chooses G (it times whole
- * evolutions each way). */
+ * Results are bitwise independent of G.  scola_plan_tune also chooses G, together with
+ * waves_per_simd (one value for all classes) and whether the Poisson numbering chosen per
+ * class is kept or flipped in every class, by timing whole evolutions each way (a choice
+ * that is fastest for one kernel alone can lose when the groups share the GPU). */
 scola_status scola_plan_concurrency(const scola_plan* plan, int32_t* groups);
 scola_status scola_plan_set_concurrency(scola_plan* plan, int32_t groups);
 scola_status scola_plan_schedule(const scola_plan* plan, scola_class_schedule* out,

@@ -134,7 +134,7 @@ template <typename T>
 hipError_t launch_poisson(const MeshArgs<T>& a, int M, const BlockMap& p1, const BlockMap& p2,
                           const BlockMap& p3, hipStream_t s, bool adjoint = false);
 template <typename T>
-// occ: waves per SIMD the kernel's registers are held to (4 or 6)
+// occ: waves per SIMD the kernel's registers are held to (6 or 8)
 hipError_t launch_particles(const ParticleArgs<T>& a, int mode, const BlockMap& m, int occ,
                             hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);

@@ -12,10 +12,10 @@
 // The deposit accumulates rounded fixed-point weights in integers (2^40 units per
 // particle in 64 bits for FP64 plans, 2^21 in 32 bits for FP32 plans): sums are exact and
 // independent of the order of the atomics, which makes every run bitwise reproducible and
-// a box computed alone bitwise equal to the same box in a batch.  The corner with the
-// largest weight takes the rounding remainder, so every particle carries exactly one unit
-// of mass, split between deposited and dropped (outside the interior nodes), and no weight
-// is negative.
+// a box computed alone bitwise equal to the same box in a batch.  The weights come from
+// exact integer splits of the unit, so every particle carries exactly one unit of mass,
+// split between deposited and dropped (outside the interior nodes), and no weight is
+// negative.
 #include <type_traits>
 
 #include "common.h"
@@ -26,28 +26,31 @@ namespace scola {
 
 namespace {
 
-// Fixed-point CiC weights of the 8 corners (offset bits x = 4, y = 2, z = 1).  Every weight
-// is rounded to the nearest unit, and the corner with the largest weight (the one nearest
-// the particle, weight at least 1/8) takes the remainder, so the eight sum to exactly one
-// unit and none is negative: no node total can fall below zero through rounding.
-__device__ inline int largest_corner(double fx, double fy, double fz) {
-  return (fx >= 0.5 ? 4 : 0) | (fy >= 0.5 ? 2 : 0) | (fz >= 0.5 ? 1 : 0);
-}
-
-__device__ inline void fixed_weights(double fx, double fy, double fz, long long (&w)[8]) {
-  long long sum = 0;
+// Fixed-point CiC weights of the 8 corners (offset bits x = 4, y = 2, z = 1) of a particle
+// at fractional offsets (fx, fy, fz), as integers of type I with `one` units per particle.
+// The unit is split along x into round(fx one) and the rest, each of the two parts along y
+// the same way, and each of the four parts along z.  Every split is exact in integers, so
+// the eight weights are non-negative and sum to exactly one unit, with no remainder to
+// place; each is within three units of its exact value.  F is the floating type the products
+// are formed in (float for 2^21 units, double for 2^40): the integers stay below 2^24 and
+// 2^53, and adding one half before truncation rounds the non-negative products.
+template <typename I, typename F>
+__device__ __forceinline__ void split_weights(F fx, F fy, F fz, I one, I (&w)[8]) {
+  const I x1 = (I)fma(fx, (F)one, F(0.5));
+  const I x[2] = {one - x1, x1};
+  I xy[4];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const double wx = (c & 4) ? fx : 1.0 - fx;
-    const double wy = (c & 2) ? fy : 1.0 - fy;
-    const double wz = (c & 1) ? fz : 1.0 - fz;
-    w[c] = __double2ll_rn(wx * wy * wz * kFixedOne);
-    sum += w[c];
+  for (int q = 0; q < 2; ++q) {
+    const I hi = (I)fma(fy, (F)x[q], F(0.5));
+    xy[2 * q] = x[q] - hi;
+    xy[2 * q + 1] = hi;
   }
-  const long long adj = (long long)kFixedOne - sum;
-  const int cl = largest_corner(fx, fy, fz);
 #pragma unroll
-  for (int c = 0; c < 8; ++c) w[c] += c == cl ? adj : 0ll;
+  for (int q = 0; q < 4; ++q) {
+    const I hi = (I)fma(fz, (F)xy[q], F(0.5));
+    w[2 * q] = xy[q] - hi;
+    w[2 * q + 1] = hi;
+  }
 }
 
 // Integer type of one particle's fixed-point corner weights: 64-bit for the 2^40 units of
@@ -56,30 +59,12 @@ template <typename T>
 using WeightT = typename std::conditional<MeshFixed<T>::bits == 40, long long, int>::type;
 
 template <typename T>
-__device__ inline void mesh_weights(double fx, double fy, double fz, WeightT<T> (&w)[8]) {
-  if constexpr (MeshFixed<T>::bits == 40) {
-    fixed_weights(fx, fy, fz, w);
-  } else {
-    // the unit scale rides on the x factor; weights are non-negative, so adding one half
-    // before truncation rounds them to the nearest unit
-    const float one = (float)(1 << MeshFixed<T>::bits);
-    const float ax[2] = {(1.0f - (float)fx) * one, (float)fx * one};
-    const float ay[2] = {1.0f - (float)fy, (float)fy}, az[2] = {1.0f - (float)fz, (float)fz};
-    float ayz[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) ayz[q] = ay[q >> 1] * az[q & 1];
-    int sum = 0;
-    int v[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      v[c] = (int)fmaf(ax[(c >> 2) & 1], ayz[c & 3], 0.5f);
-      sum += v[c];
-    }
-    const int adj = (1 << MeshFixed<T>::bits) - sum;
-    const int cl = largest_corner(fx, fy, fz);
-#pragma unroll
-    for (int c = 0; c < 8; ++c) w[c] = v[c] + (c == cl ? adj : 0);
-  }
+__device__ __forceinline__ void mesh_weights(double fx, double fy, double fz,
+                                             WeightT<T> (&w)[8]) {
+  if constexpr (MeshFixed<T>::bits == 40)
+    split_weights<long long, double>(fx, fy, fz, 1ll << 40, w);
+  else
+    split_weights<int, float>((float)fx, (float)fy, (float)fz, 1 << MeshFixed<T>::bits, w);
 }
 
 // Corner range of one particle's CiC footprint restricted to interior nodes [1, n]:
@@ -420,7 +405,7 @@ __device__ __forceinline__ void block_force(const T* __restrict__ phi, int M, do
   __syncthreads();   // every thread is done with `bounds` and the window before reuse
 }
 
-// OCC: waves per SIMD the register allocation is held to (4 or 6); a schedule choice.
+// OCC: waves per SIMD the register allocation is held to (6 or 8); a schedule choice.
 template <typename T, int MODE, int OCC>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OCC)))
 k_particles(ParticleArgs<T> a, BlockMap m) {
@@ -589,7 +574,7 @@ __global__ void __launch_bounds__(kBlock) k_output(OutputArgs<T> a, BlockMap m, 
       j0[c] = wrapi((int)fmod(fl, (double)No), No);
     }
     long long w[8];
-    fixed_weights(f[0], f[1], f[2], w);
+    split_weights<long long, double>(f[0], f[1], f[2], 1ll << 40, w);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int nx = (j0[0] + ((c >> 2) & 1)) % No, ny = (j0[1] + ((c >> 1) & 1)) % No,
@@ -657,8 +642,8 @@ template <typename T>
 hipError_t launch_particles(const ParticleArgs<T>& a, int mode, const BlockMap& m, int occ,
                             hipStream_t s) {
   switch (occ) {
-    case 4: return launch_particles_occ<T, 4>(a, mode, m, s);
     case 6: return launch_particles_occ<T, 6>(a, mode, m, s);
+    case 8: return launch_particles_occ<T, 8>(a, mode, m, s);
     default: return hipErrorInvalidValue;
   }
 }

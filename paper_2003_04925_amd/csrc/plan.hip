@@ -994,9 +994,11 @@ void capture_evolve(scola_plan* p, const std::vector<int>& tiles, void* ws) {
 // Launch-schedule autotuner.  For every size class it times, on the workspace's own
 // particles at the positions of the last step (x_res as left by the set-up, i.e. on the
 // 2LPT trajectory) with zero kick and drift so the particle state is unchanged: the fused
-// step kernel compiled for 4 or 6 waves per SIMD, each with and without the XCD-aware block
-// numbering; then the three Poisson passes with and without it.  The fastest of each is
-// kept.  The deposits and potentials it leaves are cleared or overwritten by the next
+// step kernel with and without the XCD-aware block numbering, then the three Poisson passes
+// with and without it; the fastest of each is kept.  Then whole evolutions choose, together,
+// the particle kernel's occupancy (6 or 8 waves per SIMD, all classes), whether the Poisson
+// numbering chosen alone is kept or flipped (all classes), and the number of concurrent box
+// groups.  The deposits and potentials it leaves are cleared or overwritten by the next
 // scola_evolve (which starts from L-).
 template <typename T>
 void do_tune(scola_plan* p, void* ws, hipStream_t s, int reps) {
@@ -1023,47 +1025,63 @@ void do_tune(scola_plan* p, void* ws, hipStream_t s, int reps) {
   for (size_t c = 0; c < pm.class_M.size(); ++c) {
     scola_class_schedule& cs = p->sched[c];
     float best = 1e30f;
-    for (int occ : {6, 4})
+    for (int remap : {1, 0}) {
+      BlockMap b = class_map(pm, c);
+      b.xcd_remap = remap;
+      const float ms = timed([&] {
+        hip_check(launch_particles<T>(a, kStep, b, 6, s), "tuning launch");
+      });
+      if (ms < best) {
+        best = ms;
+        cs.xcd_remap_particles = remap;
+      }
+    }
+    // the Poisson passes on a cleared mass mesh (the tuning launches above left their
+    // deposits in it), the two numberings timed in turn, twice each
+    hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.rho)),
+                              (int64_t)(rho_bytes(p) / 8), s), "zero rho");
+    float total[2] = {0.0f, 0.0f};
+    for (int round = 0; round < 2; ++round)
       for (int remap : {1, 0}) {
-        BlockMap b = class_map(pm, c);
-        b.xcd_remap = remap;
-        const float ms = timed([&] {
-          hip_check(launch_particles<T>(a, kStep, b, occ, s), "tuning launch");
-        });
+        cs.xcd_remap_mesh = remap;
+        total[remap] += timed([&] { poisson_class(p, ma, c, false, s); });
+      }
+    cs.xcd_remap_mesh = total[1] <= total[0] ? 1 : 0;
+  }
+  // the particle kernel's occupancy, the Poisson passes' block numbering (as chosen above,
+  // or flipped in every class) and the number of concurrent box groups, chosen together
+  // from whole evolutions (eager): a choice that wins for one kernel alone can lose once
+  // its launches share the GPU with other groups' kernels
+  const std::vector<int> all = subset_list(p, nullptr, 0);
+  const bool grouped = p->desc.size() >= 2 && p->cfg.schedule == SCOLA_BATCHED;
+  const std::vector<int> group_choices = grouped ? std::vector<int>{1, 2, 4}
+                                                 : std::vector<int>{p->groups};
+  std::vector<int> mesh_alone(p->sched.size());
+  for (size_t c = 0; c < p->sched.size(); ++c) mesh_alone[c] = p->sched[c].xcd_remap_mesh;
+  float best = 1e30f;
+  int occ_choice = 6, flip_choice = 0, group_choice = p->groups;
+  for (int occ : {6, 8})
+    for (int flip : {0, 1}) {
+      for (size_t c = 0; c < p->sched.size(); ++c) {
+        p->sched[c].waves_per_simd = occ;
+        p->sched[c].xcd_remap_mesh = mesh_alone[c] ^ flip;
+      }
+      for (int G : group_choices) {
+        p->groups = G;
+        const float ms = timed([&] { do_evolve<T>(p, all, ws, s); });
         if (ms < best) {
           best = ms;
-          cs.waves_per_simd = occ;
-          cs.xcd_remap_particles = remap;
+          occ_choice = occ;
+          flip_choice = flip;
+          group_choice = G;
         }
       }
-    best = 1e30f;
-    const int keep = cs.xcd_remap_mesh;
-    int choice = keep;
-    for (int remap : {1, 0}) {
-      cs.xcd_remap_mesh = remap;
-      const float ms = timed([&] { poisson_class(p, ma, c, false, s); });
-      if (ms < best) {
-        best = ms;
-        choice = remap;
-      }
     }
-    cs.xcd_remap_mesh = choice;
+  for (size_t c = 0; c < p->sched.size(); ++c) {
+    p->sched[c].waves_per_simd = occ_choice;
+    p->sched[c].xcd_remap_mesh = mesh_alone[c] ^ flip_choice;
   }
-  // concurrent box groups: whole evolutions (eager), one or two groups
-  if (p->desc.size() >= 2 && p->cfg.schedule == SCOLA_BATCHED) {
-    const std::vector<int> all = subset_list(p, nullptr, 0);
-    float best = 1e30f;
-    int choice = p->groups;
-    for (int G : {1, 2, 4}) {
-      p->groups = G;
-      const float ms = timed([&] { do_evolve<T>(p, all, ws, s); });
-      if (ms < best) {
-        best = ms;
-        choice = G;
-      }
-    }
-    p->groups = choice;
-  }
+  p->groups = group_choice;
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.rho)),
@@ -1319,8 +1337,8 @@ scola_status scola_plan_set_schedule(scola_plan* p, const scola_class_schedule* 
       fail(SCOLA_EINVAL, "n_classes must equal the number of box sizes of the plan");
     for (int c = 0; c < n_classes; ++c) {
       if (in[c].M != p->sched[c].M) fail(SCOLA_EINVAL, "class order or M does not match");
-      if (in[c].waves_per_simd != 4 && in[c].waves_per_simd != 6)
-        fail(SCOLA_EINVAL, "waves_per_simd must be 4 or 6");
+      if (in[c].waves_per_simd != 6 && in[c].waves_per_simd != 8)
+        fail(SCOLA_EINVAL, "waves_per_simd must be 6 or 8");
       if ((in[c].xcd_remap_particles | in[c].xcd_remap_mesh) & ~1)
         fail(SCOLA_EINVAL, "xcd_remap flags must be 0 or 1");
     }
