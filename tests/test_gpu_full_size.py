@@ -5,7 +5,7 @@ c2 (128^3 particles, 64 boxes of 64^3, 20 steps) and c3 (256^3, 157 boxes of 48^
 112^3, 20 steps): the oracle evolves a few sampled boxes one by one (boxes are independent
 after the set-up, Sec. 3.2) and the final positions of their core particles are compared.
 Bars (FP32 against the FP64 oracle): every sampled particle within 1e-4 cell, and equal cell
-indices for every particle more than 1e-4 cell from a face (measured: 6.6e-6 cell on c2,
+indices for every particle more than 1e-4 cell from a face (measured: 6.4e-6 cell on c2,
 1.2e-5 cell on c3).
 
 c5 (512^3, 512 boxes of 96^3, 30 steps) is too large for the oracle within a test; it is
