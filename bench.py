@@ -78,8 +78,13 @@ def time_evolve(torch, sim, steps, warmup):
     return start.elapsed_time(stop) / steps, wall
 
 
-def time_kernel(torch, fn, reps):
-    """Average duration of one launch, HIP events around each call on the current stream."""
+def time_kernel(torch, fn, reps, warmup=None):
+    """Average duration of one launch, HIP events around each call on the current stream,
+    after `warmup` untimed calls (default: as many as timed ones) so the clocks and caches
+    have settled, as for the warm-up steps of the evolution."""
+    for _ in range(reps if warmup is None else warmup):
+        fn()
+    torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(reps)]
     for a, b in evs:
