@@ -134,6 +134,30 @@ __device__ __forceinline__ double stage_partner(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// own + s * (own in the partner lane of stage B), FP32, for the four stages whose partner
+// is one DPP move away: the move rides on the multiply-add itself (the compiler does not
+// fold a DPP source into a multiply-add whose addend is also its destination).  The
+// leading two wait states are the ones a DPP read of a VGPR written by the previous VALU
+// instruction needs; the hazard checker does not look inside inline assembly.
+template <int B>
+__device__ __forceinline__ float fma_partner(float own, float s) {
+  static_assert(B >= 0 && B <= 3, "DPP stage");
+  float acc = own;
+  if constexpr (B == 0)
+    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf"
+        : "+v"(acc) : "v"(own), "v"(s));
+  if constexpr (B == 1)
+    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf"
+        : "+v"(acc) : "v"(own), "v"(s));
+  if constexpr (B == 2)
+    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_half_mirror row_mask:0xf bank_mask:0xf"
+        : "+v"(acc) : "v"(own), "v"(s));
+  if constexpr (B == 3)
+    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_mirror row_mask:0xf bank_mask:0xf"
+        : "+v"(acc) : "v"(own), "v"(s));
+  return acc;
+}
+
 // One radix-2 decimation-in-frequency stage on data bit B (distance S = 2^B) of K x R
 // independent 32-point transforms across lanes, without divergent branches: every lane
 // forms v = own + s * partner with s = +1 where its data bit B is clear and -1 where it is
@@ -155,8 +179,13 @@ __device__ __forceinline__ void dif_stage(cx<T> (&x)[K][R], const cx<T>* __restr
 #pragma unroll
     for (int k1 = 0; k1 < R; ++k1) {
       cx<T> v;
-      v.x = fma(stage_partner<B>(x[k][k1].x), s, x[k][k1].x);
-      v.y = fma(stage_partner<B>(x[k][k1].y), s, x[k][k1].y);
+      if constexpr (std::is_same<T, float>::value && B < 4) {
+        v.x = fma_partner<B>(x[k][k1].x, s);
+        v.y = fma_partner<B>(x[k][k1].y, s);
+      } else {
+        v.x = fma(stage_partner<B>(x[k][k1].x), s, x[k][k1].x);
+        v.y = fma(stage_partner<B>(x[k][k1].y), s, x[k][k1].y);
+      }
       if constexpr (S > 1) {
         x[k][k1].x = v.x * w.x - v.y * w.y;
         x[k][k1].y = v.x * w.y + v.y * w.x;
