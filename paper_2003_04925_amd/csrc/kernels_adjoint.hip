@@ -362,16 +362,17 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(AdjointArgs<T> a, Bloc
   double s1[3], s2[3], acc1[3], acc2[3];
   T lx[3], lp[3], xsc[3], lq1[3], lq2[3];
   // every particle stream of the pass is loaded up front, so the block waits on global
-  // memory once before its windows are staged
+  // memory once before its windows are staged; the streams are touched once per step, so
+  // they are read and written non-temporally (they do not evict the meshes from L2)
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    s1[c] = a.psi1[c * P + p];
-    s2[c] = a.psi2[c * P + p];
-    lx[c] = a.lam_x[c * P + p];
-    lp[c] = a.lam_p[c * P + p];
-    if (SCATTER) xsc[c] = a.xs[c * P + p];
-    lq1[c] = a.lam_psi1[c * P + p];
-    lq2[c] = a.lam_psi2[c * P + p];
+    s1[c] = __builtin_nontemporal_load(a.psi1 + c * P + p);
+    s2[c] = __builtin_nontemporal_load(a.psi2 + c * P + p);
+    lx[c] = __builtin_nontemporal_load(a.lam_x + c * P + p);
+    lp[c] = __builtin_nontemporal_load(a.lam_p + c * P + p);
+    if (SCATTER) xsc[c] = __builtin_nontemporal_load(a.xs + c * P + p);
+    lq1[c] = __builtin_nontemporal_load(a.lam_psi1 + c * P + p);
+    lq2[c] = __builtin_nontemporal_load(a.lam_psi2 + c * P + p);
     acc1[c] = acc2[c] = 0.0;
   }
   __shared__ T win[kWindow];
@@ -380,7 +381,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(AdjointArgs<T> a, Bloc
   if constexpr (GATHER) {
     double x[3], u[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) x[c] = (double)a.xg[c * P + p];
+    for (int c = 0; c < 3; ++c) x[c] = (double)__builtin_nontemporal_load(a.xg + c * P + p);
     lpt_position(s1, s2, idx, a.D1g, a.D2g, x, u);
     T lg[3], lu[3];
 #pragma unroll
@@ -412,10 +413,10 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(AdjointArgs<T> a, Bloc
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    if (GATHER) a.lam_x[c * P + p] = lx[c];
-    if (SCATTER) a.lam_p[c * P + p] = lp[c];
-    a.lam_psi1[c * P + p] = lq1[c] + (T)acc1[c];
-    a.lam_psi2[c * P + p] = lq2[c] + (T)acc2[c];
+    if (GATHER) __builtin_nontemporal_store(lx[c], a.lam_x + c * P + p);
+    if (SCATTER) __builtin_nontemporal_store(lp[c], a.lam_p + c * P + p);
+    __builtin_nontemporal_store(lq1[c] + (T)acc1[c], a.lam_psi1 + c * P + p);
+    __builtin_nontemporal_store(lq2[c] + (T)acc2[c], a.lam_psi2 + c * P + p);
   }
 }
 

@@ -428,10 +428,13 @@ k_particles(ParticleArgs<T> a, BlockMap m) {
   const double q[3] = {i + 0.5, j + 0.5, k + 0.5};
   double s1[3], s2[3];
   T xr[3], pr[3];
+  // the particle streams are touched once per step: non-temporal loads and stores keep
+  // them from evicting the box's mass mesh (the target of the deposit's atomics) and
+  // potential from L2
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    s1[c] = a.psi1[c * P + p];
-    s2[c] = a.psi2[c * P + p];
+    s1[c] = __builtin_nontemporal_load(a.psi1 + c * P + p);
+    s2[c] = __builtin_nontemporal_load(a.psi2 + c * P + p);
     if (MODE == kInit) {
       // operator L- (App. B): at t_0 the particles sit on their LPT trajectory and the
       // residual momentum is zero
@@ -439,7 +442,7 @@ k_particles(ParticleArgs<T> a, BlockMap m) {
       a.xres[c * P + p] = T(0);
       a.pres[c * P + p] = T(0);
     } else {
-      xr[c] = a.xres[c * P + p];
+      xr[c] = __builtin_nontemporal_load(a.xres + c * P + p);
     }
   }
   // one LDS window, first for the potential (kWindow T values), then for the block's mass
@@ -464,7 +467,7 @@ k_particles(ParticleArgs<T> a, BlockMap m) {
   for (int c = 0; c < 3; ++c) u[c] = lpt_base(q[c], sc.D1, s1[c], sc.D2, s2[c]) + (double)xr[c];
   if (kForce) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) pr[c] = a.pres[c * P + p];
+    for (int c = 0; c < 3; ++c) pr[c] = __builtin_nontemporal_load(a.pres + c * P + p);
     // the LPT terms of the kick and of the next position are formed before the force, so
     // Psi1 and Psi2 are not held across it
     const double d2 = sc.D2 - sc.D1 * sc.D1;
@@ -491,8 +494,8 @@ k_particles(ParticleArgs<T> a, BlockMap m) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       xr[c] += (T)sc.alpha * pr[c];
-      a.xout[c * P + p] = xr[c];
-      a.pres[c * P + p] = pr[c];
+      __builtin_nontemporal_store(xr[c], a.xout + c * P + p);
+      __builtin_nontemporal_store(pr[c], a.pres + c * P + p);
     }
     if (MODE == kStepNoDeposit) return;
 #pragma unroll
