@@ -363,7 +363,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(AdjointArgs<T> a, Bloc
   T lx[3], lp[3], xsc[3], lq1[3], lq2[3];
   // every particle stream of the pass is loaded up front, so the block waits on global
   // memory once before its windows are staged; the streams are touched once per step, so
-  // they are read and written non-temporally (they do not evict the meshes from L2)
+  // they are read and written non-temporally (they do not compete for cache lines with the
+  // meshes that neighbouring blocks reuse)
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     s1[c] = __builtin_nontemporal_load(a.psi1 + c * P + p);

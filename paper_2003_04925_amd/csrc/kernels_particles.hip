@@ -429,8 +429,8 @@ k_particles(ParticleArgs<T> a, BlockMap m) {
   double s1[3], s2[3];
   T xr[3], pr[3];
   // the particle streams are touched once per step: non-temporal loads and stores keep
-  // them from evicting the box's mass mesh (the target of the deposit's atomics) and
-  // potential from L2
+  // them from competing for cache lines with the box's mass mesh (the target of the
+  // deposit's atomics) and potential, which neighbouring blocks reuse
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     s1[c] = __builtin_nontemporal_load(a.psi1 + c * P + p);
