@@ -195,8 +195,50 @@ __device__ __forceinline__ void dif_stage(cx<T> (&x)[K][R], const cx<T>* __restr
     }
 }
 
+// In-register DFT of odd length R (forward): inputs n and R - n enter through their sum a_n
+// and difference b_n, because W^(n k) and W^((R - n) k) are complex conjugates; with
+// W^(n k) = c + i s, y_k = p_k + i q_k and y_(R-k) = p_k - i q_k for
+// p_k = x_0 + sum_n c a_n, q_k = sum_n s b_n (n, k = 1 .. (R - 1) / 2).  About 4 H^2
+// multiply-adds for H = (R - 1) / 2 instead of the direct sum's (R - 1)^2 complex products.
+template <int R, typename T>
+__device__ __forceinline__ void dft_odd(cx<T> (&x)[R]) {
+  constexpr int H = (R - 1) / 2;
+  cx<T> a[H + 1], b[H + 1];
+  cx<T> y0 = x[0];
+#pragma unroll
+  for (int n = 1; n <= H; ++n) {
+    a[n] = c_add(x[n], x[R - n]);
+    b[n] = c_sub(x[n], x[R - n]);
+    y0 = c_add(y0, a[n]);
+  }
+  cx<T> y[R];
+  y[0] = y0;
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    cx<T> pk = x[0], qk;
+    qk.x = T(0);
+    qk.y = T(0);
+#pragma unroll
+    for (int n = 1; n <= H; ++n) {
+      const int m = (n * k) % R;
+      const T c = (T)kDftW[R - 1][m][0], sn = (T)kDftW[R - 1][m][1];
+      pk.x = fma(c, a[n].x, pk.x);
+      pk.y = fma(c, a[n].y, pk.y);
+      qk.x = fma(sn, b[n].x, qk.x);
+      qk.y = fma(sn, b[n].y, qk.y);
+    }
+    y[k].x = pk.x - qk.y;        // p + i q
+    y[k].y = pk.y + qk.x;
+    y[R - k].x = pk.x + qk.y;    // p - i q
+    y[R - k].y = pk.y - qk.x;
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) x[k] = y[k];
+}
+
 // In-register DFT of R points (forward, W_R = exp(-2 pi i / R)): radix-2 and radix-4
-// butterflies for R = 2, 4, 8, the direct sum with compile-time twiddles otherwise.
+// butterflies for R = 2, 4, 8, the paired form for odd R, and R = 6 as two 3-point DFTs
+// (even and odd inputs) joined by one twiddled radix-2 step.
 template <int R, typename T>
 __device__ __forceinline__ void small_dft(cx<T> (&x)[R]) {
   if constexpr (R == 2) {
@@ -222,17 +264,20 @@ __device__ __forceinline__ void small_dft(cx<T> (&x)[R]) {
       x[k] = c_add(e[k], t);
       x[k + 4] = c_sub(e[k], t);
     }
-  } else if constexpr (R > 1) {
-    cx<T> y[R];
+  } else if constexpr (R == 6) {
+    cx<T> e[3] = {x[0], x[2], x[4]}, o[3] = {x[1], x[3], x[5]};
+    dft_odd<3, T>(e);
+    dft_odd<3, T>(o);
 #pragma unroll
-    for (int k1 = 0; k1 < R; ++k1) {
-      cx<T> acc = x[0];
-#pragma unroll
-      for (int n2 = 1; n2 < R; ++n2) acc = c_add(acc, mul_wr<T>(x[n2], R, (n2 * k1) % R));
-      y[k1] = acc;
+    for (int k = 0; k < 3; ++k) {
+      const cx<T> t = mul_wr<T>(o[k], 6, k);
+      x[k] = c_add(e[k], t);
+      x[k + 3] = c_sub(e[k], t);
     }
-#pragma unroll
-    for (int k1 = 0; k1 < R; ++k1) x[k1] = y[k1];
+  } else if constexpr (R % 2 == 1 && R > 1) {
+    dft_odd<R, T>(x);
+  } else {
+    static_assert(R == 1, "in-register DFT lengths: 1 to 8");
   }
 }
 
