@@ -138,7 +138,7 @@ __device__ __forceinline__ double stage_partner(double v) {
 // is one DPP move away: the move rides on the multiply-add itself (the compiler does not
 // fold a DPP source into a multiply-add whose addend is also its destination).  The
 // leading two wait states are the ones a DPP read of a VGPR written by the previous VALU
-// instruction needs; the hazard checker does not look inside inline assembly.
+// instruction needs; the compiler's hazard recognizer does not look inside inline assembly.
 template <int B>
 __device__ __forceinline__ float fma_partner(float own, float s) {
   static_assert(B >= 0 && B <= 3, "DPP stage");

@@ -3,7 +3,7 @@
 The Poisson passes fold each radix-2 stage's cross-lane move into the multiply-add with
 inline assembly that begins with two wait states, which covers a DPP read of a VGPR written
 by the previous VALU instruction.  The other DPP hazard, a VALU write of EXEC, needs five;
-the compiler's hazard checker does not look inside inline assembly, so this test compiles
+the compiler's hazard recognizer does not look inside inline assembly, so this test compiles
 the Poisson kernels for gfx950 and requires that no EXEC-writing VALU instruction and no
 branch target lies among the four instructions before any of those blocks.
 """
@@ -48,7 +48,7 @@ def dpp_hazards(asm_text, mnemonic="v_fmac_f32_dpp", window=4):
     return count, problems
 
 
-def test_checker_flags_an_exec_write_and_a_label():
+def test_scan_flags_an_exec_write_and_a_label():
     bad = "\n".join(["\tv_cmpx_eq_u32_e32 0, v1", "\ts_nop 1",
                      "\tv_fmac_f32_dpp v4, v4, v3 row_mirror row_mask:0xf bank_mask:0xf"])
     assert dpp_hazards(bad)[1]
