@@ -428,7 +428,7 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m
   constexpr int M = 16 * R, n = M - 1, Mp = M + 3;
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
-  T* plane = reinterpret_cast<T*>(smem + 2 * kMaxM * sizeof(cx<T>)) + kMaxM;
+  T* plane = reinterpret_cast<T*>(smem + 2 * M * sizeof(cx<T>));
   load_twiddles(tw, a, t);
   const int64_t base = t.g_off + (int64_t)x * n * n;
   const double* bc = a.bc0 + t.h_off;
@@ -547,8 +547,8 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p2(MeshArgs<T> a, BlockMap m
   constexpr int pitch = kPencilChunk + 1;
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
-  T* ev = reinterpret_cast<T*>(smem + 2 * kMaxM * sizeof(cx<T>));
-  T* tile = ev + kMaxM;
+  T* ev = reinterpret_cast<T*>(smem + 2 * M * sizeof(cx<T>));
+  T* tile = ev + M;
   load_twiddles(tw, a, t);
   for (int i = threadIdx.x; i < n; i += blockDim.x) ev[i] = a.eigen[t.ev_off + i];
   // thread -> (x row x0 + 8 i, z column zc): rows of 32 consecutive z, coalesced
@@ -592,7 +592,7 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p3(MeshArgs<T> a, BlockMap m
   }
   extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
-  T* plane = reinterpret_cast<T*>(smem + 2 * kMaxM * sizeof(cx<T>)) + kMaxM;
+  T* plane = reinterpret_cast<T*>(smem + 2 * M * sizeof(cx<T>));
   load_twiddles(tw, a, t);
   const int x = local;
   const int64_t base = t.g_off + (int64_t)x * n * n;
@@ -710,13 +710,15 @@ inline unsigned padded_grid(const BlockMap& m) {
 
 }  // namespace
 
+// Dynamic LDS of each pass for boxes of M nodes: the 2M twiddles, then P1 the (M-1)^2 plane,
+// P2 the M eigenvalues and an (M-1) x 33 pencil tile, P3 the plane with its padded border
+// ((M+3)^2).  Sized per M and per pass, so small boxes keep more blocks per CU.
 template <typename T>
-size_t poisson_lds_bytes(int M) {
-  const int n = M - 1;
-  const size_t tw = 2 * kMaxM * sizeof(cx<T>) + kMaxM * sizeof(T);   // twiddles, eigenvalues
-  const size_t plane = (size_t)(M + 3) * (M + 3) * sizeof(T);   // plane and its padded border
-  const size_t pencil = (size_t)n * (kPencilChunk + 1) * sizeof(T);
-  return tw + (plane > pencil ? plane : pencil);
+size_t poisson_lds_bytes(int M, int pass) {
+  const size_t n = (size_t)M - 1, tw = 2 * (size_t)M * sizeof(cx<T>);
+  if (pass == 1) return tw + n * n * sizeof(T);
+  if (pass == 2) return tw + ((size_t)M + n * (kPencilChunk + 1)) * sizeof(T);
+  return tw + (size_t)(M + 3) * (M + 3) * sizeof(T);
 }
 
 namespace {
@@ -724,27 +726,28 @@ namespace {
 template <typename T, int R, bool ADJ>
 hipError_t launch_poisson_R(const MeshArgs<T>& a, const BlockMap& p1, const BlockMap& p2,
                             const BlockMap& p3, hipStream_t s) {
-  const size_t lds = poisson_lds_bytes<T>(16 * R);
-  if (lds > 65536) {
+  const size_t l1 = poisson_lds_bytes<T>(16 * R, 1), l2 = poisson_lds_bytes<T>(16 * R, 2),
+               l3 = poisson_lds_bytes<T>(16 * R, 3);
+  if (l1 > 65536 || l2 > 65536 || l3 > 65536) {
     static bool done = false;     // allow more than 64 KiB of dynamic LDS (160 KiB on gfx950)
     if (!done) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p1<T, R, ADJ>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)l1);
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p2<T, R>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2);
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p3<T, R, ADJ>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3);
       (void)hipGetLastError();
       done = true;
     }
   }
   if (p1.count > 0)
-    hipLaunchKernelGGL((k_poisson_p1<T, R, ADJ>), dim3(padded_grid(p1)), dim3(kBlock), lds, s,
+    hipLaunchKernelGGL((k_poisson_p1<T, R, ADJ>), dim3(padded_grid(p1)), dim3(kBlock), l1, s,
                        a, p1);
   if (p2.count > 0)
-    hipLaunchKernelGGL((k_poisson_p2<T, R>), dim3(padded_grid(p2)), dim3(kBlock), lds, s, a, p2);
+    hipLaunchKernelGGL((k_poisson_p2<T, R>), dim3(padded_grid(p2)), dim3(kBlock), l2, s, a, p2);
   if (p3.count > 0)
-    hipLaunchKernelGGL((k_poisson_p3<T, R, ADJ>), dim3(padded_grid(p3)), dim3(kBlock), lds, s,
+    hipLaunchKernelGGL((k_poisson_p3<T, R, ADJ>), dim3(padded_grid(p3)), dim3(kBlock), l3, s,
                        a, p3);
   return hipGetLastError();
 }
@@ -778,7 +781,7 @@ template hipError_t launch_poisson<float>(const MeshArgs<float>&, int, const Blo
                                           const BlockMap&, const BlockMap&, hipStream_t, bool);
 template hipError_t launch_poisson<double>(const MeshArgs<double>&, int, const BlockMap&,
                                            const BlockMap&, const BlockMap&, hipStream_t, bool);
-template size_t poisson_lds_bytes<float>(int);
-template size_t poisson_lds_bytes<double>(int);
+template size_t poisson_lds_bytes<float>(int, int);
+template size_t poisson_lds_bytes<double>(int, int);
 
 }  // namespace scola
