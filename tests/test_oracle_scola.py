@@ -186,14 +186,6 @@ def test_linear_growth_of_single_mode():
     assert 3.0 < sims[2] / sims[1] < 5.0
 
 
-def test_zeldovich_limit_no_force_residual():
-    # Zero-amplitude ICs: nothing moves, p_res stays zero.
-    steps, final = cola_schedule(Cosmology(), 0.05, 1.0, 3, want_final_kick=True)
-    z = np.zeros((3, 8, 8, 8))
-    out = evolve_box(z, z, np.zeros((11, 11, 11)), steps, final)
-    assert np.abs(out["x_res"]).max() < 1e-14 and np.abs(out["p"]).max() < 1e-14
-
-
 # --- sCOLA versus tCOLA (Sec. 4.3, eq. test_setup4) --------------------------------------
 def test_box_with_true_density_and_potential_reproduces_tcola():
     N, L = 16, 400.0
