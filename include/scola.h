@@ -160,6 +160,26 @@ scola_status scola_forward(scola_plan* plan, const double* d_white_noise, void* 
                            void* d_mom, void* d_density, const int32_t* tile_subset,
                            int32_t n_subset, void* d_workspace, hipStream_t stream);
 
+/* Size of the library's static device workspace (per GPU) used by scola_forward_noalloc. */
+#define SCOLA_STATIC_WORKSPACE_BYTES (128u << 20)
+
+/* scola_forward for callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid hipMalloc): the same set-up, evolution and outputs
+ * over all tiles, with the workspace taken from a static device array of the library
+ * (SCOLA_STATIC_WORKSPACE_BYTES = 128 MiB per GPU, held from the first call on a GPU until
+ * the process ends) instead of the caller's.  The call allocates nothing (no hipMalloc,
+ * stream, event or graph): it runs eagerly on `stream` with one box group.  Outputs are as
+ * for scola_forward with tile_subset = NULL.
+ * Errors: SCOLA_EINVAL if the plan's workspace (scola_workspace_size) exceeds the static
+ * size, if white noise is NULL, if d_mom is given without cfg.want_momenta, or if the
+ * current device is not the plan's.  Every call on a GPU uses that GPU's one static array
+ * and overwrites what the previous call left there, so calls that overlap in time on one
+ * GPU (on different streams or from different threads or plans) race and must be
+ * serialised by the caller.  The reverse mode is not available from this workspace, and
+ * the call-order state of caller workspaces is left as it was. */
+scola_status scola_forward_noalloc(scola_plan* plan, const double* d_white_noise, void* d_pos,
+                                   void* d_mom, void* d_density, hipStream_t stream);
+
 /* Reverse mode of scola_forward for a loss on the output density: given d loss / d delta_out
  * (R [N_out^3], device), writes d loss / d white noise (double [N_p^3], device).  Needs a
  * plan with checkpoint_every > 0 and a preceding scola_forward over all tiles on the same

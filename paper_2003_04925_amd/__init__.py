@@ -9,12 +9,12 @@ from dataclasses import dataclass
 
 from . import _lib
 from ._lib import (SCOLA_BATCHED, SCOLA_FP32, SCOLA_FP64, SCOLA_PER_TILE, FIXED_BITS,
-                   ScolaError)
+                   STATIC_WORKSPACE_BYTES, ScolaError)
 
 __all__ = ["Simulation", "DensityFunction", "CosmologyParams", "uniform_tiling",
            "particle_order", "schedule_table",
            "linear_power", "ScolaError", "SCOLA_FP32", "SCOLA_FP64", "SCOLA_BATCHED",
-           "SCOLA_PER_TILE", "FIXED_BITS"]
+           "SCOLA_PER_TILE", "FIXED_BITS", "STATIC_WORKSPACE_BYTES"]
 
 
 @dataclass
@@ -204,6 +204,23 @@ class Simulation:
             if mom is not None else None,
             self._ptr(dens, self.real, (self.N_out,) * 3) if dens is not None else None,
             sub, n, self._ws, self._stream()))
+        return dict(pos=pos, mom=mom, density=dens)
+
+    def forward_noalloc(self, white_noise, density=True, momenta=None):
+        """forward() over all tiles through scola_forward_noalloc: the library's static
+        device workspace instead of this object's (the outputs are still allocated here)."""
+        t = self.torch
+        Np = self.Np
+        momenta = self.want_momenta if momenta is None else momenta
+        pos = t.empty((3, Np, Np, Np), dtype=self.real, device=self.device)
+        mom = t.empty_like(pos) if momenta else None
+        dens = t.empty((self.N_out,) * 3, dtype=self.real, device=self.device) if density else None
+        _lib.check(_lib.lib().scola_forward_noalloc(
+            self._plan, self._ptr(white_noise, t.float64, (Np, Np, Np)),
+            self._ptr(pos, self.real, pos.shape),
+            self._ptr(mom, self.real, pos.shape) if mom is not None else None,
+            self._ptr(dens, self.real, (self.N_out,) * 3) if dens is not None else None,
+            self._stream()))
         return dict(pos=pos, mom=mom, density=dens)
 
     def backward(self, grad_density):

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libscola.so")
 SCOLA_FP32, SCOLA_FP64 = 0, 1
 SCOLA_BATCHED, SCOLA_PER_TILE = 0, 1
 FIXED_BITS = 40
+STATIC_WORKSPACE_BYTES = 128 << 20   # SCOLA_STATIC_WORKSPACE_BYTES
 
 STATUS = {0: "SCOLA_OK", -1: "SCOLA_EINVAL", -2: "SCOLA_ENOMEM", -3: "SCOLA_EDEVICE",
           -4: "SCOLA_ESTATE", -5: "SCOLA_EUNSUPPORTED"}
@@ -73,6 +74,7 @@ _SIGS = {
     "scola_workspace_size": ([_P, ctypes.POINTER(ctypes.c_size_t)], _I),
     "scola_workspace_layout": ([_P, ctypes.POINTER(Layout)], _I),
     "scola_forward": ([_P, _P, _P, _P, _P, ctypes.POINTER(_I), _I, _P, _P], _I),
+    "scola_forward_noalloc": ([_P, _P, _P, _P, _P, _P], _I),
     "scola_setup": ([_P, _P, _P, _P], _I),
     "scola_backward": ([_P, _P, _P, _P, _P], _I),
     "scola_evolve": ([_P, ctypes.POINTER(_I), _I, _P, _P], _I),

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -713,8 +714,11 @@ void zero_node_ranges(const scola_plan* p, const std::vector<int>& tiles, T* arr
                               r.second * (int64_t)(sizeof(T) / 4), s), "zero");
 }
 
+// allow_groups = false keeps the whole evolution on `s` (no plan-owned streams or events
+// are created or used).
 template <typename T>
-void do_evolve(scola_plan* p, const std::vector<int>& tiles, void* ws, hipStream_t s) {
+void do_evolve(scola_plan* p, const std::vector<int>& tiles, void* ws, hipStream_t s,
+               bool allow_groups = true) {
   const bool batched = p->cfg.schedule == SCOLA_BATCHED && tiles.size() == p->desc.size();
   hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped)),
                             (int64_t)p->desc.size() + 1, s), "zero dropped");
@@ -746,7 +750,7 @@ void do_evolve(scola_plan* p, const std::vector<int>& tiles, void* ws, hipStream
       r.particles(kFinalKick, sc);
     }
   };
-  const int G = batched ? std::min<int>(p->groups, (int)tiles.size()) : 1;
+  const int G = batched && allow_groups ? std::min<int>(p->groups, (int)tiles.size()) : 1;
   if (batched && G > 1) {
     // G shares of every size class advance concurrently on G streams, so one share's
     // Poisson passes overlap another share's particle kernel
@@ -1093,6 +1097,34 @@ void do_tune(scola_plan* p, void* ws, hipStream_t s, int reps) {
 
 }  // namespace
 
+// Static device workspace of scola_forward_noalloc: one copy per GPU, held until the process
+// ends.  In host code `scratch` is only a host-side handle of the symbol: its device address
+// on a GPU is obtained once per device with hipGetSymbolAddress (with that device current)
+// and only that address is ever passed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[SCOLA_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first call per device).
+void* static_workspace(int device) {
+  if (device < 0 || device >= kMaxDevices) fail(SCOLA_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!ptr || reinterpret_cast<uintptr_t>(ptr) % 256)
+      fail(SCOLA_EDEVICE, "static workspace address is not 256-byte aligned");
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* scola_status_string(scola_status s) {
@@ -1369,6 +1401,34 @@ scola_status scola_forward(scola_plan* p, const double* w, void* pos, void* mom,
   st = scola_evolve(p, subset, n_subset, ws, s);
   if (st != SCOLA_OK) return st;
   return scola_output(p, pos, mom, dens, subset, n_subset, ws, s);
+}
+
+scola_status scola_forward_noalloc(scola_plan* p, const double* w, void* pos, void* mom,
+                                   void* dens, hipStream_t s) {
+  return guarded([&] {
+    if (!p) fail(SCOLA_EINVAL, "plan is NULL");
+    if (!w) fail(SCOLA_EINVAL, "white noise is NULL");
+    if (p->lay.total > (size_t)SCOLA_STATIC_WORKSPACE_BYTES)
+      fail(SCOLA_EINVAL, "the plan needs a workspace of " + std::to_string(p->lay.total) +
+                             " bytes, more than the static workspace of " +
+                             std::to_string((size_t)SCOLA_STATIC_WORKSPACE_BYTES) + " bytes");
+    if (mom && !p->cfg.want_momenta) fail(SCOLA_EINVAL, "d_mom needs cfg.want_momenta");
+    int dev = -1;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != p->device) fail(SCOLA_EINVAL, "current device differs from the plan's device");
+    void* ws = static_workspace(dev);
+    const std::vector<int> tiles = subset_list(p, nullptr, 0);
+    if (p->is64) {
+      do_setup<double>(p, w, ws, s);
+      do_evolve<double>(p, tiles, ws, s, false);
+      do_output<double>(p, pos, mom, dens, tiles, ws, s);
+    } else {
+      do_setup<float>(p, w, ws, s);
+      do_evolve<float>(p, tiles, ws, s, false);
+      do_output<float>(p, pos, mom, dens, tiles, ws, s);
+    }
+    // no caller workspace was touched, so their call-order state stands
+  });
 }
 
 scola_status scola_backward(scola_plan* p, const void* grad_density, double* grad_w, void* ws,
