@@ -1,0 +1,98 @@
+"""Oracle parity at the box shapes of the two largest workloads, on lattices small enough
+for the FP64 oracle.
+
+c5 shape: boxes of 64^3 core + 16 buffer (96^3 particles, 95^3 Poisson unknowns) at the c5
+cell size L/N_p = 1000/512 = 1.953 Mpc/h, 30 FP32 steps -- here L = 250 Mpc/h with 128^3
+particles and 2^3 tiles -- run as bench.py runs its workloads (set up, autotuned, the
+evolution replayed as a hipGraph).  Bar: the benchmark spec's 1e-4 cell on every particle of the
+sampled box, equal cell indices away from faces.
+
+c4 shape: the reverse mode with checkpoints every 5 steps over 20 FP32 steps on boxes of
+32^3 core + 16 buffer (64^3) at the c4 cell size 3.906 Mpc/h -- here L = 250 Mpc/h with 64^3
+particles and 2^3 tiles -- against the oracle's reverse-mode reference (torch float64
+autograd of the same chain).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def test_c5_shaped_boxes_match_oracle(torch):
+    import paper_2003_04925_amd as S
+    from oracle.run import run_scola
+    from oracle.tiling import uniform_tiling
+    Np, L, tps, buf, n = 128, 250.0, 2, 16, 30
+    say("c5-shaped: 8 boxes of 96^3, 1.953 Mpc/h cells, 30 FP32 steps")
+    tiles = S.uniform_tiling(Np, tps, buf)
+    sim = S.Simulation(L, Np, tiles, n, precision="fp32")
+    w = torch.from_numpy(synthetic.white_noise(Np, 42)).cuda()
+    sim.setup(w)
+    say("  tuned", sim.tune(reps=2), "groups", sim.groups)
+    sim.forward(w)                           # eager; the next one is captured and replayed
+    out = sim.forward(w)
+    torch.cuda.synchronize()
+    sample = [5]
+    ora = run_scola(synthetic.white_noise(Np, 42), L, uniform_tiling(Np, tps, buf), n_steps=n,
+                    tile_subset=sample)
+    cell = L / Np
+    u_ora = ora["pos_cells"]
+    have = np.isfinite(u_ora).all(axis=0)
+    u_gpu = out["pos"].double().cpu().numpy() / cell
+    d = (u_gpu - np.mod(u_ora, Np) + Np / 2) % Np - Np / 2
+    d = np.abs(d)[:, have].max(axis=0)
+    uo = np.mod(u_ora[:, have], Np)
+    frac = uo - np.floor(uo)
+    far = (np.minimum(frac, 1 - frac) > 1e-4).all(axis=0)
+    same = (np.floor(np.mod(u_gpu[:, have], Np)) == np.floor(uo)).all(axis=0)
+    mism = int((far & ~same).sum())
+    disp = np.abs((u_ora[:, have] - np.floor(u_ora[:, have])) - 0.5).max()
+    say(f"  box {sample}: {int(have.sum())} particles, max {d.max():.3e} cell, p99.9 "
+        f"{np.quantile(d, 0.999):.3e} cell, index mismatches away from faces {mism}")
+    assert int(have.sum()) == 64 ** 3 and disp > 0.1
+    assert d.max() < 1e-4 and mism == 0
+
+
+def test_c4_shaped_fp32_gradient_matches_oracle(torch):
+    import paper_2003_04925_amd as S
+    from oracle.adjoint import loss_and_gradient
+    from oracle.tiling import uniform_tiling
+    Np, L, tps, buf, n, ck = 64, 250.0, 2, 16, 20, 5
+    say("c4-shaped adjoint: 8 boxes of 64^3, 20 FP32 steps, checkpoint every 5")
+    sim = S.Simulation(L, Np, S.uniform_tiling(Np, tps, buf), n, precision="fp32",
+                       checkpoint_every=ck)
+    w = torch.from_numpy(synthetic.white_noise(Np, 3)).cuda()
+    t = torch.from_numpy(synthetic.loss_target(Np, 43)).cuda().float()
+    sim.setup(w)
+    sim.tune(reps=2)
+    dens = sim.forward(w)["density"]
+    loss = float(((dens.double() - t.double()) ** 2).sum())
+    g = sim.backward(2.0 * (dens - t)).cpu().numpy()
+    torch.cuda.synchronize()
+    oloss, og, _ = loss_and_gradient(synthetic.white_noise(Np, 3), L,
+                                     uniform_tiling(Np, tps, buf),
+                                     synthetic.loss_target(Np, 43), n_steps=n)
+    cos = float((g * og).sum() / np.sqrt((g * g).sum() * (og * og).sum()))
+    rel = float(np.sqrt(((g - og) ** 2).sum() / (og * og).sum()))
+    mx = float(np.abs(g - og).max() / np.abs(og).max())
+    say(f"  loss {loss:.9e} oracle {oloss:.9e}; cosine 1 - {1 - cos:.3e}, rel L2 {rel:.3e}, "
+        f"max {mx:.3e} of the largest entry")
+    assert loss == pytest.approx(oloss, rel=1e-5)
+    assert cos > 1 - 1e-6 and rel < 2e-3

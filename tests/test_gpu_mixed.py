@@ -59,7 +59,7 @@ def oracle_run():
     return w, run_scola(w, L, tiles, n_steps=n)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-8), ("fp32", 1e-3)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-8), ("fp32", 1e-4)])
 def test_mixed_batch_matches_oracle(torch, oracle_run, precision, tol):
     import paper_2003_04925_amd as S
     w, ora = oracle_run
@@ -77,6 +77,11 @@ def test_mixed_batch_matches_oracle(torch, oracle_run, precision, tol):
     say("  max |dx| cells", np.abs(d).max(), "p99.9", np.quantile(np.abs(d), 0.999),
         "max |d delta|", dd)
     assert np.abs(d).max() < tol
+    u_o = ora["pos"] / cell
+    u_g = out["pos"].double().cpu().numpy() / cell
+    frac = u_o - np.floor(u_o)
+    far = (np.minimum(frac, 1 - frac) > 1e-4).all(axis=0)
+    assert ((np.floor(u_g) == np.floor(u_o)).all(axis=0) | ~far).all()
     assert dd < (1e-8 if precision == "fp64" else 1e-3)
 
 
