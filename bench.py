@@ -14,7 +14,10 @@ Workloads (particles per side, box side, tiling):
       per-tile (the plain path)
 Roofline: the dominant kernel is the fused particle step; its algorithmic traffic is 96 B
 per particle (x_res and p_res read and written in FP32, Psi1 and Psi2 read in FP64), timed
-with HIP events around single launches on the stream it runs on.
+with HIP events around single launches on the stream it runs on.  roofline.whole_step adds
+the Poisson solve (16 B per interior node) and takes the measured time of one KDK step of
+the evolution, i.e. every kernel of the step.
+CPU baseline: the FP64 oracle running the whole c1 workload, boxes in parallel processes.
 """
 import argparse
 import json
@@ -62,6 +65,17 @@ def measured_traffic():
         return None
 
 
+def whole_step(P, G, ms_per_kdk):
+    """All kernels of one KDK step against the HBM roofline: algorithmic bytes 96 B per box
+    particle (x_res, p_res read and written in FP32, Psi1, Psi2 read in FP64) + 16 B per
+    interior mesh node (delta written and read, Phi written and read, FP32) over the
+    measured time of one KDK step of the evolution."""
+    b = 96 * P + 16 * G
+    gbs = b / (ms_per_kdk * 1e-3) / 1e9
+    return {"bytes_per_kdk_step": b, "ms_per_kdk_step": ms_per_kdk, "achieved": gbs,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+
+
 def time_evolve(torch, sim, steps, warmup):
     # the second call records the evolution as a hipGraph; timed calls replay it
     for _ in range(max(warmup, 2)):
@@ -96,55 +110,82 @@ def time_kernel(torch, fn, reps, warmup=None):
     return sum(ts) / len(ts), ts[len(ts) // 2]
 
 
-def cpu_baseline(wl, budget_s=20.0):
-    """The FP64 oracle on a bounded sample: one box of the workload, as many KDK steps of
-    the workload's schedule as fit the budget, single thread."""
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo) and its logical CPU count."""
+    name = platform.processor() or "unknown CPU"
     try:
-        from threadpoolctl import threadpool_limits
-    except Exception:          # pragma: no cover
-        threadpool_limits = None
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return name, os.cpu_count() or 1
+
+
+def _oracle_box(args):
+    """One box of the oracle run (worker process): evolution of tile t, timed alone."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.scola import evolve_box
+    s1, s2, bc0, steps = args
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        evolve_box(s1, s2, bc0, steps)
+        return time.perf_counter() - t0
+
+
+def cpu_baseline(name="c1", max_workers=16):
+    """The FP64 oracle on the host's cores: the whole workload `name` (c1: 8 boxes of 48^3,
+    10 steps), the full-box set-up once, then its boxes evolved in parallel worker
+    processes (one box per process, as the boxes are independent), single-threaded BLAS in
+    each.  value = box particles x steps / wall time of the parallel evolution."""
+    import multiprocessing as mp
+
     import numpy as np
 
     import synthetic
     from oracle.cosmology import Cosmology, cola_schedule
-    from oracle.run import setup_full_box
-    from oracle.scola import box_force, lattice_positions
-    from oracle.tiling import Tile, boundary_potential0, extract_box_field
+    from oracle.run import box_inputs, setup_full_box
+    from oracle.tiling import uniform_tiling
 
-    ctx = threadpool_limits(1) if threadpool_limits else None
+    wl = synthetic.WORKLOADS[name]
+    c = Cosmology()
+    t0 = time.perf_counter()
+    phi1, phi2, psi1, psi2 = setup_full_box(synthetic.white_noise(wl.Np, 42), wl.L, c, wl.a_i)
+    tiles = uniform_tiling(wl.Np, wl.tiles_per_side, wl.buffer)
+    steps, _ = cola_schedule(c, wl.a_i, wl.a_f, wl.n_steps)
+    jobs = [(*box_inputs(psi1, psi2, phi1, t), steps) for t in tiles]
+    setup_s = time.perf_counter() - t0
+    model, ncpu = cpu_model()
+    workers = max(1, min(len(jobs), ncpu, max_workers))
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS",
+                                          "MKL_NUM_THREADS")}
+    for k in env:
+        os.environ[k] = "1"
     try:
-        c = Cosmology()
-        Np = wl.Np
-        phi1, phi2, psi1, psi2 = setup_full_box(synthetic.white_noise(Np, 42), wl.L, c, wl.a_i)
-        n = Np // wl.tiles_per_side
-        tile = Tile((0, 0, 0), n, wl.buffer)
-        M = tile.M
-        s1 = extract_box_field(psi1, tile).reshape(3, -1)
-        s2 = extract_box_field(psi2, tile).reshape(3, -1)
-        bc0 = boundary_potential0(phi1, tile)
-        steps, _ = cola_schedule(c, wl.a_i, wl.a_f, wl.n_steps)
-        q = lattice_positions(M).reshape(3, -1)
-        x_res = np.zeros_like(q)
-        p_res = np.zeros_like(q)
-        u = q - steps[0]["D1"] * s1 + steps[0]["D2"] * s2
+        # fork: called before this process touches the GPU (see main)
+        ctx = mp.get_context("fork")
         t0 = time.perf_counter()
-        g, _, _ = box_force(u, M, steps[0]["D1"] * bc0)
-        done = 0
-        for st in steps:
-            p_res += st["beta"] * (g - st["D1"] * s1 + (st["D2"] - st["D1"] ** 2) * s2)
-            x_res += st["alpha"] * p_res
-            u = q - st["D1_next"] * s1 + st["D2_next"] * s2 + x_res
-            g, _, _ = box_force(u, M, st["D1_next"] * bc0)
-            done += 1
-            if time.perf_counter() - t0 > budget_s:
-                break
-        dt = time.perf_counter() - t0
+        with ctx.Pool(workers) as pool:
+            per_box = pool.map(_oracle_box, jobs)
+        wall = time.perf_counter() - t0
     finally:
-        if ctx is not None:
-            ctx.unregister() if hasattr(ctx, "unregister") else None
-    return dict(value=M ** 3 * done / dt, unit="particle-steps/s", cores=1, kind="oracle",
-                sample=f"one {M}^3 box of {wl.name}, {done} KDK steps (force evaluation "
-                       f"included), FP64 NumPy, 1 thread, {platform.processor() or 'host CPU'}")
+        for k, v in env.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    P = sum(t.M ** 3 for t in tiles)
+    return dict(value=P * wl.n_steps / wall, unit="particle-steps/s", cores=workers,
+                kind="oracle",
+                sample=f"{name} in full: {len(tiles)} boxes of {tiles[0].M}^3, {wl.n_steps} "
+                       f"KDK steps, FP64 NumPy, one box per worker process ({workers} "
+                       f"processes, 1 BLAS thread each) on {model} ({ncpu} logical CPUs "
+                       f"visible); evolution wall {wall:.1f} s (pool start included), "
+                       f"per-box CPU {np.mean(per_box):.1f} s, full-box set-up {setup_s:.1f} s",
+                cpu_model=model, host_logical_cpus=ncpu, evolution_wall_s=wall,
+                setup_s=setup_s)
 
 
 def adjoint_timing(torch, S, synthetic, name="c4", reps=3):
@@ -197,13 +238,15 @@ def workload_rate(torch, S, synthetic, name, steps=3, warmup=2):
     sched = sim.tune(reps=3)
     ms, _ = time_evolve(torch, sim, steps, warmup)
     info = sim.info()
+    nodes = sum((M - 1) ** 3 for _, M, _, _ in sim.box_slices())
     out = {"workload": f"{name}: L={wl.L:g} Mpc/h, {wl.Np}^3 particles, {info['n_tiles']} "
                        f"boxes, {wl.n_steps} steps, {sim.precision} batched",
            "value": info["n_particles"] * wl.n_steps / (ms * 1e-3), "unit": "particle-steps/s",
            "ms_per_evolve": ms, "box_particles": info["n_particles"],
            "useful_particle_steps_per_s": wl.Np ** 3 * wl.n_steps / (ms * 1e-3),
            "launch_schedule": {str(k): v for k, v in sched.items()},
-           "concurrent_box_groups": sim.groups}
+           "concurrent_box_groups": sim.groups,
+           "whole_step_roofline": whole_step(info["n_particles"], nodes, ms / wl.n_steps)}
     del sim
     torch.cuda.empty_cache()
     return out
@@ -231,6 +274,13 @@ def main():
               "no multi-GPU path (see the design notes for how it would shard).",
               file=sys.stderr)
         sys.exit(2)
+
+    # the CPU baseline runs first, before this process initialises the GPU, so that its
+    # worker processes are forked from a process with no device state
+    cpu = None
+    if not args.no_cpu_baseline and not args.adjoint_only and not args.kernels_only \
+            and args.workload == "c2":
+        cpu = cpu_baseline("c1")
 
     import torch
 
@@ -291,6 +341,7 @@ def main():
         torch, lambda: sim.op_step(row[1], 0.0, row[3], row[4], row[3], row[4], True), 20)
     pois_avg, _ = time_kernel(torch, lambda: sim.op_poisson(row[3]), 20)
     algo_bytes = 96 * P if sim.precision == "fp32" else 144 * P
+    G = sum((M - 1) ** 3 for _, M, _, _ in sim.box_slices())
     traffic = measured_traffic() if wl.name == "c2" else None
     achieved = algo_bytes / (step_avg * 1e-3) / 1e9
 
@@ -302,6 +353,9 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "step": f"one benchmark step = one whole evolution of every box ({wl.n_steps} KDK "
+                f"steps: deposits, Poisson solves, fused particle steps)",
+        "ms_per_kdk_step": ms / wl.n_steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -323,7 +377,9 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic if sim.precision == "fp32" else None,
                      "kernel": "k_particles<float,1> (fused interp+kick+drift+deposit)",
-                     "algorithmic_bytes_per_launch": algo_bytes},
+                     "algorithmic_bytes_per_launch": algo_bytes,
+                     "whole_step": whole_step(P, G, ms / wl.n_steps)
+                     if sim.precision == "fp32" else None},
     }
     if not args.no_fp64 and args.workload == "c2":
         wl1 = synthetic.WORKLOADS["c1"]
@@ -355,8 +411,8 @@ def main():
             except Exception as exc:          # noqa: BLE001 - reported in the JSON line
                 result[key] = {"error": f"{type(exc).__name__}: {exc}"}
                 torch.cuda.empty_cache()
-    if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(wl)
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
     print(json.dumps(result), flush=True)
 
 

@@ -2,18 +2,21 @@
 
     python -m paper_2003_04925_amd.build
 
-Every .hip / .cpp file under csrc/ is compiled by hipcc in one invocation into a shared
-library exporting the C ABI declared in include/scola.h.
+Every .hip / .cpp file under csrc/ is compiled by hipcc into an object (in parallel, under
+_build/), then the objects are linked into a shared library exporting the C ABI declared in
+include/scola.h.
 """
 import glob
 import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libscola.so")
+OBJ_DIR = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 
 
@@ -24,21 +27,34 @@ def hipcc():
     return exe
 
 
-def build(verbose=False):
-    srcs = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")) +
-                  glob.glob(os.path.join(HERE, "csrc", "*.cpp")))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
-           # packed FP32 instructions are disabled for every device function
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-result", "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(HERE, "csrc"), *srcs, "-o", tmp]
+def flags():
+    return ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+            # packed FP32 instructions are disabled for every device function
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wno-unused-result", "-I", os.path.join(ROOT, "include"),
+            "-I", os.path.join(HERE, "csrc")]
+
+
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed")
+        raise RuntimeError("hipcc failed: " + " ".join(cmd[-3:]))
+
+
+def build(verbose=False, jobs=None):
+    srcs = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")) +
+                  glob.glob(os.path.join(HERE, "csrc", "*.cpp")))
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    objs = [os.path.join(OBJ_DIR, os.path.basename(s) + ".o") for s in srcs]
+    cmds = [[hipcc(), *flags(), "-c", s, "-o", o] for s, o in zip(srcs, objs)]
+    jobs = jobs or min(len(cmds), max(1, min(8, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(jobs) as ex:
+        list(ex.map(lambda c: _run(c, verbose), cmds))
+    tmp = LIB + ".tmp"
+    _run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 
