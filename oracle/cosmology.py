@@ -120,8 +120,12 @@ def time_grid(a_i, a_f, n_steps):
     return a_i + (a_f - a_i) * np.arange(n_steps + 1, dtype=np.float64) / n_steps
 
 
-def cola_schedule(cosmo, a_i, a_f, n_steps, want_final_kick=False):
+def cola_schedule(cosmo, a_i, a_f, n_steps, want_final_kick=False, discretisation="modified",
+                  n_lpt=N_LPT):
     """Scalars of the KDK operator E~ of App. B (eq. operator_E with K~, D~).
+
+    discretisation "modified" uses the time factors alpha~, beta~ with u(a) = a^n_lpt;
+    "standard" uses eq. alpha-beta-standard (integrals of the drift and kick prefactors).
 
     Reading: the product in eq. (operator_E) runs over i = 0..n-1 so that the last drift
     ends at t_{n+1} = a_f; with n_steps = n+1 drifts there are n_steps kicks before the
@@ -133,20 +137,26 @@ def cola_schedule(cosmo, a_i, a_f, n_steps, want_final_kick=False):
     t = time_grid(a_i, a_f, n_steps)
     half = 0.5 * (t[:-1] + t[1:])
     D1, dD1, D2, dD2 = cosmo.growth(t, a_i)
+    if discretisation == "standard":
+        beta = lambda ai, af, aD: cosmo.beta_standard(ai, af)
+        alpha = lambda ai, af, aK: cosmo.alpha_standard(ai, af)
+    else:
+        beta = lambda ai, af, aD: cosmo.beta_tilde(ai, af, aD, n_lpt)
+        alpha = lambda ai, af, aK: cosmo.alpha_tilde(ai, af, aK, n_lpt)
     steps = []
     for k in range(n_steps):
         aK_i = t[0] if k == 0 else half[k - 1]
         aK_f = half[k]
         steps.append(dict(
             a_D=t[k], a_next=t[k + 1],
-            beta=cosmo.beta_tilde(aK_i, aK_f, t[k]),
-            alpha=cosmo.alpha_tilde(t[k], t[k + 1], half[k]),
+            beta=beta(aK_i, aK_f, t[k]),
+            alpha=alpha(t[k], t[k + 1], half[k]),
             D1=D1[k], D2=D2[k], D1_next=D1[k + 1], D2_next=D2[k + 1],
         ))
     final = None
     if want_final_kick:
         n = n_steps
-        final = dict(a_D=t[n], beta=cosmo.beta_tilde(half[n - 1], t[n], t[n]),
+        final = dict(a_D=t[n], beta=beta(half[n - 1], t[n], t[n]),
                      D1=D1[n], D2=D2[n], dD1=dD1[n], dD2=dD2[n],
                      inv_drift=1.0 / cosmo.drift_prefactor(t[n]))
     return steps, final

@@ -54,15 +54,20 @@ def output_density(x_cells, Np, N_out):
 
 
 def run_scola(white_noise, L, tiles, cosmo=None, a_i=0.05, a_f=1.0, n_steps=10,
-              want_momenta=False, N_out=None, tile_subset=None):
+              want_momenta=False, N_out=None, tile_subset=None, discretisation="modified",
+              n_lpt=-2.5, tile_a_f=None):
     """Full tiled sCOLA run.  Returns dict with positions (3, Np, Np, Np) in Mpc/h in
     [0, L), momenta (or None) in Mpc/h (H0 = 1 units), the output density and the per-box
-    raw results.  Entries of tiles outside tile_subset are left NaN in the outputs."""
+    raw results.  Entries of tiles outside tile_subset are left NaN in the outputs.
+    discretisation, n_lpt: the time factors of App. B (see cola_schedule).
+    tile_a_f: optional final scale factor per tile (Sec. 5.1: tiles need not share one final
+    time; 0 or None entries mean a_f); each tile takes n_steps steps from a_i to its own."""
     cosmo = cosmo or Cosmology()
     Np = white_noise.shape[0]
     N_out = N_out or Np
     phi1, phi2, psi1, psi2 = setup_full_box(white_noise, L, cosmo, a_i)
-    steps, final = cola_schedule(cosmo, a_i, a_f, n_steps, want_final_kick=want_momenta)
+    steps, final = cola_schedule(cosmo, a_i, a_f, n_steps, want_final_kick=want_momenta,
+                                 discretisation=discretisation, n_lpt=n_lpt)
     pos = np.full((3, Np, Np, Np), np.nan)
     mom = np.full((3, Np, Np, Np), np.nan) if want_momenta else None
     boxes = {}
@@ -70,7 +75,12 @@ def run_scola(white_noise, L, tiles, cosmo=None, a_i=0.05, a_f=1.0, n_steps=10,
     for t in subset:
         tile = tiles[t]
         s1, s2, bc0 = box_inputs(psi1, psi2, phi1, tile)
-        out = evolve_box(s1, s2, bc0, steps, final)
+        st, fin = steps, final
+        if tile_a_f is not None and tile_a_f[t] and tile_a_f[t] != a_f:
+            st, fin = cola_schedule(cosmo, a_i, tile_a_f[t], n_steps,
+                                    want_final_kick=want_momenta,
+                                    discretisation=discretisation, n_lpt=n_lpt)
+        out = evolve_box(s1, s2, bc0, st, fin)
         boxes[t] = out
         gi, u = untile(tile, Np, out, "u")
         origin = np.array(tile.origin, dtype=np.float64)[:, None]

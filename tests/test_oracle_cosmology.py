@@ -58,6 +58,20 @@ def test_alpha_tilde_eds_closed_form():
         assert eds.alpha_tilde(ai, af, aK) == pytest.approx(exact, rel=1e-12)
 
 
+def test_standard_factors_eds_closed_form():
+    # App. B eq. alpha-beta-standard in EdS (E = a^-3/2): the drift prefactor 1/(a^3 E) =
+    # a^-3/2 and the kick prefactor -3/2 / (a^2 E) = -3/2 a^-1/2 integrate in closed form.
+    eds = Cosmology(Omega_m=1.0)
+    for ai, af in [(0.1, 0.2), (0.05, 0.145), (0.5, 1.0)]:
+        assert eds.alpha_standard(ai, af) == pytest.approx(
+            2.0 * (ai ** -0.5 - af ** -0.5), rel=1e-12)
+        assert eds.beta_standard(ai, af) == pytest.approx(
+            -3.0 * (af ** 0.5 - ai ** 0.5), rel=1e-12)
+    steps, _ = cola_schedule(eds, 0.1, 0.5, 4, discretisation="standard")
+    assert steps[1]["alpha"] == pytest.approx(2.0 * (0.2 ** -0.5 - 0.3 ** -0.5), rel=1e-12)
+    assert steps[1]["beta"] == pytest.approx(-3.0 * (0.25 ** 0.5 - 0.15 ** 0.5), rel=1e-12)
+
+
 def test_modified_factors_converge_to_standard_ones():
     # App. B: the modified factors approximate int D dt and int K dt; as the step shrinks
     # their ratio to the standard discretisation tends to 1 at second order.
