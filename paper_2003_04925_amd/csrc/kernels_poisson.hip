@@ -16,6 +16,7 @@
 // length 2M = 32 R (R = M / 16 in 1..8) runs on a half wavefront (32 lanes) entirely in
 // registers: each lane holds R points, an R-point DFT across registers, a twiddle, then a
 // 32-point radix-2 decimation-in-frequency FFT across lanes with xor shuffles.
+#include <atomic>
 #include <type_traits>
 
 #include "common.h"
@@ -281,17 +282,21 @@ __device__ __forceinline__ void small_dft(cx<T> (&x)[R]) {
   }
 }
 
-// K independent FFTs of length 32R on one half wavefront (interleaved for ILP); lane l
-// holds x[k][n2] = input k at position 32 n2 + n with n = fft_index(l).  On return lane l
-// holds Z_k at position k1 + R bitrev5(n) in x[k][k1] (negated where n is odd).
-// tw = W_{32R}^m, m < 32R (in LDS).
+// K independent complex FFTs of length N = 16R on one quarter wavefront (16 lanes),
+// interleaved for instruction-level parallelism.  Lane l holds x[k][n2] = input k at position
+// 16 n2 + n with n = fft_index(l) (4 bits); on return it holds Z_k at position
+// k1 + R bitrev4(n) in x[k][k1] (negated where n is odd).  The transform factors as an
+// R-point DFT across registers, the twiddle W_N^(n k1), and a 16-point radix-2
+// decimation-in-frequency FFT across lanes (every partner one DPP move away).
+// tw = W_2N^m, m < 2N (in LDS): W_N^i = tw[2 i], and the stage twiddles W_2S^m are the
+// same entries as for any N.
 template <int R, int K, typename T>
-__device__ __forceinline__ void halfwave_fft(cx<T> (&x)[K][R], const cx<T>* __restrict__ tw,
-                                             int n) {
+__device__ __forceinline__ void quarter_fft(cx<T> (&x)[K][R], const cx<T>* __restrict__ tw,
+                                            int n) {
   if constexpr (R > 1) {
     cx<T> tl[R];
 #pragma unroll
-    for (int k1 = 1; k1 < R; ++k1) tl[k1] = tw[n * k1];    // W_N^(n k1)
+    for (int k1 = 1; k1 < R; ++k1) tl[k1] = tw[2 * n * k1];    // W_N^(n k1)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       small_dft<R, T>(x[k]);
@@ -299,99 +304,204 @@ __device__ __forceinline__ void halfwave_fft(cx<T> (&x)[K][R], const cx<T>* __re
       for (int k1 = 1; k1 < R; ++k1) x[k][k1] = c_mul(x[k][k1], tl[k1]);
     }
   }
-  dif_stage<4, R, K, T>(x, tw, n);
   dif_stage<3, R, K, T>(x, tw, n);
   dif_stage<2, R, K, T>(x, tw, n);
   dif_stage<1, R, K, T>(x, tw, n);
   dif_stage<0, R, K, T>(x, tw, n);
 }
 
-// In-place DST-I (unnormalised, eq. DST_delta) of K pairs of lines (a_k, b_k), each n =
-// 16R - 1 values at the compile-time stride S in LDS; output j (1..n) of pair k is
-// multiplied by sa(k, j) / sb(k, j).  Pairs with valid[k] false are neither read nor
-// written.  Lane l loads positions m = 32 n2 + n(l) of the odd extension; the register n2
-// decides at compile time whether m lies in the lower half (a_m at index m - 1), the upper
-// half (-a_{2M-m} at index 2M - m - 1) or straddles m = M (odd R), so addresses are one
-// per-lane base plus immediate offsets.  The zero positions m = 0 and m = M read an
-// in-line entry (finite data) and are masked.
+__device__ inline int bitrev4(int l) { return (int)(__brev((unsigned)l) >> 28); }
+
+// v from the lane D places lower in the same 16-lane row (0 below the row's first lane).
+template <int D>
+__device__ __forceinline__ float row_shr(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + D, 0xF, 0xF,
+                                                    true));
+}
+template <int D>
+__device__ __forceinline__ double row_shr(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x110 + D, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x110 + D, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Inclusive prefix sum over the eight lanes t & 7 = 0..7 of each half of a 16-lane row.
+template <typename T>
+__device__ __forceinline__ T scan8(T v, int t) {
+  const int g = t & 7;
+  T s = row_shr<1>(v);
+  v += g >= 1 ? s : T(0);
+  s = row_shr<2>(v);
+  v += g >= 2 ? s : T(0);
+  s = row_shr<4>(v);
+  v += g >= 4 ? s : T(0);
+  return v;
+}
+
+// In-place DST-I (unnormalised, eq. DST_delta) of K pairs of lines (a_k, b_k), each
+// n = N - 1 = 16R - 1 values y_1..y_n at the compile-time stride S in LDS, one pair per
+// quarter wavefront; output j (1..n) of pair k is multiplied by sa(k, j) / sb(k, j).  Pairs
+// with valid[k] false are not written and has_b[k] false means line b is absent; the
+// pointers of absent lines must still point at readable LDS (their values are discarded).
+//
+// Method (the real-data sine transform through a half-length FFT of Cooley, Lewis and
+// Welch, as used in FFTPACK's sint): with y_0 = y_N = 0 and s_j = sin(pi j / N), the
+// sequence x_j = (s_j + 1/2) y_j + (s_j - 1/2) y_(N-j), j = 0..N-1, has the N-point DFT X
+// with S_2k = -Im X_k and S_(2k+1) - S_(2k-1) = Re X_k (S_-1 = -S_1): x_j splits into a part
+// symmetric under j -> N - j, which carries the odd sine sums, and an antisymmetric part,
+// which carries the even ones.  Two lines share one complex FFT, z = x^a + i x^b, separated
+// through X^a_k = (Z_k + conj Z_(N-k)) / 2 and X^b_k = (Z_k - conj Z_(N-k)) / 2i.  The
+// odd outputs are a prefix sum of Re X_k over k = 0..N/2-1, taken as a running sum inside
+// each lane followed by a scan over eight lanes.
+//
+// Steps: load and combine (lane base plus compile-time offsets), FFT, Z_k (k != N/2) written
+// over the pair's own lines (real parts to line a, imaginary parts to line b, slot k for
+// k < N/2 and k - 1 above; without line b the slots above N/2 take Im Z_(N-k), as Z is then
+// Hermitian), read back in pairs (Z_k, Z_(N-k)) by lane t & 7 for k in [R (t & 7),
+// R (t & 7) + R) of line a (t < 8) or line b (t >= 8), scan, outputs written.  A quarter
+// wavefront reads only the lines it wrote, in program order, so no barrier is needed.
 template <int R, int K, int S, typename T, typename SA, typename SB>
-__device__ __forceinline__ void dst_pairs(T* const (&la)[K], T* const (&lb)[K],
-                                          const bool (&valid)[K], const bool (&has_b)[K],
-                                          const cx<T>* tw, int l, SA sa, SB sb) {
-  constexpr int M = 16 * R;
-  const int nl = fft_index(l);   // this lane's data index within each 32-point transform
+__device__ __forceinline__ void dst_quarter(T* const (&la)[K], T* const (&lb)[K],
+                                            const bool (&valid)[K], const bool (&has_b)[K],
+                                            const cx<T>* tw, int l, SA sa, SB sb) {
+  constexpr int N = 16 * R, H = N / 2;
+  const int n = fft_index(l);    // data index of this lane (l < 16)
   cx<T> x[K][R];
 #pragma unroll
-  for (int k = 0; k < K; ++k)
-#pragma unroll
-    for (int n2 = 0; n2 < R; ++n2) {
-      const int m0 = 32 * n2;
-      int idx;
-      T sg;
-      if (m0 + 32 <= M) {
-        idx = m0 + nl - 1;
-        sg = T(1);
-        if (m0 == 0) {
-          idx = max(idx, 0);
-          sg = nl == 0 ? T(0) : T(1);
-        }
-      } else if (m0 >= M) {
-        idx = 2 * M - 1 - m0 - nl;
-        sg = T(-1);
-        if (m0 == M) {
-          idx = min(idx, M - 2);
-          sg = nl == 0 ? T(0) : T(-1);
-        }
-      } else {
-        const int m = m0 + nl;
-        const bool lo = m < M;
-        idx = min(max(lo ? m - 1 : 2 * M - m - 1, 0), M - 2);
-        sg = (m == 0 || m == M) ? T(0) : (lo ? T(1) : T(-1));
-      }
-      cx<T> v;
-      v.x = T(0);
-      v.y = T(0);
-      if (valid[k]) {
-        v.x = sg * la[k][idx * S];
-        if (has_b[k]) v.y = sg * lb[k][idx * S];
-      }
-      x[k][n2] = v;
-    }
-  halfwave_fft<R, K, T>(x, tw, nl);
-  // lane l holds Z at positions k1 + R bitrev5(n); the sine coefficients j = 1..M-1 sit on
-  // the lanes with even n (bitrev5(n) < 16)
-  const int br = bitrev5(nl);
-  if ((nl & 1) == 0) {
+  for (int n2 = 0; n2 < R; ++n2) {
+    const int j = 16 * n2 + n;
+    const T sj = -tw[j].y;                                   // sin(pi j / N)
+    const T cp = j > 0 ? sj + T(0.5) : T(0), cm = j > 0 ? sj - T(0.5) : T(0);
+    // y_j at index j - 1 and y_(N-j) at N - j - 1 = 16 (R - 1 - n2) + 15 - n: one lane base
+    // each plus compile-time offsets; j = 0 reads an in-line entry with zero weight
+    const int lo = n2 == 0 ? max(n - 1, 0) : 16 * n2 + n - 1;
+    const int hi = 16 * (R - 1 - n2) + 15 - n - (n2 == 0 && n == 0 ? 1 : 0);
+    // the loads are unconditional (absent lines point at readable LDS) and their values
+    // selected afterwards, so no branch precedes the FFT's hand-placed DPP blocks
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      if (!valid[k]) continue;
+      const T ya = la[k][lo * S], yna = la[k][hi * S];
+      const T yb = lb[k][lo * S], ynb = lb[k][hi * S];
+      cx<T> v;
+      v.x = valid[k] ? cp * ya + cm * yna : T(0);
+      v.y = valid[k] && has_b[k] ? cp * yb + cm * ynb : T(0);
+      x[k][n2] = v;
+    }
+  }
+  quarter_fft<R, K, T>(x, tw, n);
+  // lane n holds Z at k1 + R bitrev4(n), negated where n is odd
+  const int br = bitrev4(n);
+  const T sgn = (n & 1) ? T(-1) : T(1);
 #pragma unroll
-      for (int k1 = 0; k1 < R; ++k1) {
-        const int j = k1 + R * br;
-        if (k1 == 0 && br == 0) continue;
-        la[k][(j - 1) * S] = T(-0.5) * x[k][k1].y * sa(k, j);
-        if (has_b[k]) lb[k][(j - 1) * S] = T(0.5) * x[k][k1].x * sb(k, j);
+  for (int k = 0; k < K; ++k) {
+    if (!valid[k]) continue;
+#pragma unroll
+    for (int k1 = 0; k1 < R; ++k1) {
+      const int kk = k1 + R * br;
+      if (kk == H) continue;
+      const int slot = kk < H ? kk : kk - 1;
+      const T re = sgn * x[k][k1].x, im = sgn * x[k][k1].y;
+      if (has_b[k]) {
+        la[k][slot * S] = re;
+        lb[k][slot * S] = im;
+      } else {
+        la[k][slot * S] = kk < H ? re : -im;
       }
+    }
+  }
+  // read back (Z_k, Z_(N-k)) for this lane's k and form Re X_k and the even outputs; Re X_0
+  // (Re Z_0 for line a, Im Z_0 for line b: Z_0 is its own partner) is read by every lane
+  const int g = l & 7;
+  const bool line_b = l >= 8;
+  T rx[K][R], ev[K][R], half0[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    half0[k] = T(0);
+    if (valid[k]) half0[k] = T(0.5) * ((line_b && has_b[k]) ? lb[k][0] : la[k][0]);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int kk = R * g + m;                          // 0 .. N/2 - 1
+      const int sk = kk, sn = kk == 0 ? 0 : N - kk - 1;  // slots of Z_k and Z_(N-k)
+      T rz = T(0), rzn = T(0), iz = T(0), izn = T(0);
+      if (valid[k]) {
+        rz = la[k][sk * S];
+        if (has_b[k]) {
+          rzn = la[k][sn * S];
+          iz = lb[k][sk * S];
+          izn = lb[k][sn * S];
+        } else {
+          rzn = rz;
+          iz = kk == 0 ? T(0) : la[k][sn * S];
+          izn = -iz;
+        }
+      }
+      if (!line_b) {
+        rx[k][m] = T(0.5) * (rz + rzn);
+        ev[k][m] = T(0.5) * (izn - iz);
+      } else {
+        rx[k][m] = T(0.5) * (iz + izn);
+        ev[k][m] = T(0.5) * (rz - rzn);
+      }
+    }
+  }
+  // S_(2k+1) = sum_(m <= k) Re X_m - Re X_0 / 2: running sums in the lane, then the scan over
+  // the eight lanes of the line
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int m = 1; m < R; ++m) rx[k][m] += rx[k][m - 1];
+    const T incl = scan8(rx[k][R - 1], l);
+    const T offset = incl - rx[k][R - 1] - half0[k];
+#pragma unroll
+    for (int m = 0; m < R; ++m) rx[k][m] += offset;
+  }
+  // outputs: even j = 2k (k >= 1) at index 2k - 1, odd j = 2k + 1 at index 2k
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (!valid[k] || (line_b && !has_b[k])) continue;
+    T* const out = line_b ? lb[k] : la[k];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int kk = R * g + m;
+      if (kk >= 1)
+        out[(2 * kk - 1) * S] = ev[k][m] * (line_b ? sb(k, 2 * kk) : sa(k, 2 * kk));
+      out[2 * kk * S] = rx[k][m] * (line_b ? sb(k, 2 * kk + 1) : sa(k, 2 * kk + 1));
     }
   }
 }
 
+// Line pairs of a plane handled at once by one quarter wavefront (interleaved in registers):
+// a plane direction has 8R pairs for 16 quarter wavefronts, R / 2 each; the count is chosen so
+// that few register slots hold absent pairs while the registers stay below spilling.
+template <int R>
+struct PairBatch {
+  static constexpr int K = R == 3 ? 2 : 1;
+  static constexpr int rounds = (8 * R + 16 * K - 1) / (16 * K);
+};
+
 // DST-I of all lines of an n x n plane in LDS along one direction: lines at distance STEP,
-// entries at stride S; 8R line pairs, R per half wavefront, two at a time (independent
-// transforms interleaved for instruction-level parallelism; at R = 8 this takes about 104
-// VGPRs in FP32, still without spills).
+// entries at stride S.  Pair p = (lines 2p, 2p + 1) goes to quarter wavefront p mod 16.
 template <int R, int S, int STEP, typename T>
-__device__ __forceinline__ void plane_lines(T* plane, const cx<T>* tw, int hw, int l) {
-  constexpr int n = 16 * R - 1;
+__device__ __forceinline__ void plane_lines(T* plane, const cx<T>* tw, int qw, int l) {
+  constexpr int n = 16 * R - 1, pairs = 8 * R, K = PairBatch<R>::K;
   auto one = [](int, int) { return T(1); };
 #pragma unroll
-  for (int i = 0; i < R; i += 2) {
-    const int p0 = hw + 8 * i, p1 = hw + 8 * (i + 1);
-    T* const la[2] = {plane + 2 * p0 * STEP, plane + 2 * p1 * STEP};
-    T* const lb[2] = {plane + (2 * p0 + 1) * STEP, plane + (2 * p1 + 1) * STEP};
-    const bool valid[2] = {true, i + 1 < R};
-    const bool hb[2] = {2 * p0 + 1 < n, i + 1 < R && 2 * p1 + 1 < n};
-    dst_pairs<R, 2, S, T>(la, lb, valid, hb, tw, l, one, one);
+  for (int r = 0; r < PairBatch<R>::rounds; ++r) {
+    T* la[K];
+    T* lb[K];
+    bool valid[K], hb[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int pr = qw + 16 * (r * K + k);
+      valid[k] = pr < pairs;
+      hb[k] = 2 * pr + 1 < n;
+      la[k] = plane + (valid[k] ? 2 * pr : 0) * STEP;
+      lb[k] = plane + (valid[k] && hb[k] ? 2 * pr + 1 : 0) * STEP;
+    }
+    T* const (&cla)[K] = la;
+    T* const (&clb)[K] = lb;
+    dst_quarter<R, K, S, T>(cla, clb, valid, hb, tw, l, one, one);
   }
 }
 
@@ -399,10 +509,10 @@ __device__ __forceinline__ void plane_lines(T* plane, const cx<T>* tw, int hw, i
 template <int R, typename T>
 __device__ __forceinline__ void plane_dst(T* plane, const cx<T>* tw) {
   constexpr int n = 16 * R - 1;
-  const int hw = threadIdx.x >> 5, l = threadIdx.x & 31;
-  plane_lines<R, 1, n, T>(plane, tw, hw, l);
+  const int qw = threadIdx.x >> 4, l = threadIdx.x & 15;
+  plane_lines<R, 1, n, T>(plane, tw, qw, l);
   __syncthreads();
-  plane_lines<R, n, 1, T>(plane, tw, hw, l);
+  plane_lines<R, n, 1, T>(plane, tw, qw, l);
   __syncthreads();
 }
 
@@ -412,21 +522,30 @@ __device__ __forceinline__ void plane_dst(T* plane, const cx<T>* tw) {
 __device__ __forceinline__ double mass_units(unsigned long long r) { return (double)(long long)r; }
 __device__ __forceinline__ double mass_units(unsigned int r) { return (double)r; }
 
+// Value of a full-box periodic field [N^3] at the box's local node (jx, jy, jz).
+template <typename T>
+__device__ __forceinline__ T full_at(const T* f, int N, const TileDesc& t, int jx, int jy,
+                                     int jz) {
+  const int m = N - 1;   // N is a power of two
+  return f[((int64_t)((t.origin[0] + jx) & m) * N + ((t.origin[1] + jy) & m)) * N +
+           ((t.origin[2] + jz) & m)];
+}
+
 template <typename T>
 __device__ inline void load_twiddles(cx<T>* tw, const MeshArgs<T>& a, const TileDesc& t) {
   const cx<T>* src = reinterpret_cast<const cx<T>*>(a.twiddles) + t.tw_off;
   for (int i = threadIdx.x; i < 2 * t.M; i += blockDim.x) tw[i] = src[i];
 }
 
+// The three passes as device functions of one logical block L (< m.count) with the dynamic
+// LDS `smem`: called by their own kernels below and by the persistent step kernel.
 template <typename T, int R, bool ADJ>
-__global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m) {
-  const int L = logical_block(m);
-  if (L >= m.count) return;
+__device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const BlockMap& m, int L,
+                                                 unsigned char* smem) {
   const int b = m.base + L;
   const TileDesc t = a.tiles[m.tile[b]];
   const int x = m.local[b];
   constexpr int M = 16 * R, n = M - 1, Mp = M + 3;
-  extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
   T* plane = reinterpret_cast<T*>(smem + 2 * M * sizeof(cx<T>));
   load_twiddles(tw, a, t);
@@ -446,12 +565,18 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m
     // element per thread, its face values fetched before the mass so that the latencies
     // overlap); the two x-face planes need it everywhere.
     const bool xface = x == 0 || x == n - 1;
+    // Phi_BC at the padded node (A, B, C) (node = padded index - 1) over D1: Phi_BC^0, or the
+    // full-box potential over D1 in the consistency tests (D1 multiplies it back)
+    auto bcv = [&](int A, int B, int C) {
+      if (a.ov_phi) return (double)full_at(a.ov_phi, a.ov_N, t, A - 1, B - 1, C - 1) / D1;
+      return bc[((int64_t)A * Mp + B) * Mp + C];
+    };
     auto yz_term = [&](int y, int z) {
       double s = 0.0;
-      if (y == 0) s += bc[((int64_t)(x + 2) * Mp + 1) * Mp + z + 2];
-      if (y == n - 1) s += bc[((int64_t)(x + 2) * Mp + M + 1) * Mp + z + 2];
-      if (z == 0) s += bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + 1];
-      if (z == n - 1) s += bc[((int64_t)(x + 2) * Mp + y + 2) * Mp + M + 1];
+      if (y == 0) s += bcv(x + 2, 1, z + 2);
+      if (y == n - 1) s += bcv(x + 2, M + 1, z + 2);
+      if (z == 0) s += bcv(x + 2, y + 2, 1);
+      if (z == n - 1) s += bcv(x + 2, y + 2, M + 1);
       return s;
     };
     int pe = -1;
@@ -464,6 +589,7 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m
       pe = y * n + z;
       pterm = yz_term(y, z);
     }
+    unsigned long long found = 0;   // FP32 plans: the plane's total mass in units
     for (int e0 = 0; e0 < n * n; e0 += kBatch * kBlock) {
       Rho r[kBatch];
 #pragma unroll
@@ -476,9 +602,26 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m
         const int e = e0 + q * kBlock + threadIdx.x;
         if (e >= n * n) continue;
         a.rho[base + e] = Rho(0);
-        if constexpr (std::is_same<T, float>::value)
+        if constexpr (std::is_same<T, float>::value) {
           if (r[q] >= (1u << 31)) atomicAdd(a.alarm, 1ull);   // within a factor 2 of wrapping
+          found += r[q];
+        }
         plane[e] = (T)(mass_units(r[q]) * kUnit - 1.0);
+      }
+    }
+    if constexpr (std::is_same<T, float>::value) {
+      // mass identity of FP32 plans: summed over a box's planes, the mass found plus the
+      // mass dropped equals one unit per particle and deposit unless a 32-bit node wrapped
+      // (each wrap loses exactly 2^32 units); one atomic per wave
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) found += __shfl_xor(found, d);
+      if ((threadIdx.x & 63) == 0 && found != 0ull) atomicAdd(a.kept + m.tile[b], found);
+    }
+    if (a.ov_delta) {
+      // the deposit's mass was consumed above; the solve takes the full-box density
+      for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int y = e / n, z = e - (e / n) * n;
+        plane[e] = full_at(a.ov_delta, a.ov_N, t, x + 1, y + 1, z + 1);
       }
     }
     __syncthreads();
@@ -486,7 +629,7 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m
       const int A = x == 0 ? 1 : M + 1;   // padded x index of the face layer
       for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
         const int y = e / n, z = e - (e / n) * n;
-        const double s = bc[((int64_t)A * Mp + y + 2) * Mp + z + 2] + yz_term(y, z);
+        const double s = bcv(A, y + 2, z + 2) + yz_term(y, z);
         plane[e] = (T)((double)plane[e] - D1 * s);
       }
     } else {
@@ -509,35 +652,29 @@ template <int R, typename T>
 __device__ __forceinline__ void pencil_solve(T* tile, int cw, int y, int z0, const T* ev,
                                              const cx<T>* tw) {
   constexpr int M = 16 * R, pitch = kPencilChunk + 1;
-  const int hw = threadIdx.x >> 5, l = threadIdx.x & 31;
+  const int qw = threadIdx.x >> 4, l = threadIdx.x & 15;
   const T norm = T(8.0 / ((double)M * M * M));
   const T ly = ev[y];
-  // column pairs (2p, 2p+1) of the chunk, p = hw and hw + 8
-  const int p[2] = {hw, hw + 8};
-  T* const la[2] = {tile + 2 * p[0], tile + 2 * p[1]};
-  T* const lb[2] = {tile + 2 * p[0] + 1, tile + 2 * p[1] + 1};
-  const bool valid[2] = {2 * p[0] < cw, 2 * p[1] < cw};
-  const bool hb[2] = {2 * p[0] + 1 < cw, 2 * p[1] + 1 < cw};
-  T lza[2], lzb[2];
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    lza[k] = valid[k] ? ev[z0 + 2 * p[k]] : T(-1);
-    lzb[k] = hb[k] ? ev[z0 + 2 * p[k] + 1] : T(-1);
-  }
+  // column pair (2 qw, 2 qw + 1) of the chunk
+  T* const la[1] = {tile + 2 * qw};
+  T* const lb[1] = {tile + 2 * qw + 1};
+  const bool valid[1] = {2 * qw < cw};
+  const bool hb[1] = {2 * qw + 1 < cw};
+  const T lza = valid[0] ? ev[z0 + 2 * qw] : T(-1);
+  const T lzb = hb[0] ? ev[z0 + 2 * qw + 1] : T(-1);
   // forward DST along x, then Phi^{lmn} = delta^{lmn} 8/M^3 / (lambda_l + lambda_m + lambda_n)
-  auto sa = [&](int k, int j) { return norm * recip(ev[j - 1] + ly + lza[k]); };
-  auto sb = [&](int k, int j) { return norm * recip(ev[j - 1] + ly + lzb[k]); };
-  dst_pairs<R, 2, pitch, T>(la, lb, valid, hb, tw, l, sa, sb);
-  // the same half wavefront reads back only the lines it wrote
+  auto sa = [&](int, int j) { return norm * recip(ev[j - 1] + ly + lza); };
+  auto sb = [&](int, int j) { return norm * recip(ev[j - 1] + ly + lzb); };
+  dst_quarter<R, 1, pitch, T>(la, lb, valid, hb, tw, l, sa, sb);
+  // the same quarter wavefront reads back only the lines it wrote
   auto one = [](int, int) { return T(1); };
-  dst_pairs<R, 2, pitch, T>(la, lb, valid, hb, tw, l, one, one);
+  dst_quarter<R, 1, pitch, T>(la, lb, valid, hb, tw, l, one, one);
   __syncthreads();
 }
 
 template <typename T, int R>
-__global__ void __launch_bounds__(kBlock) k_poisson_p2(MeshArgs<T> a, BlockMap m) {
-  const int L = logical_block(m);
-  if (L >= m.count) return;
+__device__ __forceinline__ void poisson_p2_block(const MeshArgs<T>& a, const BlockMap& m, int L,
+                                                 unsigned char* smem) {
   const int b = m.base + L;
   const TileDesc t = a.tiles[m.tile[b]];
   constexpr int M = 16 * R, n = M - 1;
@@ -545,7 +682,6 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p2(MeshArgs<T> a, BlockMap m
   const int y = m.local[b] / nch, ch = m.local[b] - (m.local[b] / nch) * nch;
   const int z0 = ch * kPencilChunk, cw = min(kPencilChunk, n - z0);
   constexpr int pitch = kPencilChunk + 1;
-  extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
   T* ev = reinterpret_cast<T*>(smem + 2 * M * sizeof(cx<T>));
   T* tile = ev + M;
@@ -571,9 +707,8 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p2(MeshArgs<T> a, BlockMap m
 }
 
 template <typename T, int R, bool ADJ>
-__global__ void __launch_bounds__(kBlock) k_poisson_p3(MeshArgs<T> a, BlockMap m) {
-  const int L = logical_block(m);
-  if (L >= m.count) return;
+__device__ __forceinline__ void poisson_p3_block(const MeshArgs<T>& a, const BlockMap& m, int L,
+                                                 unsigned char* smem) {
   const int b = m.base + L;
   const TileDesc t = a.tiles[m.tile[b]];
   const int local = m.local[b];
@@ -586,11 +721,16 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p3(MeshArgs<T> a, BlockMap m
     // one of the four shell planes a = 0, 1, M+1, M+2 (node -1, 0, M, M+1)
     const int s = local - n;
     const int A = s < 2 ? s : M + s - 1;
+    if (a.ov_phi) {
+      for (int e = threadIdx.x; e < Mp * Mp; e += blockDim.x)
+        phi[(int64_t)A * Mp * Mp + e] = full_at(a.ov_phi, a.ov_N, t, A - 1, e / Mp - 1,
+                                                e - (e / Mp) * Mp - 1);
+      return;
+    }
     for (int e = threadIdx.x; e < Mp * Mp; e += blockDim.x)
       phi[(int64_t)A * Mp * Mp + e] = (T)(D1 * bc[(int64_t)A * Mp * Mp + e]);
     return;
   }
-  extern __shared__ __align__(16) unsigned char smem[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
   T* plane = reinterpret_cast<T*>(smem + 2 * M * sizeof(cx<T>));
   load_twiddles(tw, a, t);
@@ -654,6 +794,11 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p3(MeshArgs<T> a, BlockMap m
       const int i = q * kBlock + threadIdx.x;
       if (i < kBorder) border[i] = (T)(D1 * bval[q]);
     }
+    if (a.ov_phi)
+      for (int i = threadIdx.x; i < kBorder; i += blockDim.x) {
+        const int o = border_offset(i);
+        border[i] = full_at(a.ov_phi, a.ov_N, t, A - 1, o / Mp - 1, o - (o / Mp) * Mp - 1);
+      }
   }
   __syncthreads();
   plane_dst<R, T>(plane, tw);
@@ -703,6 +848,27 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p3(MeshArgs<T> a, BlockMap m
   for (int i = threadIdx.x; i < kBorder; i += blockDim.x) out[border_offset(i)] = border[i];
 }
 
+template <typename T, int R, bool ADJ>
+__global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int L = logical_block(m);
+  if (L < m.count) poisson_p1_block<T, R, ADJ>(a, m, L, smem);
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(kBlock) k_poisson_p2(MeshArgs<T> a, BlockMap m) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int L = logical_block(m);
+  if (L < m.count) poisson_p2_block<T, R>(a, m, L, smem);
+}
+
+template <typename T, int R, bool ADJ>
+__global__ void __launch_bounds__(kBlock) k_poisson_p3(MeshArgs<T> a, BlockMap m) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int L = logical_block(m);
+  if (L < m.count) poisson_p3_block<T, R, ADJ>(a, m, L, smem);
+}
+
 inline unsigned padded_grid(const BlockMap& m) {
   if (!m.xcd_remap) return (unsigned)m.count;
   return (unsigned)(((m.count + 7) / 8) * 8);
@@ -729,16 +895,24 @@ hipError_t launch_poisson_R(const MeshArgs<T>& a, const BlockMap& p1, const Bloc
   const size_t l1 = poisson_lds_bytes<T>(16 * R, 1), l2 = poisson_lds_bytes<T>(16 * R, 2),
                l3 = poisson_lds_bytes<T>(16 * R, 3);
   if (l1 > 65536 || l2 > 65536 || l3 > 65536) {
-    static bool done = false;     // allow more than 64 KiB of dynamic LDS (160 KiB on gfx950)
-    if (!done) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p1<T, R, ADJ>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)l1);
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p2<T, R>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2);
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p3<T, R, ADJ>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3);
-      (void)hipGetLastError();
-      done = true;
+    // allow more than 64 KiB of dynamic LDS (160 KiB on gfx950): a function attribute of
+    // each device, set once per device
+    static std::atomic<uint64_t> done{0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = dev < 64 ? (1ull << dev) : 0ull;
+    if (!bit || !(done.load() & bit)) {
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p1<T, R, ADJ>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)l1);
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p2<T, R>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2);
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p3<T, R, ADJ>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3);
+      if (e != hipSuccess) return e;
+      done.fetch_or(bit);
     }
   }
   if (p1.count > 0)

@@ -76,3 +76,51 @@ def test_poisson_dpp_blocks_have_no_exec_hazard(tmp_path):
     count, problems = dpp_hazards(out.read_text())
     assert count > 0
     assert not problems, problems[:5]
+
+
+def lds_dma_waits(asm_text):
+    """(number of direct-to-LDS loads, list of problems): after each global_load_lds, the
+    next s_barrier must be preceded by an s_waitcnt that waits for every vector memory
+    operation (vmcnt(0)), so that other waves read the staged words only once they landed."""
+    lines = [l.strip() for l in asm_text.split("\n")]
+    loads, problems = 0, []
+    for i, t in enumerate(lines):
+        if not t.startswith("global_load_lds"):
+            continue
+        loads += 1
+        waited = False
+        for u in lines[i + 1:]:
+            if u.startswith("s_waitcnt") and re.search(r"vmcnt\(0\)", u):
+                waited = True
+            if u.startswith("global_load_lds"):
+                waited = False
+            if u.startswith("s_barrier"):
+                if not waited:
+                    problems.append((i, t))
+                break
+            if u.startswith("s_endpgm"):
+                break
+    return loads, problems
+
+
+def test_lds_dma_scan_flags_a_missing_wait():
+    bad = "\tglobal_load_lds_dword v1, s[0:1]\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier"
+    assert lds_dma_waits(bad)[1]
+    ok = "\tglobal_load_lds_dword v1, s[0:1]\n\ts_waitcnt vmcnt(0)\n\ts_barrier"
+    assert lds_dma_waits(ok) == (1, [])
+
+
+def test_particle_direct_lds_staging_waits_before_barrier(tmp_path):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    out = tmp_path / "particles.s"
+    cmd = [hipcc, "-O3", "-std=c++17", "--offload-arch=gfx950", "--cuda-device-only", "-S",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result",
+           "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           os.path.join(CSRC, "kernels_particles.hip"), "-o", str(out)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    loads, problems = lds_dma_waits(out.read_text())
+    assert loads > 0
+    assert not problems, problems[:5]
