@@ -46,6 +46,8 @@ struct TileDesc {
   int64_t h_off;           // first padded node in phi/bc0 ((M+3)^3 per box)
   int32_t tw_off;          // first entry of this M's twiddle table (2M complex values)
   int32_t ev_off;          // first entry of this M's eigenvalue table (M-1 values)
+  int32_t tclass;          // time class: index of the tile's final scale factor in the plan
+  double D1f, D2f;         // growth factors at the tile's final scale factor
 };
 
 // Scalars of one fused particle step (App. B): kick factor, drift factor and the growth

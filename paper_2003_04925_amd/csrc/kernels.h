@@ -47,7 +47,8 @@ template <typename T>
 struct MeshArgs {
   const TileDesc* tiles;
   typename MeshFixed<T>::rho_t* rho;   // fixed-point mass
-  unsigned long long* alarm;           // count of FP32-plan nodes holding >= 2^31 units
+  unsigned long long* alarm;           // count of FP32-plan node visits finding >= 2^31 units
+  unsigned long long* kept;            // FP32 plans: per tile, the mass the passes found
   T* work;
   T* phi;
   const double* bc0;
@@ -58,6 +59,13 @@ struct MeshArgs {
   // the boundary-source transpose accumulated into lam_bc0
   T* lam_rho = nullptr;
   double* lam_bc0 = nullptr;
+  // consistency tests of Sec. 4.3 (forward solve only): when set, the density contrast of
+  // the interior nodes (ov_delta) and/or the potential of the face layers and the shell
+  // (ov_phi, in place of D1_bc Phi_BC^0) are taken from full-box periodic fields [N^3] at
+  // the nodes' global positions (box origin + node, wrapped)
+  const T* ov_delta = nullptr;
+  const T* ov_phi = nullptr;
+  int ov_N = 0;
 };
 
 template <typename T>
@@ -71,6 +79,7 @@ struct ParticleArgs {
   const T* phi;
   typename MeshFixed<T>::rho_t* rho;
   unsigned long long* dropped;
+  unsigned long long* deposits;   // FP32 plans: deposits per tile (for the mass identity)
   // per brick of 256 particles: the packed cell extent of its last deposit, written by
   // every depositing launch and, with use_hints, tried by the force pass before it
   // reduces the extent itself (a stale entry costs time, never a result)
@@ -166,6 +175,33 @@ hipError_t fft3d_inverse(double2* c, int N, hipStream_t s);
 hipError_t launch_ic_filter(const SetupArgs& a, hipStream_t s);
 hipError_t launch_inverse_laplacian(double2* c, int N, hipStream_t s);
 hipError_t launch_take_real(const double2* c, double* out, double scale, int64_t n, hipStream_t s);
+
+// Monolithic periodic tCOLA of the full box (N^3 particles in lattice order, [3][N^3]
+// component arrays, a periodic N^3 node grid).
+template <typename T>
+struct TcolaArgs {
+  const double* psi1;
+  const double* psi2;
+  T* xres;
+  T* pres;
+  unsigned long long* rho;   // [N^3] fixed-point mass, 2^40 units per particle
+  const T* phi;              // [N^3] periodic potential
+  int N;
+  StepScalars sc;
+};
+
+template <typename T>
+hipError_t launch_tcola_setup(const TcolaArgs<T>& a, const double* phi1, const double* phi2,
+                              hipStream_t s);
+template <typename T>
+hipError_t launch_tcola_particles(const TcolaArgs<T>& a, int mode, hipStream_t s);
+// rec_delta / rec_phi: optional N^3 arrays receiving this solve's delta and potential
+template <typename T>
+hipError_t launch_tcola_poisson(const TcolaArgs<T>& a, double2* cbuf, T* phi, T* rec_delta,
+                                T* rec_phi, hipStream_t s);
+template <typename T>
+hipError_t launch_tcola_output(const TcolaArgs<T>& a, T* pos, T* mom, unsigned long long* grid,
+                               T* density, int N_out, double cell, double L, hipStream_t s);
 
 constexpr int kPencilChunk = 32;   // z-columns per block of the x-pencil pass
 

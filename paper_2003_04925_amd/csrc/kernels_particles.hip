@@ -26,33 +26,6 @@ namespace scola {
 
 namespace {
 
-// Fixed-point CiC weights of the 8 corners (offset bits x = 4, y = 2, z = 1) of a particle
-// at fractional offsets (fx, fy, fz), as integers of type I with `one` units per particle.
-// The unit is split along x into round(fx one) and the rest, each of the two parts along y
-// the same way, and each of the four parts along z.  Every split is exact in integers, so
-// the eight weights are non-negative and sum to exactly one unit, with no remainder to
-// place; each is within three units of its exact value.  F is the floating type the products
-// are formed in (float for 2^21 units, double for 2^40): the integers stay below 2^24 and
-// 2^53, and adding one half before truncation rounds the non-negative products.
-template <typename I, typename F>
-__device__ __forceinline__ void split_weights(F fx, F fy, F fz, I one, I (&w)[8]) {
-  const I x1 = (I)fma(fx, (F)one, F(0.5));
-  const I x[2] = {one - x1, x1};
-  I xy[4];
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const I hi = (I)fma(fy, (F)x[q], F(0.5));
-    xy[2 * q] = x[q] - hi;
-    xy[2 * q + 1] = hi;
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const I hi = (I)fma(fz, (F)xy[q], F(0.5));
-    w[2 * q] = xy[q] - hi;
-    w[2 * q + 1] = hi;
-  }
-}
-
 // Integer type of one particle's fixed-point corner weights: 64-bit for the 2^40 units of
 // FP64 plans, 32-bit for the 2^21 units of FP32 plans.
 template <typename T>
@@ -333,7 +306,10 @@ __device__ __forceinline__ void block_force(const T* __restrict__ phi, int M, do
   bool held = false;
   if (hinted) {
     hint_to_slots(in, j0, cr, bounds);
-    __syncthreads();   // also completes the direct staging
+    // the direct-to-LDS loads of this wave must have landed before the barrier releases the
+    // other waves to read them: the barrier's workgroup fence does not wait for them
+    if (staged) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
     held = hint_holds(bounds);
   }
   if (!held) cr = block_cells(in, j0, bounds);
@@ -405,12 +381,11 @@ __device__ __forceinline__ void block_force(const T* __restrict__ phi, int M, do
   __syncthreads();   // every thread is done with `bounds` and the window before reuse
 }
 
-// OCC: waves per SIMD the register allocation is held to (6 or 8); a schedule choice.
-template <typename T, int MODE, int OCC>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OCC)))
-k_particles(ParticleArgs<T> a, BlockMap m) {
-  const int L = logical_block(m);
-  if (L >= m.count) return;
+// The fused particle step of logical block L (< m.count): called by k_particles below and by
+// the persistent step kernel.
+template <typename T, int MODE>
+__device__ __forceinline__ void particles_block(const ParticleArgs<T>& a, const BlockMap& m,
+                                                int L) {
   const int b = m.base + L;
   const int ti = m.tile[b];
   const TileDesc t = a.tiles[ti];
@@ -509,6 +484,18 @@ k_particles(ParticleArgs<T> a, BlockMap m) {
   if (drop != 0) atomicAdd(&block_drop, (unsigned long long)drop);
   __syncthreads();
   if (threadIdx.x == 0 && block_drop != 0ull) atomicAdd(a.dropped + ti, block_drop);
+  // FP32 plans count the deposits of every box (its first block, once per launch) for the
+  // mass identity that detects a wrapped 32-bit node (see the Poisson pass)
+  if constexpr (MeshFixed<T>::bits < 32)
+    if (threadIdx.x == 0 && m.local[b] == 0) atomicAdd(a.deposits + ti, 1ull);
+}
+
+// OCC: waves per SIMD the register allocation is held to (6 or 8); a schedule choice.
+template <typename T, int MODE, int OCC>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OCC)))
+k_particles(ParticleArgs<T> a, BlockMap m) {
+  const int L = logical_block(m);
+  if (L < m.count) particles_block<T, MODE>(a, m, L);
 }
 
 __global__ void k_zero_u32(unsigned* p, int64_t n) {
@@ -552,7 +539,8 @@ __global__ void __launch_bounds__(kBlock) k_output(OutputArgs<T> a, BlockMap m, 
   double ug[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double u = lpt_base(idx[c] + 0.5, a.D1, a.psi1[c * P + p], a.D2, a.psi2[c * P + p]) +
+    // the tile's own final growth factors (tiles may end at different scale factors)
+    const double u = lpt_base(idx[c] + 0.5, t.D1f, a.psi1[c * P + p], t.D2f, a.psi2[c * P + p]) +
                      (double)a.xres[c * P + p];
     ug[c] = t.origin[c] + u;
     if (a.pos) {

@@ -208,5 +208,32 @@ __device__ __forceinline__ CellRange block_cells_max(bool in, const int (&j0)[3]
   return cells_decode(q);
 }
 
+// Fixed-point CiC weights of the 8 corners (offset bits x = 4, y = 2, z = 1) of a particle
+// at fractional offsets (fx, fy, fz), as integers of type I with `one` units per particle.
+// The unit is split along x into round(fx one) and the rest, each of the two parts along y
+// the same way, and each of the four parts along z.  Every split is exact in integers, so
+// the eight weights are non-negative and sum to exactly one unit, with no remainder to
+// place; each is within three units of its exact value.  F is the floating type the products
+// are formed in (float for 2^21 units, double for 2^40): the integers stay below 2^24 and
+// 2^53, and adding one half before truncation rounds the non-negative products.
+template <typename I, typename F>
+__device__ __forceinline__ void split_weights(F fx, F fy, F fz, I one, I (&w)[8]) {
+  const I x1 = (I)fma(fx, (F)one, F(0.5));
+  const I x[2] = {one - x1, x1};
+  I xy[4];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const I hi = (I)fma(fy, (F)x[q], F(0.5));
+    xy[2 * q] = x[q] - hi;
+    xy[2 * q + 1] = hi;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const I hi = (I)fma(fz, (F)xy[q], F(0.5));
+    w[2 * q] = xy[q] - hi;
+    w[2 * q + 1] = hi;
+  }
+}
+
 }  // namespace
 }  // namespace scola
