@@ -24,7 +24,7 @@
  *  - Box layout: a box of M = core_n + 2 buffer particles per side holds its particles at
  *    local positions i + 1/2; PM nodes sit at integer local positions, the Dirichlet problem
  *    has M - 1 unknowns per side and the potential is padded to [-1, M+1] (FDA order 2,
- *    N_ghost = 1).  M must be a multiple of 16 in [16, 128].
+ *    N_ghost = 1).  M is one of 16, 32, 48, ..., 128 (see scola_tile).
  */
 #ifndef SCOLA_H
 #define SCOLA_H
@@ -44,11 +44,13 @@ typedef enum {
   SCOLA_ENOMEM = -2,       /* host or plan-owned device allocation failed */
   SCOLA_EDEVICE = -3,      /* a HIP call failed (launch, copy, event) */
   SCOLA_ESTATE = -4,       /* call order violated (e.g. evolve before setup) */
-  SCOLA_EUNSUPPORTED = -5  /* valid request outside what the library implements */
+  SCOLA_EUNSUPPORTED = -5, /* valid request outside what the library implements */
+  SCOLA_EOVERFLOW = -6     /* a fixed-point mesh value left its range (see scola_mass_alarm) */
 } scola_status;
 
 enum { SCOLA_FP32 = 0, SCOLA_FP64 = 1 };           /* particle/mesh arithmetic */
 enum { SCOLA_BATCHED = 0, SCOLA_PER_TILE = 1 };    /* all tiles per launch, or one tile */
+enum { SCOLA_MODIFIED = 0, SCOLA_STANDARD = 1 };   /* COLA time factors of App. B */
 
 /* Flat LambdaCDM (Sec. 4: Planck 2015 values; Omega_L = 1 - Omega_m). */
 typedef struct {
@@ -56,21 +58,47 @@ typedef struct {
 } scola_cosmology;
 
 /* One tile (Sec. 3.2, B.1): core particles [core_lo, core_lo + core_n) per axis of the
- * global lattice (indices, wrapped mod N_p), surrounded by `buffer` particles per side. */
+ * global lattice (indices, wrapped mod N_p), surrounded by `buffer` particles per side.
+ * mesh[a]: PM cells per side of the box's mesh along axis a (Sec. 3.2 B.1: N_g).  0 means
+ * M = core_n + 2 buffer, the particles per side of the box, which is the only mesh the
+ * library implements (the PM node spacing then equals the lattice spacing); any other value
+ * is refused with SCOLA_EUNSUPPORTED.
+ * Admitted box sizes: M = 16 R for R = 1..8, i.e. {16, 32, 48, 64, 80, 96, 112, 128}: the
+ * particles of a box are stored in bricks of 4 x 8 x 8 and every 1-D transform of the
+ * Poisson solve is an FFT of 16 R points on 16 lanes.  These are the members of
+ * 2^a {1, 3, 5, 7} that are multiples of 16 up to 128; other sizes of that form (24, 40, 56,
+ * 192, 256, ...) are refused with SCOLA_EUNSUPPORTED. */
 typedef struct {
   int32_t core_lo[3];
   int32_t core_n;
   int32_t buffer;
+  int32_t mesh[3];
+  double a_f;              /* final scale factor of this tile (Sec. 5.1, light cones: tiles
+                              need not share one final time): 0 -> cfg.a_f, else > a_i.  Each
+                              tile takes cfg.n_steps steps linearly spaced from a_i to its a_f;
+                              tiles of one box size and final time share launches.  The reverse
+                              mode needs one final time for all tiles (else SCOLA_EUNSUPPORTED). */
 } scola_tile;
 
 /* Run parameters (Sec. 3, Sec. 4). */
 typedef struct {
   double L;                /* box side, Mpc/h, > 0 */
-  int32_t Np;              /* particles per side; the LPT grid has N = N_p nodes; power of
-                              two in [8, 1024] */
+  int32_t Np;              /* particles per side; power of two in [8, 1024] */
+  int32_t N_lpt;           /* LPT grid nodes per side (Sec. 3.1, A.1: N); 0 -> N_p, the only
+                              grid implemented (its nodes coincide with the particles); a
+                              divisor of N_p such as N_p / 2 is refused with
+                              SCOLA_EUNSUPPORTED, anything else with SCOLA_EINVAL */
   int32_t N_out;           /* output density grid per side (0 -> N_p) */
+  int32_t fda_order;       /* finite-difference order of the Laplacian and gradient (Sec. 3.4.2,
+                              App. C.2); 0 -> 2, the only order implemented; 4 and 6 are
+                              refused with SCOLA_EUNSUPPORTED, other values with SCOLA_EINVAL */
   int32_t n_steps;         /* KDK steps, linearly spaced in a (Sec. 4), >= 1 */
   double a_i, a_f;         /* initial / final scale factor, 0 < a_i < a_f */
+  double n_lpt;            /* exponent of u(a) = a^n_LPT in the modified time factors (App. B);
+                              0 -> -2.5, the paper's value; must be finite */
+  int32_t discretisation;  /* SCOLA_MODIFIED (App. B, modified time factors with n_lpt) or
+                              SCOLA_STANDARD (App. B eq. alpha-beta-standard: integrals of
+                              the drift and kick prefactors) */
   int32_t precision;       /* SCOLA_FP32 or SCOLA_FP64 */
   int32_t schedule;        /* SCOLA_BATCHED or SCOLA_PER_TILE */
   int32_t want_momenta;    /* nonzero: evaluate the last force and apply the final half
@@ -94,11 +122,16 @@ typedef struct {
   size_t work;             /* R [G]: sine-space scratch of the Poisson solve */
   size_t phi;              /* R [H]: potential on the padded node grid [-1, M+1]^3 */
   size_t bc0;              /* double [H]: Phi_BC^0 (LEP boundary potential at D1 = 1) */
-  size_t dropped;          /* int64 [n_tiles + 1]: fixed-point mass dropped by the deposits
-                              since the last reset, per tile; then the mass alarm: the number
-                              of node visits by the Poisson pass that found >= 2^31 units on
-                              an FP32-plan node (1024 particles, within a factor 2 of the
-                              32-bit range).  scola_evolve and scola_op_deposit reset all. */
+  size_t dropped;          /* int64 [3 n_tiles + 1], counters since the last reset: the
+                              fixed-point mass dropped by the deposits, per tile; the number of
+                              node visits by the Poisson pass that found >= 2^31 units on an
+                              FP32-plan node (1024 particles, within a factor 2 of the 32-bit
+                              range); then, FP32 plans only, per tile the mass the Poisson
+                              passes found and per tile the number of deposits (mass identity:
+                              found + dropped = deposits x M^3 x 2^21 units unless a node's
+                              32-bit mass wrapped, which loses exactly 2^32 units).
+                              scola_evolve and scola_op_deposit reset all; scola_mass_alarm
+                              evaluates them. */
   size_t cells;            /* uint32 [P / 256][4]: per brick of 256 particles (lattice order
                               within a box), the block cell extent of its last deposit, packed;
                               the force pass of the next step tries it before reducing the
@@ -209,9 +242,22 @@ scola_status scola_setup(scola_plan* plan, const double* d_white_noise, void* d_
 scola_status scola_evolve(scola_plan* plan, const int32_t* tile_subset, int32_t n_subset,
                           void* d_workspace, hipStream_t stream);
 
+/* The consistency tests of Sec. 4.3 (eqs. test_setup1-4): scola_evolve over all tiles in
+ * which the density contrast of every box's interior nodes (d_delta) and/or the potential
+ * of its face layers and shell (d_phi, in place of the linearly evolving D1 Phi_BC^0) are
+ * taken at every force evaluation from full-box periodic fields, such as the record of
+ * scola_tcola_forward: R [n_force][N_p^3], evaluation k at t_k, read at the nodes' global
+ * positions (box origin + node, wrapped).  Either pointer may be NULL (both NULL is the
+ * method itself, eq. test_setup1).  With both, every box reproduces the periodic tCOLA run
+ * in its core to round-off (eq. test_setup4).  Runs eagerly on `stream` with one box group;
+ * needs scola_setup on the workspace (else SCOLA_ESTATE). */
+scola_status scola_evolve_overrides(scola_plan* plan, const void* d_delta, const void* d_phi,
+                                    void* d_workspace, hipStream_t stream);
+
 /* Launch schedule (not a quantity of the paper; results are bitwise identical under every
- * schedule).  Boxes are grouped by size M into classes (ascending M); every class has its
- * own launches of the fused particle kernel and of the Poisson passes.  Per class:
+ * schedule).  Boxes are grouped into classes of equal size M and final scale factor
+ * (ascending M); every class has its own launches of the fused particle kernel and of the
+ * Poisson passes.  Per class:
  *   waves_per_simd       6 or 8: register budget the fused particle kernel is compiled for
  *                        (6 = 80 registers, 8 = 64; FP64 plans need more than 64 and run
  *                        at the occupancy their registers allow);
@@ -311,6 +357,38 @@ scola_status scola_schedule_table(const scola_config* cfg, const scola_cosmology
                                   double* rows, int32_t rows_capacity);
 scola_status scola_linear_power(const scola_cosmology* cosmo, const double* k, double* out,
                                 int32_t n);
+
+/* Monolithic periodic tCOLA of the plan's full box (Sec. 2.2, App. A eqs. drift-cola and
+ * kick-tcola, App. B): the N_p^3 particles evolved together with a periodic PM grid of N_p^3
+ * nodes (one per lattice cell, at integer positions of the lattice coordinate whose particles
+ * sit at i + 1/2), periodic CiC deposit and interpolation, the FDA-2 Poisson equation solved
+ * by FFT (FP64 transforms), the central-difference gradient, and the plan's KDK schedule and
+ * precision; the tiling of the plan is not used.  It is the reference of the sCOLA accuracy
+ * study (Sec. 4.2) and the source of the true density and potential of the consistency tests
+ * (Sec. 4.3).
+ * d_workspace: at least scola_tcola_workspace_size bytes, 256-byte aligned (independent of
+ *   the sCOLA workspace).
+ * d_pos, d_mom, d_density: as for scola_forward (each may be NULL; d_mom needs
+ *   cfg.want_momenta).
+ * d_record_delta, d_record_phi: NULL, or R [n_force][N_p^3] arrays receiving the density
+ *   contrast and the potential of every force evaluation, n_force = n_steps (+1 with
+ *   cfg.want_momenta); evaluation k is at t_k, the first at a_i. */
+scola_status scola_tcola_workspace_size(const scola_plan* plan, size_t* bytes);
+scola_status scola_tcola_forward(scola_plan* plan, const double* d_white_noise, void* d_pos,
+                                 void* d_mom, void* d_density, void* d_record_delta,
+                                 void* d_record_phi, void* d_workspace, hipStream_t stream);
+
+/* The mass alarm of the workspace (FP32 plans; always zero for FP64 plans, whose 64-bit
+ * node masses cannot wrap): *near_limit = node visits that found at least 1024 particles'
+ * mass on a node since the last reset, *wrapped = the number of times a node's 32-bit mass
+ * wrapped (a node above 2048 particles), from the exact mass identity of every box (see
+ * scola_layout.dropped).  Valid after scola_evolve / scola_forward, and after operator-level
+ * calls in which every deposit was followed by scola_op_poisson (otherwise SCOLA_ESTATE).
+ * Synchronises `stream` (the counters are copied to the host after the work enqueued so
+ * far).  Returns SCOLA_EOVERFLOW, with the counts written and a message, when *wrapped > 0:
+ * the densities and forces of that run are invalid.  Either output pointer may be NULL. */
+scola_status scola_mass_alarm(const scola_plan* plan, const void* d_workspace,
+                              hipStream_t stream, int64_t* near_limit, int64_t* wrapped);
 
 /* Diagnostics of the plan: number of tiles, total box particles, r and p (Sec. 3.2). */
 scola_status scola_plan_info(const scola_plan* plan, int32_t* n_tiles, int64_t* n_particles,

@@ -54,17 +54,21 @@ def uniform_tiling(Np, tiles_per_side, buffer):
 
 
 def _config(L, Np, n_steps, a_i, a_f, precision, schedule, want_momenta, N_out,
-            checkpoint_every=0):
+            checkpoint_every=0, discretisation="modified", n_lpt=0.0, N_lpt=0, fda_order=0):
     prec = {"fp32": SCOLA_FP32, "fp64": SCOLA_FP64}[precision]
     sch = {"batched": SCOLA_BATCHED, "per_tile": SCOLA_PER_TILE}[schedule]
-    return _lib.Config(float(L), int(Np), int(N_out or 0), int(n_steps), float(a_i),
-                       float(a_f), prec, sch, 1 if want_momenta else 0, int(checkpoint_every))
+    disc = {"modified": _lib.SCOLA_MODIFIED, "standard": _lib.SCOLA_STANDARD}[discretisation]
+    return _lib.make_config(L, Np, n_steps, a_i, a_f, prec, sch, 1 if want_momenta else 0,
+                            N_out or 0, checkpoint_every, N_lpt=N_lpt or 0,
+                            fda_order=fda_order or 0, n_lpt=n_lpt or 0.0, discretisation=disc)
 
 
-def schedule_table(n_steps, a_i=0.05, a_f=1.0, cosmology=None):
+def schedule_table(n_steps, a_i=0.05, a_f=1.0, cosmology=None, discretisation="modified",
+                   n_lpt=0.0):
     """Host FP64 KDK scalar rows (see scola_schedule_table); no device needed."""
     import numpy as np
-    cfg = _config(1.0, 8, n_steps, a_i, a_f, "fp64", "batched", False, 0)
+    cfg = _config(1.0, 8, n_steps, a_i, a_f, "fp64", "batched", False, 0,
+                  discretisation=discretisation, n_lpt=n_lpt)
     cosmo = (cosmology or CosmologyParams()).c()
     out = np.zeros((n_steps + 1, 8))
     _lib.check(_lib.lib().scola_schedule_table(
@@ -88,14 +92,19 @@ def linear_power(k, cosmology=None):
 class Simulation:
     """A tiled-sCOLA run on one GPU (one plan + one workspace).
 
-    tiles: list of (core_lo (3 ints), core_n, buffer); or use uniform_tiling().
+    tiles: list of (core_lo (3 ints), core_n, buffer) or (core_lo, core_n, buffer, a_f) with
+    a per-tile final scale factor (0 = a_f); or use uniform_tiling().
     precision: "fp32" (state and meshes in FP32, Psi and positions FP64) or "fp64".
     schedule: "batched" (all boxes per launch) or "per_tile" (box after box).
+    discretisation: "modified" (App. B time factors with u = a^n_lpt) or "standard".
+    N_lpt, fda_order, mesh: as in include/scola.h (only the defaults are implemented; other
+    values raise ScolaError with SCOLA_EUNSUPPORTED).
     """
 
     def __init__(self, L, Np, tiles, n_steps, a_i=0.05, a_f=1.0, precision="fp32",
                  schedule="batched", want_momenta=False, N_out=None, cosmology=None,
-                 device=None, checkpoint_every=0):
+                 device=None, checkpoint_every=0, discretisation="modified", n_lpt=0.0,
+                 N_lpt=0, fda_order=0, mesh=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("a HIP device is required (the engine has no CPU path)")
@@ -109,16 +118,19 @@ class Simulation:
         self.precision = precision
         self.real = torch.float64 if precision == "fp64" else torch.float32
         self.want_momenta = bool(want_momenta)
-        self.tiles = [(tuple(int(c) for c in lo), int(n), int(b)) for lo, n, b in tiles]
+        self.tiles = [(tuple(int(c) for c in t[0]), int(t[1]), int(t[2])) for t in tiles]
+        self.tile_a_f = [float(t[3]) if len(t) > 3 else 0.0 for t in tiles]
         self.checkpoint_every = int(checkpoint_every)
         cfg = _config(L, Np, n_steps, a_i, a_f, precision, schedule, want_momenta, N_out,
-                      checkpoint_every)
+                      checkpoint_every, discretisation, n_lpt, N_lpt, fda_order)
         cosmo = (cosmology or CosmologyParams()).c()
         arr = (_lib.Tile * len(self.tiles))()
         for i, (lo, n, b) in enumerate(self.tiles):
             arr[i].core_lo[:] = lo
             arr[i].core_n = n
             arr[i].buffer = b
+            arr[i].mesh[:] = (int(mesh),) * 3
+            arr[i].a_f = self.tile_a_f[i]
         plan = ctypes.c_void_p()
         _lib.check(_lib.lib().scola_plan_create(ctypes.byref(cfg), ctypes.byref(cosmo), arr,
                                                 len(self.tiles), ctypes.byref(plan)))
@@ -127,6 +139,7 @@ class Simulation:
         _lib.check(_lib.lib().scola_workspace_layout(plan, ctypes.byref(lay)))
         self.layout = lay
         self.workspace = torch.empty(lay.total + 256, dtype=torch.uint8, device=self.device)
+        self._generation = 0          # forward() calls so far (see DensityFunction)
         shift = (-self.workspace.data_ptr()) % 256
         self._ws_off = shift
         self._ws = ctypes.c_void_p(self.workspace.data_ptr() + shift)
@@ -164,8 +177,8 @@ class Simulation:
             "rho": (t.int64 if self.precision == "fp64" else t.int32, (G,)),
             "work": (self.real, (G,)), "phi": (self.real, (H,)),
             "bc0": (t.float64, (H,)),
-            # per tile, then the FP32 mass alarm (nodes that held >= 2^31 units)
-            "dropped": (t.int64, (len(self.tiles) + 1,)),
+            # dropped per tile, near-limit count, then (FP32) mass found and deposits per tile
+            "dropped": (t.int64, (3 * len(self.tiles) + 1,)),
             # per brick of 256 particles: packed cell extent of its last deposit
             "cells": (t.int32, (P // 256, 4)),
             "phi1": (t.float64, (N, N, N)), "phi2": (t.float64, (N, N, N)),
@@ -188,8 +201,20 @@ class Simulation:
         return ctypes.c_void_p(x.data_ptr())
 
     # --- the run ---------------------------------------------------------------------
-    def forward(self, white_noise, tile_subset=None, density=True, momenta=None):
-        """Run set-up, evolution and outputs.  Returns dict(pos, mom, density)."""
+    def mass_alarm(self):
+        """(near_limit, wrapped) counts of the FP32 mass mesh since the last evolution (see
+        scola_mass_alarm); raises ScolaError (SCOLA_EOVERFLOW) when a node's mass wrapped.
+        Synchronises the current stream."""
+        near = ctypes.c_int64()
+        wrapped = ctypes.c_int64()
+        _lib.check(_lib.lib().scola_mass_alarm(self._plan, self._ws, self._stream(),
+                                               ctypes.byref(near), ctypes.byref(wrapped)))
+        return near.value, wrapped.value
+
+    def forward(self, white_noise, tile_subset=None, density=True, momenta=None, check=True):
+        """Run set-up, evolution and outputs.  Returns dict(pos, mom, density).  With check
+        (default), the FP32 mass alarm is read afterwards (one stream synchronisation) and
+        a wrapped node mass raises ScolaError."""
         t = self.torch
         Np = self.Np
         momenta = self.want_momenta if momenta is None else momenta
@@ -204,6 +229,9 @@ class Simulation:
             if mom is not None else None,
             self._ptr(dens, self.real, (self.N_out,) * 3) if dens is not None else None,
             sub, n, self._ws, self._stream()))
+        self._generation += 1
+        if check and self.precision == "fp32":
+            self.mass_alarm()
         return dict(pos=pos, mom=mom, density=dens)
 
     def forward_noalloc(self, white_noise, density=True, momenta=None):
@@ -222,6 +250,38 @@ class Simulation:
             self._ptr(dens, self.real, (self.N_out,) * 3) if dens is not None else None,
             self._stream()))
         return dict(pos=pos, mom=mom, density=dens)
+
+    def tcola_forward(self, white_noise, density=True, momenta=None, record=False):
+        """Monolithic periodic tCOLA of the full box (scola_tcola_forward) with this
+        Simulation's schedule and precision, in its own workspace (allocated on first use).
+        Returns dict(pos, mom, density, record_delta, record_phi); with record, the density
+        contrast and potential of every force evaluation, shape (n_force, Np, Np, Np)."""
+        t = self.torch
+        Np = self.Np
+        momenta = self.want_momenta if momenta is None else momenta
+        if getattr(self, "_tcola_ws", None) is None:
+            n = ctypes.c_size_t()
+            _lib.check(_lib.lib().scola_tcola_workspace_size(self._plan, ctypes.byref(n)))
+            self._tcola_buf = t.empty(n.value + 256, dtype=t.uint8, device=self.device)
+            shift = (-self._tcola_buf.data_ptr()) % 256
+            self._tcola_ws = ctypes.c_void_p(self._tcola_buf.data_ptr() + shift)
+        pos = t.empty((3, Np, Np, Np), dtype=self.real, device=self.device)
+        mom = t.empty_like(pos) if momenta else None
+        dens = t.empty((self.N_out,) * 3, dtype=self.real, device=self.device) if density else None
+        n_force = self.n_steps + (1 if self.want_momenta else 0)
+        rd = rp = None
+        if record:
+            rd = t.empty((n_force, Np, Np, Np), dtype=self.real, device=self.device)
+            rp = t.empty_like(rd)
+        _lib.check(_lib.lib().scola_tcola_forward(
+            self._plan, self._ptr(white_noise, t.float64, (Np, Np, Np)),
+            self._ptr(pos, self.real, pos.shape),
+            self._ptr(mom, self.real, pos.shape) if mom is not None else None,
+            self._ptr(dens, self.real, (self.N_out,) * 3) if dens is not None else None,
+            self._ptr(rd, self.real, rd.shape) if rd is not None else None,
+            self._ptr(rp, self.real, rp.shape) if rp is not None else None,
+            self._tcola_ws, self._stream()))
+        return dict(pos=pos, mom=mom, density=dens, record_delta=rd, record_phi=rp)
 
     def backward(self, grad_density):
         """d loss / d white noise (float64, [Np]^3) for d loss / d density (plan dtype,
@@ -242,6 +302,16 @@ class Simulation:
     def evolve(self, tile_subset=None):
         sub, n = self._subset(tile_subset)
         _lib.check(_lib.lib().scola_evolve(self._plan, sub, n, self._ws, self._stream()))
+
+    def evolve_overrides(self, delta=None, phi=None):
+        """scola_evolve_overrides: the evolution with the density contrast and/or boundary
+        potential of every force evaluation taken from full-box fields (n_force, Np, Np, Np)
+        in the plan dtype, e.g. the record of tcola_forward (Sec. 4.3 consistency tests)."""
+        n_force = self.n_steps + (1 if self.want_momenta else 0)
+        shp = (n_force, self.Np, self.Np, self.Np)
+        _lib.check(_lib.lib().scola_evolve_overrides(
+            self._plan, self._ptr(delta, self.real, shp), self._ptr(phi, self.real, shp),
+            self._ws, self._stream()))
 
     def output(self, pos=None, mom=None, density=None, tile_subset=None):
         sub, n = self._subset(tile_subset)
@@ -363,10 +433,19 @@ def _density_fn():
             @staticmethod
             def forward(ctx, w, sim):
                 ctx.sim = sim
-                return sim.forward(w, density=True)["density"]
+                out = sim.forward(w, density=True)["density"]
+                ctx.generation = sim._generation
+                return out
 
             @staticmethod
             def backward(ctx, grad_out):
+                # the library keeps one forward state per workspace: a later forward on the
+                # same Simulation has replaced the trajectory this graph was built from
+                if ctx.sim._generation != ctx.generation:
+                    raise RuntimeError(
+                        "DensityFunction.backward: the Simulation has run another forward "
+                        "since this output was computed; its reverse mode would belong to "
+                        "that later forward (use one Simulation per differentiated output)")
                 return ctx.sim.backward(grad_out.to(ctx.sim.real)), None
 
         _FN = _Density

@@ -12,11 +12,12 @@ LIB_PATH = os.path.join(_HERE, "libscola.so")
 
 SCOLA_FP32, SCOLA_FP64 = 0, 1
 SCOLA_BATCHED, SCOLA_PER_TILE = 0, 1
+SCOLA_MODIFIED, SCOLA_STANDARD = 0, 1
 FIXED_BITS = 40
 STATIC_WORKSPACE_BYTES = 128 << 20   # SCOLA_STATIC_WORKSPACE_BYTES
 
 STATUS = {0: "SCOLA_OK", -1: "SCOLA_EINVAL", -2: "SCOLA_ENOMEM", -3: "SCOLA_EDEVICE",
-          -4: "SCOLA_ESTATE", -5: "SCOLA_EUNSUPPORTED"}
+          -4: "SCOLA_ESTATE", -5: "SCOLA_EUNSUPPORTED", -6: "SCOLA_EOVERFLOW"}
 
 
 class ScolaError(RuntimeError):
@@ -33,15 +34,28 @@ class Cosmology(ctypes.Structure):
 
 class Tile(ctypes.Structure):
     _fields_ = [("core_lo", ctypes.c_int32 * 3), ("core_n", ctypes.c_int32),
-                ("buffer", ctypes.c_int32)]
+                ("buffer", ctypes.c_int32), ("mesh", ctypes.c_int32 * 3),
+                ("a_f", ctypes.c_double)]
 
 
 class Config(ctypes.Structure):
-    _fields_ = [("L", ctypes.c_double), ("Np", ctypes.c_int32), ("N_out", ctypes.c_int32),
+    _fields_ = [("L", ctypes.c_double), ("Np", ctypes.c_int32), ("N_lpt", ctypes.c_int32),
+                ("N_out", ctypes.c_int32), ("fda_order", ctypes.c_int32),
                 ("n_steps", ctypes.c_int32), ("a_i", ctypes.c_double),
-                ("a_f", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("a_f", ctypes.c_double), ("n_lpt", ctypes.c_double),
+                ("discretisation", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("want_momenta", ctypes.c_int32),
                 ("checkpoint_every", ctypes.c_int32)]
+
+
+def make_config(L, Np, n_steps, a_i, a_f, precision, schedule, want_momenta=0, N_out=0,
+                checkpoint_every=0, N_lpt=0, fda_order=0, n_lpt=0.0, discretisation=0):
+    """A Config with the fields named as in include/scola.h (zero = the default)."""
+    return Config(L=float(L), Np=int(Np), N_lpt=int(N_lpt), N_out=int(N_out),
+                  fda_order=int(fda_order), n_steps=int(n_steps), a_i=float(a_i),
+                  a_f=float(a_f), n_lpt=float(n_lpt), discretisation=int(discretisation),
+                  precision=int(precision), schedule=int(schedule),
+                  want_momenta=int(want_momenta), checkpoint_every=int(checkpoint_every))
 
 
 class Layout(ctypes.Structure):
@@ -95,6 +109,11 @@ _SIGS = {
     "scola_plan_set_concurrency": ([_P, _I], _I),
     "scola_plan_schedule": ([_P, _P, _I, ctypes.POINTER(_I)], _I),
     "scola_plan_set_schedule": ([_P, _P, _I], _I),
+    "scola_evolve_overrides": ([_P, _P, _P, _P, _P], _I),
+    "scola_tcola_workspace_size": ([_P, ctypes.POINTER(ctypes.c_size_t)], _I),
+    "scola_tcola_forward": ([_P, _P, _P, _P, _P, _P, _P, _P, _P], _I),
+    "scola_mass_alarm": ([_P, _P, _P, ctypes.POINTER(ctypes.c_int64),
+                          ctypes.POINTER(ctypes.c_int64)], _I),
     "scola_plan_info": ([_P, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_int64),
                          ctypes.POINTER(_D), ctypes.POINTER(_D)], _I),
 }

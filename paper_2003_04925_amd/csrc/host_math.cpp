@@ -131,6 +131,16 @@ double Background::beta_tilde(double ai, double af, double aD, double n) const {
   return -1.5 * Om * (std::pow(af, n) - std::pow(ai, n)) / (n * std::pow(aD, n) * aD * E(aD));
 }
 
+// App. B eq. alpha-beta-standard (t = a): alpha = int da / (a^2 H_conf), beta = -3/2 Omega_m
+// int da / (a H_conf), with H_conf = a E(a).
+double Background::alpha_standard(double ai, double af) const {
+  return integrate([&](double a) { return 1.0 / (a * a * a * E(a)); }, ai, af, 16, 16);
+}
+
+double Background::beta_standard(double ai, double af) const {
+  return -1.5 * Om * integrate([&](double a) { return 1.0 / (a * a * E(a)); }, ai, af, 16, 16);
+}
+
 // sigma^2(8 Mpc/h) of k^n_s T(k)^2 with the top-hat window, as an integral over ln k.
 double Background::sigma8_unnormalised() const {
   auto f = [&](double lnk) {

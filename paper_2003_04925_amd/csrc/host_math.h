@@ -16,6 +16,8 @@ struct Background {
               std::vector<double>& D2, std::vector<double>& dD2) const;
   double alpha_tilde(double ai, double af, double aK, double n) const;
   double beta_tilde(double ai, double af, double aD, double n) const;
+  double alpha_standard(double ai, double af) const;
+  double beta_standard(double ai, double af) const;
   double sigma8_unnormalised() const;
   void normalise();
   double power(double k) const;  // P_lin(k, a = 1), (Mpc/h)^3, k in h/Mpc

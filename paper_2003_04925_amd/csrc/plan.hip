@@ -58,18 +58,26 @@ scola_status guarded(F f) {
   }
 }
 
-// Block maps of one kernel family over all tiles.  Tiles are laid out size class by size
-// class (classes in increasing M), so every class is one contiguous block range.
+// Block maps of one kernel family over all tiles.  Tiles are laid out class by class
+// (classes of equal box size M and final scale factor, in increasing M), so every class is
+// one contiguous block range.
 struct Maps {
   std::vector<int> tile, local;
   std::vector<int> first;    // per tile: first block of that tile
   std::vector<int> count;    // per tile: number of blocks
-  std::vector<int> class_M, class_first, class_count;
+  std::vector<int> class_M, class_tc, class_first, class_count;
   int* d_tile = nullptr;
   int* d_local = nullptr;
 };
 
 }  // namespace
+
+// KDK scalars of one final scale factor (Sec. 5.1: tiles need not share one final time).
+struct TimeClass {
+  double a_f = 0.0;
+  std::vector<double> table;          // (n_steps + 1) x 8 scalar rows
+  std::vector<double> D1, D2;         // growth at t_0 .. t_n
+};
 
 struct scola_plan {
   scola_config cfg{};
@@ -80,8 +88,9 @@ struct scola_plan {
   int device = 0;
   int max_M = 0;
   int64_t P = 0, G = 0, H = 0;
-  std::vector<double> table;          // (n_steps + 1) x 8 scalar rows
-  std::vector<double> D1, D2;         // growth at t_0 .. t_n
+  std::vector<double> table;          // (n_steps + 1) x 8 scalar rows of cfg.a_f
+  std::vector<double> D1, D2;         // growth at t_0 .. t_n of cfg.a_f
+  std::vector<TimeClass> tclasses;    // [0]: cfg.a_f; then every other tile final time
   scola_layout lay{};
   TileDesc* d_tiles = nullptr;
   void* d_twiddles = nullptr;
@@ -118,19 +127,22 @@ void build_maps(Maps& m, const std::vector<TileDesc>& desc,
   m.tile.clear();
   m.local.clear();
   m.class_M.clear();
+  m.class_tc.clear();
   m.class_first.clear();
   m.class_count.clear();
   m.first.assign(desc.size(), 0);
   m.count.assign(desc.size(), 0);
-  std::vector<int> sizes;
-  for (auto& d : desc) sizes.push_back(d.M);
-  std::sort(sizes.begin(), sizes.end());
-  sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
-  for (int M : sizes) {
+  std::vector<std::pair<int, int>> keys;   // (M, time class)
+  for (auto& d : desc) keys.push_back({d.M, d.tclass});
+  std::sort(keys.begin(), keys.end());
+  keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+  for (const auto& key : keys) {
+    const int M = key.first;
     m.class_M.push_back(M);
+    m.class_tc.push_back(key.second);
     m.class_first.push_back((int)m.tile.size());
     for (size_t t = 0; t < desc.size(); ++t) {
-      if (desc[t].M != M) continue;
+      if (desc[t].M != M || desc[t].tclass != key.second) continue;
       const int n = units(desc[t]);
       m.first[t] = (int)m.tile.size();
       m.count[t] = n;
@@ -194,6 +206,21 @@ void validate(const scola_config& c, const scola_cosmology& cs, const scola_tile
   if (c.schedule != SCOLA_BATCHED && c.schedule != SCOLA_PER_TILE)
     fail(SCOLA_EINVAL, "schedule must be SCOLA_BATCHED or SCOLA_PER_TILE");
   if (c.checkpoint_every < 0) fail(SCOLA_EINVAL, "checkpoint_every must be >= 0");
+  if (c.N_lpt != 0 && c.N_lpt != c.Np) {
+    if (c.N_lpt > 0 && c.N_lpt < c.Np && c.Np % c.N_lpt == 0)
+      fail(SCOLA_EUNSUPPORTED, "N_lpt = " + std::to_string(c.N_lpt) +
+                                   ": only an LPT grid with N_lpt = Np nodes is implemented");
+    fail(SCOLA_EINVAL, "N_lpt must be 0, Np or a divisor of Np");
+  }
+  if (c.fda_order != 0 && c.fda_order != 2) {
+    if (c.fda_order == 4 || c.fda_order == 6)
+      fail(SCOLA_EUNSUPPORTED, "fda_order = " + std::to_string(c.fda_order) +
+                                   ": only finite differences of order 2 are implemented");
+    fail(SCOLA_EINVAL, "fda_order must be 0, 2, 4 or 6");
+  }
+  if (!std::isfinite(c.n_lpt)) fail(SCOLA_EINVAL, "n_lpt must be finite");
+  if (c.discretisation != SCOLA_MODIFIED && c.discretisation != SCOLA_STANDARD)
+    fail(SCOLA_EINVAL, "discretisation must be SCOLA_MODIFIED or SCOLA_STANDARD");
   if (!(cs.Omega_m > 0 && cs.Omega_m <= 1 && cs.Omega_b >= 0 && cs.Omega_b < cs.Omega_m &&
         cs.h > 0 && cs.sigma8 > 0 && cs.T_cmb > 0))
     fail(SCOLA_EINVAL, "cosmology out of range");
@@ -206,7 +233,17 @@ void validate(const scola_config& c, const scola_cosmology& cs, const scola_tile
     if (s.core_n < 1 || s.buffer < 0) fail(SCOLA_EINVAL, "tile core_n >= 1, buffer >= 0");
     if (M % 16 != 0 || M < 16 || M > kMaxM)
       fail(SCOLA_EUNSUPPORTED, "tile " + std::to_string(t) + ": M = core_n + 2 buffer = " +
-                                   std::to_string(M) + " must be a multiple of 16 in [16, 128]");
+                                   std::to_string(M) + " must be one of 16, 32, 48, ..., 128");
+    if (s.a_f != 0.0 && !(std::isfinite(s.a_f) && s.a_f > c.a_i))
+      fail(SCOLA_EINVAL, "tile " + std::to_string(t) + ": a_f must be 0 (the run's a_f) or > a_i");
+    for (int a = 0; a < 3; ++a) {
+      if (s.mesh[a] < 0) fail(SCOLA_EINVAL, "tile " + std::to_string(t) + ": mesh must be >= 0");
+      if (s.mesh[a] != 0 && s.mesh[a] != M)
+        fail(SCOLA_EUNSUPPORTED, "tile " + std::to_string(t) + ": mesh[" + std::to_string(a) +
+                                     "] = " + std::to_string(s.mesh[a]) +
+                                     ": only a mesh of M = core_n + 2 buffer cells per side "
+                                     "(node spacing = lattice spacing) is implemented");
+    }
     if (s.core_n > Np || M > 4 * Np)
       fail(SCOLA_EINVAL, "tile " + std::to_string(t) + " larger than the lattice");
     for (int a = 0; a < 3; ++a)
@@ -282,14 +319,23 @@ void compute_step_table(const scola_config& c, const Background& bg, std::vector
     D1out[k] = D1[k] / n1;
     D2out[k] = D2[k] / (n1 * n1);
   }
-  const double nlpt = -2.5;   // App. B: u(a) = a^n_LPT with the paper's n_LPT = -2.5
+  // App. B: modified time factors with u(a) = a^n_LPT (the paper's n_LPT = -2.5), or the
+  // standard ones (integrals of the drift and kick prefactors over the sub-step)
+  const double nlpt = c.n_lpt != 0.0 ? c.n_lpt : -2.5;
+  const bool standard = c.discretisation == SCOLA_STANDARD;
+  auto beta = [&](double ai, double af, double aD) {
+    return standard ? bg.beta_standard(ai, af) : bg.beta_tilde(ai, af, aD, nlpt);
+  };
+  auto alpha = [&](double ai, double af, double aK) {
+    return standard ? bg.alpha_standard(ai, af) : bg.alpha_tilde(ai, af, aK, nlpt);
+  };
   table.assign((size_t)(n + 1) * 8, 0.0);
   for (int k = 0; k < n; ++k) {
     double* r = &table[(size_t)k * 8];
     const double aKi = k == 0 ? t[0] : half[k - 1];
     r[0] = t[k];
-    r[1] = bg.beta_tilde(aKi, half[k], t[k], nlpt);
-    r[2] = bg.alpha_tilde(t[k], t[k + 1], half[k], nlpt);
+    r[1] = beta(aKi, half[k], t[k]);
+    r[2] = alpha(t[k], t[k + 1], half[k]);
     r[3] = D1out[k];
     r[4] = D2out[k];
     r[5] = D1out[k + 1];
@@ -300,7 +346,7 @@ void compute_step_table(const scola_config& c, const Background& bg, std::vector
   const double af = t[n];
   const double inv_drift = af * af * af * bg.E(af);   // 1 / drift prefactor
   r[0] = af;
-  r[1] = bg.beta_tilde(half[n - 1], af, af, nlpt);
+  r[1] = beta(half[n - 1], af, af);
   r[2] = D1out[n];
   r[3] = D2out[n];
   r[4] = -dD1[n] / n1 * inv_drift;                       // L+ : p_LPT coefficients
@@ -333,7 +379,9 @@ void build_layout(scola_plan* p) {
   l.work = take((size_t)p->G * R);
   l.phi = take((size_t)p->H * R);
   l.bc0 = take((size_t)p->H * 8);
-  l.dropped = take((p->desc.size() + 1) * 8);   // per tile, then the mass alarm
+  // per tile dropped mass, the near-limit count, then per tile the mass the Poisson passes
+  // found and the number of deposits (the mass identity of FP32 plans)
+  l.dropped = take((3 * p->desc.size() + 1) * 8);
   l.cells = take((size_t)(p->P / kBlock) * 16);   // per brick: packed cell extent
   l.phi1 = take((size_t)(N * N * N) * 8);
   l.phi2 = take((size_t)(N * N * N) * 8);
@@ -406,6 +454,7 @@ MeshArgs<T> mesh_args(scola_plan* p, void* ws, double D1_bc) {
   a.tiles = p->d_tiles;
   a.rho = reinterpret_cast<typename MeshFixed<T>::rho_t*>(ws_ptr(ws, p->lay.rho));
   a.alarm = reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped)) + p->desc.size();
+  a.kept = a.alarm + 1;
   a.work = reinterpret_cast<T*>(ws_ptr(ws, p->lay.work));
   a.phi = reinterpret_cast<T*>(ws_ptr(ws, p->lay.phi));
   a.bc0 = reinterpret_cast<const double*>(ws_ptr(ws, p->lay.bc0));
@@ -427,6 +476,7 @@ ParticleArgs<T> particle_args(scola_plan* p, void* ws, const StepScalars& sc) {
   a.phi = reinterpret_cast<const T*>(ws_ptr(ws, p->lay.phi));
   a.rho = reinterpret_cast<typename MeshFixed<T>::rho_t*>(ws_ptr(ws, p->lay.rho));
   a.dropped = reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped));
+  a.deposits = a.dropped + 2 * p->desc.size() + 1;
   a.cells = reinterpret_cast<uint4*>(ws_ptr(ws, p->lay.cells));
   a.use_hints = 1;
   a.P = p->P;
@@ -493,6 +543,34 @@ void poisson_class(const scola_plan* p, const MeshArgs<T>& a, size_t c, bool adj
   hip_check(launch_poisson<T>(a, p->p1.class_M[c], b1, b2, b3, s, adjoint), "poisson kernels");
 }
 
+// Scalars of the evolution for time class tc: the growth at t_0 (kInit), the final half
+// kick and L+ (kFinalKick), else row k of the class's step table.
+StepScalars class_scalars(const scola_plan* p, int tc, int mode, int k) {
+  const TimeClass& c = p->tclasses[tc];
+  StepScalars sc{};
+  if (mode == kInit || mode == kDepositOnly) {
+    sc.D1 = c.D1[k];
+    sc.D2 = c.D2[k];
+    return sc;
+  }
+  const double* r = &c.table[(size_t)k * 8];
+  if (mode == kFinalKick) {
+    sc.beta = r[1];
+    sc.D1 = r[2];
+    sc.D2 = r[3];
+    sc.c1 = r[4];
+    sc.c2 = r[5];
+    return sc;
+  }
+  sc.beta = r[1];
+  sc.alpha = r[2];
+  sc.D1 = r[3];
+  sc.D2 = r[4];
+  sc.D1n = r[5];
+  sc.D2n = r[6];
+  return sc;
+}
+
 // One call of each kernel family over a set of tiles: all in one launch (batched) or one
 // launch per tile.
 template <typename T>
@@ -541,9 +619,78 @@ struct Runner {
       }
     }
   }
+  // Step-indexed forms for the evolution: every class (or tile) takes the scalars of its
+  // own time class.  mode kInit: the growth at t_0; kFinalKick: the final row; otherwise
+  // row k of the step table.
+  void particles_step(int mode, int k) {
+    if (batched) {
+      const Maps& pm = p->part;
+      for (size_t c = 0; c < pm.class_M.size(); ++c) {
+        BlockMap b = class_group_map(p, pm, c, group, ngroups);
+        if (b.count == 0) continue;
+        b.xcd_remap = p->sched[c].xcd_remap_particles;
+        ParticleArgs<T> a = args_of(class_scalars(p, pm.class_tc[c], mode, k));
+        hip_check(launch_particles<T>(a, mode, b, p->sched[c].waves_per_simd, s),
+                  "particle kernel");
+      }
+    } else {
+      for (int t : tiles) {
+        const scola_class_schedule& cs = sched_of(p, p->desc[t].M);
+        BlockMap b = tile_map(p->part, t);
+        b.xcd_remap = cs.xcd_remap_particles;
+        ParticleArgs<T> a = args_of(class_scalars(p, p->desc[t].tclass, mode, k));
+        hip_check(launch_particles<T>(a, mode, b, cs.waves_per_simd, s), "particle kernel");
+      }
+    }
+  }
+  ParticleArgs<T> args_of(const StepScalars& sc) {
+    ParticleArgs<T> a = particle_args<T>(p, ws, sc);
+    if (x_in) a.xres = x_in;
+    a.xout = x_out ? x_out : a.xres;
+    if (phi) a.phi = phi;
+    return a;
+  }
+  // the Poisson solve of force evaluation k (at t_k of each class)
+  void poisson_step(int k) {
+    MeshArgs<T> a = mesh_args<T>(p, ws, 0.0);
+    if (phi) a.phi = phi;
+    if (ov_delta || ov_phi) {
+      const size_t N3 = (size_t)p->cfg.Np * p->cfg.Np * p->cfg.Np;
+      a.ov_N = p->cfg.Np;
+      if (ov_delta) a.ov_delta = ov_delta + (size_t)force * N3;
+      if (ov_phi) a.ov_phi = ov_phi + (size_t)force * N3;
+    }
+    ++force;
+    if (batched) {
+      for (size_t c = 0; c < p->p1.class_M.size(); ++c) {
+        a.D1_bc = p->tclasses[p->p1.class_tc[c]].D1[k];
+        poisson_class(p, a, c, false, s, group, ngroups);
+      }
+    } else {
+      for (int t : tiles) {
+        a.D1_bc = p->tclasses[p->desc[t].tclass].D1[k];
+        const int r = sched_of(p, p->desc[t].M).xcd_remap_mesh;
+        BlockMap b1 = tile_map(p->p1, t), b2 = tile_map(p->p2, t), b3 = tile_map(p->p3, t);
+        b1.xcd_remap = b2.xcd_remap = b3.xcd_remap = r;
+        hip_check(launch_poisson<T>(a, p->desc[t].M, b1, b2, b3, s), "poisson kernels");
+      }
+    }
+  }
+  // consistency tests (Sec. 4.3): full-box fields [n_force][N^3] replacing the density
+  // contrast and/or the boundary potential of force evaluation `force`
+  const T* ov_delta = nullptr;
+  const T* ov_phi = nullptr;
+  int force = 0;
   void poisson(double D1_bc) {
     MeshArgs<T> a = mesh_args<T>(p, ws, D1_bc);
     if (phi) a.phi = phi;
+    if (ov_delta || ov_phi) {
+      const size_t N3 = (size_t)p->cfg.Np * p->cfg.Np * p->cfg.Np;
+      a.ov_N = p->cfg.Np;
+      if (ov_delta) a.ov_delta = ov_delta + (size_t)force * N3;
+      if (ov_phi) a.ov_phi = ov_phi + (size_t)force * N3;
+    }
+    ++force;
     if (batched) {
       for (size_t c = 0; c < p->p1.class_M.size(); ++c)
         poisson_class(p, a, c, false, s, group, ngroups);
@@ -718,37 +865,28 @@ void zero_node_ranges(const scola_plan* p, const std::vector<int>& tiles, T* arr
 // are created or used).
 template <typename T>
 void do_evolve(scola_plan* p, const std::vector<int>& tiles, void* ws, hipStream_t s,
-               bool allow_groups = true) {
+               bool allow_groups = true, const T* ov_delta = nullptr,
+               const T* ov_phi = nullptr) {
   const bool batched = p->cfg.schedule == SCOLA_BATCHED && tiles.size() == p->desc.size();
   hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped)),
-                            (int64_t)p->desc.size() + 1, s), "zero dropped");
+                            3 * (int64_t)p->desc.size() + 1, s), "zero dropped");
   const int n = p->cfg.n_steps;
   auto run = [&](const std::vector<int>& set, bool b, hipStream_t s, int g, int G) {
     Runner<T> r{p, ws, s, set, b};
     r.group = g;
     r.ngroups = G;
-    StepScalars init{};
-    init.D1 = p->D1[0];
-    init.D2 = p->D2[0];
-    r.particles(kInit, init);               // L-: x_res = p_res = 0, deposit x_LPT(t_0)
-    r.poisson(p->D1[0]);
+    r.ov_delta = ov_delta;
+    r.ov_phi = ov_phi;
+    r.particles_step(kInit, 0);             // L-: x_res = p_res = 0, deposit x_LPT(t_0)
+    r.poisson_step(0);
     const int ck = p->cfg.checkpoint_every;
     for (int k = 0; k < n; ++k) {
       if (ck > 0 && k % ck == 0) copy_checkpoint<T>(p, set, k / ck, true, ws, s);
       const bool need_force = k < n - 1 || p->cfg.want_momenta;
-      r.particles(need_force ? kStep : kStepNoDeposit, row_scalars(p, k));
-      if (need_force) r.poisson(p->D1[k + 1]);
+      r.particles_step(need_force ? kStep : kStepNoDeposit, k);
+      if (need_force) r.poisson_step(k + 1);
     }
-    if (p->cfg.want_momenta) {
-      const double* f = &p->table[(size_t)n * 8];
-      StepScalars sc{};
-      sc.beta = f[1];
-      sc.D1 = f[2];
-      sc.D2 = f[3];
-      sc.c1 = f[4];
-      sc.c2 = f[5];
-      r.particles(kFinalKick, sc);
-    }
+    if (p->cfg.want_momenta) r.particles_step(kFinalKick, n);
   };
   const int G = batched && allow_groups ? std::min<int>(p->groups, (int)tiles.size()) : 1;
   if (batched && G > 1) {
@@ -1091,8 +1229,104 @@ void do_tune(scola_plan* p, void* ws, hipStream_t s, int reps) {
   hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.rho)),
                             (int64_t)(rho_bytes(p) / 8), s), "zero rho");
   hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped)),
-                            (int64_t)p->desc.size() + 1, s), "zero dropped");
+                            3 * (int64_t)p->desc.size() + 1, s), "zero dropped");
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+}  // namespace
+
+namespace {
+
+// Workspace of the monolithic periodic tCOLA run (byte offsets, 256-byte aligned).
+struct TcolaLayout {
+  size_t psi1, psi2, x_res, p_res, rho, phi, cbuf, phi1, phi2, outgrid, total;
+};
+
+TcolaLayout tcola_layout(const scola_plan* p) {
+  const size_t R = p->is64 ? 8 : 4;
+  const size_t N3 = (size_t)p->cfg.Np * p->cfg.Np * p->cfg.Np;
+  const size_t No3 = (size_t)p->cfg.N_out * p->cfg.N_out * p->cfg.N_out;
+  TcolaLayout l{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  l.psi1 = take(3 * N3 * 8);
+  l.psi2 = take(3 * N3 * 8);
+  l.x_res = take(3 * N3 * R);
+  l.p_res = take(3 * N3 * R);
+  l.rho = take(N3 * 8);
+  l.phi = take(N3 * R);
+  l.cbuf = take(N3 * 16);
+  l.phi1 = take(N3 * 8);
+  l.phi2 = take(N3 * 8);
+  l.outgrid = take(No3 * 8);
+  l.total = off;
+  return l;
+}
+
+// Sec. 2.2: the full periodic box evolved by the same KDK schedule as the boxes.
+template <typename T>
+void do_tcola(scola_plan* p, const double* w, void* pos, void* mom, void* dens, void* rec_d,
+              void* rec_p, void* ws, hipStream_t s) {
+  const TcolaLayout l = tcola_layout(p);
+  const int N = p->cfg.Np, n = p->cfg.n_steps;
+  const int64_t N3 = (int64_t)N * N * N;
+  SetupArgs sa = setup_args(p, w, ws);
+  sa.cbuf = reinterpret_cast<double2*>(ws_ptr(ws, l.cbuf));
+  sa.phi1 = reinterpret_cast<double*>(ws_ptr(ws, l.phi1));
+  sa.phi2 = reinterpret_cast<double*>(ws_ptr(ws, l.phi2));
+  hip_check(launch_setup_potentials(sa, s), "set-up potentials");
+  TcolaArgs<T> a{};
+  a.psi1 = reinterpret_cast<const double*>(ws_ptr(ws, l.psi1));
+  a.psi2 = reinterpret_cast<const double*>(ws_ptr(ws, l.psi2));
+  a.xres = reinterpret_cast<T*>(ws_ptr(ws, l.x_res));
+  a.pres = reinterpret_cast<T*>(ws_ptr(ws, l.p_res));
+  a.rho = reinterpret_cast<unsigned long long*>(ws_ptr(ws, l.rho));
+  a.phi = reinterpret_cast<const T*>(ws_ptr(ws, l.phi));
+  a.N = N;
+  T* phi = reinterpret_cast<T*>(ws_ptr(ws, l.phi));
+  hip_check(launch_tcola_setup<T>(a, sa.phi1, sa.phi2, s), "tCOLA set-up");
+  hip_check(launch_zero_u64(a.rho, N3, s), "zero rho");
+  int force = 0;
+  auto poisson = [&]() {
+    T* rd = rec_d ? reinterpret_cast<T*>(rec_d) + (size_t)force * N3 : nullptr;
+    T* rp = rec_p ? reinterpret_cast<T*>(rec_p) + (size_t)force * N3 : nullptr;
+    hip_check(launch_tcola_poisson<T>(a, sa.cbuf, phi, rd, rp, s), "tCOLA Poisson");
+    ++force;
+  };
+  a.sc = StepScalars{};
+  a.sc.D1 = p->D1[0];
+  a.sc.D2 = p->D2[0];
+  hip_check(launch_tcola_particles<T>(a, kInit, s), "tCOLA particles");
+  poisson();
+  for (int k = 0; k < n; ++k) {
+    const bool need_force = k < n - 1 || p->cfg.want_momenta;
+    a.sc = row_scalars(p, k);
+    hip_check(launch_tcola_particles<T>(a, need_force ? kStep : kStepNoDeposit, s),
+              "tCOLA particles");
+    if (need_force) poisson();
+  }
+  if (p->cfg.want_momenta) {
+    const double* f = &p->table[(size_t)n * 8];
+    a.sc = StepScalars{};
+    a.sc.beta = f[1];
+    a.sc.D1 = f[2];
+    a.sc.D2 = f[3];
+    a.sc.c1 = f[4];
+    a.sc.c2 = f[5];
+    hip_check(launch_tcola_particles<T>(a, kFinalKick, s), "tCOLA final kick");
+  }
+  a.sc = StepScalars{};
+  a.sc.D1 = p->D1[n];
+  a.sc.D2 = p->D2[n];
+  hip_check(launch_tcola_output<T>(a, reinterpret_cast<T*>(pos), reinterpret_cast<T*>(mom),
+                                   reinterpret_cast<unsigned long long*>(ws_ptr(ws, l.outgrid)),
+                                   reinterpret_cast<T*>(dens), p->cfg.N_out,
+                                   p->cfg.L / p->cfg.Np, p->cfg.L, s),
+            "tCOLA output");
 }
 
 }  // namespace
@@ -1135,6 +1369,7 @@ const char* scola_status_string(scola_status s) {
     case SCOLA_EDEVICE: return "SCOLA_EDEVICE";
     case SCOLA_ESTATE: return "SCOLA_ESTATE";
     case SCOLA_EUNSUPPORTED: return "SCOLA_EUNSUPPORTED";
+    case SCOLA_EOVERFLOW: return "SCOLA_EOVERFLOW";
   }
   return "unknown scola_status";
 }
@@ -1158,6 +1393,8 @@ scola_status scola_uniform_tiling(int32_t Np, int32_t tps, int32_t buffer, scola
           t.core_lo[2] = z * n;
           t.core_n = n;
           t.buffer = buffer;
+          t.mesh[0] = t.mesh[1] = t.mesh[2] = 0;
+          t.a_f = 0.0;
         }
   });
 }
@@ -1200,6 +1437,33 @@ scola_status scola_plan_create(const scola_config* cfg, const scola_cosmology* c
     p->G = G;
     p->H = H;
     build_step_table(p);
+    // time classes: cfg.a_f first, then every other final scale factor of a tile
+    p->tclasses.clear();
+    TimeClass tc0;
+    tc0.a_f = cfg->a_f;
+    tc0.table = p->table;
+    tc0.D1 = p->D1;
+    tc0.D2 = p->D2;
+    p->tclasses.push_back(tc0);
+    for (int t = 0; t < n_tiles; ++t) {
+      const double af = tiles[t].a_f != 0.0 ? tiles[t].a_f : cfg->a_f;
+      int c = -1;
+      for (size_t i = 0; i < p->tclasses.size(); ++i)
+        if (p->tclasses[i].a_f == af) c = (int)i;
+      if (c < 0) {
+        TimeClass tc;
+        tc.a_f = af;
+        scola_config ct = p->cfg;
+        ct.a_f = af;
+        compute_step_table(ct, p->bg, tc.table, tc.D1, tc.D2);
+        c = (int)p->tclasses.size();
+        p->tclasses.push_back(tc);
+      }
+      TileDesc& d = p->desc[t];
+      d.tclass = c;
+      d.D1f = p->tclasses[c].D1[cfg->n_steps];
+      d.D2f = p->tclasses[c].D2[cfg->n_steps];
+    }
     build_layout(p);
     if (p->is64)
       upload_tables<double>(p);
@@ -1211,7 +1475,8 @@ scola_status scola_plan_create(const scola_config* cfg, const scola_cosmology* c
     p->class_tiles.assign(p->part.class_M.size(), {});
     for (size_t c = 0; c < p->part.class_M.size(); ++c)
       for (size_t t = 0; t < p->desc.size(); ++t)
-        if (p->desc[t].M == p->part.class_M[c]) p->class_tiles[c].push_back((int)t);
+        if (p->desc[t].M == p->part.class_M[c] && p->desc[t].tclass == p->part.class_tc[c])
+          p->class_tiles[c].push_back((int)t);
     build_maps(p->p1, p->desc, [](const TileDesc& d) { return d.M - 1; });
     build_maps(p->p2, p->desc, [](const TileDesc& d) {
       return (d.M - 1) * ((d.M - 1 + kPencilChunk - 1) / kPencilChunk);
@@ -1308,6 +1573,22 @@ scola_status scola_evolve(scola_plan* p, const int32_t* subset, int32_t n_subset
       do_evolve<double>(p, tiles, ws, s);
     else
       do_evolve<float>(p, tiles, ws, s);
+  });
+}
+
+scola_status scola_evolve_overrides(scola_plan* p, const void* d_delta, const void* d_phi,
+                                    void* ws, hipStream_t s) {
+  return guarded([&] {
+    check_ws(p, ws);
+    if (p->setup_ws != ws) fail(SCOLA_ESTATE, "scola_setup has not run on this workspace");
+    const std::vector<int> tiles = subset_list(p, nullptr, 0);
+    p->forward_ws = nullptr;
+    if (p->is64)
+      do_evolve<double>(p, tiles, ws, s, false, reinterpret_cast<const double*>(d_delta),
+                        reinterpret_cast<const double*>(d_phi));
+    else
+      do_evolve<float>(p, tiles, ws, s, false, reinterpret_cast<const float*>(d_delta),
+                       reinterpret_cast<const float*>(d_phi));
   });
 }
 
@@ -1440,6 +1721,8 @@ scola_status scola_backward(scola_plan* p, const void* grad_density, double* gra
       fail(SCOLA_ESTATE, "the plan was created with checkpoint_every = 0 (no reverse mode)");
     if (p->forward_ws != ws)
       fail(SCOLA_ESTATE, "scola_backward needs a full scola_forward on this workspace first");
+    if (p->tclasses.size() > 1)
+      fail(SCOLA_EUNSUPPORTED, "the reverse mode needs one final scale factor for all tiles");
     if (p->is64)
       do_backward<double>(p, reinterpret_cast<const double*>(grad_density), grad_w, ws, s);
     else
@@ -1455,7 +1738,7 @@ scola_status scola_op_deposit(scola_plan* p, double D1, double D2, void* ws, hip
     hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.rho)),
                               (int64_t)(rho_bytes(p) / 8), s), "zero rho");
     hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped)),
-                              (int64_t)p->desc.size() + 1, s), "zero dropped");
+                              3 * (int64_t)p->desc.size() + 1, s), "zero dropped");
     StepScalars sc{};
     sc.D1 = D1;
     sc.D2 = D2;
@@ -1562,6 +1845,62 @@ scola_status scola_linear_power(const scola_cosmology* cosmo, const double* k, d
     if (!cosmo || (n > 0 && (!k || !out))) fail(SCOLA_EINVAL, "NULL argument");
     Background bg = background_of(*cosmo);
     for (int i = 0; i < n; ++i) out[i] = bg.power(k[i]);
+  });
+}
+
+scola_status scola_tcola_workspace_size(const scola_plan* p, size_t* bytes) {
+  return guarded([&] {
+    if (!p || !bytes) fail(SCOLA_EINVAL, "NULL argument");
+    *bytes = tcola_layout(p).total;
+  });
+}
+
+scola_status scola_tcola_forward(scola_plan* p, const double* w, void* pos, void* mom,
+                                 void* dens, void* rec_delta, void* rec_phi, void* ws,
+                                 hipStream_t s) {
+  return guarded([&] {
+    check_ws(p, ws);
+    if (!w) fail(SCOLA_EINVAL, "white noise is NULL");
+    if (mom && !p->cfg.want_momenta) fail(SCOLA_EINVAL, "d_mom needs cfg.want_momenta");
+    if (p->is64)
+      do_tcola<double>(p, w, pos, mom, dens, rec_delta, rec_phi, ws, s);
+    else
+      do_tcola<float>(p, w, pos, mom, dens, rec_delta, rec_phi, ws, s);
+  });
+}
+
+scola_status scola_mass_alarm(const scola_plan* p, const void* ws, hipStream_t s,
+                              int64_t* near_limit, int64_t* wrapped) {
+  return guarded([&] {
+    check_ws(p, const_cast<void*>(ws));
+    const size_t nt = p->desc.size();
+    int64_t near = 0, wraps = 0;
+    if (!p->is64) {
+      // [dropped per tile][near-limit][found per tile][deposits per tile]
+      std::vector<uint64_t> c(3 * nt + 1);
+      hip_check(hipMemcpyAsync(c.data(), static_cast<const char*>(ws) + p->lay.dropped,
+                               c.size() * 8, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+      hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+      near = (int64_t)c[nt];
+      const int bits = MeshFixed<float>::bits;
+      for (size_t t = 0; t < nt; ++t) {
+        const uint64_t M = (uint64_t)p->desc[t].M;
+        const uint64_t expect = c[2 * nt + 1 + t] * (M * M * M) << bits;
+        const uint64_t seen = c[t] + c[nt + 1 + t];
+        // every deposit has been read by a Poisson pass: the deficit is whole 2^32 units
+        if (seen > expect || ((expect - seen) & 0xffffffffull))
+          fail(SCOLA_ESTATE, "the mass counters are inconsistent: a deposit has not been "
+                             "followed by its Poisson pass (or the workspace is not the one "
+                             "the last evolution ran on)");
+        wraps += (int64_t)((expect - seen) >> 32);
+      }
+    }
+    if (near_limit) *near_limit = near;
+    if (wrapped) *wrapped = wraps;
+    if (wraps > 0)
+      fail(SCOLA_EOVERFLOW, std::to_string(wraps) + " node mass(es) wrapped the 32-bit "
+                            "fixed-point range (more than 2048 particles on one node): the "
+                            "densities and forces of this run are invalid; use an FP64 plan");
   });
 }
 
