@@ -47,9 +47,11 @@ def test_uniform_tiling():
         uniform_tiling(64, 3, 8)
 
 
-def _plan_status(L_, Np=32, tiles=None, **kw):
-    cfg = L_.Config(kw.get("L", 100.0), Np, 0, kw.get("n_steps", 4), 0.05, kw.get("a_f", 1.0),
-                    kw.get("precision", 0), 0, 0)
+def _plan_status(L_, Np=32, tiles=None, mesh=0, tile_a_f=None, **kw):
+    cfg = L_.make_config(kw.get("L", 100.0), Np, kw.get("n_steps", 4), 0.05, kw.get("a_f", 1.0),
+                         kw.get("precision", 0), 0, 0, N_lpt=kw.get("N_lpt", 0),
+                         fda_order=kw.get("fda_order", 0), n_lpt=kw.get("n_lpt", 0.0),
+                         discretisation=kw.get("discretisation", 0))
     cos = L_.Cosmology(0.31, 0.0486, 0.6774, 0.9667, 0.81, 2.7255)
     tiles = tiles or [((0, 0, 0), Np, 0)]
     arr = (L_.Tile * len(tiles))()
@@ -57,6 +59,8 @@ def _plan_status(L_, Np=32, tiles=None, **kw):
         arr[i].core_lo[:] = lo
         arr[i].core_n = n
         arr[i].buffer = b
+        arr[i].mesh[:] = (mesh,) * 3 if isinstance(mesh, int) else mesh
+        arr[i].a_f = tile_a_f[i] if tile_a_f else 0.0
     plan = ctypes.c_void_p()
     st = L_.lib().scola_plan_create(ctypes.byref(cfg), ctypes.byref(cos), arr, len(tiles),
                                     ctypes.byref(plan))
@@ -74,10 +78,55 @@ def test_plan_validation_errors():
     st, msg = _plan_status(L_, tiles=[((0, 0, 0), 16, 8), ((16, 0, 0), 16, 8)])
     assert st == -1 and "cover" in msg
     st, msg = _plan_status(L_, tiles=[((0, 0, 0), 32, 3)])
-    assert st == -5 and "multiple of 16" in msg
+    assert st == -5 and "one of 16" in msg
     over = [((0, 0, 0), 16, 8)] * 8
     st, msg = _plan_status(L_, tiles=over)
     assert st == -1 and "overlap" in msg
+
+
+def _validated(st):
+    """The plan passed validation: created (GPU) or stopped at the first HIP call (CPU)."""
+    return st in (0, -3)
+
+
+def test_config_and_tile_fields_accept_and_refuse():
+    L_ = _lib()
+    # mesh: 0 or M per axis accepted, any other size unsupported, negative invalid
+    assert _validated(_plan_status(L_, mesh=0)[0])
+    assert _validated(_plan_status(L_, mesh=32)[0])
+    st, msg = _plan_status(L_, mesh=(32, 32, 33))
+    assert st == -5 and "mesh[2]" in msg
+    assert _plan_status(L_, mesh=-1)[0] == -1
+    # box sizes of the form 2^a {1,3,5,7} outside 16 R, R = 1..8
+    st, msg = _plan_status(L_, Np=16, tiles=[((0, 0, 0), 16, 4)])      # M = 24
+    assert st == -5 and "one of 16" in msg
+    st, msg = _plan_status(L_, Np=256, tiles=[((0, 0, 0), 256, 0)])    # M = 256
+    assert st == -5
+    # fda_order: 0 and 2 accepted, 4 and 6 unsupported, others invalid
+    for o in (0, 2):
+        assert _validated(_plan_status(L_, fda_order=o)[0])
+    for o in (4, 6):
+        st, msg = _plan_status(L_, fda_order=o)
+        assert st == -5 and "order 2" in msg
+    assert _plan_status(L_, fda_order=3)[0] == -1
+    # N_lpt: 0 and Np accepted, a divisor unsupported, anything else invalid
+    for n in (0, 32):
+        assert _validated(_plan_status(L_, N_lpt=n)[0])
+    st, msg = _plan_status(L_, N_lpt=16)
+    assert st == -5 and "N_lpt" in msg
+    assert _plan_status(L_, N_lpt=7)[0] == -1
+    # n_lpt: any finite value; the discretisation switch
+    assert _validated(_plan_status(L_, n_lpt=-1.5)[0])
+    assert _plan_status(L_, n_lpt=float("nan"))[0] == -1
+    assert _validated(_plan_status(L_, discretisation=1)[0])
+    assert _plan_status(L_, discretisation=2)[0] == -1
+    assert L_.lib().scola_status_string(-6) == b"SCOLA_EOVERFLOW"
+    # per-tile final scale factor: 0 or > a_i
+    tl = [((0, 0, 0), 16, 8), ((16, 0, 0), 16, 8), ((0, 16, 0), 16, 8), ((16, 16, 0), 16, 8),
+          ((0, 0, 16), 16, 8), ((16, 0, 16), 16, 8), ((0, 16, 16), 16, 8), ((16, 16, 16), 16, 8)]
+    assert _validated(_plan_status(L_, tiles=tl, tile_a_f=[0.5] + [0.0] * 7)[0])
+    st, msg = _plan_status(L_, tiles=tl, tile_a_f=[0.01] + [0.0] * 7)
+    assert st == -1 and "a_f" in msg
 
 
 def test_schedule_table_matches_oracle():
@@ -93,6 +142,21 @@ def test_schedule_table_matches_oracle():
         np.testing.assert_allclose(t[n, :6], [final["a_D"], final["beta"], final["D1"],
                                               final["D2"], -final["dD1"] * inv,
                                               final["dD2"] * inv], rtol=1e-10)
+
+
+def test_standard_and_modified_schedules_match_oracle():
+    from oracle.cosmology import Cosmology, cola_schedule
+    from paper_2003_04925_amd import schedule_table
+    for disc, nl in (("standard", 0.0), ("modified", -1.5)):
+        t = schedule_table(10, discretisation=disc, n_lpt=nl)
+        steps, final = cola_schedule(Cosmology(), 0.05, 1.0, 10, want_final_kick=True,
+                                     discretisation=disc, n_lpt=nl if nl else -2.5)
+        o = np.array([[s["beta"], s["alpha"]] for s in steps])
+        np.testing.assert_allclose(t[:10, 1:3], o, rtol=1e-10)
+        assert t[10, 1] == pytest.approx(final["beta"], rel=1e-10)
+    # the two discretisations differ
+    assert abs(schedule_table(10, discretisation="standard")[3, 2] /
+               schedule_table(10)[3, 2] - 1) > 1e-3
 
 
 def test_linear_power_matches_oracle():

@@ -177,7 +177,10 @@ def test_concurrent_box_groups_match_one(torch, precision):
 
 def test_fp32_mass_alarm_flags_crowded_nodes(torch):
     """FP32 plans hold node masses in 32-bit integers (2^21 units per particle): the Poisson
-    pass counts nodes that reach 2^31 units (1024 particles), within a factor 2 of wrapping."""
+    pass counts nodes that reach 2^31 units (1024 particles), within a factor 2 of wrapping,
+    and every deposit addition checks the value it returns, so a node pushed past 2^32
+    units (2048 particles; after the wrap it reads as 52 particles, below the first alarm)
+    is counted too and scola_mass_alarm reports SCOLA_EOVERFLOW."""
     import paper_2003_04925_amd as S
     Np, L = 32, 128.0
     tiles = S.uniform_tiling(Np, 2, 8)
@@ -188,7 +191,7 @@ def test_fp32_mass_alarm_flags_crowded_nodes(torch):
     i = torch.arange(M ** 3, device="cuda")
     site = torch.stack([i // (M * M), (i // M) % M, i % M]).double()     # lattice order
     x = sim.view("x_res")
-    for crowd, expect in ((1000, 0), (1500, 1)):
+    for crowd, near, wrapped in ((1000, 0, 0), (1500, 1, 0), (2100, 0, 1)):
         x.zero_()
         # the first `crowd` sites of box 0 moved exactly onto node (10, 10, 10): u = q + x_res
         # with D1 = D2 = 0, and 10 - (i + 1/2) is exact in FP32
@@ -196,9 +199,20 @@ def test_fp32_mass_alarm_flags_crowded_nodes(torch):
         sim.op_deposit(0.0, 0.0)
         sim.op_poisson(1.0)
         torch.cuda.synchronize()
-        alarm = int(sim.view("dropped")[len(tiles)].cpu())
-        say("crowd", crowd, "alarm", alarm)
-        assert alarm == expect
+        counts = sim.view("dropped").cpu().tolist()
+        nt = len(tiles)
+        say("crowd", crowd, "near-limit", counts[nt], "deposits", counts[2 * nt + 1:])
+        assert counts[nt] == near and counts[2 * nt + 1:] == [1] * nt
+        # mass identity per box: found + dropped = M^3 units, short by 2^32 per wrap
+        for t in range(nt):
+            assert M ** 3 * (1 << 21) - counts[t] - counts[nt + 1 + t] == \
+                (wrapped << 32 if t == 0 else 0)
+        if wrapped:
+            with pytest.raises(S.ScolaError) as e:
+                sim.mass_alarm()
+            assert e.value.status == -6 and "2048" in str(e.value)
+        else:
+            assert sim.mass_alarm() == (near, 0)
 
 
 def _eighth_corner_remainder(f, precision):
