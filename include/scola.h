@@ -304,6 +304,23 @@ scola_status scola_plan_set_schedule(scola_plan* plan, const scola_class_schedul
  * of workspace or schedule.  enable = 0 drops it and runs every call eagerly. */
 scola_status scola_plan_set_graph(scola_plan* plan, int32_t enable);
 
+/* One persistent launch per KDK step (the batching pattern of a single fused launch per
+ * step): with enable != 0, every step of the batched evolution that deposits runs, per
+ * class, the fused particle step of all bricks and the three Poisson passes of the next
+ * force in ONE cooperative launch whose grid is the number of workgroups resident at once,
+ * the phases separated by grid-wide barriers (bounded waits; a cooperative launch fails
+ * rather than oversubscribe, so no wait can deadlock).  Results are bitwise those of the
+ * default schedule.  Runs eagerly (no hipGraph) on one box group; FP32 batched plans only
+ * (SCOLA_EUNSUPPORTED for FP64, SCOLA_EINVAL for the per-tile schedule).  It is slower than
+ * the default (the kernel carries the register and LDS needs of its heaviest phase into all
+ * of them), so the default is off.
+ * scola_plan_persistent reports the setting, the grid of the last persistent launch and the
+ * sticky count of barrier waits that gave up (always 0 unless something is wrong); it
+ * synchronises `stream`. */
+scola_status scola_plan_set_persistent(scola_plan* plan, int32_t enable);
+scola_status scola_plan_persistent(const scola_plan* plan, hipStream_t stream, int32_t* enabled,
+                                   int32_t* grid, int32_t* barrier_failures);
+
 /* Step B.2 (Sec. 3.2): core particles' positions/momenta to global lattice order, and the
  * periodic CiC density of the core particles on N_out^3 nodes (all tiles must have been
  * evolved for the density).  Any output pointer may be NULL. */

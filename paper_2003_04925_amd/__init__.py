@@ -346,6 +346,17 @@ class Simulation:
         """Replay the batched evolution as a captured hipGraph (default) or run it eagerly."""
         _lib.check(_lib.lib().scola_plan_set_graph(self._plan, 1 if enable else 0))
 
+    def set_persistent(self, enable):
+        """One persistent cooperative launch per KDK step (scola_plan_set_persistent)."""
+        _lib.check(_lib.lib().scola_plan_set_persistent(self._plan, 1 if enable else 0))
+
+    def persistent(self):
+        """dict(enabled, grid, barrier_failures) of the persistent step schedule."""
+        e, g, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(_lib.lib().scola_plan_persistent(self._plan, self._stream(), ctypes.byref(e),
+                                                    ctypes.byref(g), ctypes.byref(f)))
+        return dict(enabled=bool(e.value), grid=g.value, barrier_failures=f.value)
+
     def tune(self, reps=5):
         """Autotune the launch schedule on this workspace (after setup); returns it."""
         _lib.check(_lib.lib().scola_plan_tune(self._plan, self._ws, self._stream(), reps))

@@ -105,6 +105,9 @@ _SIGS = {
                             _I], _I),
     "scola_plan_tune": ([_P, _P, _P, _I], _I),
     "scola_plan_set_graph": ([_P, _I], _I),
+    "scola_plan_set_persistent": ([_P, _I], _I),
+    "scola_plan_persistent": ([_P, _P, ctypes.POINTER(_I), ctypes.POINTER(_I),
+                               ctypes.POINTER(_I)], _I),
     "scola_plan_concurrency": ([_P, ctypes.POINTER(_I)], _I),
     "scola_plan_set_concurrency": ([_P, _I], _I),
     "scola_plan_schedule": ([_P, _P, _I, ctypes.POINTER(_I)], _I),

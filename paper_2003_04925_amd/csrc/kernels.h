@@ -203,6 +203,16 @@ template <typename T>
 hipError_t launch_tcola_output(const TcolaArgs<T>& a, T* pos, T* mom, unsigned long long* grid,
                                T* density, int N_out, double cell, double L, hipStream_t s);
 
+// One KDK step of one box class (kStep particle pass + the next force's Poisson passes) as
+// one persistent cooperative launch (FP32 plans).  barrier: two device words, the arrival
+// counter (cleared by the launcher) and a sticky flag set if a bounded barrier wait gave
+// up; grid_out receives the grid size used.
+template <typename T>
+hipError_t launch_step_persistent(const ParticleArgs<T>& pa, const MeshArgs<T>& ma, int M,
+                                  const BlockMap& mp, const BlockMap& m1, const BlockMap& m2,
+                                  const BlockMap& m3, unsigned* barrier, hipStream_t s,
+                                  int* grid_out);
+
 constexpr int kPencilChunk = 32;   // z-columns per block of the x-pencil pass
 
 }  // namespace scola

@@ -15,6 +15,7 @@
 #include <new>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -115,6 +116,10 @@ struct scola_plan {
   uint64_t graph_version = 0;
   int graph_eager_calls = 0;
   bool is64 = false;
+  // one persistent cooperative launch per KDK step and class instead of four launches
+  bool persistent = false;
+  unsigned* d_barrier = nullptr;      // arrival counter + sticky failure flag
+  int persistent_grid = 0;
   // call-order state, keyed by the workspace it refers to
   const void* setup_ws = nullptr;
   const void* forward_ws = nullptr;   // full forward with checkpoints done on this workspace
@@ -861,6 +866,28 @@ void zero_node_ranges(const scola_plan* p, const std::vector<int>& tiles, T* arr
                               r.second * (int64_t)(sizeof(T) / 4), s), "zero");
 }
 
+// One KDK step k of every class as one persistent launch per class (FP32 batched plans):
+// the particle step and the Poisson passes of force k + 1.
+template <typename T>
+void persistent_step(scola_plan* p, void* ws, int k, hipStream_t s) {
+  if constexpr (std::is_same<T, float>::value) {
+    for (size_t c = 0; c < p->part.class_M.size(); ++c) {
+      const int tc = p->part.class_tc[c];
+      ParticleArgs<T> pa = particle_args<T>(p, ws, class_scalars(p, tc, kStep, k));
+      MeshArgs<T> ma = mesh_args<T>(p, ws, p->tclasses[tc].D1[k + 1]);
+      BlockMap mp = class_map(p->part, c), m1 = class_map(p->p1, c), m2 = class_map(p->p2, c),
+               m3 = class_map(p->p3, c);
+      mp.xcd_remap = p->sched[c].xcd_remap_particles;
+      m1.xcd_remap = m2.xcd_remap = m3.xcd_remap = p->sched[c].xcd_remap_mesh;
+      hip_check(launch_step_persistent<T>(pa, ma, p->part.class_M[c], mp, m1, m2, m3,
+                                          p->d_barrier, s, &p->persistent_grid),
+                "persistent step kernel");
+    }
+  } else {
+    fail(SCOLA_EUNSUPPORTED, "the persistent step is built for FP32 plans");
+  }
+}
+
 // allow_groups = false keeps the whole evolution on `s` (no plan-owned streams or events
 // are created or used).
 template <typename T>
@@ -870,6 +897,7 @@ void do_evolve(scola_plan* p, const std::vector<int>& tiles, void* ws, hipStream
   const bool batched = p->cfg.schedule == SCOLA_BATCHED && tiles.size() == p->desc.size();
   hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped)),
                             3 * (int64_t)p->desc.size() + 1, s), "zero dropped");
+  if (p->persistent) hip_check(launch_zero_u32(p->d_barrier, 2, s), "zero barrier");
   const int n = p->cfg.n_steps;
   auto run = [&](const std::vector<int>& set, bool b, hipStream_t s, int g, int G) {
     Runner<T> r{p, ws, s, set, b};
@@ -880,9 +908,15 @@ void do_evolve(scola_plan* p, const std::vector<int>& tiles, void* ws, hipStream
     r.particles_step(kInit, 0);             // L-: x_res = p_res = 0, deposit x_LPT(t_0)
     r.poisson_step(0);
     const int ck = p->cfg.checkpoint_every;
+    const bool fused = p->persistent && b && G == 1 && !ov_delta && !ov_phi;
     for (int k = 0; k < n; ++k) {
       if (ck > 0 && k % ck == 0) copy_checkpoint<T>(p, set, k / ck, true, ws, s);
       const bool need_force = k < n - 1 || p->cfg.want_momenta;
+      if (need_force && fused) {
+        persistent_step<T>(p, ws, k, s);
+        r.force++;
+        continue;
+      }
       r.particles_step(need_force ? kStep : kStepNoDeposit, k);
       if (need_force) r.poisson_step(k + 1);
     }
@@ -1486,6 +1520,7 @@ scola_status scola_plan_create(const scola_config* cfg, const scola_cosmology* c
     upload_maps(p->p1);
     upload_maps(p->p2);
     upload_maps(p->p3);
+    hip_check(hipMalloc(&p->d_barrier, 2 * sizeof(unsigned)), "hipMalloc(barrier)");
     hip_check(hipMalloc(&p->d_tiles, p->desc.size() * sizeof(TileDesc)), "hipMalloc(tiles)");
     hip_check(hipMemcpy(p->d_tiles, p->desc.data(), p->desc.size() * sizeof(TileDesc),
                         hipMemcpyHostToDevice), "hipMemcpy(tiles)");
@@ -1509,6 +1544,7 @@ scola_status scola_plan_destroy(scola_plan* p) {
   }
   if (p->ev_fork) hipEventDestroy(p->ev_fork);
   if (p->d_tiles) hipFree(p->d_tiles);
+  if (p->d_barrier) hipFree(p->d_barrier);
   if (p->d_twiddles) hipFree(p->d_twiddles);
   if (p->d_eigen) hipFree(p->d_eigen);
   delete p;
@@ -1549,8 +1585,8 @@ scola_status scola_evolve(scola_plan* p, const int32_t* subset, int32_t n_subset
     if (p->setup_ws != ws) fail(SCOLA_ESTATE, "scola_setup has not run on this workspace");
     const std::vector<int> tiles = subset_list(p, subset, n_subset);
     p->forward_ws = (p->cfg.checkpoint_every > 0 && tiles.size() == p->desc.size()) ? ws : nullptr;
-    const bool graphable = p->use_graph && p->cfg.schedule == SCOLA_BATCHED &&
-                           tiles.size() == p->desc.size();
+    const bool graphable = p->use_graph && !p->persistent &&
+                           p->cfg.schedule == SCOLA_BATCHED && tiles.size() == p->desc.size();
     if (graphable) {
       if (p->graph_ws != ws || p->graph_version != p->sched_version) {
         drop_graph(p);
@@ -1611,6 +1647,32 @@ scola_status scola_plan_set_graph(scola_plan* p, int32_t enable) {
     if (!p) fail(SCOLA_EINVAL, "null plan");
     p->use_graph = enable != 0;
     if (!p->use_graph) drop_graph(p);
+  });
+}
+
+scola_status scola_plan_set_persistent(scola_plan* p, int32_t enable) {
+  return guarded([&] {
+    if (!p) fail(SCOLA_EINVAL, "null plan");
+    if (enable && p->is64) fail(SCOLA_EUNSUPPORTED, "the persistent step is built for FP32 plans");
+    if (enable && p->cfg.schedule != SCOLA_BATCHED)
+      fail(SCOLA_EINVAL, "the persistent step needs the batched schedule");
+    p->persistent = enable != 0;
+    drop_graph(p);
+    ++p->sched_version;
+  });
+}
+
+scola_status scola_plan_persistent(const scola_plan* p, hipStream_t s, int32_t* enabled,
+                                   int32_t* grid, int32_t* barrier_failures) {
+  return guarded([&] {
+    if (!p) fail(SCOLA_EINVAL, "null plan");
+    unsigned w[2] = {0, 0};
+    hip_check(hipMemcpyAsync(w, p->d_barrier, sizeof(w), hipMemcpyDeviceToHost, s),
+              "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (enabled) *enabled = p->persistent ? 1 : 0;
+    if (grid) *grid = p->persistent_grid;
+    if (barrier_failures) *barrier_failures = (int32_t)w[1];
   });
 }
 

@@ -281,3 +281,29 @@ def test_rounding_remainder_leaves_no_node_below_zero(torch, precision):
     err = np.abs(phi - want).max() / np.abs(want).max()
     say("  min node total", int(rho.min()), "potential rel err", err)
     assert err < (1e-10 if precision == "fp64" else 3e-5)
+
+
+def test_persistent_step_matches_the_default_schedule(torch):
+    """One persistent cooperative launch per KDK step (particle step + Poisson passes of
+    the next force, grid-wide barriers between them) gives bitwise the results of the
+    default four-launch step, on uniform and mixed box sizes, with no barrier wait giving
+    up; FP64 plans refuse it."""
+    import paper_2003_04925_amd as S
+    from test_gpu_mixed import mixed_tiles
+    for Np, L, tiles in ((32, 128.0, S.uniform_tiling(32, 2, 8)), (64, 256.0, mixed_tiles())):
+        w = torch.from_numpy(synthetic.white_noise(Np, 23)).cuda()
+        ref = S.Simulation(L, Np, tiles, 4, precision="fp32", want_momenta=True).forward(w)
+        sim = S.Simulation(L, Np, tiles, 4, precision="fp32", want_momenta=True)
+        sim.set_persistent(True)
+        for _ in range(2):
+            out = sim.forward(w)
+            torch.cuda.synchronize()
+            st = sim.persistent()
+            say("persistent", Np, st)
+            assert st["enabled"] and st["grid"] >= 8 and st["barrier_failures"] == 0
+            for k in ("pos", "mom", "density"):
+                assert torch.equal(out[k], ref[k]), k
+    sim64 = S.Simulation(128.0, 32, S.uniform_tiling(32, 2, 8), 2, precision="fp64")
+    with pytest.raises(S.ScolaError) as e:
+        sim64.set_persistent(True)
+    assert e.value.status == -5
