@@ -17,7 +17,8 @@ per particle (x_res and p_res read and written in FP32, Psi1 and Psi2 read in FP
 with HIP events around single launches on the stream it runs on.  roofline.whole_step adds
 the Poisson solve (16 B per interior node) and takes the measured time of one KDK step of
 the evolution, i.e. every kernel of the step.
-CPU baseline: the FP64 oracle running the whole c1 workload, boxes in parallel processes.
+CPU baseline: the FP64 oracle on a sample of c2 (16 of its 64 boxes, all steps) and on the
+whole c1 workload, boxes in parallel processes.
 """
 import argparse
 import json
@@ -135,11 +136,11 @@ def _oracle_box(args):
         return time.perf_counter() - t0
 
 
-def cpu_baseline(name="c1", max_workers=16):
-    """The FP64 oracle on the host's cores: the whole workload `name` (c1: 8 boxes of 48^3,
-    10 steps), the full-box set-up once, then its boxes evolved in parallel worker
-    processes (one box per process, as the boxes are independent), single-threaded BLAS in
-    each.  value = box particles x steps / wall time of the parallel evolution."""
+def oracle_rate(name, max_boxes=None, max_workers=16):
+    """The FP64 oracle on the host's cores: workload `name` (its first max_boxes boxes, or
+    all), the full-box set-up once, then the boxes evolved in parallel worker processes (one
+    box per process, as the boxes are independent), single-threaded BLAS in each.
+    value = box particles x steps / wall time of the parallel evolution."""
     import multiprocessing as mp
 
     import numpy as np
@@ -154,38 +155,40 @@ def cpu_baseline(name="c1", max_workers=16):
     t0 = time.perf_counter()
     phi1, phi2, psi1, psi2 = setup_full_box(synthetic.white_noise(wl.Np, 42), wl.L, c, wl.a_i)
     tiles = uniform_tiling(wl.Np, wl.tiles_per_side, wl.buffer)
+    if max_boxes:
+        tiles = tiles[:max_boxes]
     steps, _ = cola_schedule(c, wl.a_i, wl.a_f, wl.n_steps)
     jobs = [(*box_inputs(psi1, psi2, phi1, t), steps) for t in tiles]
     setup_s = time.perf_counter() - t0
     model, ncpu = cpu_model()
     workers = max(1, min(len(jobs), ncpu, max_workers))
-    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS",
-                                          "MKL_NUM_THREADS")}
-    for k in env:
-        os.environ[k] = "1"
-    try:
-        # fork: called before this process touches the GPU (see main)
-        ctx = mp.get_context("fork")
-        t0 = time.perf_counter()
-        with ctx.Pool(workers) as pool:
-            per_box = pool.map(_oracle_box, jobs)
-        wall = time.perf_counter() - t0
-    finally:
-        for k, v in env.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
+    # fork: called before this process touches the GPU (see main)
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        per_box = pool.map(_oracle_box, jobs)
+    wall = time.perf_counter() - t0
     P = sum(t.M ** 3 for t in tiles)
+    n_all = wl.tiles_per_side ** 3
+    part = "in full" if len(tiles) == n_all else f"{len(tiles)} of its {n_all} boxes"
     return dict(value=P * wl.n_steps / wall, unit="particle-steps/s", cores=workers,
                 kind="oracle",
-                sample=f"{name} in full: {len(tiles)} boxes of {tiles[0].M}^3, {wl.n_steps} "
-                       f"KDK steps, FP64 NumPy, one box per worker process ({workers} "
-                       f"processes, 1 BLAS thread each) on {model} ({ncpu} logical CPUs "
-                       f"visible); evolution wall {wall:.1f} s (pool start included), "
-                       f"per-box CPU {np.mean(per_box):.1f} s, full-box set-up {setup_s:.1f} s",
+                sample=f"{name} {part}: boxes of {tiles[0].M}^3, {wl.n_steps} KDK steps, FP64 "
+                       f"NumPy, one box per worker process ({workers} processes, 1 BLAS "
+                       f"thread each) on {model} ({ncpu} logical CPUs visible); evolution wall "
+                       f"{wall:.1f} s (pool start included), CPU {np.sum(per_box):.1f} s in "
+                       f"all, full-box set-up {setup_s:.1f} s",
                 cpu_model=model, host_logical_cpus=ncpu, evolution_wall_s=wall,
-                setup_s=setup_s)
+                cpu_s=float(np.sum(per_box)), setup_s=setup_s)
+
+
+def cpu_baseline():
+    """The oracle on the benchmark's own workload c2 (a bounded sample: as many boxes as
+    worker processes, up to 16, with all 20 steps, scaled to particle-steps/s), and on the
+    plain FP64 workload c1 in full."""
+    out = oracle_rate("c2", max_boxes=16)
+    out["c1_full"] = oracle_rate("c1")
+    return out
 
 
 def adjoint_timing(torch, S, synthetic, name="c4", reps=3):
@@ -280,7 +283,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline and not args.adjoint_only and not args.kernels_only \
             and args.workload == "c2":
-        cpu = cpu_baseline("c1")
+        cpu = cpu_baseline()
 
     import torch
 
@@ -381,6 +384,22 @@ def main():
                      "whole_step": whole_step(P, G, ms / wl.n_steps)
                      if sim.precision == "fp32" else None},
     }
+    # the same evolution with one persistent cooperative launch per KDK step (the batching
+    # pattern of a single fused launch per step), for comparison with the default schedule
+    try:
+        sim.set_persistent(True)
+        pms, _ = time_evolve(torch, sim, max(3, args.steps // 2), args.warmup)
+        st = sim.persistent()
+        sim.set_persistent(False)
+        result["persistent_step"] = {
+            "ms_per_evolve": pms, "value": P * wl.n_steps / (pms * 1e-3),
+            "unit": "particle-steps/s", "vs_default": ms / pms, "grid": st["grid"],
+            "barrier_failures": st["barrier_failures"],
+            "note": "one cooperative launch per KDK step and class (particle step + the three "
+                    "Poisson passes, grid-wide barriers), eager; the default is the "
+                    "graph-replayed four-launch step"}
+    except Exception as exc:          # noqa: BLE001 - reported in the JSON line
+        result["persistent_step"] = {"error": f"{type(exc).__name__}: {exc}"}
     if not args.no_fp64 and args.workload == "c2":
         wl1 = synthetic.WORKLOADS["c1"]
         sim64 = build_sim(S, wl1)
