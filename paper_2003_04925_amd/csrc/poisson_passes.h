@@ -568,6 +568,7 @@ __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const Blo
       pterm = yz_term(y, z);
     }
     unsigned long long found = 0;   // FP32 plans: the plane's total mass in units
+    unsigned near = 0;              // FP32 plans: node masses within a factor 2 of wrapping
     for (int e0 = 0; e0 < n * n; e0 += kBatch * kBlock) {
       Rho r[kBatch];
 #pragma unroll
@@ -581,13 +582,19 @@ __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const Blo
         if (e >= n * n) continue;
         a.rho[base + e] = Rho(0);
         if constexpr (std::is_same<T, float>::value) {
-          if (r[q] >= (1u << 31)) atomicAdd(a.alarm, 1ull);   // within a factor 2 of wrapping
+          near += r[q] >> 31;
           found += r[q];
+          // FP32: the unit count converted in single precision (exact below 2^24 units,
+          // i.e. 8 particles; beyond, one rounding of relative size 2^-24, as the FP32
+          // result itself has), times 2^-21 exactly, minus one
+          plane[e] = fmaf((float)r[q], (float)kUnit, -1.0f);
+        } else {
+          plane[e] = (T)(mass_units(r[q]) * kUnit - 1.0);
         }
-        plane[e] = (T)(mass_units(r[q]) * kUnit - 1.0);
       }
     }
     if constexpr (std::is_same<T, float>::value) {
+      if (near) atomicAdd(a.alarm, (unsigned long long)near);
       // mass identity of FP32 plans: summed over a box's planes, the mass found plus the
       // mass dropped equals one unit per particle and deposit unless a 32-bit node wrapped
       // (each wrap loses exactly 2^32 units); one atomic per wave
