@@ -12,8 +12,8 @@ Workloads (particles per side, box side, tiling):
   c2  500 Mpc/h, 128^3 particles, 4^3 tiles of 32^3 + 16 buffer (64^3 boxes), 20 steps, FP32
   c1  200 Mpc/h, 64^3 particles, 2^3 tiles of 32^3 + 8 buffer (48^3 boxes), 10 steps, FP64
       per-tile (the plain path)
-Roofline: the dominant kernel is the fused particle step; its algorithmic traffic is 96 B
-per particle (x_res and p_res read and written in FP32, Psi1 and Psi2 read in FP64), timed
+Roofline: the dominant kernel is the fused particle step; its algorithmic traffic is 72 B
+per particle (x_res and p_res read and written, Psi1 and Psi2 read, all FP32), timed
 with HIP events around single launches on the stream it runs on.  roofline.whole_step adds
 the Poisson solve (16 B per interior node) and takes the measured time of one KDK step of
 the evolution, i.e. every kernel of the step.
@@ -31,6 +31,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PARTICLE_BYTES_FP32 = 72     # per particle and step: 4 x 12 B of x_res/p_res + 2 x 12 B of Psi
+PARTICLE_BYTES_FP64 = 144
 
 
 def build_sim(S, wl, precision=None, schedule=None):
@@ -67,11 +69,11 @@ def measured_traffic():
 
 
 def whole_step(P, G, ms_per_kdk):
-    """All kernels of one KDK step against the HBM roofline: algorithmic bytes 96 B per box
-    particle (x_res, p_res read and written in FP32, Psi1, Psi2 read in FP64) + 16 B per
-    interior mesh node (delta written and read, Phi written and read, FP32) over the
-    measured time of one KDK step of the evolution."""
-    b = 96 * P + 16 * G
+    """All kernels of one KDK step against the HBM roofline: algorithmic bytes 72 B per box
+    particle (x_res, p_res read and written, Psi1, Psi2 read, FP32) + 16 B per interior mesh
+    node (delta written and read, Phi written and read, FP32) over the measured time of one
+    KDK step of the evolution."""
+    b = PARTICLE_BYTES_FP32 * P + 16 * G
     gbs = b / (ms_per_kdk * 1e-3) / 1e9
     return {"bytes_per_kdk_step": b, "ms_per_kdk_step": ms_per_kdk, "achieved": gbs,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
@@ -266,6 +268,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the mixed-size (c3) and large (c5) workload lines")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="skip the persistent-step comparison (cooperative launches)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the forward + reverse timing of the adjoint workload")
     ap.add_argument("--kernels-only", action="store_true",
@@ -343,7 +347,7 @@ def main():
     step_avg, step_med = time_kernel(
         torch, lambda: sim.op_step(row[1], 0.0, row[3], row[4], row[3], row[4], True), 20)
     pois_avg, _ = time_kernel(torch, lambda: sim.op_poisson(row[3]), 20)
-    algo_bytes = 96 * P if sim.precision == "fp32" else 144 * P
+    algo_bytes = (PARTICLE_BYTES_FP32 if sim.precision == "fp32" else PARTICLE_BYTES_FP64) * P
     G = sum((M - 1) ** 3 for _, M, _, _ in sim.box_slices())
     traffic = measured_traffic() if wl.name == "c2" else None
     achieved = algo_bytes / (step_avg * 1e-3) / 1e9
@@ -387,6 +391,8 @@ def main():
     # the same evolution with one persistent cooperative launch per KDK step (the batching
     # pattern of a single fused launch per step), for comparison with the default schedule
     try:
+        if args.no_persistent:
+            raise RuntimeError("skipped (--no-persistent)")
         sim.set_persistent(True)
         pms, _ = time_evolve(torch, sim, max(3, args.steps // 2), args.warmup)
         st = sim.persistent()

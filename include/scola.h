@@ -114,7 +114,8 @@ typedef struct scola_plan scola_plan;
  * operator-level calls).  P = total box particles, G = sum (M-1)^3, H = sum (M+3)^3,
  * N = N_p, R = real type of the plan (float or double). */
 typedef struct {
-  size_t psi1, psi2;       /* double [3][P]: Psi1 = grad phi1, Psi2 = grad phi2 (cells) */
+  size_t psi1, psi2;       /* R [3][P]: Psi1 = grad phi1, Psi2 = grad phi2 (cells), differenced
+                              in FP64 and stored in the plan precision R */
   size_t x_res, p_res;     /* R [3][P]: COLA residual position and momentum (cells) */
   size_t rho;              /* fixed-point CiC mass, 2^fixed_bits units per particle: int64 [G]
                               (FP64 plans) or uint32 [G] (FP32 plans; a node holds at most

@@ -171,7 +171,7 @@ class Simulation:
         P, G, H, N = lay.n_particles, lay.n_nodes, lay.n_padded, self.Np
         rb = 8 if self.precision == "fp64" else 4
         spec = {
-            "psi1": (t.float64, (3, P)), "psi2": (t.float64, (3, P)),
+            "psi1": (self.real, (3, P)), "psi2": (self.real, (3, P)),
             "x_res": (self.real, (3, P)), "p_res": (self.real, (3, P)),
             # mass mesh: int64 (FP64 plans) or unsigned 32-bit held in an int32 view (FP32)
             "rho": (t.int64 if self.precision == "fp64" else t.int32, (G,)),

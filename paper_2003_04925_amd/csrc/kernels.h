@@ -36,8 +36,8 @@ struct BoxSetupArgs {
   int n_blocks;
   const double* phi1;
   const double* phi2;
-  double* psi1;
-  double* psi2;
+  void* psi1;               // [3][P] in the plan precision
+  void* psi2;
   double* bc0;
   int N;
   int64_t P;
@@ -71,8 +71,8 @@ struct MeshArgs {
 template <typename T>
 struct ParticleArgs {
   const TileDesc* tiles;
-  const double* psi1;
-  const double* psi2;
+  const T* psi1;            // [3][P] in the plan precision
+  const T* psi2;
   T* xres;
   T* xout;                  // x_res after the drift: xres itself, or another buffer
   T* pres;
@@ -92,8 +92,8 @@ struct ParticleArgs {
 template <typename T>
 struct OutputArgs {
   const TileDesc* tiles;
-  const double* psi1;
-  const double* psi2;
+  const T* psi1;            // [3][P] in the plan precision
+  const T* psi2;
   const T* xres;
   const T* pres;
   T* pos;
@@ -108,8 +108,8 @@ struct OutputArgs {
 template <typename T>
 struct AdjointArgs {
   const TileDesc* tiles;
-  const double* psi1;
-  const double* psi2;
+  const T* psi1;            // [3][P] in the plan precision
+  const T* psi2;
   T* lam_x;                 // adjoint of x_res, [3][P]
   T* lam_p;                 // adjoint of p_res, [3][P]
   T* lam_psi1;              // accumulated adjoint of Psi1, [3][P] (plan precision)
@@ -180,8 +180,8 @@ hipError_t launch_take_real(const double2* c, double* out, double scale, int64_t
 // component arrays, a periodic N^3 node grid).
 template <typename T>
 struct TcolaArgs {
-  const double* psi1;
-  const double* psi2;
+  const T* psi1;            // [3][N^3] in the plan precision
+  const T* psi2;
   T* xres;
   T* pres;
   unsigned long long* rho;   // [N^3] fixed-point mass, 2^40 units per particle

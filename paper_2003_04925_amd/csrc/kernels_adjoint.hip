@@ -367,8 +367,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_particles(AdjointArgs<T> a, Bloc
   // meshes that neighbouring blocks reuse)
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    s1[c] = __builtin_nontemporal_load(a.psi1 + c * P + p);
-    s2[c] = __builtin_nontemporal_load(a.psi2 + c * P + p);
+    s1[c] = (double)__builtin_nontemporal_load(a.psi1 + c * P + p);
+    s2[c] = (double)__builtin_nontemporal_load(a.psi2 + c * P + p);
     lx[c] = __builtin_nontemporal_load(a.lam_x + c * P + p);
     lp[c] = __builtin_nontemporal_load(a.lam_p + c * P + p);
     if (SCATTER) xsc[c] = __builtin_nontemporal_load(a.xs + c * P + p);

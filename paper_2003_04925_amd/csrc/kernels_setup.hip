@@ -165,7 +165,7 @@ template <typename T>
 __global__ void k_extract_psi(const TileDesc* __restrict__ tiles,
                               const int* __restrict__ blk_tile, const int* __restrict__ blk_first,
                               const double* __restrict__ phi1, const double* __restrict__ phi2,
-                              double* __restrict__ psi1, double* __restrict__ psi2,
+                              T* __restrict__ psi1, T* __restrict__ psi2,
                               T* __restrict__ xres, T* __restrict__ pres, int N, int64_t P) {
   const TileDesc t = tiles[blk_tile[blockIdx.x]];
   const int64_t pl = (int64_t)blk_first[blockIdx.x] * kBlock + threadIdx.x;
@@ -180,12 +180,14 @@ __global__ void k_extract_psi(const TileDesc* __restrict__ tiles,
     return f[((int64_t)wrap(x, N) * N + wrap(y, N)) * N + wrap(z, N)];
   };
   const int64_t p = t.p_off + pl;
-  psi1[p] = 0.5 * (at(phi1, gx + 1, gy, gz) - at(phi1, gx - 1, gy, gz));
-  psi1[P + p] = 0.5 * (at(phi1, gx, gy + 1, gz) - at(phi1, gx, gy - 1, gz));
-  psi1[2 * P + p] = 0.5 * (at(phi1, gx, gy, gz + 1) - at(phi1, gx, gy, gz - 1));
-  psi2[p] = 0.5 * (at(phi2, gx + 1, gy, gz) - at(phi2, gx - 1, gy, gz));
-  psi2[P + p] = 0.5 * (at(phi2, gx, gy + 1, gz) - at(phi2, gx, gy - 1, gz));
-  psi2[2 * P + p] = 0.5 * (at(phi2, gx, gy, gz + 1) - at(phi2, gx, gy, gz - 1));
+  // differenced in FP64, stored in the plan precision (FP32 plans keep the paper's
+  // single-precision particle record)
+  psi1[p] = (T)(0.5 * (at(phi1, gx + 1, gy, gz) - at(phi1, gx - 1, gy, gz)));
+  psi1[P + p] = (T)(0.5 * (at(phi1, gx, gy + 1, gz) - at(phi1, gx, gy - 1, gz)));
+  psi1[2 * P + p] = (T)(0.5 * (at(phi1, gx, gy, gz + 1) - at(phi1, gx, gy, gz - 1)));
+  psi2[p] = (T)(0.5 * (at(phi2, gx + 1, gy, gz) - at(phi2, gx - 1, gy, gz)));
+  psi2[P + p] = (T)(0.5 * (at(phi2, gx, gy + 1, gz) - at(phi2, gx, gy - 1, gz)));
+  psi2[2 * P + p] = (T)(0.5 * (at(phi2, gx, gy, gz + 1) - at(phi2, gx, gy, gz - 1)));
   for (int c = 0; c < 3; ++c) {
     xres[c * P + p] = T(0);
     pres[c * P + p] = T(0);
@@ -292,7 +294,8 @@ template <typename T>
 hipError_t launch_setup_boxes(const BoxSetupArgs& a, T* xres, T* pres, hipStream_t s) {
   if (a.n_blocks > 0)
     hipLaunchKernelGGL(k_extract_psi<T>, dim3(a.n_blocks), dim3(kBlock), 0, s, a.tiles,
-                       a.blk_tile, a.blk_first, a.phi1, a.phi2, a.psi1, a.psi2, xres, pres,
+                       a.blk_tile, a.blk_first, a.phi1, a.phi2, static_cast<T*>(a.psi1),
+                       static_cast<T*>(a.psi2), xres, pres,
                        a.N, a.P);
   hipLaunchKernelGGL(k_boundary_potential, dim3(64, a.n_tiles), dim3(kBlock), 0, s, a.tiles,
                      a.n_tiles, a.phi1, a.bc0, a.N);

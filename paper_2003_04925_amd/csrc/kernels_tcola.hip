@@ -37,14 +37,14 @@ __global__ void __launch_bounds__(kBlock) k_tcola_setup(TcolaArgs<T> a, const do
   auto at = [&](const double* f, int i, int j, int k) {
     return f[((int64_t)pwrap(i, N) * N + pwrap(j, N)) * N + pwrap(k, N)];
   };
-  double* s1 = const_cast<double*>(a.psi1);
-  double* s2 = const_cast<double*>(a.psi2);
-  s1[p] = 0.5 * (at(phi1, x + 1, y, z) - at(phi1, x - 1, y, z));
-  s1[n3 + p] = 0.5 * (at(phi1, x, y + 1, z) - at(phi1, x, y - 1, z));
-  s1[2 * n3 + p] = 0.5 * (at(phi1, x, y, z + 1) - at(phi1, x, y, z - 1));
-  s2[p] = 0.5 * (at(phi2, x + 1, y, z) - at(phi2, x - 1, y, z));
-  s2[n3 + p] = 0.5 * (at(phi2, x, y + 1, z) - at(phi2, x, y - 1, z));
-  s2[2 * n3 + p] = 0.5 * (at(phi2, x, y, z + 1) - at(phi2, x, y, z - 1));
+  T* s1 = const_cast<T*>(a.psi1);
+  T* s2 = const_cast<T*>(a.psi2);
+  s1[p] = (T)(0.5 * (at(phi1, x + 1, y, z) - at(phi1, x - 1, y, z)));
+  s1[n3 + p] = (T)(0.5 * (at(phi1, x, y + 1, z) - at(phi1, x, y - 1, z)));
+  s1[2 * n3 + p] = (T)(0.5 * (at(phi1, x, y, z + 1) - at(phi1, x, y, z - 1)));
+  s2[p] = (T)(0.5 * (at(phi2, x + 1, y, z) - at(phi2, x - 1, y, z)));
+  s2[n3 + p] = (T)(0.5 * (at(phi2, x, y + 1, z) - at(phi2, x, y - 1, z)));
+  s2[2 * n3 + p] = (T)(0.5 * (at(phi2, x, y, z + 1) - at(phi2, x, y, z - 1)));
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     a.xres[c * n3 + p] = T(0);

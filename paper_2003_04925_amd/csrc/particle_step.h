@@ -395,8 +395,8 @@ __device__ __forceinline__ void particles_block(const ParticleArgs<T>& a, const 
   // deposit's atomics) and potential, which neighbouring blocks reuse
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    s1[c] = __builtin_nontemporal_load(a.psi1 + c * P + p);
-    s2[c] = __builtin_nontemporal_load(a.psi2 + c * P + p);
+    s1[c] = (double)__builtin_nontemporal_load(a.psi1 + c * P + p);
+    s2[c] = (double)__builtin_nontemporal_load(a.psi2 + c * P + p);
     if (MODE == kInit) {
       // operator L- (App. B): at t_0 the particles sit on their LPT trajectory and the
       // residual momentum is zero

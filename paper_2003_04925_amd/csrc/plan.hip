@@ -376,8 +376,8 @@ void build_layout(scola_plan* p) {
     off = align256(off + bytes);
     return o;
   };
-  l.psi1 = take(3 * (size_t)p->P * 8);
-  l.psi2 = take(3 * (size_t)p->P * 8);
+  l.psi1 = take(3 * (size_t)p->P * R);
+  l.psi2 = take(3 * (size_t)p->P * R);
   l.x_res = take(3 * (size_t)p->P * R);
   l.p_res = take(3 * (size_t)p->P * R);
   l.rho = take(rho_bytes(p));
@@ -473,8 +473,8 @@ template <typename T>
 ParticleArgs<T> particle_args(scola_plan* p, void* ws, const StepScalars& sc) {
   ParticleArgs<T> a;
   a.tiles = p->d_tiles;
-  a.psi1 = reinterpret_cast<const double*>(ws_ptr(ws, p->lay.psi1));
-  a.psi2 = reinterpret_cast<const double*>(ws_ptr(ws, p->lay.psi2));
+  a.psi1 = reinterpret_cast<const T*>(ws_ptr(ws, p->lay.psi1));
+  a.psi2 = reinterpret_cast<const T*>(ws_ptr(ws, p->lay.psi2));
   a.xres = reinterpret_cast<T*>(ws_ptr(ws, p->lay.x_res));
   a.xout = a.xres;
   a.pres = reinterpret_cast<T*>(ws_ptr(ws, p->lay.p_res));
@@ -740,8 +740,8 @@ BoxSetupArgs box_setup_args(scola_plan* p, void* ws) {
   b.n_blocks = (int)p->part.tile.size();
   b.phi1 = reinterpret_cast<double*>(ws_ptr(ws, p->lay.phi1));
   b.phi2 = reinterpret_cast<double*>(ws_ptr(ws, p->lay.phi2));
-  b.psi1 = reinterpret_cast<double*>(ws_ptr(ws, p->lay.psi1));
-  b.psi2 = reinterpret_cast<double*>(ws_ptr(ws, p->lay.psi2));
+  b.psi1 = ws_ptr(ws, p->lay.psi1);
+  b.psi2 = ws_ptr(ws, p->lay.psi2);
   b.bc0 = reinterpret_cast<double*>(ws_ptr(ws, p->lay.bc0));
   b.N = p->cfg.Np;
   b.P = p->P;
@@ -942,8 +942,8 @@ void do_output(scola_plan* p, void* pos, void* mom, void* dens, const std::vecto
                void* ws, hipStream_t s) {
   OutputArgs<T> a;
   a.tiles = p->d_tiles;
-  a.psi1 = reinterpret_cast<const double*>(ws_ptr(ws, p->lay.psi1));
-  a.psi2 = reinterpret_cast<const double*>(ws_ptr(ws, p->lay.psi2));
+  a.psi1 = reinterpret_cast<const T*>(ws_ptr(ws, p->lay.psi1));
+  a.psi2 = reinterpret_cast<const T*>(ws_ptr(ws, p->lay.psi2));
   a.xres = reinterpret_cast<const T*>(ws_ptr(ws, p->lay.x_res));
   a.pres = reinterpret_cast<const T*>(ws_ptr(ws, p->lay.p_res));
   a.pos = reinterpret_cast<T*>(pos);
@@ -1000,8 +1000,8 @@ void do_backward(scola_plan* p, const T* lam_dens, double* grad_w, void* ws, hip
   const int64_t N3 = (int64_t)N * N * N;
   AdjointArgs<T> a{};
   a.tiles = p->d_tiles;
-  a.psi1 = reinterpret_cast<const double*>(ws_ptr(ws, l.psi1));
-  a.psi2 = reinterpret_cast<const double*>(ws_ptr(ws, l.psi2));
+  a.psi1 = reinterpret_cast<const T*>(ws_ptr(ws, l.psi1));
+  a.psi2 = reinterpret_cast<const T*>(ws_ptr(ws, l.psi2));
   a.lam_x = reinterpret_cast<T*>(ws_ptr(ws, l.lam_x));
   a.lam_p = reinterpret_cast<T*>(ws_ptr(ws, l.lam_p));
   a.lam_psi1 = reinterpret_cast<T*>(ws_ptr(ws, l.lam_psi1));
@@ -1287,8 +1287,8 @@ TcolaLayout tcola_layout(const scola_plan* p) {
     off = align256(off + bytes);
     return o;
   };
-  l.psi1 = take(3 * N3 * 8);
-  l.psi2 = take(3 * N3 * 8);
+  l.psi1 = take(3 * N3 * R);
+  l.psi2 = take(3 * N3 * R);
   l.x_res = take(3 * N3 * R);
   l.p_res = take(3 * N3 * R);
   l.rho = take(N3 * 8);
@@ -1314,8 +1314,8 @@ void do_tcola(scola_plan* p, const double* w, void* pos, void* mom, void* dens, 
   sa.phi2 = reinterpret_cast<double*>(ws_ptr(ws, l.phi2));
   hip_check(launch_setup_potentials(sa, s), "set-up potentials");
   TcolaArgs<T> a{};
-  a.psi1 = reinterpret_cast<const double*>(ws_ptr(ws, l.psi1));
-  a.psi2 = reinterpret_cast<const double*>(ws_ptr(ws, l.psi2));
+  a.psi1 = reinterpret_cast<const T*>(ws_ptr(ws, l.psi1));
+  a.psi2 = reinterpret_cast<const T*>(ws_ptr(ws, l.psi2));
   a.xres = reinterpret_cast<T*>(ws_ptr(ws, l.x_res));
   a.pres = reinterpret_cast<T*>(ws_ptr(ws, l.p_res));
   a.rho = reinterpret_cast<unsigned long long*>(ws_ptr(ws, l.rho));
