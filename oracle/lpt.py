@@ -15,6 +15,10 @@ Paper passages followed:
     one-dimensional gradient operations, i.e. phi_,ij = D_i (D_j phi) with the
     order-2 central difference D.
 
+  * Sec. 3 (operators): Laplacians and gradients by finite differences at order 2, 4 or 6,
+    N_ghost = 1, 2, 3 neighbours per side (fda_order arguments below; order 2 is the default
+    and the order of every run of Sec. 4).
+
 Readings where the paper is silent: the LPT grid has N = N_p nodes per side and its
 nodes coincide with the particles of the Lagrangian lattice, at q = (i + 1/2) cells; the
 FDA-2 Laplacian kernel is used in every Fourier-space Poisson solve; the zero mode of
@@ -73,6 +77,49 @@ def mode_indices(N):
     return np.fft.fftfreq(N, d=1.0 / N)
 
 
+def ghosts(order):
+    """N_ghost of an FDA order (Sec. 3): neighbours per side of the central stencils."""
+    if order not in (2, 4, 6):
+        raise ValueError("FDA order must be 2, 4 or 6")
+    return order // 2
+
+
+def first_derivative_weights(order):
+    """Weights c_k (k = 1..g) of D f(i) = sum_k c_k (f(i+k) - f(i-k)), spacing one cell,
+    from the Taylor conditions: f(i+k) - f(i-k) = 2 sum_{m odd} f^(m) k^m / m!, so the
+    derivative needs 2 sum_k c_k k = 1 and sum_k c_k k^m = 0 for m = 3, 5, .., 2g - 1."""
+    g = ghosts(order)
+    k = np.arange(1, g + 1, dtype=np.float64)
+    A = np.array([k ** m for m in range(1, 2 * g, 2)])
+    rhs = np.zeros(g)
+    rhs[0] = 0.5
+    return np.linalg.solve(A, rhs)
+
+
+def second_derivative_weights(order):
+    """Weights a_k (k = 1..g) of D2 f(i) = sum_k a_k (f(i+k) + f(i-k) - 2 f(i)), from
+    f(i+k) + f(i-k) - 2 f(i) = 2 sum_{m even >= 2} f^(m) k^m / m!: sum_k a_k k^2 = 1 and
+    sum_k a_k k^m = 0 for m = 4, 6, .., 2g."""
+    g = ghosts(order)
+    k = np.arange(1, g + 1, dtype=np.float64)
+    A = np.array([k ** m for m in range(2, 2 * g + 1, 2)])
+    rhs = np.zeros(g)
+    rhs[0] = 1.0
+    return np.linalg.solve(A, rhs)
+
+
+def fda_laplacian_kernel(N, order=2):
+    """Fourier symbol of the order-`order` finite-difference Laplacian on a periodic N^3
+    grid, spacing one cell: sum over axes of sum_k a_k (2 cos(k theta) - 2), theta =
+    2 pi m / N.  Order 2 is fda2_laplacian_kernel."""
+    if order == 2:
+        return fda2_laplacian_kernel(N)
+    a = second_derivative_weights(order)
+    th = 2.0 * np.pi * mode_indices(N) / N
+    s = sum(ak * (2.0 * np.cos((k + 1) * th) - 2.0) for k, ak in enumerate(a))
+    return s[:, None, None] + s[None, :, None] + s[None, None, :]
+
+
 def fda2_laplacian_kernel(N):
     """Fourier symbol of the order-2 finite-difference Laplacian, spacing one cell:
     -4 sum_i sin^2(pi m_i / N)."""
@@ -80,9 +127,9 @@ def fda2_laplacian_kernel(N):
     return -4.0 * (s[:, None, None] + s[None, :, None] + s[None, None, :])
 
 
-def poisson_periodic(src):
-    """Solve Delta phi = src on a periodic grid with the FDA-2 Laplacian; zero mode 0."""
-    K = fda2_laplacian_kernel(src.shape[0])
+def poisson_periodic(src, order=2):
+    """Solve Delta phi = src on a periodic grid with the FDA Laplacian; zero mode 0."""
+    K = fda_laplacian_kernel(src.shape[0], order)
     sk = np.fft.fftn(src)
     with np.errstate(divide="ignore", invalid="ignore"):
         pk = np.where(K != 0.0, sk / K, 0.0)
@@ -110,15 +157,20 @@ def initial_density(white_noise, L, cosmo, growth_ratio):
 
 
 # --- Step A.2: Lagrangian potentials ---------------------------------------------------
-def central_diff(f, axis):
-    """Order-2 central difference, spacing one cell, periodic."""
-    return 0.5 * (np.roll(f, -1, axis=axis) - np.roll(f, 1, axis=axis))
+def central_diff(f, axis, order=2):
+    """Central difference at the given FDA order, spacing one cell, periodic."""
+    if order == 2:
+        return 0.5 * (np.roll(f, -1, axis=axis) - np.roll(f, 1, axis=axis))
+    out = np.zeros_like(f)
+    for k, c in enumerate(first_derivative_weights(order), start=1):
+        out += c * (np.roll(f, -k, axis=axis) - np.roll(f, k, axis=axis))
+    return out
 
 
-def second_order_source(phi1):
+def second_order_source(phi1, order=2):
     """sum_{i>j} [phi_,ii phi_,jj - phi_,ij^2] with phi_,ij = D_i D_j phi (wide stencils)."""
-    d = [central_diff(phi1, a) for a in range(3)]
-    dd = [[central_diff(d[j], i) for j in range(3)] for i in range(3)]
+    d = [central_diff(phi1, a, order) for a in range(3)]
+    dd = [[central_diff(d[j], i, order) for j in range(3)] for i in range(3)]
     src = np.zeros_like(phi1)
     for i in range(3):
         for j in range(i):
@@ -126,16 +178,16 @@ def second_order_source(phi1):
     return src
 
 
-def lagrangian_potentials(white_noise, L, cosmo, growth_ratio):
+def lagrangian_potentials(white_noise, L, cosmo, growth_ratio, order=2):
     """phi1 = Delta^-1 delta_i and phi2 = Delta^-1 S[phi1] on the N^3 LPT grid."""
     dk = initial_density_fourier(white_noise, L, cosmo, growth_ratio)
-    K = fda2_laplacian_kernel(white_noise.shape[0])
+    K = fda_laplacian_kernel(white_noise.shape[0], order)
     with np.errstate(divide="ignore", invalid="ignore"):
         phi1 = np.fft.ifftn(np.where(K != 0.0, dk / K, 0.0)).real
-    phi2 = poisson_periodic(second_order_source(phi1))
+    phi2 = poisson_periodic(second_order_source(phi1, order), order)
     return phi1, phi2
 
 
-def displacement_vectors(phi):
-    """Psi = grad_q phi by order-2 central differences; shape (3, N, N, N)."""
-    return np.stack([central_diff(phi, a) for a in range(3)])
+def displacement_vectors(phi, order=2):
+    """Psi = grad_q phi by central differences; shape (3, N, N, N)."""
+    return np.stack([central_diff(phi, a, order) for a in range(3)])

@@ -22,17 +22,18 @@ from .tiling import (boundary_potential0, box_indices, core_mask, extract_box_fi
                      uniform_tiling)
 
 
-def setup_full_box(white_noise, L, cosmo, a_i):
+def setup_full_box(white_noise, L, cosmo, a_i, fda_order=2):
     """Steps A.1-A.2: phi1, phi2 and Psi1, Psi2 on the LPT grid (cells)."""
     D1 = cosmo.growth(np.array([1.0]), a_i)[0][0]          # D1(1) / D1(a_i)
-    phi1, phi2 = lagrangian_potentials(white_noise, L, cosmo, 1.0 / D1)
-    return phi1, phi2, displacement_vectors(phi1), displacement_vectors(phi2)
+    phi1, phi2 = lagrangian_potentials(white_noise, L, cosmo, 1.0 / D1, fda_order)
+    return (phi1, phi2, displacement_vectors(phi1, fda_order),
+            displacement_vectors(phi2, fda_order))
 
 
-def box_inputs(psi1, psi2, phi1, tile):
+def box_inputs(psi1, psi2, phi1, tile, fda_order=2):
     """Steps C.1-C.3 for one box: its Psi1, Psi2 and Phi_BC^0."""
     return (extract_box_field(psi1, tile), extract_box_field(psi2, tile),
-            boundary_potential0(phi1, tile))
+            boundary_potential0(phi1, tile, fda_order // 2))
 
 
 def untile(tile, Np, box_out, key="u"):
@@ -55,17 +56,18 @@ def output_density(x_cells, Np, N_out):
 
 def run_scola(white_noise, L, tiles, cosmo=None, a_i=0.05, a_f=1.0, n_steps=10,
               want_momenta=False, N_out=None, tile_subset=None, discretisation="modified",
-              n_lpt=-2.5, tile_a_f=None):
+              n_lpt=-2.5, tile_a_f=None, fda_order=2):
     """Full tiled sCOLA run.  Returns dict with positions (3, Np, Np, Np) in Mpc/h in
     [0, L), momenta (or None) in Mpc/h (H0 = 1 units), the output density and the per-box
     raw results.  Entries of tiles outside tile_subset are left NaN in the outputs.
     discretisation, n_lpt: the time factors of App. B (see cola_schedule).
     tile_a_f: optional final scale factor per tile (Sec. 5.1: tiles need not share one final
-    time; 0 or None entries mean a_f); each tile takes n_steps steps from a_i to its own."""
+    time; 0 or None entries mean a_f); each tile takes n_steps steps from a_i to its own.
+    fda_order: 2, 4 or 6, the order of every Laplacian and gradient (Sec. 3)."""
     cosmo = cosmo or Cosmology()
     Np = white_noise.shape[0]
     N_out = N_out or Np
-    phi1, phi2, psi1, psi2 = setup_full_box(white_noise, L, cosmo, a_i)
+    phi1, phi2, psi1, psi2 = setup_full_box(white_noise, L, cosmo, a_i, fda_order)
     steps, final = cola_schedule(cosmo, a_i, a_f, n_steps, want_final_kick=want_momenta,
                                  discretisation=discretisation, n_lpt=n_lpt)
     pos = np.full((3, Np, Np, Np), np.nan)
@@ -74,13 +76,13 @@ def run_scola(white_noise, L, tiles, cosmo=None, a_i=0.05, a_f=1.0, n_steps=10,
     subset = range(len(tiles)) if tile_subset is None else tile_subset
     for t in subset:
         tile = tiles[t]
-        s1, s2, bc0 = box_inputs(psi1, psi2, phi1, tile)
+        s1, s2, bc0 = box_inputs(psi1, psi2, phi1, tile, fda_order)
         st, fin = steps, final
         if tile_a_f is not None and tile_a_f[t] and tile_a_f[t] != a_f:
             st, fin = cola_schedule(cosmo, a_i, tile_a_f[t], n_steps,
                                     want_final_kick=want_momenta,
                                     discretisation=discretisation, n_lpt=n_lpt)
-        out = evolve_box(s1, s2, bc0, st, fin)
+        out = evolve_box(s1, s2, bc0, st, fin, fda_order=fda_order)
         boxes[t] = out
         gi, u = untile(tile, Np, out, "u")
         origin = np.array(tile.origin, dtype=np.float64)[:, None]

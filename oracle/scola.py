@@ -6,15 +6,16 @@ Paper passages followed:
   * Sec. 3.4.1: density assignment B^sCOLA = CiC of the box's particles onto the PM grid
     of the box; fractional masses that would land outside the box are ignored.
   * Sec. 3.4.2 and App. C: Dirichlet Poisson solve with Phi_BCs = D1(a_K) Phi_BC^0 (LEP),
-    Phi padded with Phi_BCs; gradient by order-2 finite differences on the nodes padded by
-    N_ghost; CiC interpolation to the particles.
+    Phi padded with Phi_BCs; gradient by finite differences (order 2, 4 or 6, Sec. 3) on
+    the nodes padded by N_ghost; CiC interpolation to the particles.
   * App. A eq. (drift-cola) and eq. (kick-scola): the kick uses
     grad(Delta^-1 delta) - D1 Psi1 + (D2 - D1^2) Psi2; the drift is unmodified.
   * App. B eqs. (D_COLA), (K_COLA) with the modified time factors, the operator E~ of
     eq. (operator_E), and the L-/L+ operators: p_res = 0 at the start, p = p_res + p_LPT
     at the end.
   * Sec. 2.2 (tCOLA) and App. A eq. (kick-tcola): the same operators on the periodic full
-    box, with an FFT Poisson solve (FDA-2 kernel), used as the monolithic comparison.
+    box, with an FFT Poisson solve (FDA kernel of the same order), used as the monolithic
+    comparison.
 
 Readings where the paper is silent: the mean density in delta is the global one (one
 particle per cell); interpolation corners outside the gradient grid [0, M]^3 contribute
@@ -25,7 +26,7 @@ from itertools import product
 
 import numpy as np
 
-from .lpt import fda2_laplacian_kernel
+from .lpt import fda_laplacian_kernel, first_derivative_weights, ghosts
 from .poisson import dirichlet_potential
 
 
@@ -59,15 +60,27 @@ def box_deposit(u, M):
     return rho - 1.0, rho.sum()
 
 
-def box_gradient(phi_pad):
-    """Order-2 central gradient of the padded potential [-1, M+1]^3 on nodes [0, M]^3."""
-    M = phi_pad.shape[0] - 3
-    c = slice(1, M + 2)
-    return np.stack([
-        0.5 * (phi_pad[2:M + 3, c, c] - phi_pad[0:M + 1, c, c]),
-        0.5 * (phi_pad[c, 2:M + 3, c] - phi_pad[c, 0:M + 1, c]),
-        0.5 * (phi_pad[c, c, 2:M + 3] - phi_pad[c, c, 0:M + 1]),
-    ])
+def box_gradient(phi_pad, order=2):
+    """Central gradient of the padded potential [-g, M+g]^3 on nodes [0, M]^3 (g = N_ghost
+    of the FDA order)."""
+    if order == 2:
+        M = phi_pad.shape[0] - 3
+        c = slice(1, M + 2)
+        return np.stack([
+            0.5 * (phi_pad[2:M + 3, c, c] - phi_pad[0:M + 1, c, c]),
+            0.5 * (phi_pad[c, 2:M + 3, c] - phi_pad[c, 0:M + 1, c]),
+            0.5 * (phi_pad[c, c, 2:M + 3] - phi_pad[c, c, 0:M + 1]),
+        ])
+    g = ghosts(order)
+    M = phi_pad.shape[0] - 1 - 2 * g
+    c = slice(g, g + M + 1)
+    out = np.zeros((3,) + (M + 1,) * 3)
+    for k, w in enumerate(first_derivative_weights(order), start=1):
+        up, dn = slice(g + k, g + k + M + 1), slice(g - k, g - k + M + 1)
+        out[0] += w * (phi_pad[up, c, c] - phi_pad[dn, c, c])
+        out[1] += w * (phi_pad[c, up, c] - phi_pad[c, dn, c])
+        out[2] += w * (phi_pad[c, c, up] - phi_pad[c, c, dn])
+    return out
 
 
 def box_interpolate(g, u):
@@ -82,19 +95,20 @@ def box_interpolate(g, u):
     return out
 
 
-def box_force(u, M, phi_bc_pad, delta=None):
+def box_force(u, M, phi_bc_pad, delta=None, order=2):
     """grad^sCOLA (Delta^sCOLA)^-1 delta^sCOLA at the particles."""
     if delta is None:
         delta, _ = box_deposit(u, M)
-    phi = dirichlet_potential(delta, phi_bc_pad)
-    return box_interpolate(box_gradient(phi), u), delta, phi
+    phi = dirichlet_potential(delta, phi_bc_pad, order=order)
+    return box_interpolate(box_gradient(phi, order), u), delta, phi
 
 
-def evolve_box(psi1, psi2, phi_bc0, steps, final=None, overrides=None, record=None):
+def evolve_box(psi1, psi2, phi_bc0, steps, final=None, overrides=None, record=None,
+               fda_order=2):
     """Evolve one sCOLA box through the KDK operator E~ (App. B).
 
     psi1, psi2: (3, M, M, M) displacement vectors of the box's particles (cells).
-    phi_bc0: (M+3)^3 padded boundary potential at D1 = 1.
+    phi_bc0: (M+1+2g)^3 padded boundary potential at D1 = 1 (g = N_ghost of fda_order).
     steps, final: from oracle.cosmology.cola_schedule.
     overrides: optional callable(k, u) -> (delta or None, phi_bc_pad or None) replacing
       delta^sCOLA and/or Phi_BCs at the k-th force evaluation (consistency tests of
@@ -112,7 +126,7 @@ def evolve_box(psi1, psi2, phi_bc0, steps, final=None, overrides=None, record=No
         delta, bc = (None, None) if overrides is None else overrides(k, u)
         if bc is None:
             bc = D1 * phi_bc0
-        g, delta, phi = box_force(u, M, bc, delta)
+        g, delta, phi = box_force(u, M, bc, delta, fda_order)
         if record is not None:
             record.append(dict(u=u.copy(), delta=delta, phi=phi, g=g))
         return g
@@ -147,16 +161,22 @@ def periodic_deposit(u, N):
     return rho - 1.0
 
 
-def periodic_potential(delta):
-    K = fda2_laplacian_kernel(delta.shape[0])
+def periodic_potential(delta, order=2):
+    K = fda_laplacian_kernel(delta.shape[0], order)
     dk = np.fft.fftn(delta)
     with np.errstate(divide="ignore", invalid="ignore"):
         pk = np.where(K != 0.0, dk / K, 0.0)
     return np.fft.ifftn(pk).real
 
 
-def periodic_gradient(phi):
-    return np.stack([0.5 * (np.roll(phi, -1, a) - np.roll(phi, 1, a)) for a in range(3)])
+def periodic_gradient(phi, order=2):
+    if order == 2:
+        return np.stack([0.5 * (np.roll(phi, -1, a) - np.roll(phi, 1, a)) for a in range(3)])
+    out = np.zeros((3,) + phi.shape)
+    for k, w in enumerate(first_derivative_weights(order), start=1):
+        for a in range(3):
+            out[a] += w * (np.roll(phi, -k, a) - np.roll(phi, k, a))
+    return out
 
 
 def periodic_interpolate(g, u):
@@ -168,7 +188,8 @@ def periodic_interpolate(g, u):
     return out
 
 
-def evolve_periodic(psi1, psi2, steps, final=None, record=None, pm_only=False, p_init=None):
+def evolve_periodic(psi1, psi2, steps, final=None, record=None, pm_only=False, p_init=None,
+                    fda_order=2):
     """Monolithic tCOLA on the periodic N^3 box (same KDK operator as evolve_box).
 
     pm_only=True switches the COLA split off (plain PM, App. A eqs. drift/kick): the kick
@@ -183,8 +204,8 @@ def evolve_periodic(psi1, psi2, steps, final=None, record=None, pm_only=False, p
 
     def force(u):
         delta = periodic_deposit(u, N)
-        phi = periodic_potential(delta)
-        g = periodic_interpolate(periodic_gradient(phi), u)
+        phi = periodic_potential(delta, fda_order)
+        g = periodic_interpolate(periodic_gradient(phi, fda_order), u)
         if record is not None:
             record.append(dict(u=u.copy(), delta=delta, phi=phi, g=g))
         return g

@@ -10,7 +10,8 @@ Paper passages followed:
   * Sec. 3.3 steps C.1-C.2: Psi1 and Psi2 inside a box equal the full-box values
     (exact boundary conditions in the LPT step), so they are gathered from the full box.
   * Sec. 3.3 step C.3 and Sec. 3.4.2 eq. (LEP): Phi_BCs(x, a_K) = D1(a_K) phi1~(x),
-    interpolated from the LPT grid to the PM grid, on a padding around the box.
+    interpolated from the LPT grid to the PM grid, on a padding around the box (N_ghost
+    layers deep beyond the faces, N_ghost = 1, 2, 3 at FDA order 2, 4, 6).
 
 Box layout (the reading used everywhere, "convention Y"): a box of M particles per side
 starts at Lagrangian index s (mod N_p); its particles sit at local positions i + 1/2,
@@ -73,14 +74,15 @@ def extract_box_field(field, tile):
     return field[..., ix[:, None, None], iy[None, :, None], iz[None, None, :]]
 
 
-def boundary_potential0(phi1, tile):
-    """Phi_BC^0 on the padded PM grid j in [-1, M+1]^3 (index j + 1): the mean of phi1
-    over the 8 LPT nodes around each PM node.  Only the shell outside [1, M-1]^3 is used;
-    interior values are left at zero."""
+def boundary_potential0(phi1, tile, ghosts=1):
+    """Phi_BC^0 on the padded PM grid j in [-g, M+g]^3 (index j + g, g = N_ghost of the FDA
+    order): the mean of phi1 over the 8 LPT nodes around each PM node.  Only the shell
+    outside [1, M-1]^3 is used; interior values are left at zero."""
     N = phi1.shape[0]
     M = tile.M
-    j = np.arange(-1, M + 2)
-    out = np.zeros((M + 3,) * 3)
+    g = ghosts
+    j = np.arange(-g, M + g + 1)
+    out = np.zeros((M + 1 + 2 * g,) * 3)
     idx = [[np.mod(o + j - 1 + d, N) for d in (0, 1)] for o in tile.origin]
     for dx in (0, 1):
         for dy in (0, 1):
@@ -88,7 +90,7 @@ def boundary_potential0(phi1, tile):
                 out += phi1[idx[0][dx][:, None, None], idx[1][dy][None, :, None],
                             idx[2][dz][None, None, :]]
     out *= 0.125
-    interior = (slice(2, M + 1),) * 3
+    interior = (slice(g + 1, g + M),) * 3
     out[interior] = 0.0
     return out
 
