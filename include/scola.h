@@ -23,8 +23,9 @@
  *    Mpc/h.  Time is the scale factor a; H0 = 1.
  *  - Box layout: a box of M = core_n + 2 buffer particles per side holds its particles at
  *    local positions i + 1/2; PM nodes sit at integer local positions, the Dirichlet problem
- *    has M - 1 unknowns per side and the potential is padded to [-1, M+1] (FDA order 2,
- *    N_ghost = 1).  M is one of 16, 32, 48, ..., 128 (see scola_tile).
+ *    has M - 1 unknowns per side and the potential is padded to [-g, M+g], g = N_ghost =
+ *    fda_order / 2 (Sec. 3: 1, 2, 3 at finite-difference order 2, 4, 6).  M is one of 16,
+ *    32, 48, ..., 128 (see scola_tile).
  */
 #ifndef SCOLA_H
 #define SCOLA_H
@@ -89,9 +90,14 @@ typedef struct {
                               divisor of N_p such as N_p / 2 is refused with
                               SCOLA_EUNSUPPORTED, anything else with SCOLA_EINVAL */
   int32_t N_out;           /* output density grid per side (0 -> N_p) */
-  int32_t fda_order;       /* finite-difference order of the Laplacian and gradient (Sec. 3.4.2,
-                              App. C.2); 0 -> 2, the only order implemented; 4 and 6 are
-                              refused with SCOLA_EUNSUPPORTED, other values with SCOLA_EINVAL */
+  int32_t fda_order;       /* finite-difference order of every Laplacian and gradient (Sec. 3;
+                              App. C.1-C.2): 2, 4 or 6 (0 -> 2, the order of Sec. 4's runs),
+                              else SCOLA_EINVAL.  Order 2 g uses g ghost layers: Phi_BCs on the
+                              g layers outside the interior, the potential padded by g.  At
+                              orders 4 and 6 the sine transform solves the wide stencil with
+                              the unknown continued antisymmetrically past each face, as
+                              App. C.2's eigenvalues imply.  scola_backward and the persistent
+                              step are built for order 2 (SCOLA_EUNSUPPORTED otherwise) */
   int32_t n_steps;         /* KDK steps, linearly spaced in a (Sec. 4), >= 1 */
   double a_i, a_f;         /* initial / final scale factor, 0 < a_i < a_f */
   double n_lpt;            /* exponent of u(a) = a^n_LPT in the modified time factors (App. B);
@@ -111,8 +117,8 @@ typedef struct {
 typedef struct scola_plan scola_plan;
 
 /* Byte offsets of the arrays held in the caller's workspace (for inspection and for
- * operator-level calls).  P = total box particles, G = sum (M-1)^3, H = sum (M+3)^3,
- * N = N_p, R = real type of the plan (float or double). */
+ * operator-level calls).  P = total box particles, G = sum (M-1)^3, H = sum (M+1+2g)^3
+ * (g = fda_order / 2), N = N_p, R = real type of the plan (float or double). */
 typedef struct {
   size_t psi1, psi2;       /* R [3][P]: Psi1 = grad phi1, Psi2 = grad phi2 (cells), differenced
                               in FP64 and stored in the plan precision R */
@@ -121,7 +127,7 @@ typedef struct {
                               (FP64 plans) or uint32 [G] (FP32 plans; a node holds at most
                               2048 particles, see `dropped`); size rounded up to 8 bytes */
   size_t work;             /* R [G]: sine-space scratch of the Poisson solve */
-  size_t phi;              /* R [H]: potential on the padded node grid [-1, M+1]^3 */
+  size_t phi;              /* R [H]: potential on the padded node grid [-g, M+g]^3 */
   size_t bc0;              /* double [H]: Phi_BC^0 (LEP boundary potential at D1 = 1) */
   size_t dropped;          /* int64 [3 n_tiles + 1], counters since the last reset: the
                               fixed-point mass dropped by the deposits, per tile; the number of
@@ -230,7 +236,7 @@ scola_status scola_backward(scola_plan* plan, const void* d_grad_density,
                             hipStream_t stream);
 
 /* Steps A.1-A.2 and C.1-C.3 (Sec. 3.1, 3.3) in FP64: white noise -> delta_i via the
- * Eisenstein-Hu spectrum (convolution approach), phi1 and phi2 with the FDA-2 kernel,
+ * Eisenstein-Hu spectrum (convolution approach), phi1 and phi2 with the FDA kernel,
  * Psi1 and Psi2 for every box particle and Phi_BC^0 on every box's padded shell.  Also
  * resets x_res = p_res = 0 (operator L-, App. B). */
 scola_status scola_setup(scola_plan* plan, const double* d_white_noise, void* d_workspace,
@@ -336,8 +342,8 @@ scola_status scola_output(scola_plan* plan, void* d_pos, void* d_mom, void* d_de
  *   u = q - D1 Psi1 + D2 Psi2 + x_res onto interior nodes [1, M-1]^3; mass that would land
  *   elsewhere is dropped and counted in `dropped`.
  * scola_op_poisson: App. C -- delta = rho / 2^fixed_bits - 1, delta' = delta - Delta Phi_BCs with
- *   Phi_BCs = D1_bc Phi_BC^0, forward DST-I, division by the FDA-2 eigenvalues, inverse
- *   DST-I; writes phi on [-1, M+1]^3 with the shell set to D1_bc Phi_BC^0 (Sec. 3.4.2).
+ *   Phi_BCs = D1_bc Phi_BC^0, forward DST-I, division by the FDA eigenvalues, inverse
+ *   DST-I; writes phi on [-g, M+g]^3 with the shell set to D1_bc Phi_BC^0 (Sec. 3.4.2).
  *   rho is left zeroed for the next deposit.
  * scola_op_step: one fused kick-drift (App. B eqs. K_COLA, D_COLA with the sCOLA kick of
  *   App. A eq. kick-scola): gradient of phi and CiC interpolation at
@@ -379,8 +385,9 @@ scola_status scola_linear_power(const scola_cosmology* cosmo, const double* k, d
 /* Monolithic periodic tCOLA of the plan's full box (Sec. 2.2, App. A eqs. drift-cola and
  * kick-tcola, App. B): the N_p^3 particles evolved together with a periodic PM grid of N_p^3
  * nodes (one per lattice cell, at integer positions of the lattice coordinate whose particles
- * sit at i + 1/2), periodic CiC deposit and interpolation, the FDA-2 Poisson equation solved
- * by FFT (FP64 transforms), the central-difference gradient, and the plan's KDK schedule and
+ * sit at i + 1/2), periodic CiC deposit and interpolation, the Poisson equation with the
+ * plan's finite-difference order solved by FFT (FP64 transforms), the central-difference
+ * gradient of the same order, and the plan's KDK schedule and
  * precision; the tiling of the plan is not used.  It is the reference of the sCOLA accuracy
  * study (Sec. 4.2) and the source of the true density and potential of the consistency tests
  * (Sec. 4.3).

@@ -94,11 +94,13 @@ class Simulation:
 
     tiles: list of (core_lo (3 ints), core_n, buffer) or (core_lo, core_n, buffer, a_f) with
     a per-tile final scale factor (0 = a_f); or use uniform_tiling().
-    precision: "fp32" (state and meshes in FP32, Psi and positions FP64) or "fp64".
+    precision: "fp32" (state, Psi and meshes in FP32, positions formed in FP64) or "fp64".
     schedule: "batched" (all boxes per launch) or "per_tile" (box after box).
     discretisation: "modified" (App. B time factors with u = a^n_lpt) or "standard".
-    N_lpt, fda_order, mesh: as in include/scola.h (only the defaults are implemented; other
-    values raise ScolaError with SCOLA_EUNSUPPORTED).
+    fda_order: 2 (default), 4 or 6, the finite-difference order of every Laplacian and
+    gradient (the reverse mode and the persistent step are built for order 2).
+    N_lpt, mesh: as in include/scola.h (only the defaults are implemented; other values raise
+    ScolaError with SCOLA_EUNSUPPORTED).
     """
 
     def __init__(self, L, Np, tiles, n_steps, a_i=0.05, a_f=1.0, precision="fp32",
@@ -121,6 +123,7 @@ class Simulation:
         self.tiles = [(tuple(int(c) for c in t[0]), int(t[1]), int(t[2])) for t in tiles]
         self.tile_a_f = [float(t[3]) if len(t) > 3 else 0.0 for t in tiles]
         self.checkpoint_every = int(checkpoint_every)
+        self.ghosts = (int(fda_order) or 2) // 2
         cfg = _config(L, Np, n_steps, a_i, a_f, precision, schedule, want_momenta, N_out,
                       checkpoint_every, discretisation, n_lpt, N_lpt, fda_order)
         cosmo = (cosmology or CosmologyParams()).c()
@@ -417,7 +420,7 @@ class Simulation:
             out.append((P, M, G, H))
             P += M ** 3
             G += (M - 1) ** 3
-            H += (M + 3) ** 3
+            H += (M + 1 + 2 * self.ghosts) ** 3
         return out
 
 

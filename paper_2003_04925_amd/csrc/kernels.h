@@ -26,6 +26,7 @@ struct SetupArgs {
   double* phi2;
   int N;
   double L, amplitude, ns, Om, Ob, h, Tcmb, growth2;
+  int ng = 1;               // finite differences of order 2 ng
 };
 
 struct BoxSetupArgs {
@@ -41,6 +42,7 @@ struct BoxSetupArgs {
   double* bc0;
   int N;
   int64_t P;
+  int ng = 1;               // finite differences of order 2 ng; Phi_BC^0 on [-ng, M+ng]^3
 };
 
 template <typename T>
@@ -53,7 +55,7 @@ struct MeshArgs {
   T* phi;
   const double* bc0;
   const void* twiddles;     // complex T, per M: 2M entries W_{2M}^m
-  const T* eigen;           // per M: lambda_l, l = 1..M-1 (FDA-2, unit spacing)
+  const T* eigen;           // per M: lambda_l, l = 1..M-1 (FDA of the plan order, unit spacing)
   double D1_bc;
   // adjoint solve only: the source is read from `work`, the result written to lam_rho, and
   // the boundary-source transpose accumulated into lam_bc0
@@ -66,6 +68,7 @@ struct MeshArgs {
   const T* ov_delta = nullptr;
   const T* ov_phi = nullptr;
   int ov_N = 0;
+  int ng = 1;                          // ghost layers: finite differences of order 2 ng
 };
 
 template <typename T>
@@ -87,6 +90,7 @@ struct ParticleArgs {
   int use_hints;
   int64_t P;
   StepScalars sc;
+  int ng = 1;               // ghost layers of the padded potential (gradient of order 2 ng)
 };
 
 template <typename T>
@@ -173,7 +177,7 @@ hipError_t launch_real_to_complex(const double* in, double2* out, int64_t n, hip
 hipError_t fft3d_forward(double2* c, int N, hipStream_t s);
 hipError_t fft3d_inverse(double2* c, int N, hipStream_t s);
 hipError_t launch_ic_filter(const SetupArgs& a, hipStream_t s);
-hipError_t launch_inverse_laplacian(double2* c, int N, hipStream_t s);
+hipError_t launch_inverse_laplacian(double2* c, int N, int ng, hipStream_t s);
 hipError_t launch_take_real(const double2* c, double* out, double scale, int64_t n, hipStream_t s);
 
 // Monolithic periodic tCOLA of the full box (N^3 particles in lattice order, [3][N^3]
@@ -188,6 +192,7 @@ struct TcolaArgs {
   const T* phi;              // [N^3] periodic potential
   int N;
   StepScalars sc;
+  int ng = 1;               // finite differences of order 2 ng
 };
 
 template <typename T>

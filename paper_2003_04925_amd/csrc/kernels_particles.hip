@@ -5,9 +5,9 @@
 //
 // Layout: structure of arrays [3][P] over all boxes, box after box, particles of a box in
 // lattice order (z fastest), so a 256-thread block reads 256 consecutive elements of each
-// of the 12 particle streams.  Psi1 and Psi2 stay FP64 and every particle position is
-// formed in FP64 (u = q - D1 Psi1 + D2 Psi2 + x_res) before its cell index is taken, so
-// cell indices do not depend on the state precision.
+// of the 12 particle streams.  Psi1 and Psi2 are held in the plan precision (differenced in
+// FP64 at set-up) and every particle position is formed in FP64 (u = q - D1 Psi1 + D2 Psi2 +
+// x_res) before its cell index is taken.
 //
 // The deposit accumulates rounded fixed-point weights in integers (2^40 units per
 // particle in 64 bits for FP64 plans, 2^21 in 32 bits for FP32 plans): sums are exact and
@@ -33,6 +33,13 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OCC
 k_particles(ParticleArgs<T> a, BlockMap m) {
   const int L = logical_block(m);
   if (L < m.count) particles_block<T, MODE>(a, m, L);
+}
+
+// The force-evaluating modes at gradient order 2 NG, NG = 2 or 3 (Sec. 3).
+template <typename T, int MODE, int NG>
+__global__ void __launch_bounds__(kBlock) k_particles_wide(ParticleArgs<T> a, BlockMap m) {
+  const int L = logical_block(m);
+  if (L < m.count) particles_block<T, MODE, NG>(a, m, L);
 }
 
 __global__ void k_zero_u32(unsigned* p, int64_t n) {
@@ -166,9 +173,38 @@ hipError_t launch_particles_occ(const ParticleArgs<T>& a, int mode, const BlockM
   return hipGetLastError();
 }
 
+template <typename T, int NG>
+hipError_t launch_particles_wide(const ParticleArgs<T>& a, int mode, const BlockMap& m,
+                                 hipStream_t s) {
+  const dim3 grid(padded_grid(m)), block(kBlock);
+  switch (mode) {
+    case kStep:
+      hipLaunchKernelGGL((k_particles_wide<T, kStep, NG>), grid, block, 0, s, a, m);
+      break;
+    case kStepNoDeposit:
+      hipLaunchKernelGGL((k_particles_wide<T, kStepNoDeposit, NG>), grid, block, 0, s, a, m);
+      break;
+    case kFinalKick:
+      hipLaunchKernelGGL((k_particles_wide<T, kFinalKick, NG>), grid, block, 0, s, a, m);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_particles(const ParticleArgs<T>& a, int mode, const BlockMap& m, int occ,
                             hipStream_t s) {
+  // the deposit-only modes do not evaluate the force: one kernel for every order
+  if (a.ng != 1 && mode != kDepositOnly && mode != kInit) {
+    if (m.count <= 0) return hipSuccess;
+    switch (a.ng) {
+      case 2: return launch_particles_wide<T, 2>(a, mode, m, s);
+      case 3: return launch_particles_wide<T, 3>(a, mode, m, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (occ) {
     case 6: return launch_particles_occ<T, 6>(a, mode, m, s);
     case 8: return launch_particles_occ<T, 8>(a, mode, m, s);

@@ -21,7 +21,7 @@
 namespace scola {
 
 template <typename T>
-size_t poisson_lds_bytes(int M, int pass);
+size_t poisson_lds_bytes(int M, int pass, int ng);
 
 namespace {
 
@@ -115,7 +115,7 @@ hipError_t launch_persistent_R(const ParticleArgs<T>& pa, const MeshArgs<T>& ma,
                                int* grid_out) {
   const void* fn = reinterpret_cast<const void*>(k_step_persistent<T, R>);
   size_t lds = 0;
-  for (int pass = 1; pass <= 3; ++pass) lds = std::max(lds, poisson_lds_bytes<T>(16 * R, pass));
+  for (int pass = 1; pass <= 3; ++pass) lds = std::max(lds, poisson_lds_bytes<T>(16 * R, pass, 1));
   hipError_t e;
   if (lds > 65536) {
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

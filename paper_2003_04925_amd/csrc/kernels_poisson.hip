@@ -4,11 +4,13 @@
 // over the (n)^3 mesh of every box, all boxes in one launch each:
 //   P1  per x-plane: fixed-point mass -> delta, delta' = delta - Delta Phi_BCs (App. C.1),
 //       forward DST-I along z then y, in LDS;
-//   P2  per (y, 32 z-columns): forward DST-I along x, division by the FDA-2 eigenvalue sum
+//   P2  per (y, 32 z-columns): forward DST-I along x, division by the FDA eigenvalue sum
 //       times the inverse normalisation 8/M^3 (App. C.2, eq. Poisson_sine_space), inverse
 //       DST-I along x;
 //   P3  per x-plane: inverse DST-I along y then z, and the potential written to the padded
-//       node grid [-1, M+1]^3 with the shell filled from Phi_BCs (Sec. 3.4.2).
+//       node grid [-g, M+g]^3 with the shell filled from Phi_BCs (Sec. 3.4.2); g = 1, 2, 3
+//       ghost layers at finite-difference order 2, 4, 6 (Sec. 3), where delta' also takes
+//       the wide stencil's reach into the g Dirichlet layers (App. C.1).
 //
 // Every 1-D DST-I of length n = M - 1 is computed through a complex FFT of length 2M of the
 // odd extension (0, a_1..a_n, 0, -a_n..-a_1) + i (same for a second line b): its transform
@@ -28,11 +30,11 @@ namespace scola {
 
 namespace {
 
-template <typename T, int R, bool ADJ>
+template <typename T, int R, bool ADJ, int NG>
 __global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int L = logical_block(m);
-  if (L < m.count) poisson_p1_block<T, R, ADJ>(a, m, L, smem);
+  if (L < m.count) poisson_p1_block<T, R, ADJ, NG>(a, m, L, smem);
 }
 
 template <typename T, int R>
@@ -42,33 +44,35 @@ __global__ void __launch_bounds__(kBlock) k_poisson_p2(MeshArgs<T> a, BlockMap m
   if (L < m.count) poisson_p2_block<T, R>(a, m, L, smem);
 }
 
-template <typename T, int R, bool ADJ>
+template <typename T, int R, bool ADJ, int NG>
 __global__ void __launch_bounds__(kBlock) k_poisson_p3(MeshArgs<T> a, BlockMap m) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int L = logical_block(m);
-  if (L < m.count) poisson_p3_block<T, R, ADJ>(a, m, L, smem);
+  if (L < m.count) poisson_p3_block<T, R, ADJ, NG>(a, m, L, smem);
 }
 
 }  // namespace
 
 // Dynamic LDS of each pass for boxes of M nodes: the 2M twiddles, then P1 the (M-1)^2 plane,
 // P2 the M eigenvalues and an (M-1) x 33 pencil tile, P3 the plane with its padded border
-// ((M+3)^2).  Sized per M and per pass, so small boxes keep more blocks per CU.
+// ((M + 1 + 2 ng)^2 for ng ghost layers).  Sized per M and per pass, so small boxes keep
+// more blocks per CU.
 template <typename T>
-size_t poisson_lds_bytes(int M, int pass) {
+size_t poisson_lds_bytes(int M, int pass, int ng) {
   const size_t n = (size_t)M - 1, tw = 2 * (size_t)M * sizeof(cx<T>);
+  const size_t Mp = (size_t)M + 1 + 2 * (size_t)ng;
   if (pass == 1) return tw + n * n * sizeof(T);
   if (pass == 2) return tw + ((size_t)M + n * (kPencilChunk + 1)) * sizeof(T);
-  return tw + (size_t)(M + 3) * (M + 3) * sizeof(T);
+  return tw + Mp * Mp * sizeof(T);
 }
 
 namespace {
 
-template <typename T, int R, bool ADJ>
+template <typename T, int R, bool ADJ, int NG>
 hipError_t launch_poisson_R(const MeshArgs<T>& a, const BlockMap& p1, const BlockMap& p2,
                             const BlockMap& p3, hipStream_t s) {
-  const size_t l1 = poisson_lds_bytes<T>(16 * R, 1), l2 = poisson_lds_bytes<T>(16 * R, 2),
-               l3 = poisson_lds_bytes<T>(16 * R, 3);
+  const size_t l1 = poisson_lds_bytes<T>(16 * R, 1, NG), l2 = poisson_lds_bytes<T>(16 * R, 2, NG),
+               l3 = poisson_lds_bytes<T>(16 * R, 3, NG);
   if (l1 > 65536 || l2 > 65536 || l3 > 65536) {
     // allow more than 64 KiB of dynamic LDS (160 KiB on gfx950): a function attribute of
     // each device, set once per device
@@ -78,25 +82,25 @@ hipError_t launch_poisson_R(const MeshArgs<T>& a, const BlockMap& p1, const Bloc
     if (e != hipSuccess) return e;
     const uint64_t bit = dev < 64 ? (1ull << dev) : 0ull;
     if (!bit || !(done.load() & bit)) {
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p1<T, R, ADJ>),
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p1<T, R, ADJ, NG>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)l1);
       if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p2<T, R>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2);
       if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p3<T, R, ADJ>),
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_poisson_p3<T, R, ADJ, NG>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)l3);
       if (e != hipSuccess) return e;
       done.fetch_or(bit);
     }
   }
   if (p1.count > 0)
-    hipLaunchKernelGGL((k_poisson_p1<T, R, ADJ>), dim3(padded_grid(p1)), dim3(kBlock), l1, s,
+    hipLaunchKernelGGL((k_poisson_p1<T, R, ADJ, NG>), dim3(padded_grid(p1)), dim3(kBlock), l1, s,
                        a, p1);
   if (p2.count > 0)
     hipLaunchKernelGGL((k_poisson_p2<T, R>), dim3(padded_grid(p2)), dim3(kBlock), l2, s, a, p2);
   if (p3.count > 0)
-    hipLaunchKernelGGL((k_poisson_p3<T, R, ADJ>), dim3(padded_grid(p3)), dim3(kBlock), l3, s,
+    hipLaunchKernelGGL((k_poisson_p3<T, R, ADJ, NG>), dim3(padded_grid(p3)), dim3(kBlock), l3, s,
                        a, p3);
   return hipGetLastError();
 }
@@ -104,8 +108,17 @@ hipError_t launch_poisson_R(const MeshArgs<T>& a, const BlockMap& p1, const Bloc
 template <typename T, int R>
 hipError_t launch_poisson_RA(const MeshArgs<T>& a, const BlockMap& p1, const BlockMap& p2,
                              const BlockMap& p3, hipStream_t s, bool adjoint) {
-  return adjoint ? launch_poisson_R<T, R, true>(a, p1, p2, p3, s)
-                 : launch_poisson_R<T, R, false>(a, p1, p2, p3, s);
+  if (adjoint) {
+    // the reverse passes exist for order 2 only (the plan refuses the others)
+    if (a.ng != 1) return hipErrorInvalidValue;
+    return launch_poisson_R<T, R, true, 1>(a, p1, p2, p3, s);
+  }
+  switch (a.ng) {
+    case 1: return launch_poisson_R<T, R, false, 1>(a, p1, p2, p3, s);
+    case 2: return launch_poisson_R<T, R, false, 2>(a, p1, p2, p3, s);
+    case 3: return launch_poisson_R<T, R, false, 3>(a, p1, p2, p3, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
@@ -130,7 +143,7 @@ template hipError_t launch_poisson<float>(const MeshArgs<float>&, int, const Blo
                                           const BlockMap&, const BlockMap&, hipStream_t, bool);
 template hipError_t launch_poisson<double>(const MeshArgs<double>&, int, const BlockMap&,
                                            const BlockMap&, const BlockMap&, hipStream_t, bool);
-template size_t poisson_lds_bytes<float>(int, int);
-template size_t poisson_lds_bytes<double>(int, int);
+template size_t poisson_lds_bytes<float>(int, int, int);
+template size_t poisson_lds_bytes<double>(int, int, int);
 
 }  // namespace scola

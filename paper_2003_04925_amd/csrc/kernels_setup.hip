@@ -3,7 +3,8 @@
 //
 // Paper: Sec. 3.1 (A.1 convolution approach; A.2 Poisson-like equations LPTpotential1/2,
 // second-order source by nine 1-D gradient operations), Sec. 3.3 (C.1-C.3: exact Psi in
-// the box, Phi_BCs interpolated from the LPT grid to the PM grid), Sec. 4 (FDA order 2).
+// the box, Phi_BCs interpolated from the LPT grid to the PM grid), Sec. 3 (finite
+// differences of order 2, 4 or 6: ng = 1, 2, 3 neighbours per side; Sec. 4 runs order 2).
 #include "common.h"
 #include "kernels.h"
 
@@ -91,19 +92,41 @@ __global__ void k_take_real(const double2* __restrict__ in, double* __restrict__
   if (i < n) out[i] = in[i].x * scale;
 }
 
-// Fourier symbol of the FDA-2 Laplacian, one-cell spacing: -4 sum sin^2(pi m / N).
-__device__ inline double fda2_symbol(int mx, int my, int mz, int N) {
-  double sx = sinpi((double)mx / N), sy = sinpi((double)my / N), sz = sinpi((double)mz / N);
-  return -4.0 * (sx * sx + sy * sy + sz * sz);
+// Central-difference weights of order 2 ng: first derivative sum_k c_k (f(i+k) - f(i-k)),
+// c = (1/2), (2/3, -1/12), (3/4, -3/20, 1/60); second derivative
+// sum_k a_k (f(i+k) + f(i-k) - 2 f(i)), a = (1), (4/3, -1/12), (3/2, -3/20, 1/90).
+__device__ inline double d1_weight(int ng, int k) {
+  return ng == 1 ? 0.5
+       : ng == 2 ? (k == 1 ? 2.0 / 3.0 : -1.0 / 12.0)
+                 : (k == 1 ? 0.75 : k == 2 ? -0.15 : 1.0 / 60.0);
+}
+__device__ inline double d2_weight(int ng, int k) {
+  return ng == 1 ? 1.0
+       : ng == 2 ? (k == 1 ? 4.0 / 3.0 : -1.0 / 12.0)
+                 : (k == 1 ? 1.5 : k == 2 ? -0.15 : 1.0 / 90.0);
+}
+
+// Fourier symbol of the FDA Laplacian of order 2 ng, one-cell spacing: per axis
+// sum_k a_k (2 cos(2 pi k m / N) - 2), i.e. -4 sin^2(pi m / N) at order 2.
+__device__ inline double fda_symbol(int mx, int my, int mz, int N, int ng) {
+  if (ng == 1) {
+    double sx = sinpi((double)mx / N), sy = sinpi((double)my / N), sz = sinpi((double)mz / N);
+    return -4.0 * (sx * sx + sy * sy + sz * sz);
+  }
+  double s = 0.0;
+  for (int k = 1; k <= ng; ++k)
+    s += d2_weight(ng, k) * (2.0 * (cospi(2.0 * k * mx / N) + cospi(2.0 * k * my / N) +
+                                    cospi(2.0 * k * mz / N)) - 6.0);
+  return s;
 }
 
 __device__ inline int signed_mode(int i, int N) { return i < N / 2 ? i : i - N; }
 
 // A.1 + A.2 (first order): multiply FFT(w) by sqrt(P(k, a_i) N^3 / L^3) and divide by the
-// FDA-2 Laplacian symbol; the zero mode is set to zero.
+// FDA Laplacian symbol; the zero mode is set to zero.
 __global__ void k_ic_filter(double2* __restrict__ c, int N, double L, double amplitude,
                             double ns, double Om, double Ob, double h, double Tcmb,
-                            double growth2) {
+                            double growth2, int ng) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n3 = (int64_t)N * N * N;
   if (i >= n3) return;
@@ -117,12 +140,12 @@ __global__ void k_ic_filter(double2* __restrict__ c, int N, double L, double amp
   const double k = kf * sqrt((double)mx * mx + (double)my * my + (double)mz * mz);
   const double T = eh_nowiggle_transfer(k, Om, Ob, h, Tcmb);
   const double P = amplitude * pow(k, ns) * T * T * growth2;
-  const double f = sqrt(P * (double)N * N * N / (L * L * L)) / fda2_symbol(mx, my, mz, N);
+  const double f = sqrt(P * (double)N * N * N / (L * L * L)) / fda_symbol(mx, my, mz, N, ng);
   c[i] = make_double2(c[i].x * f, c[i].y * f);
 }
 
-// Division by the FDA-2 Laplacian symbol (A.2, second order), zero mode to zero.
-__global__ void k_inverse_laplacian(double2* __restrict__ c, int N) {
+// Division by the FDA Laplacian symbol (A.2, second order), zero mode to zero.
+__global__ void k_inverse_laplacian(double2* __restrict__ c, int N, int ng) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n3 = (int64_t)N * N * N;
   if (i >= n3) return;
@@ -132,15 +155,15 @@ __global__ void k_inverse_laplacian(double2* __restrict__ c, int N) {
     c[i] = make_double2(0.0, 0.0);
     return;
   }
-  const double inv = 1.0 / fda2_symbol(mx, my, mz, N);
+  const double inv = 1.0 / fda_symbol(mx, my, mz, N, ng);
   c[i] = make_double2(c[i].x * inv, c[i].y * inv);
 }
 
 // Second-order source sum_{i>j} [phi_,ii phi_,jj - phi_,ij^2] with phi_,ij = D_i D_j phi,
-// D the order-2 central difference (wide stencils), periodic; written as complex input of
-// the next FFT.
+// D the central difference of order 2 ng (wide stencils), periodic; written as complex
+// input of the next FFT.
 __global__ void k_second_order_source(const double* __restrict__ phi, double2* __restrict__ out,
-                                      int N) {
+                                      int N, int ng) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n3 = (int64_t)N * N * N;
   if (i >= n3) return;
@@ -148,6 +171,32 @@ __global__ void k_second_order_source(const double* __restrict__ phi, double2* _
   auto P = [&](int dx, int dy, int dz) {
     return phi[((int64_t)wrap(x + dx, N) * N + wrap(y + dy, N)) * N + wrap(z + dz, N)];
   };
+  if (ng > 1) {
+    // D_i (D_j phi) = sum_k c_k sum_l c_l [phi(+k e_i + l e_j) - phi(+k e_i - l e_j)
+    //                                      - phi(-k e_i + l e_j) + phi(-k e_i - l e_j)]
+    double d[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = a; b < 3; ++b) {
+        double acc = 0.0;
+        for (int k = 1; k <= ng; ++k)
+          for (int l = 1; l <= ng; ++l) {
+            double t = 0.0;
+            for (int sk = -1; sk <= 1; sk += 2)
+              for (int sl = -1; sl <= 1; sl += 2) {
+                int o[3] = {0, 0, 0};
+                o[a] += sk * k;
+                o[b] += sl * l;
+                t += sk * sl * P(o[0], o[1], o[2]);
+              }
+            acc += d1_weight(ng, k) * d1_weight(ng, l) * t;
+          }
+        d[a][b] = d[b][a] = acc;
+      }
+    const double s = d[1][1] * d[0][0] - d[0][1] * d[0][1] + d[2][2] * d[0][0] -
+                     d[0][2] * d[0][2] + d[2][2] * d[1][1] - d[1][2] * d[1][2];
+    out[i] = make_double2(s, 0.0);
+    return;
+  }
   const double c0 = P(0, 0, 0);
   const double xx = 0.25 * (P(2, 0, 0) - 2.0 * c0 + P(-2, 0, 0));
   const double yy = 0.25 * (P(0, 2, 0) - 2.0 * c0 + P(0, -2, 0));
@@ -166,7 +215,8 @@ __global__ void k_extract_psi(const TileDesc* __restrict__ tiles,
                               const int* __restrict__ blk_tile, const int* __restrict__ blk_first,
                               const double* __restrict__ phi1, const double* __restrict__ phi2,
                               T* __restrict__ psi1, T* __restrict__ psi2,
-                              T* __restrict__ xres, T* __restrict__ pres, int N, int64_t P) {
+                              T* __restrict__ xres, T* __restrict__ pres, int N, int64_t P,
+                              int ng) {
   const TileDesc t = tiles[blk_tile[blockIdx.x]];
   const int64_t pl = (int64_t)blk_first[blockIdx.x] * kBlock + threadIdx.x;
   const int M = t.M;
@@ -182,33 +232,50 @@ __global__ void k_extract_psi(const TileDesc* __restrict__ tiles,
   const int64_t p = t.p_off + pl;
   // differenced in FP64, stored in the plan precision (FP32 plans keep the paper's
   // single-precision particle record)
-  psi1[p] = (T)(0.5 * (at(phi1, gx + 1, gy, gz) - at(phi1, gx - 1, gy, gz)));
-  psi1[P + p] = (T)(0.5 * (at(phi1, gx, gy + 1, gz) - at(phi1, gx, gy - 1, gz)));
-  psi1[2 * P + p] = (T)(0.5 * (at(phi1, gx, gy, gz + 1) - at(phi1, gx, gy, gz - 1)));
-  psi2[p] = (T)(0.5 * (at(phi2, gx + 1, gy, gz) - at(phi2, gx - 1, gy, gz)));
-  psi2[P + p] = (T)(0.5 * (at(phi2, gx, gy + 1, gz) - at(phi2, gx, gy - 1, gz)));
-  psi2[2 * P + p] = (T)(0.5 * (at(phi2, gx, gy, gz + 1) - at(phi2, gx, gy, gz - 1)));
+  if (ng == 1) {
+    psi1[p] = (T)(0.5 * (at(phi1, gx + 1, gy, gz) - at(phi1, gx - 1, gy, gz)));
+    psi1[P + p] = (T)(0.5 * (at(phi1, gx, gy + 1, gz) - at(phi1, gx, gy - 1, gz)));
+    psi1[2 * P + p] = (T)(0.5 * (at(phi1, gx, gy, gz + 1) - at(phi1, gx, gy, gz - 1)));
+    psi2[p] = (T)(0.5 * (at(phi2, gx + 1, gy, gz) - at(phi2, gx - 1, gy, gz)));
+    psi2[P + p] = (T)(0.5 * (at(phi2, gx, gy + 1, gz) - at(phi2, gx, gy - 1, gz)));
+    psi2[2 * P + p] = (T)(0.5 * (at(phi2, gx, gy, gz + 1) - at(phi2, gx, gy, gz - 1)));
+  } else {
+    double s1[3] = {0.0, 0.0, 0.0}, s2[3] = {0.0, 0.0, 0.0};
+    for (int k = 1; k <= ng; ++k) {
+      const double c = d1_weight(ng, k);
+      s1[0] += c * (at(phi1, gx + k, gy, gz) - at(phi1, gx - k, gy, gz));
+      s1[1] += c * (at(phi1, gx, gy + k, gz) - at(phi1, gx, gy - k, gz));
+      s1[2] += c * (at(phi1, gx, gy, gz + k) - at(phi1, gx, gy, gz - k));
+      s2[0] += c * (at(phi2, gx + k, gy, gz) - at(phi2, gx - k, gy, gz));
+      s2[1] += c * (at(phi2, gx, gy + k, gz) - at(phi2, gx, gy - k, gz));
+      s2[2] += c * (at(phi2, gx, gy, gz + k) - at(phi2, gx, gy, gz - k));
+    }
+    for (int c = 0; c < 3; ++c) {
+      psi1[c * P + p] = (T)s1[c];
+      psi2[c * P + p] = (T)s2[c];
+    }
+  }
   for (int c = 0; c < 3; ++c) {
     xres[c * P + p] = T(0);
     pres[c * P + p] = T(0);
   }
 }
 
-// C.3: Phi_BC^0 at the padded PM nodes j in [-1, M+1]^3 outside [1, M-1]^3: trilinear
+// C.3: Phi_BC^0 at the padded PM nodes j in [-ng, M+ng]^3 outside [1, M-1]^3: trilinear
 // interpolation of phi1 at the PM node, i.e. the mean of the 8 LPT nodes around it (PM
 // nodes sit half a cell from the LPT nodes).  Interior entries are set to zero.
 __global__ void k_boundary_potential(const TileDesc* __restrict__ tiles, int n_tiles,
                                      const double* __restrict__ phi1, double* __restrict__ bc0,
-                                     int N) {
+                                     int N, int ng) {
   const int ti = blockIdx.y;
   if (ti >= n_tiles) return;
   const TileDesc t = tiles[ti];
-  const int Mp = t.M + 3;
+  const int Mp = t.M + 1 + 2 * ng;
   const int64_t n = (int64_t)Mp * Mp * Mp;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int a = (int)(e / ((int64_t)Mp * Mp)) - 1, b = (int)((e / Mp) % Mp) - 1,
-              c = (int)(e % Mp) - 1;
+    const int a = (int)(e / ((int64_t)Mp * Mp)) - ng, b = (int)((e / Mp) % Mp) - ng,
+              c = (int)(e % Mp) - ng;
     double v = 0.0;
     const bool inside = a >= 1 && a <= t.M - 1 && b >= 1 && b <= t.M - 1 && c >= 1 &&
                         c <= t.M - 1;
@@ -252,13 +319,13 @@ hipError_t fft3d_inverse(double2* c, int N, hipStream_t s) { return fft3d(c, N, 
 hipError_t launch_ic_filter(const SetupArgs& a, hipStream_t s) {
   const int64_t n3 = (int64_t)a.N * a.N * a.N;
   hipLaunchKernelGGL(k_ic_filter, dim3(grid1(n3)), dim3(kBlock), 0, s, a.cbuf, a.N, a.L,
-                     a.amplitude, a.ns, a.Om, a.Ob, a.h, a.Tcmb, a.growth2);
+                     a.amplitude, a.ns, a.Om, a.Ob, a.h, a.Tcmb, a.growth2, a.ng);
   return hipGetLastError();
 }
 
-hipError_t launch_inverse_laplacian(double2* c, int N, hipStream_t s) {
+hipError_t launch_inverse_laplacian(double2* c, int N, int ng, hipStream_t s) {
   const int64_t n3 = (int64_t)N * N * N;
-  hipLaunchKernelGGL(k_inverse_laplacian, dim3(grid1(n3)), dim3(kBlock), 0, s, c, N);
+  hipLaunchKernelGGL(k_inverse_laplacian, dim3(grid1(n3)), dim3(kBlock), 0, s, c, N, ng);
   return hipGetLastError();
 }
 
@@ -276,14 +343,14 @@ hipError_t launch_setup_potentials(const SetupArgs& a, hipStream_t s) {
   hipError_t e = fft3d(a.cbuf, N, -1.0, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_ic_filter, dim3(grid1(n3)), dim3(kBlock), 0, s, a.cbuf, N, a.L,
-                     a.amplitude, a.ns, a.Om, a.Ob, a.h, a.Tcmb, a.growth2);
+                     a.amplitude, a.ns, a.Om, a.Ob, a.h, a.Tcmb, a.growth2, a.ng);
   if ((e = fft3d(a.cbuf, N, +1.0, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_take_real, dim3(grid1(n3)), dim3(kBlock), 0, s, a.cbuf, a.phi1,
                      1.0 / (double)n3, n3);
   hipLaunchKernelGGL(k_second_order_source, dim3(grid1(n3)), dim3(kBlock), 0, s, a.phi1,
-                     a.cbuf, N);
+                     a.cbuf, N, a.ng);
   if ((e = fft3d(a.cbuf, N, -1.0, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_inverse_laplacian, dim3(grid1(n3)), dim3(kBlock), 0, s, a.cbuf, N);
+  hipLaunchKernelGGL(k_inverse_laplacian, dim3(grid1(n3)), dim3(kBlock), 0, s, a.cbuf, N, a.ng);
   if ((e = fft3d(a.cbuf, N, +1.0, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_take_real, dim3(grid1(n3)), dim3(kBlock), 0, s, a.cbuf, a.phi2,
                      1.0 / (double)n3, n3);
@@ -296,9 +363,9 @@ hipError_t launch_setup_boxes(const BoxSetupArgs& a, T* xres, T* pres, hipStream
     hipLaunchKernelGGL(k_extract_psi<T>, dim3(a.n_blocks), dim3(kBlock), 0, s, a.tiles,
                        a.blk_tile, a.blk_first, a.phi1, a.phi2, static_cast<T*>(a.psi1),
                        static_cast<T*>(a.psi2), xres, pres,
-                       a.N, a.P);
+                       a.N, a.P, a.ng);
   hipLaunchKernelGGL(k_boundary_potential, dim3(64, a.n_tiles), dim3(kBlock), 0, s, a.tiles,
-                     a.n_tiles, a.phi1, a.bc0, a.N);
+                     a.n_tiles, a.phi1, a.bc0, a.N, a.ng);
   return hipGetLastError();
 }
 

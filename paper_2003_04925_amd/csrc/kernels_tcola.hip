@@ -6,9 +6,10 @@
 //
 // The operators are those of the boxes without the box cut: CiC deposit onto the periodic
 // node grid (nodes at integer positions, one per lattice cell, global mean density one
-// particle per cell), the FDA-2 Poisson equation solved in Fourier space (the Laplacian's
-// symbol -4 sum sin^2(k/2), zero mode removed), the central-difference gradient and CiC
-// interpolation, then the same COLA kick and drift.  Particles are in lattice order; every
+// particle per cell), the Poisson equation solved in Fourier space with the symbol of the
+// finite-difference Laplacian of the plan's order (-4 sum sin^2(k/2) at order 2, zero mode
+// removed), the central-difference gradient of the same order and CiC interpolation, then
+// the same COLA kick and drift.  Particles are in lattice order; every
 // position is formed in FP64 as in the box kernels; deposits are 64-bit fixed point (2^40
 // units per particle), exact and order independent.  The Poisson solve reuses the FP64
 // FFTs of the set-up (a reference path: its cost is not part of the sCOLA step).
@@ -21,6 +22,14 @@
 namespace scola {
 
 namespace {
+
+// Central first-difference weights of order 2 ng: (1/2), (2/3, -1/12), (3/4, -3/20, 1/60).
+__device__ inline double tc_grad_weight(int ng, int k) {
+  return ng == 1 ? 0.5
+       : ng == 2 ? (k == 1 ? 2.0 / 3.0 : -1.0 / 12.0)
+                 : (k == 1 ? 0.75 : k == 2 ? -0.15 : 1.0 / 60.0);
+}
+
 
 __device__ __forceinline__ int pwrap(int i, int N) { return i & (N - 1); }   // N: power of 2
 
@@ -39,12 +48,20 @@ __global__ void __launch_bounds__(kBlock) k_tcola_setup(TcolaArgs<T> a, const do
   };
   T* s1 = const_cast<T*>(a.psi1);
   T* s2 = const_cast<T*>(a.psi2);
-  s1[p] = (T)(0.5 * (at(phi1, x + 1, y, z) - at(phi1, x - 1, y, z)));
-  s1[n3 + p] = (T)(0.5 * (at(phi1, x, y + 1, z) - at(phi1, x, y - 1, z)));
-  s1[2 * n3 + p] = (T)(0.5 * (at(phi1, x, y, z + 1) - at(phi1, x, y, z - 1)));
-  s2[p] = (T)(0.5 * (at(phi2, x + 1, y, z) - at(phi2, x - 1, y, z)));
-  s2[n3 + p] = (T)(0.5 * (at(phi2, x, y + 1, z) - at(phi2, x, y - 1, z)));
-  s2[2 * n3 + p] = (T)(0.5 * (at(phi2, x, y, z + 1) - at(phi2, x, y, z - 1)));
+  double g1[3] = {0.0, 0.0, 0.0}, g2[3] = {0.0, 0.0, 0.0};
+  for (int k = 1; k <= a.ng; ++k) {
+    const double c = tc_grad_weight(a.ng, k);
+    g1[0] += c * (at(phi1, x + k, y, z) - at(phi1, x - k, y, z));
+    g1[1] += c * (at(phi1, x, y + k, z) - at(phi1, x, y - k, z));
+    g1[2] += c * (at(phi1, x, y, z + k) - at(phi1, x, y, z - k));
+    g2[0] += c * (at(phi2, x + k, y, z) - at(phi2, x - k, y, z));
+    g2[1] += c * (at(phi2, x, y + k, z) - at(phi2, x, y - k, z));
+    g2[2] += c * (at(phi2, x, y, z + k) - at(phi2, x, y, z - k));
+  }
+  for (int c = 0; c < 3; ++c) {
+    s1[c * n3 + p] = (T)g1[c];
+    s2[c * n3 + p] = (T)g2[c];
+  }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     a.xres[c * n3 + p] = T(0);
@@ -102,9 +119,23 @@ __global__ void __launch_bounds__(kBlock) k_tcola_particles(TcolaArgs<T> a) {
           const T w = (cx ? f[0] : T(1) - f[0]) * (cy ? f[1] : T(1) - f[1]) *
                       (cz ? f[2] : T(1) - f[2]);
           const int i = j0[0] + cx, j = j0[1] + cy, k = j0[2] + cz;
-          g[0] += w * (T(0.5) * (ph(i + 1, j, k) - ph(i - 1, j, k)));
-          g[1] += w * (T(0.5) * (ph(i, j + 1, k) - ph(i, j - 1, k)));
-          g[2] += w * (T(0.5) * (ph(i, j, k + 1) - ph(i, j, k - 1)));
+          if (a.ng == 1) {
+            g[0] += w * (T(0.5) * (ph(i + 1, j, k) - ph(i - 1, j, k)));
+            g[1] += w * (T(0.5) * (ph(i, j + 1, k) - ph(i, j - 1, k)));
+            g[2] += w * (T(0.5) * (ph(i, j, k + 1) - ph(i, j, k - 1)));
+          } else {
+            // central difference of order 2 ng
+            T sx = 0, sy = 0, sz = 0;
+            for (int o = 1; o <= a.ng; ++o) {
+              const T c = (T)tc_grad_weight(a.ng, o);
+              sx += c * (ph(i + o, j, k) - ph(i - o, j, k));
+              sy += c * (ph(i, j + o, k) - ph(i, j - o, k));
+              sz += c * (ph(i, j, k + o) - ph(i, j, k - o));
+            }
+            g[0] += w * sx;
+            g[1] += w * sy;
+            g[2] += w * sz;
+          }
         }
     const double d2 = sc.D2 - sc.D1 * sc.D1;
 #pragma unroll
@@ -255,7 +286,7 @@ hipError_t launch_tcola_particles(const TcolaArgs<T>& a, int mode, hipStream_t s
   return hipGetLastError();
 }
 
-// The FDA-2 Poisson solve of the periodic box: mass mesh -> delta -> potential (FP64 FFTs).
+// The FDA Poisson solve of the periodic box: mass mesh -> delta -> potential (FP64 FFTs).
 template <typename T>
 hipError_t launch_tcola_poisson(const TcolaArgs<T>& a, double2* cbuf, T* phi, T* rec_delta,
                                 T* rec_phi, hipStream_t s) {
@@ -266,7 +297,7 @@ hipError_t launch_tcola_poisson(const TcolaArgs<T>& a, double2* cbuf, T* phi, T*
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = fft3d_forward(cbuf, N, s)) != hipSuccess) return e;
-  if ((e = launch_inverse_laplacian(cbuf, N, s)) != hipSuccess) return e;
+  if ((e = launch_inverse_laplacian(cbuf, N, a.ng, s)) != hipSuccess) return e;
   if ((e = fft3d_inverse(cbuf, N, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_tcola_potential<T>, dim3(blocks_of(n3)), dim3(kBlock), 0, s, cbuf, phi,
                      rec_phi, n3);

@@ -368,9 +368,109 @@ __device__ __forceinline__ void block_force(const T* __restrict__ phi, int M, do
   __syncthreads();   // every thread is done with `bounds` and the window before reuse
 }
 
+// Weights c_k (k = 1..NG) of the central first difference of order 2 NG,
+// sum_k c_k (f(i+k) - f(i-k)): (1/2), (2/3, -1/12), (3/4, -3/20, 1/60).
+template <int NG>
+__device__ __forceinline__ constexpr double grad_weight(int k) {
+  return NG == 1 ? 0.5
+       : NG == 2 ? (k == 1 ? 2.0 / 3.0 : -1.0 / 12.0)
+                 : (k == 1 ? 0.75 : k == 2 ? -0.15 : 1.0 / 60.0);
+}
+
+// grad^sCOLA + B-bar^sCOLA at one particle with the gradient of order 2 NG (NG > 1): at each
+// CiC corner c in [0, M] (others carry zero weight) the component along axis a is
+// sum_k c_k (Phi(c + k e_a) - Phi(c - k e_a)); `at(kx, ky, kz)` returns the potential at
+// node j0 - NG + k (k in 0..2 NG + 1 per axis; a finite stand-in where only zero weights
+// use it).
+template <typename T, int NG, typename At>
+__device__ __forceinline__ void gather_force_wide(int M, const int (&j0)[3], const T (&fr)[3],
+                                                  At at, T (&g)[3]) {
+  T w[3][2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    w[a][0] = j0[a] >= 0 ? T(1) - fr[a] : T(0);
+    w[a][1] = j0[a] + 1 <= M ? fr[a] : T(0);
+  }
+  T gx = 0, gy = 0, gz = 0;
+#pragma unroll 1
+  for (int c = 0; c < 8; ++c) {
+    const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
+    const T wc = w[0][dx] * w[1][dy] * w[2][dz];
+    const int X = NG + dx, Y = NG + dy, Z = NG + dz;
+    T sx = 0, sy = 0, sz = 0;
+#pragma unroll
+    for (int k = 1; k <= NG; ++k) {
+      const T ck = (T)grad_weight<NG>(k);
+      sx += ck * (at(X + k, Y, Z) - at(X - k, Y, Z));
+      sy += ck * (at(X, Y + k, Z) - at(X, Y - k, Z));
+      sz += ck * (at(X, Y, Z + k) - at(X, Y, Z - k));
+    }
+    gx += wc * sx;
+    gy += wc * sy;
+    gz += wc * sz;
+  }
+  g[0] = gx;
+  g[1] = gy;
+  g[2] = gz;
+}
+
+// Force at u for the 256 particles of a block at gradient order 2 NG (NG > 1) on the padded
+// potential [-NG, M + NG]^3: the block's stencil nodes [min j0 - NG, max j0 + 1 + NG] are
+// staged in an LDS window sized to that extent when it fits, else gathered from global
+// memory; coordinates are clamped into the padded grid, which changes only reads that
+// carry zero weight.  Must be called by all threads of the block.
+template <typename T, int NG>
+__device__ __forceinline__ void block_force_wide(const T* __restrict__ phi, int M, double ux,
+                                                 double uy, double uz, T* win, int* bounds,
+                                                 T (&g)[3]) {
+  g[0] = g[1] = g[2] = T(0);
+  const double hiu = (double)M + 1.0;
+  const bool in = ux >= -1.0 && ux < hiu && uy >= -1.0 && uy < hiu && uz >= -1.0 && uz < hiu;
+  const double u[3] = {ux, uy, uz};
+  int j0[3] = {0, 0, 0};
+  T fr[3] = {T(0), T(0), T(0)};
+  if (in) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double fl = floor(u[a]);
+      j0[a] = (int)fl;
+      fr[a] = (T)(u[a] - fl);
+    }
+  }
+  const int Mp = M + 1 + 2 * NG;
+  auto cl = [&](int v) { return min(max(v, -NG), M + NG) + NG; };   // padded index
+  const CellRange cr = block_cells(in, j0, bounds);
+  if (cr.any) {
+    const int ox = cr.lo[0] - NG, oy = cr.lo[1] - NG, oz = cr.lo[2] - NG;
+    const int wx = cr.hi[0] - cr.lo[0] + 2 + 2 * NG, wy = cr.hi[1] - cr.lo[1] + 2 + 2 * NG,
+              wz = cr.hi[2] - cr.lo[2] + 2 + 2 * NG;
+    const int wyz = wy * wz;
+    if (wx * wyz <= kWindow) {
+      for (int pos = threadIdx.x; pos < wyz; pos += blockDim.x) {
+        const int ey = pos / wz, ez = pos - ey * wz;
+        const int64_t col = (int64_t)cl(oy + ey) * Mp + cl(oz + ez);
+        for (int x = 0; x < wx; ++x) win[x * wyz + pos] = phi[(int64_t)cl(ox + x) * Mp * Mp + col];
+      }
+      __syncthreads();
+      if (in) {
+        const int bx = j0[0] - NG - ox, by = j0[1] - NG - oy, bz = j0[2] - NG - oz;
+        gather_force_wide<T, NG>(M, j0, fr, [&](int kx, int ky, int kz) {
+          return win[((bx + kx) * wy + by + ky) * wz + bz + kz];
+        }, g);
+      }
+    } else if (in) {
+      gather_force_wide<T, NG>(M, j0, fr, [&](int kx, int ky, int kz) {
+        return phi[((int64_t)cl(j0[0] - NG + kx) * Mp + cl(j0[1] - NG + ky)) * Mp +
+                   cl(j0[2] - NG + kz)];
+      }, g);
+    }
+  }
+  __syncthreads();   // every thread is done with `bounds` and the window before reuse
+}
+
 // The fused particle step of logical block L (< m.count): called by k_particles below and by
 // the persistent step kernel.
-template <typename T, int MODE>
+template <typename T, int MODE, int NG = 1>
 __device__ __forceinline__ void particles_block(const ParticleArgs<T>& a, const BlockMap& m,
                                                 int L) {
   const int b = m.base + L;
@@ -384,7 +484,9 @@ __device__ __forceinline__ void particles_block(const ParticleArgs<T>& a, const 
   uint4* const hint = a.cells + (t.p_off / kBlock + m.local[b]);
   constexpr bool kForce = MODE != kDepositOnly && MODE != kInit;
   uint4 h = make_uint4(0u, 0u, 0u, 0u);
-  if (kForce && a.use_hints) h = *hint;
+  // the kept extents place the fixed window of the order-2 gradient only
+  const bool use_hints = NG == 1 && a.use_hints != 0;
+  if (kForce && use_hints) h = *hint;
   int i, j, k;
   brick_site(pl, M, i, j, k);
   const double q[3] = {i + 0.5, j + 0.5, k + 0.5};
@@ -413,7 +515,7 @@ __device__ __forceinline__ void particles_block(const ParticleArgs<T>& a, const 
   __shared__ int bounds[kCellScratch];
   // the potential window placed from the kept extent is requested while the particle
   // streams are still in flight
-  const bool hinted = kForce && a.use_hints != 0;
+  const bool hinted = kForce && use_hints;
   CellRange hc;
   bool staged = false;
   if (hinted) {
@@ -444,8 +546,12 @@ __device__ __forceinline__ void particles_block(const ParticleArgs<T>& a, const 
       asm volatile("" : "+v"(lpt[c]), "+v"(un[c]));
     }
     T g[3];
-    block_force<T>(a.phi + t.h_off, M, u[0], u[1], u[2], reinterpret_cast<T*>(win), bounds,
-                   hinted, hc, staged, g);
+    if constexpr (NG == 1)
+      block_force<T>(a.phi + t.h_off, M, u[0], u[1], u[2], reinterpret_cast<T*>(win), bounds,
+                     hinted, hc, staged, g);
+    else
+      block_force_wide<T, NG>(a.phi + t.h_off, M, u[0], u[1], u[2], reinterpret_cast<T*>(win),
+                              bounds, g);
 #pragma unroll
     for (int c = 0; c < 3; ++c) pr[c] += (T)sc.beta * (g[c] - lpt[c]);
     if (MODE == kFinalKick) {

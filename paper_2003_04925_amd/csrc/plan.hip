@@ -116,6 +116,7 @@ struct scola_plan {
   uint64_t graph_version = 0;
   int graph_eager_calls = 0;
   bool is64 = false;
+  int ng = 1;                         // ghost layers: finite differences of order 2 ng
   // one persistent cooperative launch per KDK step and class instead of four launches
   bool persistent = false;
   unsigned* d_barrier = nullptr;      // arrival counter + sticky failure flag
@@ -217,12 +218,8 @@ void validate(const scola_config& c, const scola_cosmology& cs, const scola_tile
                                    ": only an LPT grid with N_lpt = Np nodes is implemented");
     fail(SCOLA_EINVAL, "N_lpt must be 0, Np or a divisor of Np");
   }
-  if (c.fda_order != 0 && c.fda_order != 2) {
-    if (c.fda_order == 4 || c.fda_order == 6)
-      fail(SCOLA_EUNSUPPORTED, "fda_order = " + std::to_string(c.fda_order) +
-                                   ": only finite differences of order 2 are implemented");
+  if (c.fda_order != 0 && c.fda_order != 2 && c.fda_order != 4 && c.fda_order != 6)
     fail(SCOLA_EINVAL, "fda_order must be 0, 2, 4 or 6");
-  }
   if (!std::isfinite(c.n_lpt)) fail(SCOLA_EINVAL, "n_lpt must be finite");
   if (c.discretisation != SCOLA_MODIFIED && c.discretisation != SCOLA_STANDARD)
     fail(SCOLA_EINVAL, "discretisation must be SCOLA_MODIFIED or SCOLA_STANDARD");
@@ -270,8 +267,10 @@ void validate(const scola_config& c, const scola_cosmology& cs, const scola_tile
 
 template <typename T>
 void upload_tables(scola_plan* p) {
-  // twiddles W_{2M}^m and FDA-2 eigenvalues -4 sin^2(pi l / (2M)) per distinct M (FP64 on
-  // the host, stored in the plan's precision)
+  // twiddles W_{2M}^m and the FDA eigenvalues of App. C.2 per distinct M (FP64 on the host,
+  // stored in the plan's precision): with s(x) = sin^2(x) and theta = pi l / M,
+  //   order 2: -4 s(theta/2); order 4: (s(theta) - 16 s(theta/2)) / 3;
+  //   order 6: -(2 s(3 theta/2) - 27 s(theta) + 270 s(theta/2)) / 45
   std::map<int, std::pair<int, int>> offs;
   std::vector<T> tw, ev;
   for (auto& d : p->desc) {
@@ -283,8 +282,18 @@ void upload_tables(scola_plan* p) {
       tw.push_back((T)(-std::sin(2.0 * M_PI * m / N)));
     }
     for (int l = 1; l < d.M; ++l) {
-      const double s = std::sin(M_PI * l / (2.0 * d.M));
-      ev.push_back((T)(-4.0 * s * s));
+      const double th = M_PI * l / d.M;
+      auto s2 = [](double x) { return std::sin(x) * std::sin(x); };
+      double v;
+      if (p->ng == 1) {
+        const double s = std::sin(M_PI * l / (2.0 * d.M));
+        v = -4.0 * s * s;
+      } else if (p->ng == 2) {
+        v = (s2(th) - 16.0 * s2(0.5 * th)) / 3.0;
+      } else {
+        v = -(2.0 * s2(1.5 * th) - 27.0 * s2(th) + 270.0 * s2(0.5 * th)) / 45.0;
+      }
+      ev.push_back((T)v);
     }
     offs[d.M] = {tw_off, ev_off};
   }
@@ -466,6 +475,7 @@ MeshArgs<T> mesh_args(scola_plan* p, void* ws, double D1_bc) {
   a.twiddles = p->d_twiddles;
   a.eigen = reinterpret_cast<const T*>(p->d_eigen);
   a.D1_bc = D1_bc;
+  a.ng = p->ng;
   return a;
 }
 
@@ -486,6 +496,7 @@ ParticleArgs<T> particle_args(scola_plan* p, void* ws, const StepScalars& sc) {
   a.use_hints = 1;
   a.P = p->P;
   a.sc = sc;
+  a.ng = p->ng;
   return a;
 }
 
@@ -728,6 +739,7 @@ SetupArgs setup_args(scola_plan* p, const double* w, void* ws) {
   std::vector<double> q = {p->cfg.a_i, 1.0}, D1, dD1, D2, dD2;
   p->bg.growth(q, D1, dD1, D2, dD2);
   a.growth2 = (D1[0] / D1[1]) * (D1[0] / D1[1]);
+  a.ng = p->ng;
   return a;
 }
 
@@ -745,6 +757,7 @@ BoxSetupArgs box_setup_args(scola_plan* p, void* ws) {
   b.bc0 = reinterpret_cast<double*>(ws_ptr(ws, p->lay.bc0));
   b.N = p->cfg.Np;
   b.P = p->P;
+  b.ng = p->ng;
   return b;
 }
 
@@ -1116,7 +1129,7 @@ void do_backward(scola_plan* p, const T* lam_dens, double* grad_w, void* ws, hip
             "adjoint set-up scatter");
   hip_check(launch_adj_phi_from_psi(lam_psig, lam_phi1, cbuf, N, s), "adjoint D^T");
   hip_check(fft3d_forward(cbuf, N, s), "fft");
-  hip_check(launch_inverse_laplacian(cbuf, N, s), "adjoint Poisson (2LPT)");
+  hip_check(launch_inverse_laplacian(cbuf, N, p->ng, s), "adjoint Poisson (2LPT)");
   hip_check(fft3d_inverse(cbuf, N, s), "fft");
   hip_check(launch_take_real(cbuf, lam_s, 1.0 / (double)N3, N3, s), "take real");
   hip_check(launch_adj_source(reinterpret_cast<const double*>(ws_ptr(ws, l.phi1)), lam_s, f6,
@@ -1321,6 +1334,7 @@ void do_tcola(scola_plan* p, const double* w, void* pos, void* mom, void* dens, 
   a.rho = reinterpret_cast<unsigned long long*>(ws_ptr(ws, l.rho));
   a.phi = reinterpret_cast<const T*>(ws_ptr(ws, l.phi));
   a.N = N;
+  a.ng = p->ng;
   T* phi = reinterpret_cast<T*>(ws_ptr(ws, l.phi));
   hip_check(launch_tcola_setup<T>(a, sa.phi1, sa.phi2, s), "tCOLA set-up");
   hip_check(launch_zero_u64(a.rho, N3, s), "zero rho");
@@ -1445,6 +1459,7 @@ scola_status scola_plan_create(const scola_config* cfg, const scola_cosmology* c
     if (p->cfg.N_out == 0) p->cfg.N_out = cfg->Np;
     p->cosmo = *cosmo;
     p->is64 = cfg->precision == SCOLA_FP64;
+    p->ng = p->cfg.fda_order > 0 ? p->cfg.fda_order / 2 : 1;
     p->tiles.assign(tiles, tiles + n_tiles);
     hip_check(hipGetDevice(&p->device), "hipGetDevice");
     p->bg = background_of(*cosmo);
@@ -1463,7 +1478,8 @@ scola_status scola_plan_create(const scola_config* cfg, const scola_cosmology* c
       d.h_off = H;
       P += (int64_t)d.M * d.M * d.M;
       G += (int64_t)(d.M - 1) * (d.M - 1) * (d.M - 1);
-      H += (int64_t)(d.M + 3) * (d.M + 3) * (d.M + 3);
+      const int64_t Mp = d.M + 1 + 2 * p->ng;
+      H += Mp * Mp * Mp;
       p->max_M = std::max(p->max_M, d.M);
       p->desc.push_back(d);
     }
@@ -1515,7 +1531,9 @@ scola_status scola_plan_create(const scola_config* cfg, const scola_cosmology* c
     build_maps(p->p2, p->desc, [](const TileDesc& d) {
       return (d.M - 1) * ((d.M - 1 + kPencilChunk - 1) / kPencilChunk);
     });
-    build_maps(p->p3, p->desc, [](const TileDesc& d) { return d.M - 1 + 4; });
+    // the interior x planes, then the 2 (ng + 1) shell planes
+    const int ng = p->ng;
+    build_maps(p->p3, p->desc, [ng](const TileDesc& d) { return d.M - 1 + 2 * (ng + 1); });
     upload_maps(p->part);
     upload_maps(p->p1);
     upload_maps(p->p2);
@@ -1656,6 +1674,8 @@ scola_status scola_plan_set_persistent(scola_plan* p, int32_t enable) {
     if (enable && p->is64) fail(SCOLA_EUNSUPPORTED, "the persistent step is built for FP32 plans");
     if (enable && p->cfg.schedule != SCOLA_BATCHED)
       fail(SCOLA_EINVAL, "the persistent step needs the batched schedule");
+    if (enable && p->ng != 1)
+      fail(SCOLA_EUNSUPPORTED, "the persistent step is built for finite differences of order 2");
     p->persistent = enable != 0;
     drop_graph(p);
     ++p->sched_version;
@@ -1785,6 +1805,8 @@ scola_status scola_backward(scola_plan* p, const void* grad_density, double* gra
       fail(SCOLA_ESTATE, "scola_backward needs a full scola_forward on this workspace first");
     if (p->tclasses.size() > 1)
       fail(SCOLA_EUNSUPPORTED, "the reverse mode needs one final scale factor for all tiles");
+    if (p->ng != 1)
+      fail(SCOLA_EUNSUPPORTED, "the reverse mode is built for finite differences of order 2");
     if (p->is64)
       do_backward<double>(p, reinterpret_cast<const double*>(grad_density), grad_w, ws, s);
     else

@@ -517,13 +517,26 @@ __device__ inline void load_twiddles(cx<T>* tw, const MeshArgs<T>& a, const Tile
 
 // The three passes as device functions of one logical block L (< m.count) with the dynamic
 // LDS `smem`: called by their own kernels below and by the persistent step kernel.
-template <typename T, int R, bool ADJ>
+// Weights a_k (k = 1..NG) of the central second difference of order 2 NG, sum_k a_k (f(i+k)
+// + f(i-k) - 2 f(i)): (1), (4/3, -1/12), (3/2, -3/20, 1/90).
+template <int NG>
+__device__ __forceinline__ constexpr double lap_weight(int k) {
+  return NG == 1 ? 1.0
+       : NG == 2 ? (k == 1 ? 4.0 / 3.0 : -1.0 / 12.0)
+                 : (k == 1 ? 1.5 : k == 2 ? -0.15 : 1.0 / 90.0);
+}
+
+// NG: ghost layers of the finite-difference order 2 NG (Sec. 3): the box's Phi_BC^0 and
+// potential live on the padded nodes [-NG, M + NG]^3 (padded index = node + NG), and
+// Phi_BCs occupies the NG layers outside the interior on each side.
+template <typename T, int R, bool ADJ, int NG = 1>
 __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const BlockMap& m, int L,
                                                  unsigned char* smem) {
+  static_assert(!ADJ || NG == 1, "the reverse passes exist for order 2 only");
   const int b = m.base + L;
   const TileDesc t = a.tiles[m.tile[b]];
   const int x = m.local[b];
-  constexpr int M = 16 * R, n = M - 1, Mp = M + 3;
+  constexpr int M = 16 * R, n = M - 1, Mp = M + 1 + 2 * NG;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
   T* plane = reinterpret_cast<T*>(smem + 2 * M * sizeof(cx<T>));
   load_twiddles(tw, a, t);
@@ -546,7 +559,7 @@ __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const Blo
     // Phi_BC at the padded node (A, B, C) (node = padded index - 1) over D1: Phi_BC^0, or the
     // full-box potential over D1 in the consistency tests (D1 multiplies it back)
     auto bcv = [&](int A, int B, int C) {
-      if (a.ov_phi) return (double)full_at(a.ov_phi, a.ov_N, t, A - 1, B - 1, C - 1) / D1;
+      if (a.ov_phi) return (double)full_at(a.ov_phi, a.ov_N, t, A - NG, B - NG, C - NG) / D1;
       return bc[((int64_t)A * Mp + B) * Mp + C];
     };
     auto yz_term = [&](int y, int z) {
@@ -559,7 +572,7 @@ __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const Blo
     };
     int pe = -1;
     double pterm = 0.0;
-    if (!xface && (int)threadIdx.x < 4 * (n - 1)) {
+    if (NG == 1 && !xface && (int)threadIdx.x < 4 * (n - 1)) {
       // perimeter of the plane: i < n - 1 first row, then last column, last row, first column
       const int i = threadIdx.x, side = i / (n - 1), o = i - side * (n - 1);
       const int y = side == 0 ? 0 : side == 1 ? o : side == 2 ? n - 1 : n - 1 - o;
@@ -610,7 +623,29 @@ __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const Blo
       }
     }
     __syncthreads();
-    if (xface) {
+    if constexpr (NG > 1) {
+      // wide stencils: an interior node within NG of a face picks up, along each axis,
+      // a_k Phi_BCs at the nodes k = 1..NG away that lie outside [1, M-1]
+      const int jx = x + 1;
+      const bool xb = jx <= NG || jx >= M - NG;
+      for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int jy = e / n + 1, jz = e - (e / n) * n + 1;
+        if (!(xb || jy <= NG || jy >= M - NG || jz <= NG || jz >= M - NG)) continue;
+        double s = 0.0;
+#pragma unroll
+        for (int k = 1; k <= NG; ++k) {
+          double o = 0.0;
+          if (jx - k <= 0) o += bcv(jx - k + NG, jy + NG, jz + NG);
+          if (jx + k >= M) o += bcv(jx + k + NG, jy + NG, jz + NG);
+          if (jy - k <= 0) o += bcv(jx + NG, jy - k + NG, jz + NG);
+          if (jy + k >= M) o += bcv(jx + NG, jy + k + NG, jz + NG);
+          if (jz - k <= 0) o += bcv(jx + NG, jy + NG, jz - k + NG);
+          if (jz + k >= M) o += bcv(jx + NG, jy + NG, jz + k + NG);
+          s += lap_weight<NG>(k) * o;
+        }
+        plane[e] = (T)((double)plane[e] - D1 * s);
+      }
+    } else if (xface) {
       const int A = x == 0 ? 1 : M + 1;   // padded x index of the face layer
       for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
         const int y = e / n, z = e - (e / n) * n;
@@ -691,25 +726,27 @@ __device__ __forceinline__ void poisson_p2_block(const MeshArgs<T>& a, const Blo
   }
 }
 
-template <typename T, int R, bool ADJ>
+template <typename T, int R, bool ADJ, int NG = 1>
 __device__ __forceinline__ void poisson_p3_block(const MeshArgs<T>& a, const BlockMap& m, int L,
                                                  unsigned char* smem) {
+  static_assert(!ADJ || NG == 1, "the reverse passes exist for order 2 only");
   const int b = m.base + L;
   const TileDesc t = a.tiles[m.tile[b]];
   const int local = m.local[b];
-  constexpr int M = 16 * R, n = M - 1, Mp = M + 3;
+  constexpr int M = 16 * R, n = M - 1, Mp = M + 1 + 2 * NG;
   const double* bc = a.bc0 + t.h_off;
   T* phi = a.phi + t.h_off;
   const double D1 = a.D1_bc;
   if (local >= n) {
     if (ADJ) return;
-    // one of the four shell planes a = 0, 1, M+1, M+2 (node -1, 0, M, M+1)
+    // one of the 2 (NG + 1) shell planes: padded x index 0..NG (nodes -NG..0) and
+    // M + NG..M + 2 NG (nodes M..M + NG)
     const int s = local - n;
-    const int A = s < 2 ? s : M + s - 1;
+    const int A = s <= NG ? s : M + s - 1;
     if (a.ov_phi) {
       for (int e = threadIdx.x; e < Mp * Mp; e += blockDim.x)
-        phi[(int64_t)A * Mp * Mp + e] = full_at(a.ov_phi, a.ov_N, t, A - 1, e / Mp - 1,
-                                                e - (e / Mp) * Mp - 1);
+        phi[(int64_t)A * Mp * Mp + e] = full_at(a.ov_phi, a.ov_N, t, A - NG, e / Mp - NG,
+                                                e - (e / Mp) * Mp - NG);
       return;
     }
     for (int e = threadIdx.x; e < Mp * Mp; e += blockDim.x)
@@ -721,23 +758,25 @@ __device__ __forceinline__ void poisson_p3_block(const MeshArgs<T>& a, const Blo
   load_twiddles(tw, a, t);
   const int x = local;
   const int64_t base = t.g_off + (int64_t)x * n * n;
-  const int A = x + 2;
-  // the padded plane's border (two layers on each side) takes D1 Phi_BC^0: those values
+  const int A = x + 1 + NG;
+  // the padded plane's border (NG + 1 layers on each side) takes D1 Phi_BC^0: those values
   // are fetched first so that their latency overlaps the load of the plane.  Border
-  // element i: rows 0, 1, M+1, M+2 whole, then columns 0, 1, M+1, M+2 of rows 2..M.
+  // element i: rows 0..NG and M+NG..M+2NG whole, then columns 0..NG and M+NG..M+2NG of the
+  // rows in between.
   constexpr int kBorder = Mp * Mp - n * n;
   constexpr int kPerThread = (kBorder + kBlock - 1) / kBlock;
+  constexpr int kW = 2 * (NG + 1);   // border rows, and border columns per inner row
   T* border = plane + n * n;   // the border values, staged in LDS behind the plane
   auto border_offset = [](int i) {
     int B, C;
-    if (i < 4 * Mp) {
+    if (i < kW * Mp) {
       const int r = i / Mp;
-      B = r < 2 ? r : M - 1 + r;
+      B = r <= NG ? r : M - 1 + r;
       C = i - r * Mp;
     } else {
-      const int j = i - 4 * Mp, c = j & 3;
-      B = 2 + (j >> 2);
-      C = c < 2 ? c : M - 1 + c;
+      const int j = i - kW * Mp, r = j / kW, c = j - r * kW;
+      B = NG + 1 + r;
+      C = c <= NG ? c : M - 1 + c;
     }
     return B * Mp + C;
   };
@@ -782,7 +821,7 @@ __device__ __forceinline__ void poisson_p3_block(const MeshArgs<T>& a, const Blo
     if (a.ov_phi)
       for (int i = threadIdx.x; i < kBorder; i += blockDim.x) {
         const int o = border_offset(i);
-        border[i] = full_at(a.ov_phi, a.ov_N, t, A - 1, o / Mp - 1, o - (o / Mp) * Mp - 1);
+        border[i] = full_at(a.ov_phi, a.ov_N, t, A - NG, o / Mp - NG, o - (o / Mp) * Mp - NG);
       }
   }
   __syncthreads();
@@ -828,7 +867,7 @@ __device__ __forceinline__ void poisson_p3_block(const MeshArgs<T>& a, const Blo
   T* out = phi + (int64_t)A * Mp * Mp;
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
     const int y = e / n, z = e - (e / n) * n;
-    out[(y + 2) * Mp + z + 2] = plane[e];
+    out[(y + 1 + NG) * Mp + z + 1 + NG] = plane[e];
   }
   for (int i = threadIdx.x; i < kBorder; i += blockDim.x) out[border_offset(i)] = border[i];
 }

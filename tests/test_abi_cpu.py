@@ -102,13 +102,11 @@ def test_config_and_tile_fields_accept_and_refuse():
     assert st == -5 and "one of 16" in msg
     st, msg = _plan_status(L_, Np=256, tiles=[((0, 0, 0), 256, 0)])    # M = 256
     assert st == -5
-    # fda_order: 0 and 2 accepted, 4 and 6 unsupported, others invalid
-    for o in (0, 2):
+    # fda_order: 0, 2, 4 and 6 accepted, others invalid
+    for o in (0, 2, 4, 6):
         assert _validated(_plan_status(L_, fda_order=o)[0])
-    for o in (4, 6):
-        st, msg = _plan_status(L_, fda_order=o)
-        assert st == -5 and "order 2" in msg
-    assert _plan_status(L_, fda_order=3)[0] == -1
+    for o in (3, 8, -2):
+        assert _plan_status(L_, fda_order=o)[0] == -1
     # N_lpt: 0 and Np accepted, a divisor unsupported, anything else invalid
     for n in (0, 32):
         assert _validated(_plan_status(L_, N_lpt=n)[0])
