@@ -36,7 +36,7 @@ def test_recorded_traffic_follows_the_kernel_sources():
     got = bench.measured_traffic()
     if current:
         assert got == float(fields["traffic_bytes_per_launch"])
-        # the recorded traffic is at least the algorithmic 96 B per particle of c2
-        assert got >= 96 * 16777216
+        # the recorded traffic is at least the algorithmic bytes per particle of c2
+        assert got >= bench.PARTICLE_BYTES_FP32 * 16777216
     else:
         assert got is None
