@@ -97,6 +97,15 @@ __device__ __forceinline__ P* byte_offset(P* base, unsigned bytes) {
   using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
   return reinterpret_cast<P*>(reinterpret_cast<C*>(base) + bytes);
 }
+// A raw buffer resource over `bytes` bytes at p (stride 0; word 3 = 32-bit data format, the
+// gfx9 value).  Buffer loads and atomics address base + SGPR offset + 32-bit VGPR offset, so
+// a block-uniform row offset costs no vector instruction, and accesses at or beyond `bytes`
+// are discarded by the hardware (loads return 0).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
+
 static_assert(kFw * kFw * kFw == kWindow, "fixed window = LDS window");
 static_assert(kFw * kFw == kBlock, "one window column per thread");
 

@@ -107,9 +107,20 @@ __device__ __forceinline__ long long deposit_block(typename MeshFixed<T>::rho_t*
       Rho v[kFw];
 #pragma unroll
       for (int xi = 0; xi < kFw; ++xi) v[xi] = (xi >= xa && xi < xb) ? win[t + kFwX * xi] : Rho(0);
+      if constexpr (sizeof(Rho) == 4) {
+        // 32-bit words: buffer atomics over the box's mesh, the plane a scalar offset
+        const __amdgpu_buffer_rsrc_t rs = buffer_of(rho, (unsigned)(n * n * n * (int)sizeof(Rho)));
 #pragma unroll
-      for (int xi = 0; xi < kFw; ++xi)
-        if (v[xi] != 0) atomicAdd(byte_offset(rho + (int64_t)(ox - 1 + xi) * (n * n), gcol), v[xi]);
+        for (int xi = 0; xi < kFw; ++xi)
+          if (v[xi] != 0)
+            __builtin_amdgcn_raw_ptr_buffer_atomic_add_i32(
+                (int)v[xi], rs, gcol, (ox - 1 + xi) * (n * n) * (int)sizeof(Rho), 0);
+      } else {
+#pragma unroll
+        for (int xi = 0; xi < kFw; ++xi)
+          if (v[xi] != 0)
+            atomicAdd(byte_offset(rho + (int64_t)(ox - 1 + xi) * (n * n), gcol), v[xi]);
+      }
     }
     return dropped;
   }
@@ -246,14 +257,19 @@ __device__ __forceinline__ bool stage_window_direct(const T* __restrict__ phi, i
     if (ty < ey && tz < ez) {
       const int ny = min(max(oy + ty, -1), M + 1), nz = min(max(oz + tz, -1), M + 1);
       const unsigned gcol = (unsigned)(((ny + 1) * Mp + (nz + 1)) * (int)sizeof(T));
-      T* const wave_base = win + (t & ~63);
+      // the wave's first window word, a wave-uniform value held in a scalar register (the
+      // LDS destination of these loads is a scalar base)
+      T* const wave_base = win + __builtin_amdgcn_readfirstlane(t & ~63);
+      // the box's padded potential as a buffer: plane nx + 1 is a scalar offset, the column
+      // the lane's 32-bit offset
+      const __amdgpu_buffer_rsrc_t rs = buffer_of(phi, (unsigned)(Mp2 * Mp * (int)sizeof(T)));
 #pragma unroll
       for (int xi = 0; xi < kFw; ++xi)
         if (xi < ex) {
           const int nx = min(max(ox + xi, -1), M + 1);
-          __builtin_amdgcn_global_load_lds(
-              (const void*)byte_offset(phi + (int64_t)(nx + 1) * Mp2, gcol),
-              (__attribute__((address_space(3))) void*)(wave_base + kFwX * xi), 4, 0, 0);
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(
+              rs, (__attribute__((address_space(3))) void*)(wave_base + kFwX * xi), 4, gcol,
+              (nx + 1) * Mp2 * (int)sizeof(T), 0, 0);
         }
     }
     return true;
@@ -477,36 +493,56 @@ __device__ __forceinline__ void particles_block(const ParticleArgs<T>& a, const 
   const int ti = m.tile[b];
   const TileDesc t = a.tiles[ti];
   const int M = t.M;
-  const int64_t pl = (int64_t)m.local[b] * kBlock + threadIdx.x;   // one brick per block
-  const int64_t p = t.p_off + pl;
+  const int local = m.local[b];          // the block's brick of 4 x 8 x 8 lattice sites
+  const int tid = threadIdx.x;
+  // the brick's first particle (block-uniform): every particle stream of the block is a
+  // uniform base plus the thread's 32-bit offset, so the address arithmetic stays scalar
+  const int64_t p0 = t.p_off + (int64_t)local * kBlock;
   const int64_t P = a.P;
   // the block's cell extent as the previous deposit of these positions left it
-  uint4* const hint = a.cells + (t.p_off / kBlock + m.local[b]);
+  uint4* const hint = a.cells + (t.p_off / kBlock + local);
   constexpr bool kForce = MODE != kDepositOnly && MODE != kInit;
   uint4 h = make_uint4(0u, 0u, 0u, 0u);
   // the kept extents place the fixed window of the order-2 gradient only
   const bool use_hints = NG == 1 && a.use_hints != 0;
   if (kForce && use_hints) h = *hint;
-  int i, j, k;
-  brick_site(pl, M, i, j, k);
+  // lattice site: the brick's corner from the uniform brick index, the thread's place in the
+  // brick from its index (the layout of brick_site)
+  const int nb = M >> 3;
+  const int i = (local / (nb * nb)) * 4 + (tid >> 6);
+  const int j = ((local / nb) % nb) * 8 + ((tid >> 3) & 7);
+  const int k = (local % nb) * 8 + (tid & 7);
   const double q[3] = {i + 0.5, j + 0.5, k + 0.5};
   double s1[3], s2[3];
   T xr[3], pr[3];
+  const T* ps1[3];
+  const T* ps2[3];
+  T* pxr[3];
+  T* pxo[3];
+  T* ppr[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    ps1[c] = a.psi1 + (c * P + p0);
+    ps2[c] = a.psi2 + (c * P + p0);
+    pxr[c] = a.xres + (c * P + p0);
+    pxo[c] = a.xout + (c * P + p0);
+    ppr[c] = a.pres + (c * P + p0);
+  }
   // the particle streams are touched once per step: non-temporal loads and stores keep
   // them from competing for cache lines with the box's mass mesh (the target of the
   // deposit's atomics) and potential, which neighbouring blocks reuse
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    s1[c] = (double)__builtin_nontemporal_load(a.psi1 + c * P + p);
-    s2[c] = (double)__builtin_nontemporal_load(a.psi2 + c * P + p);
+    s1[c] = (double)__builtin_nontemporal_load(ps1[c] + tid);
+    s2[c] = (double)__builtin_nontemporal_load(ps2[c] + tid);
     if (MODE == kInit) {
       // operator L- (App. B): at t_0 the particles sit on their LPT trajectory and the
       // residual momentum is zero
       xr[c] = T(0);
-      a.xres[c * P + p] = T(0);
-      a.pres[c * P + p] = T(0);
+      pxr[c][tid] = T(0);
+      ppr[c][tid] = T(0);
     } else {
-      xr[c] = __builtin_nontemporal_load(a.xres + c * P + p);
+      xr[c] = __builtin_nontemporal_load(pxr[c] + tid);
     }
   }
   // one LDS window, first for the potential (kWindow T values), then for the block's mass
@@ -531,7 +567,7 @@ __device__ __forceinline__ void particles_block(const ParticleArgs<T>& a, const 
   for (int c = 0; c < 3; ++c) u[c] = lpt_base(q[c], sc.D1, s1[c], sc.D2, s2[c]) + (double)xr[c];
   if (kForce) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) pr[c] = __builtin_nontemporal_load(a.pres + c * P + p);
+    for (int c = 0; c < 3; ++c) pr[c] = __builtin_nontemporal_load(ppr[c] + tid);
     // the LPT terms of the kick and of the next position are formed before the force, so
     // Psi1 and Psi2 are not held across it
     const double d2 = sc.D2 - sc.D1 * sc.D1;
@@ -556,14 +592,14 @@ __device__ __forceinline__ void particles_block(const ParticleArgs<T>& a, const 
     for (int c = 0; c < 3; ++c) pr[c] += (T)sc.beta * (g[c] - lpt[c]);
     if (MODE == kFinalKick) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) a.pres[c * P + p] = pr[c] + (T)(sc.c1 * s1[c] + sc.c2 * s2[c]);
+      for (int c = 0; c < 3; ++c) ppr[c][tid] = pr[c] + (T)(sc.c1 * s1[c] + sc.c2 * s2[c]);
       return;
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       xr[c] += (T)sc.alpha * pr[c];
-      __builtin_nontemporal_store(xr[c], a.xout + c * P + p);
-      __builtin_nontemporal_store(pr[c], a.pres + c * P + p);
+      __builtin_nontemporal_store(xr[c], pxo[c] + tid);
+      __builtin_nontemporal_store(pr[c], ppr[c] + tid);
     }
     if (MODE == kStepNoDeposit) return;
 #pragma unroll
@@ -580,7 +616,7 @@ __device__ __forceinline__ void particles_block(const ParticleArgs<T>& a, const 
   // FP32 plans count the deposits of every box (its first block, once per launch) for the
   // mass identity that detects a wrapped 32-bit node (see the Poisson pass)
   if constexpr (MeshFixed<T>::bits < 32)
-    if (threadIdx.x == 0 && m.local[b] == 0) atomicAdd(a.deposits + ti, 1ull);
+    if (threadIdx.x == 0 && local == 0) atomicAdd(a.deposits + ti, 1ull);
 }
 
 }  // namespace

@@ -78,21 +78,27 @@ def test_poisson_dpp_blocks_have_no_exec_hazard(tmp_path):
     assert not problems, problems[:5]
 
 
+def is_lds_dma(t):
+    """A load that writes LDS directly: global_load_lds_* or a buffer load with the lds bit."""
+    return t.startswith("global_load_lds") or (t.startswith("buffer_load") and
+                                               re.search(r"\blds\b", t) is not None)
+
+
 def lds_dma_waits(asm_text):
-    """(number of direct-to-LDS loads, list of problems): after each global_load_lds, the
+    """(number of direct-to-LDS loads, list of problems): after each direct-to-LDS load, the
     next s_barrier must be preceded by an s_waitcnt that waits for every vector memory
     operation (vmcnt(0)), so that other waves read the staged words only once they landed."""
     lines = [l.strip() for l in asm_text.split("\n")]
     loads, problems = 0, []
     for i, t in enumerate(lines):
-        if not t.startswith("global_load_lds"):
+        if not is_lds_dma(t):
             continue
         loads += 1
         waited = False
         for u in lines[i + 1:]:
             if u.startswith("s_waitcnt") and re.search(r"vmcnt\(0\)", u):
                 waited = True
-            if u.startswith("global_load_lds"):
+            if is_lds_dma(u):
                 waited = False
             if u.startswith("s_barrier"):
                 if not waited:
@@ -108,6 +114,11 @@ def test_lds_dma_scan_flags_a_missing_wait():
     assert lds_dma_waits(bad)[1]
     ok = "\tglobal_load_lds_dword v1, s[0:1]\n\ts_waitcnt vmcnt(0)\n\ts_barrier"
     assert lds_dma_waits(ok) == (1, [])
+    bad = "\tbuffer_load_dword v0, s[0:3], s4 offen lds\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier"
+    assert lds_dma_waits(bad)[1]
+    ok = "\tbuffer_load_dword v0, s[0:3], s4 offen lds\n\ts_waitcnt vmcnt(0)\n\ts_barrier"
+    assert lds_dma_waits(ok) == (1, [])
+    assert lds_dma_waits("\tbuffer_load_dword v0, s[0:3], s4 offen\n\ts_barrier") == (0, [])
 
 
 def test_particle_direct_lds_staging_waits_before_barrier(tmp_path):
