@@ -19,8 +19,9 @@ Paper passages followed:
     N_ghost = 1, 2, 3 neighbours per side (fda_order arguments below; order 2 is the default
     and the order of every run of Sec. 4).
 
-Readings where the paper is silent: the LPT grid has N = N_p nodes per side and its
-nodes coincide with the particles of the Lagrangian lattice, at q = (i + 1/2) cells; the
+Readings where the paper is silent: the LPT grid has N = N_p nodes per side by default (or
+N = N_p / 2, as in the paper's runs) and its node m sits at the centre (m + 1/2) L / N of
+its cell, so with N = N_p the nodes coincide with the particles at q = (i + 1/2) cells; the
 FDA-2 Laplacian kernel is used in every Fourier-space Poisson solve; the zero mode of
 every potential is zero; the no-wiggle Eisenstein-Hu transfer function is used with
 T_CMB = 2.7255 K; sigma_8 uses the top-hat window of radius 8 Mpc/h at a = 1.

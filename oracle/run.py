@@ -9,6 +9,9 @@ Paper passages followed:
   * Sec. 4.1: the final density is the CiC assignment of all particles to a grid.
   * Sec. 4.2: P(k) and R(k) estimators with 100 log bins from 2 pi / L to 1 h/Mpc.
 
+  * Sec. 3.3 C.2 and Sec. 4: with an LPT grid of N = N_p / 2 nodes per side, Psi is
+    differenced on the LPT grid and interpolated (CiC) to the particles.
+
 Readings: the output density grid has N_out nodes per side at integer multiples of
 L / N_out (N_out = N_p by default), assigned with periodic CiC from the core particles
 only; delta_out = count * (N_out/N_p)^3 - 1.
@@ -19,7 +22,7 @@ from .cosmology import Cosmology, cola_schedule
 from .lpt import lagrangian_potentials, displacement_vectors
 from .scola import cic_corners, evolve_box
 from .tiling import (boundary_potential0, box_indices, core_mask, extract_box_field,
-                     uniform_tiling)
+                     psi_at_particles, uniform_tiling)
 
 
 def setup_full_box(white_noise, L, cosmo, a_i, fda_order=2):
@@ -30,10 +33,11 @@ def setup_full_box(white_noise, L, cosmo, a_i, fda_order=2):
             displacement_vectors(phi2, fda_order))
 
 
-def box_inputs(psi1, psi2, phi1, tile, fda_order=2):
-    """Steps C.1-C.3 for one box: its Psi1, Psi2 and Phi_BC^0."""
+def box_inputs(psi1, psi2, phi1, tile, fda_order=2, Np=None):
+    """Steps C.1-C.3 for one box: its Psi1, Psi2 and Phi_BC^0.  psi1, psi2 are at the
+    lattice sites (N_p^3); phi1 is on the LPT grid (of N_p, or fewer nodes when Np says so)."""
     return (extract_box_field(psi1, tile), extract_box_field(psi2, tile),
-            boundary_potential0(phi1, tile, fda_order // 2))
+            boundary_potential0(phi1, tile, fda_order // 2, Np))
 
 
 def untile(tile, Np, box_out, key="u"):
@@ -56,18 +60,24 @@ def output_density(x_cells, Np, N_out):
 
 def run_scola(white_noise, L, tiles, cosmo=None, a_i=0.05, a_f=1.0, n_steps=10,
               want_momenta=False, N_out=None, tile_subset=None, discretisation="modified",
-              n_lpt=-2.5, tile_a_f=None, fda_order=2):
+              n_lpt=-2.5, tile_a_f=None, fda_order=2, Np=None):
     """Full tiled sCOLA run.  Returns dict with positions (3, Np, Np, Np) in Mpc/h in
     [0, L), momenta (or None) in Mpc/h (H0 = 1 units), the output density and the per-box
     raw results.  Entries of tiles outside tile_subset are left NaN in the outputs.
     discretisation, n_lpt: the time factors of App. B (see cola_schedule).
     tile_a_f: optional final scale factor per tile (Sec. 5.1: tiles need not share one final
     time; 0 or None entries mean a_f); each tile takes n_steps steps from a_i to its own.
-    fda_order: 2, 4 or 6, the order of every Laplacian and gradient (Sec. 3)."""
+    fda_order: 2, 4 or 6, the order of every Laplacian and gradient (Sec. 3).
+    Np: particles per side when the white noise lives on a coarser LPT grid (N = its side,
+    N_p / N an integer; Sec. 3.3 C.2 and Sec. 4): Psi is then interpolated to the particles
+    and Phi_BC^0 to the PM nodes (tiling.psi_at_particles, boundary_potential0_coarse)."""
     cosmo = cosmo or Cosmology()
-    Np = white_noise.shape[0]
+    N_lpt = white_noise.shape[0]
+    Np = Np or N_lpt
     N_out = N_out or Np
     phi1, phi2, psi1, psi2 = setup_full_box(white_noise, L, cosmo, a_i, fda_order)
+    if N_lpt != Np:
+        psi1, psi2 = psi_at_particles(psi1, Np), psi_at_particles(psi2, Np)
     steps, final = cola_schedule(cosmo, a_i, a_f, n_steps, want_final_kick=want_momenta,
                                  discretisation=discretisation, n_lpt=n_lpt)
     pos = np.full((3, Np, Np, Np), np.nan)
@@ -76,7 +86,7 @@ def run_scola(white_noise, L, tiles, cosmo=None, a_i=0.05, a_f=1.0, n_steps=10,
     subset = range(len(tiles)) if tile_subset is None else tile_subset
     for t in subset:
         tile = tiles[t]
-        s1, s2, bc0 = box_inputs(psi1, psi2, phi1, tile, fda_order)
+        s1, s2, bc0 = box_inputs(psi1, psi2, phi1, tile, fda_order, Np)
         st, fin = steps, final
         if tile_a_f is not None and tile_a_f[t] and tile_a_f[t] != a_f:
             st, fin = cola_schedule(cosmo, a_i, tile_a_f[t], n_steps,

@@ -74,11 +74,14 @@ def extract_box_field(field, tile):
     return field[..., ix[:, None, None], iy[None, :, None], iz[None, None, :]]
 
 
-def boundary_potential0(phi1, tile, ghosts=1):
+def boundary_potential0(phi1, tile, ghosts=1, Np=None):
     """Phi_BC^0 on the padded PM grid j in [-g, M+g]^3 (index j + g, g = N_ghost of the FDA
     order): the mean of phi1 over the 8 LPT nodes around each PM node.  Only the shell
-    outside [1, M-1]^3 is used; interior values are left at zero."""
+    outside [1, M-1]^3 is used; interior values are left at zero.  With an LPT grid coarser
+    than the lattice (Np given and larger than phi1's N), see boundary_potential0_coarse."""
     N = phi1.shape[0]
+    if Np is not None and Np != N:
+        return boundary_potential0_coarse(phi1, tile, Np, ghosts)
     M = tile.M
     g = ghosts
     j = np.arange(-g, M + g + 1)
@@ -101,3 +104,62 @@ def core_mask(tile):
     c = np.zeros(M, dtype=bool)
     c[tile.buffer:tile.buffer + tile.core_n] = True
     return c[:, None, None] & c[None, :, None] & c[None, None, :]
+
+
+# --- LPT grid coarser than the lattice (Sec. 3.3 C.2, Sec. 4: N = N_p / 2) ---------------
+def lpt_coordinate(x_cells, Np, N):
+    """Coordinate on the LPT grid of a lattice-cell position x: LPT node m sits at the centre
+    (m + 1/2) (N_p / N) of its coarse cell, so u = x N / N_p - 1/2 (N = N_p: u = x - 1/2)."""
+    return np.asarray(x_cells, dtype=np.float64) * (N / Np) - 0.5
+
+
+def cic_periodic_1d(u, N):
+    """(indices (2, n), weights (2, n)) of 1-D CiC on a periodic grid at coordinates u."""
+    j0 = np.floor(u).astype(np.int64)
+    f = u - j0
+    return np.stack([np.mod(j0, N), np.mod(j0 + 1, N)]), np.stack([1.0 - f, f])
+
+
+def interpolate_lpt_grid(field, points, Np):
+    """CiC (B-bar) of field [..., N, N, N] on the periodic LPT grid at lattice-cell positions
+    points (3, n); returns [..., n]."""
+    N = field.shape[-1]
+    idx = []
+    wts = []
+    for a in range(3):
+        i, w = cic_periodic_1d(lpt_coordinate(points[a], Np, N), N)
+        idx.append(i)
+        wts.append(w)
+    out = 0.0
+    for dx in (0, 1):
+        for dy in (0, 1):
+            for dz in (0, 1):
+                w = wts[0][dx] * wts[1][dy] * wts[2][dz]
+                out = out + w * field[..., idx[0][dx], idx[1][dy], idx[2][dz]]
+    return out
+
+
+def psi_at_particles(psi_grid, Np):
+    """Sec. 3.3 C.2: Psi = grad phi on the LPT grid (coarse-cell units, as
+    lpt.displacement_vectors returns it) interpolated by CiC to the Lagrangian lattice sites
+    q = i + 1/2 and converted to lattice cells (x N_p / N).  Shape (3, Np, Np, Np)."""
+    N = psi_grid.shape[-1]
+    i = np.arange(Np) + 0.5
+    q = np.stack(np.meshgrid(i, i, i, indexing="ij")).reshape(3, -1)
+    return (Np / N) * interpolate_lpt_grid(psi_grid, q, Np).reshape(psi_grid.shape[:-3] +
+                                                                     (Np, Np, Np))
+
+
+def boundary_potential0_coarse(phi1, tile, Np, ghosts=1):
+    """Phi_BC^0 with an LPT grid of N < N_p nodes: phi1 (coarse-cell^2 units) interpolated by
+    CiC to the padded PM nodes [-g, M+g]^3 at lattice-cell positions origin + j, converted
+    to lattice cells^2 (x (N_p / N)^2); interior values zero."""
+    N = phi1.shape[0]
+    M = tile.M
+    g = ghosts
+    j = np.arange(-g, M + g + 1)
+    X = [o + j for o in tile.origin]
+    pts = np.stack(np.meshgrid(X[0], X[1], X[2], indexing="ij")).reshape(3, -1).astype(float)
+    out = ((Np / N) ** 2 * interpolate_lpt_grid(phi1, pts, Np)).reshape((M + 1 + 2 * g,) * 3)
+    out[(slice(g + 1, g + M),) * 3] = 0.0
+    return out
