@@ -85,10 +85,14 @@ typedef struct {
 typedef struct {
   double L;                /* box side, Mpc/h, > 0 */
   int32_t Np;              /* particles per side; power of two in [8, 1024] */
-  int32_t N_lpt;           /* LPT grid nodes per side (Sec. 3.1, A.1: N); 0 -> N_p, the only
-                              grid implemented (its nodes coincide with the particles); a
-                              divisor of N_p such as N_p / 2 is refused with
-                              SCOLA_EUNSUPPORTED, anything else with SCOLA_EINVAL */
+  int32_t N_lpt;           /* LPT grid nodes per side (Sec. 3.1, A.1: N): 0 -> N_p (the nodes
+                              coincide with the particles), or a power-of-two divisor of N_p of
+                              at least 8, e.g. N_p / 2 as in Sec. 4 (node m at the cell centre
+                              (m + 1/2) L / N; Psi differenced on the grid and interpolated by
+                              CiC to the particles, Sec. 3.3 C.2; Phi_BC^0 interpolated by CiC
+                              to the PM nodes); anything else SCOLA_EINVAL.  The white noise
+                              lives on this grid.  scola_backward and scola_tcola_forward are
+                              built for N_lpt = N_p (SCOLA_EUNSUPPORTED otherwise) */
   int32_t N_out;           /* output density grid per side (0 -> N_p) */
   int32_t fda_order;       /* finite-difference order of every Laplacian and gradient (Sec. 3;
                               App. C.1-C.2): 2, 4 or 6 (0 -> 2, the order of Sec. 4's runs),
@@ -191,7 +195,7 @@ scola_status scola_workspace_layout(const scola_plan* plan, scola_layout* out);
  * tiles (Sec. 5.1, node failures: any tile can be recomputed alone, with bitwise the same
  * result as in the full run); other tiles' output entries are left untouched and the
  * density is not produced (d_density must then be NULL).
- * d_white_noise: double [N_p^3] unit white noise (Sec. 3.1, A.1).
+ * d_white_noise: double [N_lpt^3] unit white noise on the LPT grid (Sec. 3.1, A.1).
  * d_pos: R [3][N_p^3] final positions in [0, L) Mpc/h at the global lattice index.
  * d_mom: R [3][N_p^3] final momenta p = dx/da / drift_prefactor (Mpc/h, H0 = 1), or NULL;
  *        requires cfg.want_momenta.
@@ -221,7 +225,7 @@ scola_status scola_forward_noalloc(scola_plan* plan, const double* d_white_noise
                                    void* d_mom, void* d_density, hipStream_t stream);
 
 /* Reverse mode of scola_forward for a loss on the output density: given d loss / d delta_out
- * (R [N_out^3], device), writes d loss / d white noise (double [N_p^3], device).  Needs a
+ * (R [N_out^3], device), writes d loss / d white noise (double [N_lpt^3], device).  Needs a
  * plan with checkpoint_every > 0 and a preceding scola_forward over all tiles on the same
  * workspace (else SCOLA_ESTATE).  Segments of checkpoint_every steps are recomputed from
  * the checkpoints, then reversed step by step: transpose of the drift and kick, of the

@@ -99,7 +99,9 @@ class Simulation:
     discretisation: "modified" (App. B time factors with u = a^n_lpt) or "standard".
     fda_order: 2 (default), 4 or 6, the finite-difference order of every Laplacian and
     gradient (the reverse mode and the persistent step are built for order 2).
-    N_lpt, mesh: as in include/scola.h (only the defaults are implemented; other values raise
+    N_lpt: LPT grid nodes per side (default Np; or a power-of-two divisor such as Np // 2):
+    the white noise has N_lpt^3 entries (the reverse mode and tCOLA need N_lpt = Np).
+    mesh: as in include/scola.h (only the default is implemented; other values raise
     ScolaError with SCOLA_EUNSUPPORTED).
     """
 
@@ -124,6 +126,7 @@ class Simulation:
         self.tile_a_f = [float(t[3]) if len(t) > 3 else 0.0 for t in tiles]
         self.checkpoint_every = int(checkpoint_every)
         self.ghosts = (int(fda_order) or 2) // 2
+        self.N_lpt = int(N_lpt or Np)
         cfg = _config(L, Np, n_steps, a_i, a_f, precision, schedule, want_momenta, N_out,
                       checkpoint_every, discretisation, n_lpt, N_lpt, fda_order)
         cosmo = (cosmology or CosmologyParams()).c()
@@ -184,7 +187,7 @@ class Simulation:
             "dropped": (t.int64, (3 * len(self.tiles) + 1,)),
             # per brick of 256 particles: packed cell extent of its last deposit
             "cells": (t.int32, (P // 256, 4)),
-            "phi1": (t.float64, (N, N, N)), "phi2": (t.float64, (N, N, N)),
+            "phi1": (t.float64, (self.N_lpt,) * 3), "phi2": (t.float64, (self.N_lpt,) * 3),
             "outgrid": (t.int64, (self.N_out,) * 3),
         }[name]
         dtype, shape = spec
@@ -227,7 +230,7 @@ class Simulation:
                 if density and tile_subset is None else None)
         sub, n = self._subset(tile_subset)
         _lib.check(_lib.lib().scola_forward(
-            self._plan, self._ptr(white_noise, t.float64, (Np, Np, Np)),
+            self._plan, self._ptr(white_noise, t.float64, (self.N_lpt,) * 3),
             self._ptr(pos, self.real, pos.shape), self._ptr(mom, self.real, pos.shape)
             if mom is not None else None,
             self._ptr(dens, self.real, (self.N_out,) * 3) if dens is not None else None,
@@ -247,7 +250,7 @@ class Simulation:
         mom = t.empty_like(pos) if momenta else None
         dens = t.empty((self.N_out,) * 3, dtype=self.real, device=self.device) if density else None
         _lib.check(_lib.lib().scola_forward_noalloc(
-            self._plan, self._ptr(white_noise, t.float64, (Np, Np, Np)),
+            self._plan, self._ptr(white_noise, t.float64, (self.N_lpt,) * 3),
             self._ptr(pos, self.real, pos.shape),
             self._ptr(mom, self.real, pos.shape) if mom is not None else None,
             self._ptr(dens, self.real, (self.N_out,) * 3) if dens is not None else None,
@@ -277,7 +280,7 @@ class Simulation:
             rd = t.empty((n_force, Np, Np, Np), dtype=self.real, device=self.device)
             rp = t.empty_like(rd)
         _lib.check(_lib.lib().scola_tcola_forward(
-            self._plan, self._ptr(white_noise, t.float64, (Np, Np, Np)),
+            self._plan, self._ptr(white_noise, t.float64, (self.N_lpt,) * 3),
             self._ptr(pos, self.real, pos.shape),
             self._ptr(mom, self.real, pos.shape) if mom is not None else None,
             self._ptr(dens, self.real, (self.N_out,) * 3) if dens is not None else None,
@@ -290,7 +293,7 @@ class Simulation:
         """d loss / d white noise (float64, [Np]^3) for d loss / d density (plan dtype,
         [N_out]^3); needs checkpoint_every > 0 and a preceding forward()."""
         t = self.torch
-        grad_w = t.empty((self.Np,) * 3, dtype=t.float64, device=self.device)
+        grad_w = t.empty((self.N_lpt,) * 3, dtype=t.float64, device=self.device)
         _lib.check(_lib.lib().scola_backward(
             self._plan, self._ptr(grad_density.contiguous(), self.real, (self.N_out,) * 3),
             self._ptr(grad_w, t.float64, grad_w.shape), self._ws, self._stream()))
@@ -299,7 +302,7 @@ class Simulation:
     def setup(self, white_noise):
         t = self.torch
         _lib.check(_lib.lib().scola_setup(
-            self._plan, self._ptr(white_noise, t.float64, (self.Np,) * 3), self._ws,
+            self._plan, self._ptr(white_noise, t.float64, (self.N_lpt,) * 3), self._ws,
             self._stream()))
 
     def evolve(self, tile_subset=None):

@@ -40,9 +40,10 @@ struct BoxSetupArgs {
   void* psi1;               // [3][P] in the plan precision
   void* psi2;
   double* bc0;
-  int N;
+  int N;                    // LPT grid nodes per side
   int64_t P;
   int ng = 1;               // finite differences of order 2 ng; Phi_BC^0 on [-ng, M+ng]^3
+  int Np = 0;               // lattice particles per side (a multiple of N)
 };
 
 template <typename T>

@@ -208,15 +208,19 @@ __global__ void k_second_order_source(const double* __restrict__ phi, double2* _
   out[i] = make_double2(s, 0.0);
 }
 
-// C.1-C.2: Psi1 = D phi1 and Psi2 = D phi2 at every box particle (LPT nodes coincide with
-// the particles, so no interpolation); also the operator L- (x_res = p_res = 0).
+// C.1-C.2: Psi1 = D phi1 and Psi2 = D phi2 at every box particle; also the operator L-
+// (x_res = p_res = 0).  With an LPT grid of N = Np nodes per side the nodes coincide with
+// the particles (no interpolation); with N < Np (Np / N an integer) the node m sits at the
+// centre (m + 1/2) Np / N of its cell, the gradient is taken at the 8 nodes around the
+// particle's LPT coordinate u = (g + 1/2) N / Np - 1/2 and interpolated by CiC, then
+// converted from LPT-grid cells to lattice cells (x Np / N).
 template <typename T>
 __global__ void k_extract_psi(const TileDesc* __restrict__ tiles,
                               const int* __restrict__ blk_tile, const int* __restrict__ blk_first,
                               const double* __restrict__ phi1, const double* __restrict__ phi2,
                               T* __restrict__ psi1, T* __restrict__ psi2,
                               T* __restrict__ xres, T* __restrict__ pres, int N, int64_t P,
-                              int ng) {
+                              int ng, int Np) {
   const TileDesc t = tiles[blk_tile[blockIdx.x]];
   const int64_t pl = (int64_t)blk_first[blockIdx.x] * kBlock + threadIdx.x;
   const int M = t.M;
@@ -224,12 +228,49 @@ __global__ void k_extract_psi(const TileDesc* __restrict__ tiles,
   if (pl >= M3) return;
   int i, j, k;
   brick_site(pl, M, i, j, k);
-  const int gx = wrap(t.origin[0] + i, N), gy = wrap(t.origin[1] + j, N),
-            gz = wrap(t.origin[2] + k, N);
   auto at = [&](const double* f, int x, int y, int z) {
     return f[((int64_t)wrap(x, N) * N + wrap(y, N)) * N + wrap(z, N)];
   };
   const int64_t p = t.p_off + pl;
+  if (N != Np) {
+    const int g[3] = {wrap(t.origin[0] + i, Np), wrap(t.origin[1] + j, Np),
+                      wrap(t.origin[2] + k, Np)};
+    const double r = (double)N / (double)Np;
+    int m0[3];
+    double w[3][2];
+    for (int c = 0; c < 3; ++c) {
+      const double u = ((double)g[c] + 0.5) * r - 0.5;
+      const double fl = floor(u);
+      m0[c] = (int)fl;
+      w[c][1] = u - fl;
+      w[c][0] = 1.0 - w[c][1];
+    }
+    double s1[3] = {0.0, 0.0, 0.0}, s2[3] = {0.0, 0.0, 0.0};
+    for (int cn = 0; cn < 8; ++cn) {
+      const int dx = (cn >> 2) & 1, dy = (cn >> 1) & 1, dz = cn & 1;
+      const double wc = w[0][dx] * w[1][dy] * w[2][dz];
+      const int x = m0[0] + dx, y = m0[1] + dy, z = m0[2] + dz;
+      for (int kk = 1; kk <= ng; ++kk) {
+        const double c = wc * d1_weight(ng, kk);
+        s1[0] += c * (at(phi1, x + kk, y, z) - at(phi1, x - kk, y, z));
+        s1[1] += c * (at(phi1, x, y + kk, z) - at(phi1, x, y - kk, z));
+        s1[2] += c * (at(phi1, x, y, z + kk) - at(phi1, x, y, z - kk));
+        s2[0] += c * (at(phi2, x + kk, y, z) - at(phi2, x - kk, y, z));
+        s2[1] += c * (at(phi2, x, y + kk, z) - at(phi2, x, y - kk, z));
+        s2[2] += c * (at(phi2, x, y, z + kk) - at(phi2, x, y, z - kk));
+      }
+    }
+    const double scale = (double)Np / (double)N;
+    for (int c = 0; c < 3; ++c) {
+      psi1[c * P + p] = (T)(scale * s1[c]);
+      psi2[c * P + p] = (T)(scale * s2[c]);
+      xres[c * P + p] = T(0);
+      pres[c * P + p] = T(0);
+    }
+    return;
+  }
+  const int gx = wrap(t.origin[0] + i, N), gy = wrap(t.origin[1] + j, N),
+            gz = wrap(t.origin[2] + k, N);
   // differenced in FP64, stored in the plan precision (FP32 plans keep the paper's
   // single-precision particle record)
   if (ng == 1) {
@@ -262,11 +303,11 @@ __global__ void k_extract_psi(const TileDesc* __restrict__ tiles,
 }
 
 // C.3: Phi_BC^0 at the padded PM nodes j in [-ng, M+ng]^3 outside [1, M-1]^3: trilinear
-// interpolation of phi1 at the PM node, i.e. the mean of the 8 LPT nodes around it (PM
-// nodes sit half a cell from the LPT nodes).  Interior entries are set to zero.
+// interpolation of phi1 at the PM node, i.e. with N = Np the mean of the 8 LPT nodes around
+// it (PM nodes sit half a cell from the LPT nodes).  Interior entries are set to zero.
 __global__ void k_boundary_potential(const TileDesc* __restrict__ tiles, int n_tiles,
                                      const double* __restrict__ phi1, double* __restrict__ bc0,
-                                     int N, int ng) {
+                                     int N, int ng, int Np) {
   const int ti = blockIdx.y;
   if (ti >= n_tiles) return;
   const TileDesc t = tiles[ti];
@@ -279,7 +320,28 @@ __global__ void k_boundary_potential(const TileDesc* __restrict__ tiles, int n_t
     double v = 0.0;
     const bool inside = a >= 1 && a <= t.M - 1 && b >= 1 && b <= t.M - 1 && c >= 1 &&
                         c <= t.M - 1;
-    if (!inside) {
+    if (!inside && N != Np) {
+      // LPT grid coarser than the lattice: CiC at the node's LPT coordinate X N / Np - 1/2,
+      // converted from LPT-grid cells^2 to lattice cells^2
+      const double r = (double)N / (double)Np;
+      const int X[3] = {t.origin[0] + a, t.origin[1] + b, t.origin[2] + c};
+      int m0[3];
+      double w[3][2];
+      for (int d = 0; d < 3; ++d) {
+        const double u = (double)X[d] * r - 0.5;
+        const double fl = floor(u);
+        m0[d] = (int)fl;
+        w[d][1] = u - fl;
+        w[d][0] = 1.0 - w[d][1];
+      }
+      for (int cn = 0; cn < 8; ++cn) {
+        const int dx = (cn >> 2) & 1, dy = (cn >> 1) & 1, dz = cn & 1;
+        v += w[0][dx] * w[1][dy] * w[2][dz] *
+             phi1[((int64_t)wrap(m0[0] + dx, N) * N + wrap(m0[1] + dy, N)) * N +
+                  wrap(m0[2] + dz, N)];
+      }
+      v *= ((double)Np / (double)N) * ((double)Np / (double)N);
+    } else if (!inside) {
       const int gx = t.origin[0] + a, gy = t.origin[1] + b, gz = t.origin[2] + c;
       for (int dx = -1; dx <= 0; ++dx)
         for (int dy = -1; dy <= 0; ++dy)
@@ -363,9 +425,9 @@ hipError_t launch_setup_boxes(const BoxSetupArgs& a, T* xres, T* pres, hipStream
     hipLaunchKernelGGL(k_extract_psi<T>, dim3(a.n_blocks), dim3(kBlock), 0, s, a.tiles,
                        a.blk_tile, a.blk_first, a.phi1, a.phi2, static_cast<T*>(a.psi1),
                        static_cast<T*>(a.psi2), xres, pres,
-                       a.N, a.P, a.ng);
+                       a.N, a.P, a.ng, a.Np);
   hipLaunchKernelGGL(k_boundary_potential, dim3(64, a.n_tiles), dim3(kBlock), 0, s, a.tiles,
-                     a.n_tiles, a.phi1, a.bc0, a.N, a.ng);
+                     a.n_tiles, a.phi1, a.bc0, a.N, a.ng, a.Np);
   return hipGetLastError();
 }
 

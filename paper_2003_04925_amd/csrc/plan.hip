@@ -117,6 +117,7 @@ struct scola_plan {
   int graph_eager_calls = 0;
   bool is64 = false;
   int ng = 1;                         // ghost layers: finite differences of order 2 ng
+  int N_lpt = 0;                      // LPT grid nodes per side (Np or a divisor of it)
   // one persistent cooperative launch per KDK step and class instead of four launches
   bool persistent = false;
   unsigned* d_barrier = nullptr;      // arrival counter + sticky failure flag
@@ -213,10 +214,9 @@ void validate(const scola_config& c, const scola_cosmology& cs, const scola_tile
     fail(SCOLA_EINVAL, "schedule must be SCOLA_BATCHED or SCOLA_PER_TILE");
   if (c.checkpoint_every < 0) fail(SCOLA_EINVAL, "checkpoint_every must be >= 0");
   if (c.N_lpt != 0 && c.N_lpt != c.Np) {
-    if (c.N_lpt > 0 && c.N_lpt < c.Np && c.Np % c.N_lpt == 0)
-      fail(SCOLA_EUNSUPPORTED, "N_lpt = " + std::to_string(c.N_lpt) +
-                                   ": only an LPT grid with N_lpt = Np nodes is implemented");
-    fail(SCOLA_EINVAL, "N_lpt must be 0, Np or a divisor of Np");
+    // a coarser LPT grid: a power-of-two divisor of Np (its FFTs are radix 2) of >= 8 nodes
+    if (!(c.N_lpt >= 8 && c.N_lpt < c.Np && is_pow2(c.N_lpt) && c.Np % c.N_lpt == 0))
+      fail(SCOLA_EINVAL, "N_lpt must be 0, Np or a power-of-two divisor of Np of at least 8");
   }
   if (c.fda_order != 0 && c.fda_order != 2 && c.fda_order != 4 && c.fda_order != 6)
     fail(SCOLA_EINVAL, "fda_order must be 0, 2, 4 or 6");
@@ -397,9 +397,10 @@ void build_layout(scola_plan* p) {
   // found and the number of deposits (the mass identity of FP32 plans)
   l.dropped = take((3 * p->desc.size() + 1) * 8);
   l.cells = take((size_t)(p->P / kBlock) * 16);   // per brick: packed cell extent
-  l.phi1 = take((size_t)(N * N * N) * 8);
-  l.phi2 = take((size_t)(N * N * N) * 8);
-  l.cbuf = take((size_t)(N * N * N) * 16);
+  const size_t NL = (size_t)p->N_lpt;   // the set-up fields live on the LPT grid
+  l.phi1 = take(NL * NL * NL * 8);
+  l.phi2 = take(NL * NL * NL * 8);
+  l.cbuf = take(NL * NL * NL * 16);
   l.outgrid = take((size_t)(No * No * No) * 8);
   const int c = p->cfg.checkpoint_every;
   if (c > 0) {
@@ -727,7 +728,7 @@ SetupArgs setup_args(scola_plan* p, const double* w, void* ws) {
   a.cbuf = reinterpret_cast<double2*>(ws_ptr(ws, p->lay.cbuf));
   a.phi1 = reinterpret_cast<double*>(ws_ptr(ws, p->lay.phi1));
   a.phi2 = reinterpret_cast<double*>(ws_ptr(ws, p->lay.phi2));
-  a.N = p->cfg.Np;
+  a.N = p->N_lpt;
   a.L = p->cfg.L;
   a.amplitude = p->bg.amplitude;
   a.ns = p->bg.ns;
@@ -755,9 +756,10 @@ BoxSetupArgs box_setup_args(scola_plan* p, void* ws) {
   b.psi1 = ws_ptr(ws, p->lay.psi1);
   b.psi2 = ws_ptr(ws, p->lay.psi2);
   b.bc0 = reinterpret_cast<double*>(ws_ptr(ws, p->lay.bc0));
-  b.N = p->cfg.Np;
+  b.N = p->N_lpt;
   b.P = p->P;
   b.ng = p->ng;
+  b.Np = p->cfg.Np;
   return b;
 }
 
@@ -1460,6 +1462,7 @@ scola_status scola_plan_create(const scola_config* cfg, const scola_cosmology* c
     p->cosmo = *cosmo;
     p->is64 = cfg->precision == SCOLA_FP64;
     p->ng = p->cfg.fda_order > 0 ? p->cfg.fda_order / 2 : 1;
+    p->N_lpt = p->cfg.N_lpt > 0 ? p->cfg.N_lpt : p->cfg.Np;
     p->tiles.assign(tiles, tiles + n_tiles);
     hip_check(hipGetDevice(&p->device), "hipGetDevice");
     p->bg = background_of(*cosmo);
@@ -1807,6 +1810,8 @@ scola_status scola_backward(scola_plan* p, const void* grad_density, double* gra
       fail(SCOLA_EUNSUPPORTED, "the reverse mode needs one final scale factor for all tiles");
     if (p->ng != 1)
       fail(SCOLA_EUNSUPPORTED, "the reverse mode is built for finite differences of order 2");
+    if (p->N_lpt != p->cfg.Np)
+      fail(SCOLA_EUNSUPPORTED, "the reverse mode is built for an LPT grid of Np nodes per side");
     if (p->is64)
       do_backward<double>(p, reinterpret_cast<const double*>(grad_density), grad_w, ws, s);
     else
@@ -1946,6 +1951,8 @@ scola_status scola_tcola_forward(scola_plan* p, const double* w, void* pos, void
     check_ws(p, ws);
     if (!w) fail(SCOLA_EINVAL, "white noise is NULL");
     if (mom && !p->cfg.want_momenta) fail(SCOLA_EINVAL, "d_mom needs cfg.want_momenta");
+    if (p->N_lpt != p->cfg.Np)
+      fail(SCOLA_EUNSUPPORTED, "tCOLA is built for an LPT grid of Np nodes per side");
     if (p->is64)
       do_tcola<double>(p, w, pos, mom, dens, rec_delta, rec_phi, ws, s);
     else

@@ -544,10 +544,12 @@ __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const Blo
   const double* bc = a.bc0 + t.h_off;
   const double D1 = a.D1_bc;
   if constexpr (ADJ) {
+    const T* const wk = a.work + base;
 #pragma unroll 8
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) plane[e] = a.work[base + e];
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) plane[e] = wk[e];
   } else {
     using Rho = typename MeshFixed<T>::rho_t;
+    Rho* const rp = a.rho + base;   // the plane's first node (block-uniform)
     constexpr int kBatch = 16;   // independent loads in flight per thread
     constexpr double kUnit = 1.0 / (double)(1ll << MeshFixed<T>::bits);
     // delta' = delta - Delta Phi_BCs (App. C.1): an interior node next to a face takes
@@ -587,13 +589,13 @@ __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const Blo
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
         const int e = e0 + q * kBlock + threadIdx.x;
-        r[q] = e < n * n ? a.rho[base + e] : Rho(0);
+        r[q] = e < n * n ? rp[e] : Rho(0);
       }
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
         const int e = e0 + q * kBlock + threadIdx.x;
         if (e >= n * n) continue;
-        a.rho[base + e] = Rho(0);
+        rp[e] = Rho(0);
         if constexpr (std::is_same<T, float>::value) {
           near += r[q] >> 31;
           found += r[q];
@@ -665,7 +667,8 @@ __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const Blo
   }
   __syncthreads();
   plane_dst<R, T>(plane, tw);
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) a.work[base + e] = plane[e];
+  T* const wk = a.work + base;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) wk[e] = plane[e];
 }
 
 template <int R, typename T>
@@ -711,18 +714,21 @@ __device__ __forceinline__ void poisson_p2_block(const MeshArgs<T>& a, const Blo
   static_assert(kPencilChunk == 32 && kBlock == 256, "eight rows of 32 columns per sweep");
   const int zc = threadIdx.x & 31, x0 = threadIdx.x >> 5;
   const bool zin = zc < cw;
-  T* col = a.work + t.g_off + (int64_t)y * n + z0 + zc;
+  // the chunk's first column (block-uniform) plus the thread's 32-bit offset; each sweep of
+  // eight rows adds a uniform 8 n^2
+  T* const col = a.work + t.g_off + (int64_t)y * n + z0;
+  const int lo = x0 * n * n + zc;
 #pragma unroll
   for (int i = 0; i < (n + 7) / 8; ++i) {
     const int x = x0 + 8 * i;
-    if (zin && x < n) tile[x * pitch + zc] = col[(int64_t)x * n * n];
+    if (zin && x < n) tile[x * pitch + zc] = (col + (int64_t)8 * i * n * n)[lo];
   }
   __syncthreads();
   pencil_solve<R, T>(tile, cw, y, z0, ev, tw);
 #pragma unroll
   for (int i = 0; i < (n + 7) / 8; ++i) {
     const int x = x0 + 8 * i;
-    if (zin && x < n) col[(int64_t)x * n * n] = tile[x * pitch + zc];
+    if (zin && x < n) (col + (int64_t)8 * i * n * n)[lo] = tile[x * pitch + zc];
   }
 }
 
@@ -810,8 +816,9 @@ __device__ __forceinline__ void poisson_p3_block(const MeshArgs<T>& a, const Blo
       if (iz >= 0) oz = lb[iz];
     }
   }
+  const T* const wk = a.work + base;
 #pragma unroll 8
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) plane[e] = a.work[base + e];
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) plane[e] = wk[e];
   if constexpr (!ADJ) {
 #pragma unroll
     for (int q = 0; q < kPerThread; ++q) {
@@ -829,9 +836,11 @@ __device__ __forceinline__ void poisson_p3_block(const MeshArgs<T>& a, const Blo
   if constexpr (ADJ) {
     // lam_rho = lam_delta', and the plane of `work` is cleared (the next reverse step
     // accumulates into a zeroed source)
+    T* const lr = a.lam_rho + base;
+    T* const wz = a.work + base;
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-      a.lam_rho[base + e] = plane[e];
-      a.work[base + e] = T(0);
+      lr[e] = plane[e];
+      wz[e] = T(0);
     }
     if (xface) {
       for (int e = threadIdx.x; e < n * n; e += blockDim.x) {

@@ -107,12 +107,12 @@ def test_config_and_tile_fields_accept_and_refuse():
         assert _validated(_plan_status(L_, fda_order=o)[0])
     for o in (3, 8, -2):
         assert _plan_status(L_, fda_order=o)[0] == -1
-    # N_lpt: 0 and Np accepted, a divisor unsupported, anything else invalid
-    for n in (0, 32):
+    # N_lpt: 0, Np and power-of-two divisors of Np >= 8 accepted, anything else invalid
+    for n in (0, 32, 16, 8):
         assert _validated(_plan_status(L_, N_lpt=n)[0])
-    st, msg = _plan_status(L_, N_lpt=16)
-    assert st == -5 and "N_lpt" in msg
-    assert _plan_status(L_, N_lpt=7)[0] == -1
+    for n in (7, 4, 64, 24, -16):
+        st, msg = _plan_status(L_, N_lpt=n)
+        assert st == -1 and "N_lpt" in msg
     # n_lpt: any finite value; the discretisation switch
     assert _validated(_plan_status(L_, n_lpt=-1.5)[0])
     assert _plan_status(L_, n_lpt=float("nan"))[0] == -1
