@@ -937,7 +937,9 @@ void do_evolve(scola_plan* p, const std::vector<int>& tiles, void* ws, hipStream
     }
     if (p->cfg.want_momenta) r.particles_step(kFinalKick, n);
   };
-  const int G = batched && allow_groups ? std::min<int>(p->groups, (int)tiles.size()) : 1;
+  // the persistent step runs every class on the caller's stream (one group)
+  const int G = batched && allow_groups && !p->persistent
+                    ? std::min<int>(p->groups, (int)tiles.size()) : 1;
   if (batched && G > 1) {
     // G shares of every size class advance concurrently on G streams, so one share's
     // Poisson passes overlap another share's particle kernel
