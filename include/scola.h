@@ -144,10 +144,15 @@ typedef struct {
                               scola_evolve and scola_op_deposit reset all; scola_mass_alarm
                               evaluates them. */
   size_t cells;            /* uint32 [P / 256][4]: per brick of 256 particles (lattice order
-                              within a box), the block cell extent of its last deposit, packed;
-                              the force pass of the next step tries it before reducing the
-                              extent itself.  Any content is valid: a stale entry costs time
-                              and changes no result. */
+                              within a box), words 0-2: the block cell extent of its last
+                              deposit, packed; the force pass of the next step tries it before
+                              reducing the extent itself.  Any content there is valid: a stale
+                              entry costs time and changes no result.  Word 3, FP32 plans: the
+                              mass the brick's last deposit dropped, which the Poisson pass
+                              consuming that deposit (within scola_op_deposit and
+                              scola_op_step, the call itself) adds to `dropped` and clears; it
+                              is 0 between calls, and a value written there is counted as
+                              dropped mass by the next Poisson pass. */
   size_t phi1, phi2;       /* double [N^3]: Lagrangian potentials (Sec. 3.1, A.2) */
   size_t cbuf;             /* double2 [N^3]: FFT scratch */
   size_t outgrid;          /* int64 [N_out^3]: fixed-point output density */

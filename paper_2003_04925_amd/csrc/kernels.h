@@ -52,6 +52,11 @@ struct MeshArgs {
   typename MeshFixed<T>::rho_t* rho;   // fixed-point mass
   unsigned long long* alarm;           // count of FP32-plan node visits finding >= 2^31 units
   unsigned long long* kept;            // FP32 plans: per tile, the mass the passes found
+  // FP32 plans: the per-tile dropped mass, and the particle bricks' hints (four words per
+  // brick of 256 particles), whose word 3 holds the mass the brick's last deposit dropped
+  // until the pass consuming that deposit folds it into `dropped` and clears it
+  unsigned long long* dropped;
+  unsigned* hints;
   T* work;
   T* phi;
   const double* bc0;
@@ -84,9 +89,10 @@ struct ParticleArgs {
   typename MeshFixed<T>::rho_t* rho;
   unsigned long long* dropped;
   unsigned long long* deposits;   // FP32 plans: deposits per tile (for the mass identity)
-  // per brick of 256 particles: the packed cell extent of its last deposit, written by
-  // every depositing launch and, with use_hints, tried by the force pass before it
-  // reduces the extent itself (a stale entry costs time, never a result)
+  // per brick of 256 particles: the packed cell extent of its last deposit (words 0-2),
+  // written by every depositing launch and, with use_hints, tried by the force pass before
+  // it reduces the extent itself (a stale entry costs time, never a result); word 3 holds,
+  // in FP32 plans, the mass the deposit dropped until the Poisson pass folds it
   uint4* cells;
   int use_hints;
   int64_t P;
@@ -153,6 +159,10 @@ hipError_t launch_particles(const ParticleArgs<T>& a, int mode, const BlockMap& 
                             hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
 hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t s);
+// Folds word 3 of the bricks' hints (FP32 deposits' dropped mass) of tiles [0, n_tiles)
+// into dropped[tile] and clears it: for a deposit that no Poisson pass consumes.
+hipError_t launch_fold_drops(const TileDesc* tiles, int n_tiles, unsigned* hints,
+                             unsigned long long* dropped, hipStream_t s);
 template <typename T>
 hipError_t launch_output(const OutputArgs<T>& a, const BlockMap& m, bool density,
                          T* density_out, hipStream_t s);

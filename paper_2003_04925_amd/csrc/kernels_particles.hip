@@ -128,7 +128,32 @@ __global__ void k_density_convert(const unsigned long long* __restrict__ grid, T
     out[i] = (T)((double)(long long)grid[i] * kFixedInv * scale - 1.0);
 }
 
+// One block per tile: the dropped mass of the tile's bricks (word 3 of each brick's hint,
+// left by an FP32 deposit) summed into the tile's counter, and the words cleared.
+__global__ void k_fold_drops(const TileDesc* __restrict__ tiles, unsigned* hints,
+                             unsigned long long* dropped) {
+  const TileDesc t = tiles[blockIdx.x];
+  const int64_t b0 = t.p_off / kBlock, nb = (int64_t)t.M * t.M * t.M / kBlock;
+  unsigned long long d = 0;
+  for (int64_t e = threadIdx.x; e < nb; e += blockDim.x) {
+    unsigned* w = hints + 4 * (b0 + e) + 3;
+    d += *w;
+    *w = 0u;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) d += __shfl_xor(d, o);
+  if ((threadIdx.x & 63) == 0 && d != 0ull) atomicAdd(dropped + blockIdx.x, d);
+}
+
 }  // namespace
+
+hipError_t launch_fold_drops(const TileDesc* tiles, int n_tiles, unsigned* hints,
+                             unsigned long long* dropped, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_drops, dim3((unsigned)n_tiles), dim3(kBlock), 0, s, tiles, hints,
+                     dropped);
+  return hipGetLastError();
+}
 
 hipError_t launch_zero_u32(unsigned* p, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;

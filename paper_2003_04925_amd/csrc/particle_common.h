@@ -46,6 +46,16 @@ __device__ __forceinline__ int wave_max(int v) {
              max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
+// Wave-wide sum of an unsigned value (no wrap-around assumed), uniform across the wave.
+__device__ __forceinline__ unsigned wave_sum(unsigned v) {
+  v += (unsigned)lane_xor<1>((int)v);
+  v += (unsigned)lane_xor<2>((int)v);
+  v += (unsigned)lane_xor<4>((int)v);
+  v += (unsigned)lane_xor<8>((int)v);
+  return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
+         __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
+}
+
 constexpr int kWindow = 4096;   // LDS window entries per block (potential or mass)
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));

@@ -48,10 +48,13 @@ __device__ inline bool deposit_footprint(int M, double ux, double uy, double uz,
 // B^sCOLA for the 256 particles of one block (one Lagrangian brick): CiC of every particle
 // onto interior nodes [1, M-1]^3 of its box, privatised in an LDS window that covers the
 // block's Eulerian footprint, then one global atomic per touched interior node.  Integer
-// sums make every window form give identical results.  Returns the fixed-point mass this
-// thread dropped (the eight weights sum to exactly one unit, so dropped = unit - kept).
-// When hint_out is not null, the block's packed cell extent is stored there for the force
-// pass at the same positions.  Must be called by all threads of the block.
+// sums make every window form give identical results.  The block's packed cell extent is
+// stored at hint_out (words 0-2) for the force pass at the same positions.  The mass a
+// particle drops is one unit minus what it keeps (the eight weights sum to exactly one
+// unit).  FP32 plans store the block's total (at most 256 x 2^21 units) in word 3 of
+// hint_out, for the Poisson pass that consumes this deposit to fold into the box's counter,
+// and return 0; FP64 plans store 0 there and return this thread's dropped mass.  Must be
+// called by all threads of the block.
 template <typename T>
 __device__ __forceinline__ long long deposit_block(typename MeshFixed<T>::rho_t* __restrict__ rho, int M,
                                           bool active, double ux, double uy, double uz,
@@ -78,20 +81,39 @@ __device__ __forceinline__ long long deposit_block(typename MeshFixed<T>::rho_t*
     for (int c = 0; c < 8; ++c)
       if (inner[0][(c >> 2) & 1] && inner[1][(c >> 1) & 1] && inner[2][c & 1]) kept += w[c];
   }
-  const long long dropped = active ? (1ll << MeshFixed<T>::bits) - (long long)kept : 0;
+  long long dropped = active ? (1ll << MeshFixed<T>::bits) - (long long)kept : 0;
+  constexpr bool kBlockDrop = MeshFixed<T>::bits < 32;
+  if constexpr (kBlockDrop) {
+    // the wave's dropped mass in the slot that block_cells leaves free (read after its
+    // barrier): no atomics on the box's counter, whose word all blocks of the box share
+    const unsigned d = wave_sum((unsigned)dropped);
+    if ((threadIdx.x & 63) == 0) bounds[3 * kWaves + (threadIdx.x >> 6)] = (int)d;
+    dropped = 0;
+  }
+  // the whole LDS window (every form below uses at most kWindow entries) is cleared before
+  // the barrier of the extent reduction, which then also orders the clearing before the
+  // accumulation; the caller's last use of the window ended at a barrier
+  {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int xi = 0; xi < kFw; ++xi) win[t + kFwX * xi] = W(0);
+  }
   unsigned q[3];
   const CellRange cr = block_cells(in, j0, bounds, q);
-  if (hint_out != nullptr && threadIdx.x == 0) *hint_out = make_uint4(q[0], q[1], q[2], 0u);
+  if (threadIdx.x == 0) {
+    unsigned bd = 0u;
+    if constexpr (kBlockDrop) {
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) bd += (unsigned)bounds[3 * kWaves + w];
+    }
+    *hint_out = make_uint4(q[0], q[1], q[2], bd);
+  }
   if (!cr.any) return dropped;
   // the corners of the block's particles span [min j0, max j0 + 1] per axis
   const int ox = cr.lo[0], oy = cr.lo[1], oz = cr.lo[2];
   const int ex = cr.hi[0] - ox + 2, ey = cr.hi[1] - oy + 2, ez = cr.hi[2] - oz + 2;
   if (ex <= kFw && ey <= kFw && ez <= kFw) {
     const int t = threadIdx.x, ty = t / kFw, tz = t % kFw;
-#pragma unroll
-    for (int xi = 0; xi < kFw; ++xi)
-      if (xi < ex) win[t + kFwX * xi] = W(0);
-    __syncthreads();
     if (in) {
       // all eight corners go to the window; only interior nodes are flushed
       W* wp = win + (j0[0] - ox) * kFwX + (j0[1] - oy) * kFwY + (j0[2] - oz);
@@ -131,10 +153,6 @@ __device__ __forceinline__ long long deposit_block(typename MeshFixed<T>::rho_t*
   const int wx = hx - lx + 1, wy = hy - ly + 1, wz = hz - lz + 1;
   const int wyz = wy * wz, vol = wx * wyz;
   const bool use_lds = vol <= kWindow;
-  if (use_lds) {
-    for (int e = threadIdx.x; e < vol; e += blockDim.x) win[e] = W(0);
-    __syncthreads();
-  }
   if (in) {
     // window index of corner (0, 0, 0); interior corners add dx wyz + dy wz + dz
     const int base = ((j0[0] - lx) * wy + (j0[1] - ly)) * wz + (j0[2] - lz);
@@ -605,14 +623,21 @@ __device__ __forceinline__ void particles_block(const ParticleArgs<T>& a, const 
 #pragma unroll
     for (int c = 0; c < 3; ++c) u[c] = un[c] + (double)xr[c];
   }
-  __shared__ unsigned long long block_drop;
-  if (threadIdx.x == 0) block_drop = 0ull;
-  const long long drop = deposit_block<T>(a.rho + t.g_off, M, true, u[0], u[1], u[2],
-                                          reinterpret_cast<typename MeshFixed<T>::window_t*>(win),
-                                          bounds, hint);
-  if (drop != 0) atomicAdd(&block_drop, (unsigned long long)drop);
-  __syncthreads();
-  if (threadIdx.x == 0 && block_drop != 0ull) atomicAdd(a.dropped + ti, block_drop);
+  if constexpr (MeshFixed<T>::bits < 32) {
+    // FP32: the block's dropped mass travels in its hint (folded by the Poisson pass)
+    deposit_block<T>(a.rho + t.g_off, M, true, u[0], u[1], u[2],
+                     reinterpret_cast<typename MeshFixed<T>::window_t*>(win), bounds, hint);
+  } else {
+    __shared__ unsigned long long block_drop;
+    if (threadIdx.x == 0) block_drop = 0ull;
+    const long long drop =
+        deposit_block<T>(a.rho + t.g_off, M, true, u[0], u[1], u[2],
+                         reinterpret_cast<typename MeshFixed<T>::window_t*>(win), bounds, hint);
+    // one atomic per block on the box's counter, which all blocks of the box share
+    if (drop != 0) atomicAdd(&block_drop, (unsigned long long)drop);
+    __syncthreads();
+    if (threadIdx.x == 0 && block_drop != 0ull) atomicAdd(a.dropped + ti, block_drop);
+  }
   // FP32 plans count the deposits of every box (its first block, once per launch) for the
   // mass identity that detects a wrapped 32-bit node (see the Poisson pass)
   if constexpr (MeshFixed<T>::bits < 32)

@@ -463,6 +463,16 @@ std::vector<int> subset_list(const scola_plan* p, const int32_t* subset, int32_t
   return out;
 }
 
+// FP32 deposits leave each brick's dropped mass in word 3 of its hint for the Poisson pass
+// that consumes them; a deposit that no pass follows (the operator-level calls) folds it
+// into the per-tile counters here.
+void fold_drops(scola_plan* p, void* ws, hipStream_t s) {
+  hip_check(launch_fold_drops(p->d_tiles, (int)p->desc.size(),
+                              reinterpret_cast<unsigned*>(ws_ptr(ws, p->lay.cells)),
+                              reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped)),
+                              s), "fold dropped mass");
+}
+
 template <typename T>
 MeshArgs<T> mesh_args(scola_plan* p, void* ws, double D1_bc) {
   MeshArgs<T> a;
@@ -470,6 +480,8 @@ MeshArgs<T> mesh_args(scola_plan* p, void* ws, double D1_bc) {
   a.rho = reinterpret_cast<typename MeshFixed<T>::rho_t*>(ws_ptr(ws, p->lay.rho));
   a.alarm = reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped)) + p->desc.size();
   a.kept = a.alarm + 1;
+  a.dropped = a.alarm - p->desc.size();
+  a.hints = reinterpret_cast<unsigned*>(ws_ptr(ws, p->lay.cells));
   a.work = reinterpret_cast<T*>(ws_ptr(ws, p->lay.work));
   a.phi = reinterpret_cast<T*>(ws_ptr(ws, p->lay.phi));
   a.bc0 = reinterpret_cast<const double*>(ws_ptr(ws, p->lay.bc0));
@@ -1281,6 +1293,9 @@ void do_tune(scola_plan* p, void* ws, hipStream_t s, int reps) {
                             (int64_t)(rho_bytes(p) / 8), s), "zero rho");
   hip_check(launch_zero_u64(reinterpret_cast<unsigned long long*>(ws_ptr(ws, p->lay.dropped)),
                             3 * (int64_t)p->desc.size() + 1, s), "zero dropped");
+  // the tuning launches leave extents and unfolded dropped mass in the hints
+  hip_check(launch_zero_u32(reinterpret_cast<unsigned*>(ws_ptr(ws, p->lay.cells)),
+                            (p->P / kBlock) * 4, s), "zero cell hints");
   hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
@@ -1839,6 +1854,7 @@ scola_status scola_op_deposit(scola_plan* p, double D1, double D2, void* ws, hip
     } else {
       Runner<float> r{p, ws, s, subset_list(p, nullptr, 0), true};
       r.particles(kDepositOnly, sc);
+      fold_drops(p, ws, s);
     }
   });
 }
@@ -1876,6 +1892,7 @@ scola_status scola_op_step(scola_plan* p, double beta, double alpha, double D1, 
     } else {
       Runner<float> r{p, ws, s, subset_list(p, nullptr, 0), true};
       r.particles(mode, sc);
+      if (deposit) fold_drops(p, ws, s);
     }
   });
 }

@@ -582,6 +582,19 @@ __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const Blo
       pe = y * n + z;
       pterm = yz_term(y, z);
     }
+    // FP32 plans: the mass the deposit dropped, left per brick of kBlock particles in word 3
+    // of the brick's hint; the box's n blocks fold bricks [x nb / n, (x + 1) nb / n) each
+    // into the box's counter and clear them
+    constexpr int nb = M * M * M / kBlock;
+    const int f0 = x * nb / n, f1 = (x + 1) * nb / n;
+    unsigned long long drop = 0;
+    if constexpr (std::is_same<T, float>::value) {
+      unsigned* const hw = a.hints + (t.p_off / kBlock) * 4 + 3;
+      for (int e = f0 + (int)threadIdx.x; e < f1; e += kBlock) {
+        drop += hw[4 * e];
+        hw[4 * e] = 0u;
+      }
+    }
     unsigned long long found = 0;   // FP32 plans: the plane's total mass in units
     unsigned near = 0;              // FP32 plans: node masses within a factor 2 of wrapping
     for (int e0 = 0; e0 < n * n; e0 += kBatch * kBlock) {
@@ -616,6 +629,11 @@ __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const Blo
 #pragma unroll
       for (int d = 32; d >= 1; d >>= 1) found += __shfl_xor(found, d);
       if ((threadIdx.x & 63) == 0 && found != 0ull) atomicAdd(a.kept + m.tile[b], found);
+      if ((int)(threadIdx.x & ~63u) < f1 - f0) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) drop += __shfl_xor(drop, d);
+        if ((threadIdx.x & 63) == 0 && drop != 0ull) atomicAdd(a.dropped + m.tile[b], drop);
+      }
     }
     if (a.ov_delta) {
       // the deposit's mass was consumed above; the solve takes the full-box density
