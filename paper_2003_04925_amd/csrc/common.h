@@ -47,6 +47,7 @@ struct TileDesc {
   int32_t tw_off;          // first entry of this M's twiddle table (2M complex values)
   int32_t ev_off;          // first entry of this M's eigenvalue table (M-1 values)
   int32_t tclass;          // time class: index of the tile's final scale factor in the plan
+  int32_t dm_off;          // FP32 plans: first half of this M's split sine matrix
   double D1f, D2f;         // growth factors at the tile's final scale factor
 };
 

@@ -62,6 +62,9 @@ struct MeshArgs {
   const double* bc0;
   const void* twiddles;     // complex T, per M: 2M entries W_{2M}^m
   const T* eigen;           // per M: lambda_l, l = 1..M-1 (FDA of the plan order, unit spacing)
+  // FP32 plans, per M: the DST-I sine matrix S[j][k] = sin(pi (j+1)(k+1) / M), j, k < M - 1,
+  // as FP16 halves hi then lo (M rows of 32 ceil(M / 32) values each, zero-padded)
+  const void* sine;
   double D1_bc;
   // adjoint solve only: the source is read from `work`, the result written to lam_rho, and
   // the boundary-source transpose accumulated into lam_bc0
@@ -229,6 +232,11 @@ hipError_t launch_step_persistent(const ParticleArgs<T>& pa, const MeshArgs<T>& 
                                   const BlockMap& m3, unsigned* barrier, hipStream_t s,
                                   int* grid_out);
 
-constexpr int kPencilChunk = 32;   // z-columns per block of the x-pencil pass
+constexpr int kPencilChunk = 32;       // z-columns per block of the x-pencil pass (FFT)
+constexpr int kPencilChunkMfma = 64;   // the same for FP32 plans (matrix-core pass)
+template <typename T>
+__host__ __device__ constexpr int pencil_chunk() {
+  return sizeof(T) == 4 ? kPencilChunkMfma : kPencilChunk;
+}
 
 }  // namespace scola

@@ -18,6 +18,7 @@
 // length 2M = 32 R (R = M / 16 in 1..8) runs on a half wavefront (32 lanes) entirely in
 // registers: each lane holds R points, an R-point DFT across registers, a twiddle, then a
 // 32-point radix-2 decimation-in-frequency FFT across lanes with xor shuffles.
+#include <algorithm>
 #include <atomic>
 #include <type_traits>
 
@@ -30,22 +31,33 @@ namespace scola {
 
 namespace {
 
+// Waves per SIMD the FP32 passes are compiled for: their matrix-core transforms leave them
+// latency-bound, so boxes up to 64^3 ask for full occupancy (at most 64 registers a lane);
+// larger boxes and FP64 plans take what their registers allow.
+template <typename T, int R>
+constexpr int pass_waves() {
+  return std::is_same<T, float>::value && R <= 4 ? 8 : 1;
+}
+
 template <typename T, int R, bool ADJ, int NG>
-__global__ void __launch_bounds__(kBlock) k_poisson_p1(MeshArgs<T> a, BlockMap m) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(pass_waves<T, R>())))
+k_poisson_p1(MeshArgs<T> a, BlockMap m) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int L = logical_block(m);
   if (L < m.count) poisson_p1_block<T, R, ADJ, NG>(a, m, L, smem);
 }
 
 template <typename T, int R>
-__global__ void __launch_bounds__(kBlock) k_poisson_p2(MeshArgs<T> a, BlockMap m) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(pass_waves<T, R>())))
+k_poisson_p2(MeshArgs<T> a, BlockMap m) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int L = logical_block(m);
   if (L < m.count) poisson_p2_block<T, R>(a, m, L, smem);
 }
 
 template <typename T, int R, bool ADJ, int NG>
-__global__ void __launch_bounds__(kBlock) k_poisson_p3(MeshArgs<T> a, BlockMap m) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(pass_waves<T, R>())))
+k_poisson_p3(MeshArgs<T> a, BlockMap m) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int L = logical_block(m);
   if (L < m.count) poisson_p3_block<T, R, ADJ, NG>(a, m, L, smem);
@@ -61,6 +73,21 @@ template <typename T>
 size_t poisson_lds_bytes(int M, int pass, int ng) {
   const size_t n = (size_t)M - 1, tw = 2 * (size_t)M * sizeof(cx<T>);
   const size_t Mp = (size_t)M + 1 + 2 * (size_t)ng;
+  if (std::is_same<T, float>::value) {
+    // matrix-core transforms: block-maximum slots, then the plane region (the plane or the
+    // split lines that alias it); P2: the eigenvalues, then the split lines of the chunk's
+    // 32 columns aliased by the output tile; P3: the border values behind the plane region
+    const int R = M / 16;
+    const size_t region = std::max(n * n * sizeof(float), mfma_split_bytes(R));
+    if (pass == 1) return kMfmaHead + region;
+    if (pass == 2) {
+      const size_t lines =
+          (size_t)kPencilChunkMfma * (32 * ((R + 1) / 2) + 8) * 2 * sizeof(_Float16);
+      return kMfmaHead + (size_t)M * sizeof(float) +
+             std::max(n * (kPencilChunkMfma + 1) * sizeof(float), lines);
+    }
+    return kMfmaHead + region + (Mp * Mp - n * n) * sizeof(float);
+  }
   if (pass == 1) return tw + n * n * sizeof(T);
   if (pass == 2) return tw + ((size_t)M + n * (kPencilChunk + 1)) * sizeof(T);
   return tw + Mp * Mp * sizeof(T);

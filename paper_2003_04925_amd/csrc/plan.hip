@@ -96,6 +96,7 @@ struct scola_plan {
   TileDesc* d_tiles = nullptr;
   void* d_twiddles = nullptr;
   void* d_eigen = nullptr;
+  void* d_sine = nullptr;      // FP32 plans: split sine matrices of the matrix-core DST
   Maps part, p1, p2, p3;
   // launch schedule per size class (index as part.class_M), chosen by scola_plan_tune
   std::vector<scola_class_schedule> sched;
@@ -301,6 +302,34 @@ void upload_tables(scola_plan* p) {
     d.tw_off = offs[d.M].first;
     d.ev_off = offs[d.M].second;
   }
+  if (sizeof(T) == 4) {
+    // FP32 plans: per M, the DST-I matrix S[j][k] = sin(pi (j+1)(k+1) / M) (App. C.2, eq.
+    // DST_delta) for j, k < M - 1, zero-padded to M rows of K = 32 ceil(M / 32) columns, as
+    // FP16 hi = fp16(S) and lo = fp16(S - hi) (hi table, then lo table); (j+1)(k+1) is taken
+    // modulo 2M so that the sine is evaluated at an argument below 2 pi
+    std::map<int, int> soff;
+    std::vector<_Float16> sm;
+    for (auto& d : p->desc) {
+      if (!soff.count(d.M)) {
+        const int M = d.M, K = 32 * ((M + 31) / 32);
+        soff[M] = (int)sm.size();
+        std::vector<_Float16> hi((size_t)M * K, (_Float16)0.0f), lo((size_t)M * K, (_Float16)0.0f);
+        for (int j = 0; j < M - 1; ++j)
+          for (int k = 0; k < M - 1; ++k) {
+            const double v = std::sin(M_PI * (double)(((j + 1) * (k + 1)) % (2 * M)) / M);
+            const _Float16 h = (_Float16)(float)v;
+            hi[(size_t)j * K + k] = h;
+            lo[(size_t)j * K + k] = (_Float16)(float)(v - (double)(float)h);
+          }
+        sm.insert(sm.end(), hi.begin(), hi.end());
+        sm.insert(sm.end(), lo.begin(), lo.end());
+      }
+      d.dm_off = soff[d.M];
+    }
+    hip_check(hipMalloc(&p->d_sine, sm.size() * sizeof(_Float16)), "hipMalloc(sine)");
+    hip_check(hipMemcpy(p->d_sine, sm.data(), sm.size() * sizeof(_Float16), hipMemcpyHostToDevice),
+              "hipMemcpy(sine)");
+  }
   hip_check(hipMalloc(&p->d_twiddles, tw.size() * sizeof(T)), "hipMalloc(twiddles)");
   hip_check(hipMemcpy(p->d_twiddles, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice),
             "hipMemcpy(twiddles)");
@@ -487,6 +516,7 @@ MeshArgs<T> mesh_args(scola_plan* p, void* ws, double D1_bc) {
   a.bc0 = reinterpret_cast<const double*>(ws_ptr(ws, p->lay.bc0));
   a.twiddles = p->d_twiddles;
   a.eigen = reinterpret_cast<const T*>(p->d_eigen);
+  a.sine = p->d_sine;
   a.D1_bc = D1_bc;
   a.ng = p->ng;
   return a;
@@ -1548,8 +1578,9 @@ scola_status scola_plan_create(const scola_config* cfg, const scola_cosmology* c
         if (p->desc[t].M == p->part.class_M[c] && p->desc[t].tclass == p->part.class_tc[c])
           p->class_tiles[c].push_back((int)t);
     build_maps(p->p1, p->desc, [](const TileDesc& d) { return d.M - 1; });
-    build_maps(p->p2, p->desc, [](const TileDesc& d) {
-      return (d.M - 1) * ((d.M - 1 + kPencilChunk - 1) / kPencilChunk);
+    const int chunk = p->is64 ? pencil_chunk<double>() : pencil_chunk<float>();
+    build_maps(p->p2, p->desc, [chunk](const TileDesc& d) {
+      return (d.M - 1) * ((d.M - 1 + chunk - 1) / chunk);
     });
     // the interior x planes, then the 2 (ng + 1) shell planes
     const int ng = p->ng;
@@ -1585,6 +1616,7 @@ scola_status scola_plan_destroy(scola_plan* p) {
   if (p->d_barrier) hipFree(p->d_barrier);
   if (p->d_twiddles) hipFree(p->d_twiddles);
   if (p->d_eigen) hipFree(p->d_eigen);
+  if (p->d_sine) hipFree(p->d_sine);
   delete p;
   return SCOLA_OK;
 }

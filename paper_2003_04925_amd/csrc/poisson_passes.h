@@ -1,6 +1,7 @@
-// Device code of the Dirichlet Poisson solve by DST-I (App. C): the in-register and
-// cross-lane FFTs, the half-length sine transform of two lines, and the three passes as
-// device functions of one logical block (see kernels_poisson.hip for the pass structure).
+// Device code of the Dirichlet Poisson solve by DST-I (App. C): for FP64 plans the
+// in-register and cross-lane FFTs and the half-length sine transform of two lines; for FP32
+// plans the matrix-core products of dst_mfma.h; and the three passes as device functions of
+// one logical block (see kernels_poisson.hip for the pass structure).
 #pragma once
 
 #include <type_traits>
@@ -8,6 +9,7 @@
 #include "common.h"
 #include "kernels.h"
 #include "particle_common.h"
+#include "dst_mfma.h"
 
 namespace scola {
 
@@ -113,30 +115,6 @@ __device__ __forceinline__ double stage_partner(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// own + s * (own in the partner lane of stage B), FP32, for the four stages whose partner
-// is one DPP move away: the move rides on the multiply-add itself (the compiler does not
-// fold a DPP source into a multiply-add whose addend is also its destination).  The
-// leading two wait states are the ones a DPP read of a VGPR written by the previous VALU
-// instruction needs; the compiler's hazard recognizer does not look inside inline assembly.
-template <int B>
-__device__ __forceinline__ float fma_partner(float own, float s) {
-  static_assert(B >= 0 && B <= 3, "DPP stage");
-  float acc = own;
-  if constexpr (B == 0)
-    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf"
-        : "+v"(acc) : "v"(own), "v"(s));
-  if constexpr (B == 1)
-    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf"
-        : "+v"(acc) : "v"(own), "v"(s));
-  if constexpr (B == 2)
-    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_half_mirror row_mask:0xf bank_mask:0xf"
-        : "+v"(acc) : "v"(own), "v"(s));
-  if constexpr (B == 3)
-    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_mirror row_mask:0xf bank_mask:0xf"
-        : "+v"(acc) : "v"(own), "v"(s));
-  return acc;
-}
-
 // One radix-2 decimation-in-frequency stage on data bit B (distance S = 2^B) of K x R
 // independent 32-point transforms across lanes, without divergent branches: every lane
 // forms v = own + s * partner with s = +1 where its data bit B is clear and -1 where it is
@@ -158,13 +136,8 @@ __device__ __forceinline__ void dif_stage(cx<T> (&x)[K][R], const cx<T>* __restr
 #pragma unroll
     for (int k1 = 0; k1 < R; ++k1) {
       cx<T> v;
-      if constexpr (std::is_same<T, float>::value && B < 4) {
-        v.x = fma_partner<B>(x[k][k1].x, s);
-        v.y = fma_partner<B>(x[k][k1].y, s);
-      } else {
-        v.x = fma(stage_partner<B>(x[k][k1].x), s, x[k][k1].x);
-        v.y = fma(stage_partner<B>(x[k][k1].y), s, x[k][k1].y);
-      }
+      v.x = fma(stage_partner<B>(x[k][k1].x), s, x[k][k1].x);
+      v.y = fma(stage_partner<B>(x[k][k1].y), s, x[k][k1].y);
       if constexpr (S > 1) {
         x[k][k1].x = v.x * w.x - v.y * w.y;
         x[k][k1].y = v.x * w.y + v.y * w.x;
@@ -526,6 +499,44 @@ __device__ __forceinline__ constexpr double lap_weight(int k) {
                  : (k == 1 ? 1.5 : k == 2 ? -0.15 : 1.0 / 90.0);
 }
 
+// What a pass's plane transform needs in registers: the wave's sine fragments for FP32
+// plans (requested at the start of the pass), nothing for the FFT.
+template <typename T, int R>
+struct PlaneOperands {
+  __device__ void load(const MeshArgs<T>&, const TileDesc&) {}
+};
+template <int R>
+struct PlaneOperands<float, R> {
+  SineFrag<R> s;
+  __device__ void load(const MeshArgs<float>& a, const TileDesc& t) {
+    s = load_sine<R>(reinterpret_cast<const _Float16*>(a.sine) + t.dm_off);
+  }
+};
+
+// The unnormalised 2-D DST-I of a pass's n x n plane in LDS: on the matrix cores for FP32
+// plans (split lines aliasing the plane, slots at the start of smem), else by the FFT with
+// the twiddles at the start of smem.
+template <typename T, int R>
+__device__ __forceinline__ void plane_transform(T* plane, unsigned char* smem,
+                                                const PlaneOperands<T, R>& op) {
+  if constexpr (std::is_same<T, float>::value)
+    plane_dst_mfma<R>(plane, reinterpret_cast<_Float16*>(plane), reinterpret_cast<float*>(smem),
+                      op.s);
+  else
+    plane_dst<R, T>(plane, reinterpret_cast<const cx<T>*>(smem));
+}
+
+// Floats of a pass's plane region: the n x n plane, or for FP32 plans the larger of it and
+// the split lines that alias it.
+template <typename T, int R>
+__host__ __device__ constexpr size_t plane_region_elems() {
+  return std::is_same<T, float>::value
+             ? ((size_t)(16 * R - 1) * (16 * R - 1) * sizeof(float) > mfma_split_bytes(R)
+                    ? (size_t)(16 * R - 1) * (16 * R - 1)
+                    : mfma_split_bytes(R) / sizeof(float))
+             : (size_t)(16 * R - 1) * (16 * R - 1);
+}
+
 // NG: ghost layers of the finite-difference order 2 NG (Sec. 3): the box's Phi_BC^0 and
 // potential live on the padded nodes [-NG, M + NG]^3 (padded index = node + NG), and
 // Phi_BCs occupies the NG layers outside the interior on each side.
@@ -537,13 +548,17 @@ __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const Blo
   const TileDesc t = a.tiles[m.tile[b]];
   const int x = m.local[b];
   constexpr int M = 16 * R, n = M - 1, Mp = M + 1 + 2 * NG;
+  // FP32 plans transform on the matrix cores (no twiddles: the block-maximum slots lead)
+  constexpr bool kMfma = std::is_same<T, float>::value;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
-  T* plane = reinterpret_cast<T*>(smem + 2 * M * sizeof(cx<T>));
-  load_twiddles(tw, a, t);
+  T* plane = reinterpret_cast<T*>(smem + (kMfma ? kMfmaHead : 2 * M * sizeof(cx<T>)));
+  if constexpr (!kMfma) load_twiddles(tw, a, t);
+  PlaneOperands<T, R> op;
   const int64_t base = t.g_off + (int64_t)x * n * n;
   const double* bc = a.bc0 + t.h_off;
   const double D1 = a.D1_bc;
   if constexpr (ADJ) {
+    op.load(a, t);
     const T* const wk = a.work + base;
 #pragma unroll 8
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) plane[e] = wk[e];
@@ -621,6 +636,8 @@ __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const Blo
         }
       }
     }
+    // the transform's operands, requested once the mass batch has left the registers
+    op.load(a, t);
     if constexpr (std::is_same<T, float>::value) {
       if (near) atomicAdd(a.alarm, (unsigned long long)near);
       // mass identity of FP32 plans: summed over a box's planes, the mass found plus the
@@ -684,7 +701,7 @@ __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const Blo
     }
   }
   __syncthreads();
-  plane_dst<R, T>(plane, tw);
+  plane_transform<T, R>(plane, smem, op);
   T* const wk = a.work + base;
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) wk[e] = plane[e];
 }
@@ -719,9 +736,15 @@ __device__ __forceinline__ void poisson_p2_block(const MeshArgs<T>& a, const Blo
   const int b = m.base + L;
   const TileDesc t = a.tiles[m.tile[b]];
   constexpr int M = 16 * R, n = M - 1;
-  const int nch = (n + kPencilChunk - 1) / kPencilChunk;
+  constexpr int C = pencil_chunk<T>();
+  const int nch = (n + C - 1) / C;
   const int y = m.local[b] / nch, ch = m.local[b] - (m.local[b] / nch) * nch;
-  const int z0 = ch * kPencilChunk, cw = min(kPencilChunk, n - z0);
+  const int z0 = ch * C, cw = min(C, n - z0);
+  if constexpr (std::is_same<T, float>::value) {
+    pencils_mfma<R>(a.work + t.g_off + (int64_t)y * n + z0, y, z0, cw, a.eigen + t.ev_off,
+                    reinterpret_cast<const _Float16*>(a.sine) + t.dm_off, smem);
+    return;
+  }
   constexpr int pitch = kPencilChunk + 1;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
   T* ev = reinterpret_cast<T*>(smem + 2 * M * sizeof(cx<T>));
@@ -777,9 +800,12 @@ __device__ __forceinline__ void poisson_p3_block(const MeshArgs<T>& a, const Blo
       phi[(int64_t)A * Mp * Mp + e] = (T)(D1 * bc[(int64_t)A * Mp * Mp + e]);
     return;
   }
+  constexpr bool kMfma = std::is_same<T, float>::value;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
-  T* plane = reinterpret_cast<T*>(smem + 2 * M * sizeof(cx<T>));
-  load_twiddles(tw, a, t);
+  T* plane = reinterpret_cast<T*>(smem + (kMfma ? kMfmaHead : 2 * M * sizeof(cx<T>)));
+  if constexpr (!kMfma) load_twiddles(tw, a, t);
+  PlaneOperands<T, R> op;
+  op.load(a, t);
   const int x = local;
   const int64_t base = t.g_off + (int64_t)x * n * n;
   const int A = x + 1 + NG;
@@ -790,7 +816,8 @@ __device__ __forceinline__ void poisson_p3_block(const MeshArgs<T>& a, const Blo
   constexpr int kBorder = Mp * Mp - n * n;
   constexpr int kPerThread = (kBorder + kBlock - 1) / kBlock;
   constexpr int kW = 2 * (NG + 1);   // border rows, and border columns per inner row
-  T* border = plane + n * n;   // the border values, staged in LDS behind the plane
+  // the border values, staged in LDS behind the plane region
+  T* border = plane + plane_region_elems<T, R>();
   auto border_offset = [](int i) {
     int B, C;
     if (i < kW * Mp) {
@@ -850,7 +877,7 @@ __device__ __forceinline__ void poisson_p3_block(const MeshArgs<T>& a, const Blo
       }
   }
   __syncthreads();
-  plane_dst<R, T>(plane, tw);
+  plane_transform<T, R>(plane, smem, op);
   if constexpr (ADJ) {
     // lam_rho = lam_delta', and the plane of `work` is cleared (the next reverse step
     // accumulates into a zeroed source)

@@ -1,11 +1,9 @@
-"""Wait states around the hand-placed DPP multiply-adds of the FFT stages (CPU, no GPU).
+"""Properties of the compiled kernels that the tests on the GPU cannot see (CPU, no GPU).
 
-The Poisson passes fold each radix-2 stage's cross-lane move into the multiply-add with
-inline assembly that begins with two wait states, which covers a DPP read of a VGPR written
-by the previous VALU instruction.  The other DPP hazard, a VALU write of EXEC, needs five;
-the compiler's hazard recognizer does not look inside inline assembly, so this test compiles
-the Poisson kernels for gfx950 and requires that no EXEC-writing VALU instruction and no
-branch target lies among the four instructions before any of those blocks.
+The FP32 Poisson passes run their sine transforms on the matrix cores and are compiled for
+full occupancy: the listing must hold the FP16 matrix instructions and no scratch spills for
+the boxes up to 64^3.  The particle step stages windows into LDS with direct-to-LDS loads: a
+wave must wait for them before the barrier after which other waves read the staged words.
 """
 import os
 import re
@@ -18,64 +16,52 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2003_04925_amd", "csrc")
 
 
-def _is_instruction(line):
-    t = line.strip()
-    return bool(t) and not t.startswith((";", ".")) and not t.endswith(":")
-
-
-def dpp_hazards(asm_text, mnemonic="v_fmac_f32_dpp", window=4):
-    """(number of inline DPP multiply-adds, list of problems) for an assembly listing."""
-    lines = asm_text.split("\n")
-    problems, count = [], 0
-    for i, line in enumerate(lines):
-        if mnemonic not in line:
-            continue
-        count += 1
-        before, j = [], i - 1
-        while j >= 0 and len(before) < window + 1:
-            t = lines[j].strip()
-            if re.match(r"^[\w.$]+:", t):
-                before.append("label " + t)
-                break
-            if _is_instruction(lines[j]):
-                before.append(t)
-            j -= 1
-        # before[0] is the block's own s_nop; the next `window` entries precede the block
-        assert before and before[0].startswith("s_nop"), before[:2]
-        for t in before[1:window + 1]:
-            if t.startswith("label") or t.startswith("v_cmpx") or re.search(r"\bexec\b", t):
-                problems.append((i, t))
-    return count, problems
-
-
-def test_scan_flags_an_exec_write_and_a_label():
-    bad = "\n".join(["\tv_cmpx_eq_u32_e32 0, v1", "\ts_nop 1",
-                     "\tv_fmac_f32_dpp v4, v4, v3 row_mirror row_mask:0xf bank_mask:0xf"])
-    assert dpp_hazards(bad)[1]
-    lab = "\n".join([".LBB0_3:", "\tv_add_f32_e32 v1, v2, v3", "\ts_nop 1",
-                     "\tv_fmac_f32_dpp v4, v4, v3 row_mirror row_mask:0xf bank_mask:0xf"])
-    assert dpp_hazards(lab)[1]
-    ok = "\n".join(["\tv_add_f32_e32 v1, v2, v3", "\tv_mul_f32_e32 v5, v2, v3",
-                    "\tv_mul_f32_e32 v6, v2, v3", "\tv_mul_f32_e32 v7, v2, v3",
-                    "\tv_mul_f32_e32 v8, v2, v3", "\ts_nop 1",
-                    "\tv_fmac_f32_dpp v4, v4, v3 row_mirror row_mask:0xf bank_mask:0xf"])
-    assert dpp_hazards(ok) == (1, [])
-
-
-def test_poisson_dpp_blocks_have_no_exec_hazard(tmp_path):
+def _compile(tmp_path, source):
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(hipcc):
         pytest.skip("hipcc not available")
-    out = tmp_path / "poisson.s"
+    out = tmp_path / (source + ".s")
     cmd = [hipcc, "-O3", "-std=c++17", "--offload-arch=gfx950", "--cuda-device-only", "-S",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result",
-           "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           os.path.join(CSRC, "kernels_poisson.hip"), "-o", str(out)]
+           "-I", os.path.join(ROOT, "include"), "-I", CSRC, os.path.join(CSRC, source),
+           "-o", str(out)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]
-    count, problems = dpp_hazards(out.read_text())
-    assert count > 0
-    assert not problems, problems[:5]
+    return out.read_text()
+
+
+def kernel_bodies(asm_text, pattern):
+    """{mangled name: body text} of the kernels whose names match `pattern`."""
+    out = {}
+    for m in re.finditer(r"^(_Z\w+):[^\n]*\n(.*?)^\.Lfunc_end", asm_text, re.M | re.S):
+        if re.search(pattern, m.group(1)):
+            out[m.group(1)] = m.group(2)
+    return out
+
+
+def kernel_meta(asm_text, name):
+    """The code-object metadata entry (.name, .private_segment_fixed_size, .vgpr_count, ...)
+    of one kernel: the kernel list's entries start at two spaces of indentation."""
+    pos = asm_text.index(".name:           " + name + "\n")
+    start = asm_text.rfind("\n  - ", 0, pos)
+    end = asm_text.find("\n  - ", pos)
+    return asm_text[start:end if end > 0 else len(asm_text)]
+
+
+def test_fp32_poisson_passes_use_the_matrix_cores_without_spills(tmp_path):
+    asm = _compile(tmp_path, "kernels_poisson.hip")
+    # FP32 passes of boxes of 16, 32, 48 and 64 nodes (R = 1..4), forward solve, order 2
+    bodies = kernel_bodies(asm, r"k_poisson_p([13]IfLi[1-4]ELb0ELi1E|2IfLi[1-4]E)")
+    names = sorted(bodies)
+    assert len(names) == 12, names
+    for n in names:
+        assert "v_mfma_f32_16x16x32_f16" in bodies[n], n
+        meta = kernel_meta(asm, n)
+        spill = re.search(r"\.private_segment_fixed_size:\s+(\d+)", meta)
+        assert spill and int(spill.group(1)) == 0, (n, spill.group(0) if spill else None)
+    # the FP64 passes keep the FFT (no matrix instructions)
+    for n, body in kernel_bodies(asm, r"k_poisson_p[123]IdLi4E").items():
+        assert "v_mfma" not in body, n
 
 
 def is_lds_dma(t):
@@ -122,16 +108,6 @@ def test_lds_dma_scan_flags_a_missing_wait():
 
 
 def test_particle_direct_lds_staging_waits_before_barrier(tmp_path):
-    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
-    if not os.path.exists(hipcc):
-        pytest.skip("hipcc not available")
-    out = tmp_path / "particles.s"
-    cmd = [hipcc, "-O3", "-std=c++17", "--offload-arch=gfx950", "--cuda-device-only", "-S",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result",
-           "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           os.path.join(CSRC, "kernels_particles.hip"), "-o", str(out)]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    assert r.returncode == 0, r.stderr[-2000:]
-    loads, problems = lds_dma_waits(out.read_text())
+    loads, problems = lds_dma_waits(_compile(tmp_path, "kernels_particles.hip"))
     assert loads > 0
     assert not problems, problems[:5]
