@@ -11,6 +11,7 @@
 // measures faster (the persistent kernel runs every phase at the occupancy the heaviest
 // phase allows).
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 #include "kernels.h"
@@ -65,11 +66,19 @@ __device__ __forceinline__ void grid_barrier(unsigned* counter, unsigned phase) 
   __syncthreads();
 }
 
+// Waves per SIMD the persistent step is compiled for: FP32 boxes up to 64^3 ask for 4, what
+// its LDS (the particle window plus the largest pass) allows anyway; without it the
+// matrix-core passes inlined here let the register count grow until only 3 fit.
 template <typename T, int R>
-__global__ void __launch_bounds__(kBlock) k_step_persistent(ParticleArgs<T> pa, MeshArgs<T> ma,
-                                                            BlockMap mp, BlockMap m1,
-                                                            BlockMap m2, BlockMap m3,
-                                                            unsigned* barrier) {
+constexpr int persistent_waves() {
+  return std::is_same<T, float>::value && R <= 4 ? 4 : 1;
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(persistent_waves<T, R>())))
+k_step_persistent(ParticleArgs<T> pa, MeshArgs<T> ma, BlockMap mp, BlockMap m1, BlockMap m2,
+                  BlockMap m3, unsigned* barrier) {
   extern __shared__ __align__(16) unsigned char smem[];
   {
     const Sweep w(mp);
