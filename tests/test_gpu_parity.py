@@ -4,8 +4,10 @@ Every GPU call goes through the C ABI (libscola.so via the ctypes binding).  Inp
 seeded and synthetic; the oracle gets the same inputs.  Tolerances:
   * integer work (fixed-point mass, conservation): exact;
   * FP64 path: 1e-9 relative (the fixed-point deposit quantises weights to 2^-40);
-  * FP32 path: potential 3e-5 of its maximum; one step from an identical state moves
-    positions by less than 1e-5 cell away from the oracle (the bar is 1e-4 cell).
+  * FP32 path: potential 3e-6 of its maximum (the matrix-core DST carries operands of 22
+    significant bits and accumulates in FP32; measured 3e-7 to 9e-7 for M = 16 ... 128);
+    one step from an identical state moves positions by less than 1e-5 cell away from the
+    oracle (the bar is 1e-4 cell).
 """
 import sys
 
@@ -159,7 +161,7 @@ def test_poisson_matches_oracle(torch, precision):
     phi = sim.view("phi").double().cpu().numpy()
     bc = sim.view("bc0").cpu().numpy()
     assert int(np.abs(sim.view("rho").cpu().numpy()).max()) == 0     # left zeroed
-    tol = 1e-10 if precision == "fp64" else 3e-5
+    tol = 1e-10 if precision == "fp64" else 3e-6
     for t, (po, M, go, ho) in enumerate(sim.box_slices()):
         delta = rho[go:go + (M - 1) ** 3].reshape((M - 1,) * 3) / 2.0 ** sim.layout.fixed_bits - 1.0
         want = dirichlet_potential(delta, D1 * bc[ho:ho + (M + 3) ** 3].reshape((M + 3,) * 3))
@@ -195,7 +197,7 @@ def test_poisson_every_fft_radix(torch, precision, Np, buffer):
     got = phi[:(M + 3) ** 3].reshape((M + 3,) * 3)
     err = np.abs(got - want).max() / np.abs(want).max()
     say("  rel err", err)
-    assert err < (1e-10 if precision == "fp64" else 3e-5)
+    assert err < (1e-10 if precision == "fp64" else 3e-6)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
