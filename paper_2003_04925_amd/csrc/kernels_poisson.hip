@@ -32,11 +32,13 @@ namespace scola {
 namespace {
 
 // Waves per SIMD the FP32 passes are compiled for: their matrix-core transforms leave them
-// latency-bound, so boxes up to 64^3 ask for full occupancy (at most 64 registers a lane);
-// larger boxes and FP64 plans take what their registers allow.
+// latency-bound, so boxes up to 64^3 ask for full occupancy (at most 64 registers a lane),
+// and boxes of 80^3 for the 4 that their LDS allows (c3: 1.01 -> 0.98 ms per solve); at
+// 96^3 that would spill (c5: 4.25 -> 4.68 ms), so larger boxes and FP64 plans take what
+// their registers allow.
 template <typename T, int R>
 constexpr int pass_waves() {
-  return std::is_same<T, float>::value && R <= 4 ? 8 : 1;
+  return !std::is_same<T, float>::value ? 1 : R <= 4 ? 8 : R == 5 ? 4 : 1;
 }
 
 template <typename T, int R, bool ADJ, int NG>
