@@ -513,6 +513,13 @@ struct PlaneOperands<float, R> {
   }
 };
 
+// FP32 plans, first pass: the waves' sums of the plane's mass, in the LDS head behind the
+// block-maximum slots of the transform (which use its first 2 kBlock / 64 floats).
+__device__ __forceinline__ unsigned long long* found_slots(unsigned char* smem) {
+  static_assert(kMfmaHead >= 32 + 8 * (kBlock / 64), "LDS head holds both slot sets");
+  return reinterpret_cast<unsigned long long*>(smem + 32);
+}
+
 // The unnormalised 2-D DST-I of a pass's n x n plane in LDS: on the matrix cores for FP32
 // plans (split lines aliasing the plane, slots at the start of smem), else by the FFT with
 // the twiddles at the start of smem.
@@ -642,10 +649,13 @@ __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const Blo
       if (near) atomicAdd(a.alarm, (unsigned long long)near);
       // mass identity of FP32 plans: summed over a box's planes, the mass found plus the
       // mass dropped equals one unit per particle and deposit unless a 32-bit node wrapped
-      // (each wrap loses exactly 2^32 units); one atomic per wave
+      // (each wrap loses exactly 2^32 units).  One atomic per block: the n blocks of a box
+      // add to one word and the counters of 16 boxes share a cache line, so the waves'
+      // sums meet in LDS first (behind the block-maximum slots; added up after the barrier
+      // before the transform)
 #pragma unroll
       for (int d = 32; d >= 1; d >>= 1) found += __shfl_xor(found, d);
-      if ((threadIdx.x & 63) == 0 && found != 0ull) atomicAdd(a.kept + m.tile[b], found);
+      if ((threadIdx.x & 63) == 0) found_slots(smem)[threadIdx.x >> 6] = found;
       if ((int)(threadIdx.x & ~63u) < f1 - f0) {
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) drop += __shfl_xor(drop, d);
@@ -701,6 +711,14 @@ __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const Blo
     }
   }
   __syncthreads();
+  if constexpr (!ADJ && std::is_same<T, float>::value) {
+    if (threadIdx.x == 0) {
+      unsigned long long f = 0;
+#pragma unroll
+      for (int w = 0; w < kBlock / 64; ++w) f += found_slots(smem)[w];
+      if (f != 0ull) atomicAdd(a.kept + m.tile[b], f);
+    }
+  }
   plane_transform<T, R>(plane, smem, op);
   T* const wk = a.work + base;
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) wk[e] = plane[e];
