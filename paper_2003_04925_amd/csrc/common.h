@@ -56,6 +56,9 @@ struct TileDesc {
 struct StepScalars {
   double beta, alpha, D1, D2, D1n, D2n;
   double c1, c2;            // L+ coefficients (final kick only)
+  // an evolution's start without stored zeros: L- (kInit) does not write x_res = p_res = 0,
+  // and the first step takes them as zero instead of reading them
+  int fresh;
 };
 
 // Cross-lane exchange v[lane ^ S] within 32-lane groups without LDS traffic: xor 1 and 2

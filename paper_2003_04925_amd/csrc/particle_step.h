@@ -548,7 +548,9 @@ __device__ __forceinline__ void particles_block(const ParticleArgs<T>& a, const 
   }
   // the particle streams are touched once per step: non-temporal loads and stores keep
   // them from competing for cache lines with the box's mass mesh (the target of the
-  // deposit's atomics) and potential, which neighbouring blocks reuse
+  // deposit's atomics) and potential, which neighbouring blocks reuse.  `fresh` (uniform):
+  // L- leaves x_res = p_res = 0 unwritten and the first step takes them as zero
+  const bool fresh = a.sc.fresh != 0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     s1[c] = (double)__builtin_nontemporal_load(ps1[c] + tid);
@@ -557,10 +559,12 @@ __device__ __forceinline__ void particles_block(const ParticleArgs<T>& a, const 
       // operator L- (App. B): at t_0 the particles sit on their LPT trajectory and the
       // residual momentum is zero
       xr[c] = T(0);
-      pxr[c][tid] = T(0);
-      ppr[c][tid] = T(0);
+      if (!fresh) {
+        pxr[c][tid] = T(0);
+        ppr[c][tid] = T(0);
+      }
     } else {
-      xr[c] = __builtin_nontemporal_load(pxr[c] + tid);
+      xr[c] = fresh ? T(0) : __builtin_nontemporal_load(pxr[c] + tid);
     }
   }
   // one LDS window, first for the potential (kWindow T values), then for the block's mass
@@ -585,7 +589,7 @@ __device__ __forceinline__ void particles_block(const ParticleArgs<T>& a, const 
   for (int c = 0; c < 3; ++c) u[c] = lpt_base(q[c], sc.D1, s1[c], sc.D2, s2[c]) + (double)xr[c];
   if (kForce) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) pr[c] = __builtin_nontemporal_load(ppr[c] + tid);
+    for (int c = 0; c < 3; ++c) pr[c] = fresh ? T(0) : __builtin_nontemporal_load(ppr[c] + tid);
     // the LPT terms of the kick and of the next position are formed before the force, so
     // Psi1 and Psi2 are not held across it
     const double d2 = sc.D2 - sc.D1 * sc.D1;

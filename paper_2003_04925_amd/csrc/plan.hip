@@ -645,6 +645,8 @@ struct Runner {
   T* x_out = nullptr;
   T* phi = nullptr;
   int group = 0, ngroups = 1;   // batched: this group's share of every class
+  // the evolution starts without writing the zeros of L- (no checkpoint reads them)
+  bool fresh_start = false;
 
   std::vector<BlockMap> maps(const Maps& m) const {
     std::vector<BlockMap> out;
@@ -682,13 +684,19 @@ struct Runner {
   // own time class.  mode kInit: the growth at t_0; kFinalKick: the final row; otherwise
   // row k of the step table.
   void particles_step(int mode, int k) {
+    // L- and the first step of an evolution that starts fresh (see StepScalars::fresh)
+    auto scalars = [&](int tc) {
+      StepScalars sc = class_scalars(p, tc, mode, k);
+      sc.fresh = fresh_start && k == 0 && mode != kFinalKick ? 1 : 0;
+      return sc;
+    };
     if (batched) {
       const Maps& pm = p->part;
       for (size_t c = 0; c < pm.class_M.size(); ++c) {
         BlockMap b = class_group_map(p, pm, c, group, ngroups);
         if (b.count == 0) continue;
         b.xcd_remap = p->sched[c].xcd_remap_particles;
-        ParticleArgs<T> a = args_of(class_scalars(p, pm.class_tc[c], mode, k));
+        ParticleArgs<T> a = args_of(scalars(pm.class_tc[c]));
         hip_check(launch_particles<T>(a, mode, b, p->sched[c].waves_per_simd, s),
                   "particle kernel");
       }
@@ -697,7 +705,7 @@ struct Runner {
         const scola_class_schedule& cs = sched_of(p, p->desc[t].M);
         BlockMap b = tile_map(p->part, t);
         b.xcd_remap = cs.xcd_remap_particles;
-        ParticleArgs<T> a = args_of(class_scalars(p, p->desc[t].tclass, mode, k));
+        ParticleArgs<T> a = args_of(scalars(p->desc[t].tclass));
         hip_check(launch_particles<T>(a, mode, b, cs.waves_per_simd, s), "particle kernel");
       }
     }
@@ -926,11 +934,13 @@ void zero_node_ranges(const scola_plan* p, const std::vector<int>& tiles, T* arr
 // One KDK step k of every class as one persistent launch per class (FP32 batched plans):
 // the particle step and the Poisson passes of force k + 1.
 template <typename T>
-void persistent_step(scola_plan* p, void* ws, int k, hipStream_t s) {
+void persistent_step(scola_plan* p, void* ws, int k, bool fresh, hipStream_t s) {
   if constexpr (std::is_same<T, float>::value) {
     for (size_t c = 0; c < p->part.class_M.size(); ++c) {
       const int tc = p->part.class_tc[c];
-      ParticleArgs<T> pa = particle_args<T>(p, ws, class_scalars(p, tc, kStep, k));
+      StepScalars sc = class_scalars(p, tc, kStep, k);
+      sc.fresh = fresh ? 1 : 0;
+      ParticleArgs<T> pa = particle_args<T>(p, ws, sc);
       MeshArgs<T> ma = mesh_args<T>(p, ws, p->tclasses[tc].D1[k + 1]);
       BlockMap mp = class_map(p->part, c), m1 = class_map(p->p1, c), m2 = class_map(p->p2, c),
                m3 = class_map(p->p3, c);
@@ -962,15 +972,19 @@ void do_evolve(scola_plan* p, const std::vector<int>& tiles, void* ws, hipStream
     r.ngroups = G;
     r.ov_delta = ov_delta;
     r.ov_phi = ov_phi;
+    const int ck = p->cfg.checkpoint_every;
+    // without checkpoints nothing reads x_res, p_res before the first step writes them, so
+    // L- leaves them unwritten and the first step takes them as zero (48 bytes a particle
+    // less per evolution); a checkpoint of step 0 needs the stored zeros
+    r.fresh_start = ck <= 0;
     r.particles_step(kInit, 0);             // L-: x_res = p_res = 0, deposit x_LPT(t_0)
     r.poisson_step(0);
-    const int ck = p->cfg.checkpoint_every;
     const bool fused = p->persistent && b && G == 1 && !ov_delta && !ov_phi;
     for (int k = 0; k < n; ++k) {
       if (ck > 0 && k % ck == 0) copy_checkpoint<T>(p, set, k / ck, true, ws, s);
       const bool need_force = k < n - 1 || p->cfg.want_momenta;
       if (need_force && fused) {
-        persistent_step<T>(p, ws, k, s);
+        persistent_step<T>(p, ws, k, r.fresh_start && k == 0, s);
         r.force++;
         continue;
       }
