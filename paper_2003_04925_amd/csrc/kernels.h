@@ -66,6 +66,12 @@ struct MeshArgs {
   // as FP16 halves hi then lo (M rows of 32 ceil(M / 32) values each, zero-padded)
   const void* sine;
   double D1_bc;
+  // order 2, forward solves of an evolution: bit 1, the third pass leaves each interior x
+  // plane's boundary-source perimeter terms (the first pass's sums of Phi_BC^0 at the
+  // face-layer neighbours, FP64) at the start of that plane of `work`, which it has
+  // consumed; bit 0, the first pass of the next solve reads them there (one contiguous run)
+  // instead of gathering them from Phi_BC^0, whose z-face values lie one per cache line
+  int bc_handoff = 0;
   // adjoint solve only: the source is read from `work`, the result written to lam_rho, and
   // the boundary-source transpose accumulated into lam_bc0
   T* lam_rho = nullptr;

@@ -69,12 +69,14 @@ k_poisson_p3(MeshArgs<T> a, BlockMap m) {
 
 // Dynamic LDS of each pass for boxes of M nodes: the 2M twiddles, then P1 the (M-1)^2 plane,
 // P2 the M eigenvalues and an (M-1) x 33 pencil tile, P3 the plane with its padded border
-// ((M + 1 + 2 ng)^2 for ng ghost layers).  Sized per M and per pass, so small boxes keep
-// more blocks per CU.
+// ((M + 1 + 2 ng)^2 for ng ghost layers) and the perimeter terms it hands on.  Sized per M
+// and per pass, so small boxes keep more blocks per CU.
 template <typename T>
 size_t poisson_lds_bytes(int M, int pass, int ng) {
   const size_t n = (size_t)M - 1, tw = 2 * (size_t)M * sizeof(cx<T>);
   const size_t Mp = (size_t)M + 1 + 2 * (size_t)ng;
+  // P3: the perimeter terms it hands to the next solve's P1, 8-byte aligned behind the border
+  const size_t terms = 8 + 4 * (n - 1) * sizeof(double);
   if (std::is_same<T, float>::value) {
     // matrix-core transforms: block-maximum slots, then the plane region (the plane or the
     // split lines that alias it); P2: the eigenvalues, then the split lines of the chunk's
@@ -88,11 +90,11 @@ size_t poisson_lds_bytes(int M, int pass, int ng) {
       return kMfmaHead + (size_t)M * sizeof(float) +
              std::max(n * (kPencilChunkMfma + 1) * sizeof(float), lines);
     }
-    return kMfmaHead + region + (Mp * Mp - n * n) * sizeof(float);
+    return kMfmaHead + region + (Mp * Mp - n * n) * sizeof(float) + terms;
   }
   if (pass == 1) return tw + n * n * sizeof(T);
   if (pass == 2) return tw + ((size_t)M + n * (kPencilChunk + 1)) * sizeof(T);
-  return tw + Mp * Mp * sizeof(T);
+  return tw + Mp * Mp * sizeof(T) + terms;
 }
 
 namespace {

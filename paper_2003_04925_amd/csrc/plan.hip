@@ -721,6 +721,9 @@ struct Runner {
   void poisson_step(int k) {
     MeshArgs<T> a = mesh_args<T>(p, ws, 0.0);
     if (phi) a.phi = phi;
+    // the boundary-source perimeter terms pass from each solve's P3 to the next one's P1
+    // through the consumed work planes (the first solve of an evolution gathers them)
+    if (!ov_delta && !ov_phi) a.bc_handoff = k == 0 ? 2 : 3;
     if (ov_delta || ov_phi) {
       const size_t N3 = (size_t)p->cfg.Np * p->cfg.Np * p->cfg.Np;
       a.ov_N = p->cfg.Np;
@@ -942,6 +945,7 @@ void persistent_step(scola_plan* p, void* ws, int k, bool fresh, hipStream_t s) 
       sc.fresh = fresh ? 1 : 0;
       ParticleArgs<T> pa = particle_args<T>(p, ws, sc);
       MeshArgs<T> ma = mesh_args<T>(p, ws, p->tclasses[tc].D1[k + 1]);
+      ma.bc_handoff = 3;   // solve k + 1 of an evolution (see Runner::poisson_step)
       BlockMap mp = class_map(p->part, c), m1 = class_map(p->p1, c), m2 = class_map(p->p2, c),
                m3 = class_map(p->p3, c);
       mp.xcd_remap = p->sched[c].xcd_remap_particles;

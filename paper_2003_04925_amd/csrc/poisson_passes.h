@@ -513,6 +513,29 @@ struct PlaneOperands<float, R> {
   }
 };
 
+// Element i < 4 (n - 1) of the perimeter of an n x n plane: the first row (y = 0), then the
+// last column, the last row backwards and the first column backwards.
+__device__ __forceinline__ void perimeter_yz(int i, int n, int& y, int& z) {
+  const int side = i / (n - 1), o = i - side * (n - 1);
+  y = side == 0 ? 0 : side == 1 ? o : side == 2 ? n - 1 : n - 1 - o;
+  z = side == 0 ? o : side == 1 ? n - 1 : side == 2 ? n - 1 - o : 0;
+}
+
+// Inverse of perimeter_yz: the perimeter index of node (y, z) on the perimeter.
+__device__ __forceinline__ int perimeter_index(int y, int z, int n) {
+  if (y == 0) return z;
+  if (z == n - 1) return (n - 1) + y;
+  if (y == n - 1) return 2 * (n - 1) + (n - 1 - z);
+  return 3 * (n - 1) + (n - 1 - y);
+}
+
+// Where a plane's perimeter terms wait in its consumed `work` plane (MeshArgs::bc_handoff):
+// the plane's first 8-byte aligned address; 4 (n - 1) doubles fit in its n^2 values.
+template <typename T>
+__device__ __forceinline__ double* handoff_terms(T* plane) {
+  return reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(plane) + 7) & ~uintptr_t(7));
+}
+
 // FP32 plans, first pass: the waves' sums of the plane's mass, in the LDS head behind the
 // block-maximum slots of the transform (which use its first 2 kBlock / 64 floats).
 __device__ __forceinline__ unsigned long long* found_slots(unsigned char* smem) {
@@ -596,13 +619,14 @@ __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const Blo
     };
     int pe = -1;
     double pterm = 0.0;
+    // the previous solve's third pass left the perimeter terms in this plane of `work`
+    const double* const pin =
+        NG == 1 && (a.bc_handoff & 1) && !a.ov_phi ? handoff_terms(a.work + base) : nullptr;
     if (NG == 1 && !xface && (int)threadIdx.x < 4 * (n - 1)) {
-      // perimeter of the plane: i < n - 1 first row, then last column, last row, first column
-      const int i = threadIdx.x, side = i / (n - 1), o = i - side * (n - 1);
-      const int y = side == 0 ? 0 : side == 1 ? o : side == 2 ? n - 1 : n - 1 - o;
-      const int z = side == 0 ? o : side == 1 ? n - 1 : side == 2 ? n - 1 - o : 0;
+      int y, z;
+      perimeter_yz(threadIdx.x, n, y, z);
       pe = y * n + z;
-      pterm = yz_term(y, z);
+      pterm = pin ? pin[threadIdx.x] : yz_term(y, z);
     }
     // FP32 plans: the mass the deposit dropped, left per brick of kBlock particles in word 3
     // of the brick's hint; the box's n blocks fold bricks [x nb / n, (x + 1) nb / n) each
@@ -702,10 +726,9 @@ __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const Blo
     } else {
       // the remaining perimeter elements of planes wider than the block
       for (int i = threadIdx.x + blockDim.x; i < 4 * (n - 1); i += blockDim.x) {
-        const int side = i / (n - 1), o = i - side * (n - 1);
-        const int y = side == 0 ? 0 : side == 1 ? o : side == 2 ? n - 1 : n - 1 - o;
-        const int z = side == 0 ? o : side == 1 ? n - 1 : side == 2 ? n - 1 - o : 0;
-        plane[y * n + z] = (T)((double)plane[y * n + z] - D1 * yz_term(y, z));
+        int y, z;
+        perimeter_yz(i, n, y, z);
+        plane[y * n + z] = (T)((double)plane[y * n + z] - D1 * (pin ? pin[i] : yz_term(y, z)));
       }
       if (pe >= 0) plane[pe] = (T)((double)plane[pe] - D1 * pterm);
     }
@@ -882,11 +905,22 @@ __device__ __forceinline__ void poisson_p3_block(const MeshArgs<T>& a, const Blo
   const T* const wk = a.work + base;
 #pragma unroll 8
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) plane[e] = wk[e];
+  // order 2, evolution: the first pass of the next solve takes this plane's perimeter terms
+  // (the same padded plane A's face-layer values, which bval holds) from its `work` plane;
+  // they are summed in LDS behind the border in the first pass's order (the y face, then
+  // the z face), one writer per term in each of two phases around the barrier below
+  const bool hand_out = NG == 1 && !ADJ && (a.bc_handoff & 2) != 0;
+  double* const pacc = handoff_terms(border + kBorder);
   if constexpr (!ADJ) {
 #pragma unroll
     for (int q = 0; q < kPerThread; ++q) {
       const int i = q * kBlock + threadIdx.x;
       if (i < kBorder) border[i] = (T)(D1 * bval[q]);
+      // rows B = 1 and B = M + 1: the y faces of interior rows y = 0 and y = n - 1
+      if (hand_out && i >= Mp && i < 3 * Mp) {
+        const int C = i - (i >= 2 * Mp ? 2 * Mp : Mp);
+        if (C >= 2 && C <= M) pacc[perimeter_index(i < 2 * Mp ? 0 : n - 1, C - 2, n)] = bval[q];
+      }
     }
     if (a.ov_phi)
       for (int i = threadIdx.x; i < kBorder; i += blockDim.x) {
@@ -895,7 +929,27 @@ __device__ __forceinline__ void poisson_p3_block(const MeshArgs<T>& a, const Blo
       }
   }
   __syncthreads();
+  if (hand_out) {
+    // columns C = 1 and C = M + 1 of the inner rows: the z faces of z = 0 and z = n - 1,
+    // added to the y face's value at the four corners
+#pragma unroll
+    for (int q = 0; q < kPerThread; ++q) {
+      const int i = q * kBlock + threadIdx.x;
+      if (i >= 4 * Mp && i < kBorder) {
+        const int j = i - 4 * Mp, y = j >> 2, c = j & 3;
+        if (c == 1 || c == 2) {
+          const int pi = perimeter_index(y, c == 1 ? 0 : n - 1, n);
+          pacc[pi] = (y == 0 || y == n - 1) ? pacc[pi] + bval[q] : bval[q];
+        }
+      }
+    }
+  }
   plane_transform<T, R>(plane, smem, op);
+  if (hand_out) {
+    // the work plane was read into LDS before the barriers of the transform
+    double* const out = handoff_terms(a.work + base);
+    for (int i = threadIdx.x; i < 4 * (n - 1); i += blockDim.x) out[i] = pacc[i];
+  }
   if constexpr (ADJ) {
     // lam_rho = lam_delta', and the plane of `work` is cleared (the next reverse step
     // accumulates into a zeroed source)
