@@ -72,6 +72,6 @@ def test_accuracy_statement(torch, oracle_c1, precision, schedule):
     if precision == "fp64":
         assert dmax < 1e-8 and pk_err < 1e-9 and idx_mismatch == 0
     else:
-        # the benchmark spec's bar: 1e-4 cell, equal cell indices away from faces
+        # the FP32 accuracy bar: 1e-4 cell, equal cell indices away from faces
         assert dmax < 1e-4 and d999 < 2e-5 and idx_mismatch == 0 and pk_err < 1e-5
         assert dens_err < 1e-3

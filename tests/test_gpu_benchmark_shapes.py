@@ -4,7 +4,7 @@ for the FP64 oracle.
 c5 shape: boxes of 64^3 core + 16 buffer (96^3 particles, 95^3 Poisson unknowns) at the c5
 cell size L/N_p = 1000/512 = 1.953 Mpc/h, 30 FP32 steps -- here L = 250 Mpc/h with 128^3
 particles and 2^3 tiles -- run as bench.py runs its workloads (set up, autotuned, the
-evolution replayed as a hipGraph).  Bar: the benchmark spec's 1e-4 cell on every particle of the
+evolution replayed as a hipGraph).  Bar: the FP32 accuracy bar of 1e-4 cell on every particle of the
 sampled box, equal cell indices away from faces.
 
 c4 shape: the reverse mode with checkpoints every 5 steps over 20 FP32 steps on boxes of
