@@ -629,10 +629,11 @@ __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const Blo
       pterm = pin ? pin[threadIdx.x] : yz_term(y, z);
     }
     // FP32 plans: the mass the deposit dropped, left per brick of kBlock particles in word 3
-    // of the brick's hint; the box's n blocks fold bricks [x nb / n, (x + 1) nb / n) each
-    // into the box's counter and clear them
+    // of the brick's hint; block x = 1 of the box (an interior plane, lighter than the x
+    // faces) folds all nb of them into the box's counter and clears them, so the counter
+    // takes a few atomics per solve rather than one per block
     constexpr int nb = M * M * M / kBlock;
-    const int f0 = x * nb / n, f1 = (x + 1) * nb / n;
+    const int f0 = 0, f1 = x == 1 ? nb : 0;
     unsigned long long drop = 0;
     if constexpr (std::is_same<T, float>::value) {
       unsigned* const hw = a.hints + (t.p_off / kBlock) * 4 + 3;
