@@ -94,9 +94,12 @@ __device__ __forceinline__ long long deposit_block(typename MeshFixed<T>::rho_t*
   // the barrier of the extent reduction, which then also orders the clearing before the
   // accumulation; the caller's last use of the window ended at a barrier
   {
-    const int t = threadIdx.x;
+    // 16-byte stores (the window is 16-byte aligned and a multiple of kBlock x 16 bytes)
+    constexpr int kClear = kWindow * (int)sizeof(W) / 16 / kBlock;
+    static_assert(kClear * 16 * kBlock == kWindow * (int)sizeof(W), "whole window");
+    uint4* const w4 = reinterpret_cast<uint4*>(win);
 #pragma unroll
-    for (int xi = 0; xi < kFw; ++xi) win[t + kFwX * xi] = W(0);
+    for (int k = 0; k < kClear; ++k) w4[threadIdx.x + kBlock * k] = make_uint4(0u, 0u, 0u, 0u);
   }
   unsigned q[3];
   const CellRange cr = block_cells(in, j0, bounds, q);
@@ -126,18 +129,26 @@ __device__ __forceinline__ long long deposit_block(typename MeshFixed<T>::rho_t*
     if (ty < ey && tz < ez && ny >= 1 && ny <= n && nz >= 1 && nz <= n) {
       const int xa = max(1 - ox, 0), xb = min(n + 1 - ox, ex);   // interior x planes
       const unsigned gcol = (unsigned)(((ny - 1) * n + (nz - 1)) * (int)sizeof(Rho));
-      Rho v[kFw];
-#pragma unroll
-      for (int xi = 0; xi < kFw; ++xi) v[xi] = (xi >= xa && xi < xb) ? win[t + kFwX * xi] : Rho(0);
       if constexpr (sizeof(Rho) == 4) {
-        // 32-bit words: buffer atomics over the box's mesh, the plane a scalar offset
+        // 32-bit words: buffer atomics over the box's mesh, the plane a scalar offset; the
+        // block-uniform plane range [xa, xb) in groups of four (reads first, then atomics),
+        // so the planes beyond the block's extent cost nothing
         const __amdgpu_buffer_rsrc_t rs = buffer_of(rho, (unsigned)(n * n * n * (int)sizeof(Rho)));
+        for (int x0 = xa; x0 < xb; x0 += 4) {
+          Rho v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v[u] = x0 + u < xb ? win[t + kFwX * (x0 + u)] : Rho(0);
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (v[u] != 0)
+              __builtin_amdgcn_raw_ptr_buffer_atomic_add_i32(
+                  (int)v[u], rs, gcol, (ox - 1 + x0 + u) * (n * n) * (int)sizeof(Rho), 0);
+        }
+      } else {
+        Rho v[kFw];
 #pragma unroll
         for (int xi = 0; xi < kFw; ++xi)
-          if (v[xi] != 0)
-            __builtin_amdgcn_raw_ptr_buffer_atomic_add_i32(
-                (int)v[xi], rs, gcol, (ox - 1 + xi) * (n * n) * (int)sizeof(Rho), 0);
-      } else {
+          v[xi] = (xi >= xa && xi < xb) ? win[t + kFwX * xi] : Rho(0);
 #pragma unroll
         for (int xi = 0; xi < kFw; ++xi)
           if (v[xi] != 0)
@@ -569,7 +580,7 @@ __device__ __forceinline__ void particles_block(const ParticleArgs<T>& a, const 
   }
   // one LDS window, first for the potential (kWindow T values), then for the block's mass
   // (kWindow fixed-point accumulators)
-  __shared__ unsigned long long win[kWindow * sizeof(T) / 8];
+  __shared__ __align__(16) unsigned long long win[kWindow * sizeof(T) / 8];
   __shared__ int bounds[kCellScratch];
   // the potential window placed from the kept extent is requested while the particle
   // streams are still in flight
