@@ -4,20 +4,19 @@
 // over the (n)^3 mesh of every box, all boxes in one launch each:
 //   P1  per x-plane: fixed-point mass -> delta, delta' = delta - Delta Phi_BCs (App. C.1),
 //       forward DST-I along z then y, in LDS;
-//   P2  per (y, 32 z-columns): forward DST-I along x, division by the FDA eigenvalue sum
-//       times the inverse normalisation 8/M^3 (App. C.2, eq. Poisson_sine_space), inverse
-//       DST-I along x;
+//   P2  per (y, chunk of z-columns: 64 in FP32 plans, 32 in FP64): forward DST-I along x,
+//       division by the FDA eigenvalue sum times the inverse normalisation 8/M^3 (App. C.2,
+//       eq. Poisson_sine_space), inverse DST-I along x;
 //   P3  per x-plane: inverse DST-I along y then z, and the potential written to the padded
 //       node grid [-g, M+g]^3 with the shell filled from Phi_BCs (Sec. 3.4.2); g = 1, 2, 3
 //       ghost layers at finite-difference order 2, 4, 6 (Sec. 3), where delta' also takes
 //       the wide stencil's reach into the g Dirichlet layers (App. C.1).
 //
-// Every 1-D DST-I of length n = M - 1 is computed through a complex FFT of length 2M of the
-// odd extension (0, a_1..a_n, 0, -a_n..-a_1) + i (same for a second line b): its transform
-// is Z_k = -2i S[a]_k + 2 S[b]_k, so two sine transforms come from one FFT.  The FFT of
-// length 2M = 32 R (R = M / 16 in 1..8) runs on a half wavefront (32 lanes) entirely in
-// registers: each lane holds R points, an R-point DFT across registers, a twiddle, then a
-// 32-point radix-2 decimation-in-frequency FFT across lanes with xor shuffles.
+// FP32 plans form every DST-I as a product with the sine matrix on the matrix cores
+// (dst_mfma.h: split FP16 operands, FP32 accumulation); FP64 plans use the real-data sine
+// transform through a half-length complex FFT on a quarter wavefront (poisson_passes.h).
+// Within an evolution, P3 leaves each plane's boundary-source perimeter terms in its
+// consumed work plane for the next solve's P1 (MeshArgs::bc_handoff).
 #include <algorithm>
 #include <atomic>
 #include <type_traits>
@@ -67,10 +66,12 @@ k_poisson_p3(MeshArgs<T> a, BlockMap m) {
 
 }  // namespace
 
-// Dynamic LDS of each pass for boxes of M nodes: the 2M twiddles, then P1 the (M-1)^2 plane,
-// P2 the M eigenvalues and an (M-1) x 33 pencil tile, P3 the plane with its padded border
-// ((M + 1 + 2 ng)^2 for ng ghost layers) and the perimeter terms it hands on.  Sized per M
-// and per pass, so small boxes keep more blocks per CU.
+// Dynamic LDS of each pass for boxes of M nodes: FP64 plans the 2M twiddles, then P1 the
+// (M-1)^2 plane, P2 the M eigenvalues and an (M-1) x 33 pencil tile, P3 the plane with its
+// padded border ((M + 1 + 2 ng)^2 for ng ghost layers); FP32 plans the block-maximum slots,
+// then the plane region (the plane or the split lines aliasing it), P2 the eigenvalues and
+// the chunk's split lines aliased by its output tile; P3 also the perimeter terms it hands
+// on.  Sized per M and per pass, so small boxes keep more blocks per CU.
 template <typename T>
 size_t poisson_lds_bytes(int M, int pass, int ng) {
   const size_t n = (size_t)M - 1, tw = 2 * (size_t)M * sizeof(cx<T>);
