@@ -65,8 +65,9 @@ typedef struct {
  * library implements (the PM node spacing then equals the lattice spacing); any other value
  * is refused with SCOLA_EUNSUPPORTED.
  * Admitted box sizes: M = 16 R for R = 1..8, i.e. {16, 32, 48, 64, 80, 96, 112, 128}: the
- * particles of a box are stored in bricks of 4 x 8 x 8 and every 1-D transform of the
- * Poisson solve is an FFT of 16 R points on 16 lanes.  These are the members of
+ * particles of a box are stored in bricks of 4 x 8 x 8, and every 1-D sine transform of the
+ * Poisson solve is a product with 16-row sine-matrix tiles (FP32 plans) or an FFT of 16 R
+ * points on 16 lanes (FP64 plans).  These are the members of
  * 2^a {1, 3, 5, 7} that are multiples of 16 up to 128; other sizes of that form (24, 40, 56,
  * 192, 256, ...) are refused with SCOLA_EUNSUPPORTED. */
 typedef struct {

@@ -83,11 +83,12 @@ __device__ __forceinline__ cx<T> mul_wr(cx<T> a, int R, int m) {
   return r;
 }
 
-// Lane l of a half wavefront holds data index n(l) of the 32-point transforms across lanes.
-// The lane bits are a GF(2)-linear relabelling of the data bits chosen so that the partner
-// of every radix-2 stage is a single DPP move away: data bit 0 -> lane xor 1, bit 1 -> xor 2
-// (quad permutations), bit 2 -> xor 7 (half-row mirror), bit 3 -> xor 15 (row mirror), bit
-// 4 -> xor 16 (ds_swizzle across the two 16-lane rows).  n(0) = 0.
+// Lane l of a quarter wavefront holds data index n(l) of the 16-point transforms across
+// lanes.  The lane bits are a GF(2)-linear relabelling of the data bits chosen so that the
+// partner of every radix-2 stage is a single DPP move away: data bit 0 -> lane xor 1, bit 1
+// -> xor 2 (quad permutations), bit 2 -> xor 7 (half-row mirror), bit 3 -> xor 15 (row
+// mirror).  n(0) = 0.  stage_partner also offers bit 4 -> xor 16 (ds_swizzle across two
+// 16-lane rows) for transforms over 32 lanes, which the solver does not use.
 __device__ __forceinline__ int fft_index(int l) {
   const int l0 = l & 1, l1 = (l >> 1) & 1, l2 = (l >> 2) & 1, l3 = (l >> 3) & 1;
   return (l0 ^ l2) | ((l1 ^ l2) << 1) | ((l2 ^ l3) << 2) | (l & 0x18);
@@ -116,13 +117,12 @@ __device__ __forceinline__ double stage_partner(double v) {
 }
 
 // One radix-2 decimation-in-frequency stage on data bit B (distance S = 2^B) of K x R
-// independent 32-point transforms across lanes, without divergent branches: every lane
+// independent 16-point transforms across lanes, without divergent branches: every lane
 // forms v = own + s * partner with s = +1 where its data bit B is clear and -1 where it is
 // set, i.e. a + b on the lower and -(a - b) on the upper element of each pair; the upper
 // element's twiddle is taken negated, -W_{2S}^(n mod S) = W_{32R}^(((n mod S) 16/S + 16) R),
 // which restores (a - b) W_{2S}^(n mod S).  The last stage (S = 1) has no twiddle and leaves
-// the upper elements negated; those hold the outputs 16..31 of each transform, which the
-// sine transform never uses.
+// the upper elements (odd n) negated; the caller undoes that sign where it reads them.
 template <int B, int R, int K, typename T>
 __device__ __forceinline__ void dif_stage(cx<T> (&x)[K][R], const cx<T>* __restrict__ tw,
                                           int n) {
