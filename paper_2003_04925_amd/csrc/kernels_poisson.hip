@@ -34,14 +34,19 @@ namespace {
 // latency-bound, so boxes up to 64^3 ask for full occupancy (at most 64 registers a lane),
 // and boxes of 80^3 for the 4 that their LDS allows (c3: 1.01 -> 0.98 ms per solve); at
 // 96^3 that would spill (c5: 4.25 -> 4.68 ms), so larger boxes and FP64 plans take what
-// their registers allow.
-template <typename T, int R>
+// their registers allow.  The 64^3 reverse passes, the 64^3 first pass at orders 4 and 6
+// and the 48^3 first pass at order 6 need a few more registers than 64: they take 7 waves
+// (72 registers) rather than spill to scratch.
+template <typename T, int R, bool ADJ = false, int NG = 1>
 constexpr int pass_waves() {
-  return !std::is_same<T, float>::value ? 1 : R <= 4 ? 8 : R == 5 ? 4 : 1;
+  if (!std::is_same<T, float>::value) return 1;
+  if ((R == 4 && (ADJ || NG > 1)) || (R == 3 && NG == 3)) return 7;
+  return R <= 4 ? 8 : R == 5 ? 4 : 1;
 }
 
 template <typename T, int R, bool ADJ, int NG>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(pass_waves<T, R>())))
+__global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(pass_waves<T, R, ADJ, NG>())))
 k_poisson_p1(MeshArgs<T> a, BlockMap m) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int L = logical_block(m);
@@ -57,7 +62,8 @@ k_poisson_p2(MeshArgs<T> a, BlockMap m) {
 }
 
 template <typename T, int R, bool ADJ, int NG>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(pass_waves<T, R>())))
+__global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(pass_waves<T, R, ADJ, NG>())))
 k_poisson_p3(MeshArgs<T> a, BlockMap m) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int L = logical_block(m);

@@ -378,36 +378,37 @@ __device__ __forceinline__ void block_force(const T* __restrict__ phi, int M, do
         gather_force<T>(M, j0, fr,
                         [&](int kx, int ky, int kz) { return wp[kx * kFwX + ky * kFwY + kz]; }, g);
       }
-    } else {
-      // sized window over the padded grid; stencil coordinates are clamped into
-      // [-1, M+1], which changes only reads that carry zero weight
-      const int lx = max(ox, -1), ly = max(oy, -1), lz = max(oz, -1);
-      const int wx = min(cr.hi[0] + 2, M + 1) - lx + 1, wy = min(cr.hi[1] + 2, M + 1) - ly + 1,
-                wz = min(cr.hi[2] + 2, M + 1) - lz + 1;
-      const int wyz = wy * wz;
-      auto cl = [&](int v) { return min(max(v, -1), M + 1); };
-      if (wx * wyz <= kWindow) {
-        const float inv_wz = 1.0f / (float)wz;
-        const unsigned gstep = (unsigned)Mp2;
-        for (int pos = threadIdx.x; pos < wyz; pos += blockDim.x) {
-          const int ey2 = (int)(((float)pos + 0.5f) * inv_wz), ez2 = pos - ey2 * wz;
-          unsigned widx = (unsigned)pos;
-          unsigned gidx = idx3(lx + 1, ly + ey2 + 1, lz + ez2 + 1, Mp, Mp);
+    } else if (ex * ey * ez <= kWindow) {
+      // window sized to the extent, laid out like the fixed one with runtime pitches
+      // (x: ey ez, y: ez): nodes outside the padded grid are zero, as in the fixed form, so
+      // the stencil reads need no clamping
+      const int eyz = ey * ez;
+      const float inv_ez = 1.0f / (float)ez;
+      for (int pos = threadIdx.x; pos < eyz; pos += blockDim.x) {
+        const int ey2 = (int)(((float)pos + 0.5f) * inv_ez), ez2 = pos - ey2 * ez;
+        const int ny = oy + ey2, nz = oz + ez2;
+        const bool col = ny >= -1 && ny <= M + 1 && nz >= -1 && nz <= M + 1;
+        const int xa = max(-1 - ox, 0), xb = col ? min(M + 2 - ox, ex) : 0;
+        const int gcol = (ny + 1) * Mp + (nz + 1);
 #pragma unroll 4
-          for (int x = 0; x < wx; ++x, widx += (unsigned)wyz, gidx += gstep) win[widx] = phi[gidx];
-        }
-        __syncthreads();
-        if (in)
-          gather_force_rolled<T>(M, j0, fr, [&](int kx, int ky, int kz) {
-            return win[idx3(cl(j0[0] - 1 + kx) - lx, cl(j0[1] - 1 + ky) - ly,
-                            cl(j0[2] - 1 + kz) - lz, wy, wz)];
-          }, g);
-      } else if (in) {
+        for (int x = 0; x < ex; ++x)
+          win[pos + x * eyz] = x >= xa && x < xb ? phi[(int64_t)(ox + 1 + x) * Mp2 + gcol] : T(0);
+      }
+      __syncthreads();
+      if (in) {
+        const T* wp = win + ((j0[0] - 1 - ox) * ey + (j0[1] - 1 - oy)) * ez + (j0[2] - 1 - oz);
         gather_force_rolled<T>(M, j0, fr, [&](int kx, int ky, int kz) {
-          return phi[idx3(cl(j0[0] - 1 + kx) + 1, cl(j0[1] - 1 + ky) + 1,
-                          cl(j0[2] - 1 + kz) + 1, Mp, Mp)];
+          return wp[kx * eyz + ky * ez + kz];
         }, g);
       }
+    } else if (in) {
+      // global memory; stencil coordinates are clamped into [-1, M+1], which changes only
+      // reads that carry zero weight
+      auto cl = [&](int v) { return min(max(v, -1), M + 1); };
+      gather_force_rolled<T>(M, j0, fr, [&](int kx, int ky, int kz) {
+        return phi[idx3(cl(j0[0] - 1 + kx) + 1, cl(j0[1] - 1 + ky) + 1,
+                        cl(j0[2] - 1 + kz) + 1, Mp, Mp)];
+      }, g);
     }
   }
   __syncthreads();   // every thread is done with `bounds` and the window before reuse

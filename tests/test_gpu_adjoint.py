@@ -92,7 +92,7 @@ def test_fp64_gradient_with_wide_windows_and_coarse_output(torch):
     forms = set()
     for t in otiles:
         u = evolve_box(_box(psi1, t), _box(psi2, t), _boundary_potential0(phi1, t), steps)
-        forms |= set(window_forms(u.detach().numpy().reshape(3, -1), t.M).tolist())
+        forms |= set(window_forms(u.detach().numpy().reshape(3, -1), t.M, clamped=True).tolist())
     say("  window forms at the final step", sorted(forms))
     assert {0, 1, 2} <= forms
     target = 0.5 * synthetic.normal((N_out,) * 3, 1.0, 43)

@@ -241,10 +241,12 @@ def test_one_step_from_identical_state(torch, precision, M_buffer):
         np.testing.assert_allclose(got, want, atol=dep_tol(precision))
 
 
-def window_forms(u, M):
+def window_forms(u, M, clamped=False):
     """Which LDS window form each 4 x 8 x 8 brick of a box takes for its force stencils, from
     positions u (3, M^3) in lattice order: 0 = fixed 16^3 window, 1 = window sized to the
-    block's extent (at most 4096 nodes), 2 = global memory; -1 = no particle inside."""
+    block's stencil extent (at most 4096 nodes), 2 = global memory; -1 = no particle inside.
+    The forward step sizes its window to the whole extent; the reverse pass (`clamped`) to
+    the part of it inside the padded grid [-1, M + 1]."""
     M4, M8 = M // 4, M // 8
     j0 = np.floor(u).reshape(3, M4, 4, M8, 8, M8, 8).transpose(0, 1, 3, 5, 2, 4, 6)
     j0 = j0.reshape(3, -1, 256)
@@ -260,7 +262,10 @@ def window_forms(u, M):
         if (hi - lo + 4 <= 16).all():
             forms.append(0)
             continue
-        vol = np.prod(np.minimum(hi + 2, M + 1) - np.maximum(lo - 1, -1) + 1)
+        if clamped:
+            vol = np.prod(np.minimum(hi + 2, M + 1) - np.maximum(lo - 1, -1) + 1)
+        else:
+            vol = np.prod(hi - lo + 4)
         forms.append(1 if vol <= 4096 else 2)
     return np.array(forms)
 

@@ -1,8 +1,8 @@
 """Properties of the compiled kernels that the tests on the GPU cannot see (CPU, no GPU).
 
 The FP32 Poisson passes run their sine transforms on the matrix cores and are compiled for
-full occupancy: the listing must hold the FP16 matrix instructions and no scratch spills for
-the boxes up to 64^3.  The particle step stages windows into LDS with direct-to-LDS loads: a
+high occupancy: the listing must hold the FP16 matrix instructions and no scratch spills for
+the boxes up to 64^3, forward and reverse, at every finite-difference order.  The particle step stages windows into LDS with direct-to-LDS loads: a
 wave must wait for them before the barrier after which other waves read the staged words.
 """
 import os
@@ -50,10 +50,11 @@ def kernel_meta(asm_text, name):
 
 def test_fp32_poisson_passes_use_the_matrix_cores_without_spills(tmp_path):
     asm = _compile(tmp_path, "kernels_poisson.hip")
-    # FP32 passes of boxes of 16, 32, 48 and 64 nodes (R = 1..4), forward solve, order 2
-    bodies = kernel_bodies(asm, r"k_poisson_p([13]IfLi[1-4]ELb0ELi1E|2IfLi[1-4]E)")
+    # FP32 passes of boxes of 16, 32, 48 and 64 nodes (R = 1..4): P1 and P3 of the forward
+    # solve at orders 2, 4, 6 and of the reverse solve (order 2), and P2
+    bodies = kernel_bodies(asm, r"k_poisson_p([13]IfLi[1-4]ELb[01]ELi[123]E|2IfLi[1-4]E)")
     names = sorted(bodies)
-    assert len(names) == 12, names
+    assert len(names) == 2 * 4 * 4 + 4, names
     for n in names:
         assert "v_mfma_f32_16x16x32_f16" in bodies[n], n
         meta = kernel_meta(asm, n)
