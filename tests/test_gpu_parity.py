@@ -201,12 +201,12 @@ def test_poisson_every_fft_radix(torch, precision, Np, buffer):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-@pytest.mark.parametrize("M_buffer", [(2, 8), (1, 24)])
+@pytest.mark.parametrize("M_buffer", [(2, 8, 32), (1, 24, 32), (1, 32, 64)])
 def test_one_step_from_identical_state(torch, precision, M_buffer):
+    """Boxes of 32^3, 80^3 and 128^3 (the largest admitted size)."""
     from oracle.scola import box_deposit, box_gradient, box_interpolate
-    tps, buf = M_buffer
-    say("one-step parity", precision, "tiles/side", tps, "buffer", buf)
-    Np = 32
+    tps, buf, Np = M_buffer
+    say("one-step parity", precision, "Np", Np, "tiles/side", tps, "buffer", buf)
     sim = make_sim(torch, precision, Np=Np, tps=tps, buffer=buf)
     sim.setup(torch.from_numpy(synthetic.white_noise(Np, 14)).cuda())
     xr, pr = seeded_state(sim, torch, 7, spread=2.0, pscale=0.5)
@@ -466,3 +466,25 @@ def test_determinism_and_tile_recompute(torch):
     per = make_sim(torch, "fp32", Np=Np, n_steps=3, schedule="per_tile")
     c = per.forward(w)["pos"]
     assert torch.equal(c, a)
+
+
+def test_tile_subset_refusals_and_order(torch):
+    """An empty subset, tile indices out of range and a repeated tile are refused with
+    SCOLA_EINVAL; a valid subset gives bitwise the same boxes in any order, also right after
+    a refused call."""
+    import paper_2003_04925_amd as S
+    say("tile subset refusals and order")
+    Np = 32
+    sim = make_sim(torch, "fp32", Np=Np, n_steps=3)
+    w = torch.from_numpy(synthetic.white_noise(Np, 16)).cuda()
+    a = sim.forward(w, tile_subset=[2, 5])["pos"].clone()
+    nt = len(sim.tiles)
+    for bad in ([], [-1], [nt], [5, 5]):
+        with pytest.raises(S.ScolaError) as e:
+            sim.forward(w, tile_subset=bad)
+        assert e.value.status == -1, bad
+    b = sim.forward(w, tile_subset=[5, 2])["pos"]
+    for t in (2, 5):
+        lo, n, _ = sim.tiles[t]
+        sl = (slice(None),) + tuple(slice(c, c + n) for c in lo)
+        assert torch.equal(a[sl], b[sl]), t
