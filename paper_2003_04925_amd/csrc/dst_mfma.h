@@ -266,14 +266,17 @@ __device__ __forceinline__ void plane_dst_mfma(float* plane, _Float16* buf, floa
   __syncthreads();
 }
 
-// The x pencils of one chunk of the pencil pass (fixed y, z columns z0 .. z0 + cw - 1 < z0 +
-// C, C = kPencilChunkMfma): forward DST-I along x, Phi^{lmn} = delta^{lmn} 8 / M^3 /
-// (lambda_l + lambda_m + lambda_n) (eq. Poisson_sine_space), inverse DST-I along x.  `col`
-// is the chunk's first node (x = 0, y, z0) of the box's work array; smem holds the
-// block-maximum slots (kMfmaHead), the eigenvalues (M floats), then the split lines of the C
-// columns, which the output tile (n rows of C + 1 floats) later overwrites.
+// The x pencils of one chunk of the pencil pass: the cw <= C (C = kPencilChunkMfma)
+// consecutive pencils p0 .. p0 + cw - 1 of the box's n^2 pencils, pencil p = n y + z (the
+// (y, z) column p / n, p mod n, so a chunk may span two rows): forward DST-I along x,
+// Phi^{lmn} = delta^{lmn} 8 / M^3 / (lambda_l + lambda_m + lambda_n) (eq.
+// Poisson_sine_space), inverse DST-I along x.  `col` is the chunk's first node (x = 0,
+// pencil p0) of the box's work array, where the chunk's nodes of one x plane are C
+// consecutive words; smem holds the block-maximum slots (kMfmaHead), the eigenvalues (M
+// floats), then the split lines of the C columns, which the output tile (n rows of C + 1
+// floats) later overwrites.
 template <int R>
-__device__ __forceinline__ void pencils_mfma(float* __restrict__ col, int y, int z0, int cw,
+__device__ __forceinline__ void pencils_mfma(float* __restrict__ col, int p0, int cw,
                                              const float* __restrict__ eigen,
                                              const _Float16* __restrict__ S,
                                              unsigned char* smem) {
@@ -313,7 +316,16 @@ __device__ __forceinline__ void pencils_mfma(float* __restrict__ col, int y, int
   // forward along x, then the sine-space solve
   f4 d[D::TW][LT];
   sine_times_lines<R, LT>(s, bh, bl, d);
-  const float norm = (float)(8.0 / ((double)M * M * M)), ly = ev[y];
+  const float norm = (float)(8.0 / ((double)M * M * M));
+  // lambda_m and lambda_n of the lane's column in each line tile (pencil p0 + 16 lt + l mod
+  // 16; columns beyond the chunk take index 0 and a zero factor below)
+  float ly[LT], lz[LT];
+#pragma unroll
+  for (int lt = 0; lt < LT; ++lt) {
+    const int c = 16 * lt + (l & 15), p = c < cw ? p0 + c : 0, py = p / n;
+    ly[lt] = ev[py];
+    lz[lt] = ev[p - py * n];
+  }
   float m2 = 0.0f;
 #pragma unroll
   for (int tw = 0; tw < D::TW; ++tw)
@@ -324,7 +336,7 @@ __device__ __forceinline__ void pencils_mfma(float* __restrict__ col, int y, int
         const int kx = 16 * (w + D::kWavesPerBlock * tw) + 4 * (l >> 4) + r;
         const int z = 16 * lt + (l & 15);
         const float f =
-            (kx < n && z < cw) ? norm * __builtin_amdgcn_rcpf(ev[kx] + ly + ev[z0 + z]) : 0.0f;
+            (kx < n && z < cw) ? norm * __builtin_amdgcn_rcpf(ev[kx] + ly[lt] + lz[lt]) : 0.0f;
         d[tw][lt][r] *= f;
         m2 = fmaxf(m2, fabsf(d[tw][lt][r]));
       }

@@ -779,14 +779,17 @@ __device__ __forceinline__ void poisson_p2_block(const MeshArgs<T>& a, const Blo
   const TileDesc t = a.tiles[m.tile[b]];
   constexpr int M = 16 * R, n = M - 1;
   constexpr int C = pencil_chunk<T>();
-  const int nch = (n + C - 1) / C;
-  const int y = m.local[b] / nch, ch = m.local[b] - (m.local[b] / nch) * nch;
-  const int z0 = ch * C, cw = min(C, n - z0);
   if constexpr (std::is_same<T, float>::value) {
-    pencils_mfma<R>(a.work + t.g_off + (int64_t)y * n + z0, y, z0, cw, a.eigen + t.ev_off,
+    // chunks of C consecutive pencils of the box's n^2 (only the box's last one partial)
+    const int p0 = m.local[b] * C, cw = min(C, n * n - p0);
+    pencils_mfma<R>(a.work + t.g_off + p0, p0, cw, a.eigen + t.ev_off,
                     reinterpret_cast<const _Float16*>(a.sine) + t.dm_off, smem);
     return;
   }
+  // FP64 plans: chunks of C z columns of one y row
+  const int nch = (n + C - 1) / C;
+  const int y = m.local[b] / nch, ch = m.local[b] - (m.local[b] / nch) * nch;
+  const int z0 = ch * C, cw = min(C, n - z0);
   constexpr int pitch = kPencilChunk + 1;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
   T* ev = reinterpret_cast<T*>(smem + 2 * M * sizeof(cx<T>));
