@@ -4,10 +4,9 @@
 // over the (n)^3 mesh of every box, all boxes in one launch each:
 //   P1  per x-plane: fixed-point mass -> delta, delta' = delta - Delta Phi_BCs (App. C.1),
 //       forward DST-I along z then y, in LDS;
-//   P2  per chunk of x pencils (FP32 plans: 64 consecutive (y, z) pencils of the box's n^2;
-//       FP64: 32 z columns of one y row): forward DST-I along x, division by the FDA
-//       eigenvalue sum times the inverse normalisation 8/M^3 (App. C.2, eq.
-//       Poisson_sine_space), inverse DST-I along x;
+//   P2  per chunk of consecutive x pencils of the box's n^2 (64 in FP32 plans, 32 in FP64):
+//       forward DST-I along x, division by the FDA eigenvalue sum times the inverse
+//       normalisation 8/M^3 (App. C.2, eq. Poisson_sine_space), inverse DST-I along x;
 //   P3  per x-plane: inverse DST-I along y then z, and the potential written to the padded
 //       node grid [-g, M+g]^3 with the shell filled from Phi_BCs (Sec. 3.4.2); g = 1, 2, 3
 //       ghost layers at finite-difference order 2, 4, 6 (Sec. 3), where delta' also takes

@@ -1596,13 +1596,10 @@ scola_status scola_plan_create(const scola_config* cfg, const scola_cosmology* c
         if (p->desc[t].M == p->part.class_M[c] && p->desc[t].tclass == p->part.class_tc[c])
           p->class_tiles[c].push_back((int)t);
     build_maps(p->p1, p->desc, [](const TileDesc& d) { return d.M - 1; });
-    // the pencil pass: FP32 plans take chunks of consecutive pencils of the box's (M - 1)^2,
-    // FP64 plans chunks of z columns of one y row
-    const bool is64 = p->is64;
-    build_maps(p->p2, p->desc, [is64](const TileDesc& d) {
-      const int n = d.M - 1;
-      if (is64) return n * ((n + pencil_chunk<double>() - 1) / pencil_chunk<double>());
-      return (n * n + pencil_chunk<float>() - 1) / pencil_chunk<float>();
+    // the pencil pass: chunks of consecutive pencils of the box's (M - 1)^2
+    const int chunk = p->is64 ? pencil_chunk<double>() : pencil_chunk<float>();
+    build_maps(p->p2, p->desc, [chunk](const TileDesc& d) {
+      return ((d.M - 1) * (d.M - 1) + chunk - 1) / chunk;
     });
     // the interior x planes, then the 2 (ng + 1) shell planes
     const int ng = p->ng;

@@ -748,23 +748,25 @@ __device__ __forceinline__ void poisson_p1_block(const MeshArgs<T>& a, const Blo
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) wk[e] = plane[e];
 }
 
+// The cw <= kPencilChunk x pencils p0 .. p0 + cw - 1 (pencil p = n y + z) staged in `tile`
+// (x rows of kPencilChunk + 1): forward DST-I, the sine-space solve, inverse DST-I.
 template <int R, typename T>
-__device__ __forceinline__ void pencil_solve(T* tile, int cw, int y, int z0, const T* ev,
+__device__ __forceinline__ void pencil_solve(T* tile, int cw, int p0, const T* ev,
                                              const cx<T>* tw) {
-  constexpr int M = 16 * R, pitch = kPencilChunk + 1;
+  constexpr int M = 16 * R, n = M - 1, pitch = kPencilChunk + 1;
   const int qw = threadIdx.x >> 4, l = threadIdx.x & 15;
   const T norm = T(8.0 / ((double)M * M * M));
-  const T ly = ev[y];
-  // column pair (2 qw, 2 qw + 1) of the chunk
+  // column pair (2 qw, 2 qw + 1) of the chunk, and lambda_m, lambda_n of each
   T* const la[1] = {tile + 2 * qw};
   T* const lb[1] = {tile + 2 * qw + 1};
   const bool valid[1] = {2 * qw < cw};
   const bool hb[1] = {2 * qw + 1 < cw};
-  const T lza = valid[0] ? ev[z0 + 2 * qw] : T(-1);
-  const T lzb = hb[0] ? ev[z0 + 2 * qw + 1] : T(-1);
+  const int pa = p0 + 2 * qw, pb = pa + 1, ya = pa / n, yb = pb / n;
+  const T lya = valid[0] ? ev[ya] : T(-1), lza = valid[0] ? ev[pa - ya * n] : T(-1);
+  const T lyb = hb[0] ? ev[yb] : T(-1), lzb = hb[0] ? ev[pb - yb * n] : T(-1);
   // forward DST along x, then Phi^{lmn} = delta^{lmn} 8/M^3 / (lambda_l + lambda_m + lambda_n)
-  auto sa = [&](int, int j) { return norm * recip(ev[j - 1] + ly + lza); };
-  auto sb = [&](int, int j) { return norm * recip(ev[j - 1] + ly + lzb); };
+  auto sa = [&](int, int j) { return norm * recip(ev[j - 1] + lya + lza); };
+  auto sb = [&](int, int j) { return norm * recip(ev[j - 1] + lyb + lzb); };
   dst_quarter<R, 1, pitch, T>(la, lb, valid, hb, tw, l, sa, sb);
   // the same quarter wavefront reads back only the lines it wrote
   auto one = [](int, int) { return T(1); };
@@ -779,30 +781,27 @@ __device__ __forceinline__ void poisson_p2_block(const MeshArgs<T>& a, const Blo
   const TileDesc t = a.tiles[m.tile[b]];
   constexpr int M = 16 * R, n = M - 1;
   constexpr int C = pencil_chunk<T>();
+  // chunks of C consecutive pencils of the box's n^2 (only the box's last one partial); the
+  // chunk's nodes of one x plane are C consecutive words
+  const int p0 = m.local[b] * C, cw = min(C, n * n - p0);
   if constexpr (std::is_same<T, float>::value) {
-    // chunks of C consecutive pencils of the box's n^2 (only the box's last one partial)
-    const int p0 = m.local[b] * C, cw = min(C, n * n - p0);
     pencils_mfma<R>(a.work + t.g_off + p0, p0, cw, a.eigen + t.ev_off,
                     reinterpret_cast<const _Float16*>(a.sine) + t.dm_off, smem);
     return;
   }
-  // FP64 plans: chunks of C z columns of one y row
-  const int nch = (n + C - 1) / C;
-  const int y = m.local[b] / nch, ch = m.local[b] - (m.local[b] / nch) * nch;
-  const int z0 = ch * C, cw = min(C, n - z0);
   constexpr int pitch = kPencilChunk + 1;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
   T* ev = reinterpret_cast<T*>(smem + 2 * M * sizeof(cx<T>));
   T* tile = ev + M;
   load_twiddles(tw, a, t);
   for (int i = threadIdx.x; i < n; i += blockDim.x) ev[i] = a.eigen[t.ev_off + i];
-  // thread -> (x row x0 + 8 i, z column zc): rows of 32 consecutive z, coalesced
+  // thread -> (x row x0 + 8 i, chunk column zc): rows of 32 consecutive pencils, coalesced
   static_assert(kPencilChunk == 32 && kBlock == 256, "eight rows of 32 columns per sweep");
   const int zc = threadIdx.x & 31, x0 = threadIdx.x >> 5;
   const bool zin = zc < cw;
-  // the chunk's first column (block-uniform) plus the thread's 32-bit offset; each sweep of
+  // the chunk's first pencil (block-uniform) plus the thread's 32-bit offset; each sweep of
   // eight rows adds a uniform 8 n^2
-  T* const col = a.work + t.g_off + (int64_t)y * n + z0;
+  T* const col = a.work + t.g_off + p0;
   const int lo = x0 * n * n + zc;
 #pragma unroll
   for (int i = 0; i < (n + 7) / 8; ++i) {
@@ -810,7 +809,7 @@ __device__ __forceinline__ void poisson_p2_block(const MeshArgs<T>& a, const Blo
     if (zin && x < n) tile[x * pitch + zc] = (col + (int64_t)8 * i * n * n)[lo];
   }
   __syncthreads();
-  pencil_solve<R, T>(tile, cw, y, z0, ev, tw);
+  pencil_solve<R, T>(tile, cw, p0, ev, tw);
 #pragma unroll
   for (int i = 0; i < (n + 7) / 8; ++i) {
     const int x = x0 + 8 * i;
