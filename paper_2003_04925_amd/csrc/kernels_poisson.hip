@@ -73,35 +73,33 @@ k_poisson_p3(MeshArgs<T> a, BlockMap m) {
 }  // namespace
 
 // Dynamic LDS of each pass for boxes of M nodes: FP64 plans the 2M twiddles, then P1 the
-// (M-1)^2 plane, P2 the M eigenvalues and an (M-1) x 33 pencil tile, P3 the plane with its
-// padded border ((M + 1 + 2 ng)^2 for ng ghost layers); FP32 plans the block-maximum slots,
-// then the plane region (the plane or the split lines aliasing it), P2 the eigenvalues and
-// the chunk's split lines aliased by its output tile; P3 also the perimeter terms it hands
-// on.  Sized per M and per pass, so small boxes keep more blocks per CU.
+// (M-1)^2 plane, P2 the M eigenvalues and an (M-1) x 33 pencil tile, P3 the plane and the
+// perimeter terms it hands on; FP32 plans the block-maximum slots, then the plane region
+// (the plane or the split lines aliasing it, whose tail beyond the plane holds P3's
+// perimeter terms before the transform), P2 the eigenvalues and the chunk's split lines
+// aliased by its output tile.  P3 holds the padded plane's border in registers.  Sized per
+// M and per pass, so small boxes keep more blocks per CU.
 template <typename T>
 size_t poisson_lds_bytes(int M, int pass, int ng) {
+  (void)ng;
   const size_t n = (size_t)M - 1, tw = 2 * (size_t)M * sizeof(cx<T>);
-  const size_t Mp = (size_t)M + 1 + 2 * (size_t)ng;
-  // P3: the perimeter terms it hands to the next solve's P1, 8-byte aligned behind the border
+  // P3: the perimeter terms it hands to the next solve's P1, 8-byte aligned behind the plane
   const size_t terms = 8 + 4 * (n - 1) * sizeof(double);
   if (std::is_same<T, float>::value) {
     // matrix-core transforms: block-maximum slots, then the plane region (the plane or the
     // split lines that alias it); P2: the eigenvalues, then the split lines of the chunk's
-    // 32 columns aliased by the output tile; P3: the border values behind the plane region
+    // columns aliased by the output tile
     const int R = M / 16;
     const size_t region = std::max(n * n * sizeof(float), mfma_split_bytes(R));
-    if (pass == 1) return kMfmaHead + region;
-    if (pass == 2) {
-      const size_t lines =
-          (size_t)kPencilChunkMfma * (32 * ((R + 1) / 2) + 8) * 2 * sizeof(_Float16);
-      return kMfmaHead + (size_t)M * sizeof(float) +
-             std::max(n * (kPencilChunkMfma + 1) * sizeof(float), lines);
-    }
-    return kMfmaHead + region + (Mp * Mp - n * n) * sizeof(float) + terms;
+    if (pass == 1 || pass == 3) return kMfmaHead + region;
+    const size_t lines =
+        (size_t)kPencilChunkMfma * (32 * ((R + 1) / 2) + 8) * 2 * sizeof(_Float16);
+    return kMfmaHead + (size_t)M * sizeof(float) +
+           std::max(n * (kPencilChunkMfma + 1) * sizeof(float), lines);
   }
   if (pass == 1) return tw + n * n * sizeof(T);
   if (pass == 2) return tw + ((size_t)M + n * (kPencilChunk + 1)) * sizeof(T);
-  return tw + Mp * Mp * sizeof(T) + terms;
+  return tw + n * n * sizeof(T) + terms;
 }
 
 namespace {

@@ -854,14 +854,12 @@ __device__ __forceinline__ void poisson_p3_block(const MeshArgs<T>& a, const Blo
   const int64_t base = t.g_off + (int64_t)x * n * n;
   const int A = x + 1 + NG;
   // the padded plane's border (NG + 1 layers on each side) takes D1 Phi_BC^0: those values
-  // are fetched first so that their latency overlaps the load of the plane.  Border
-  // element i: rows 0..NG and M+NG..M+2NG whole, then columns 0..NG and M+NG..M+2NG of the
-  // rows in between.
+  // are fetched first so that their latency overlaps the load of the plane, and held in
+  // registers until the plane is written.  Border element i: rows 0..NG and M+NG..M+2NG
+  // whole, then columns 0..NG and M+NG..M+2NG of the rows in between.
   constexpr int kBorder = Mp * Mp - n * n;
   constexpr int kPerThread = (kBorder + kBlock - 1) / kBlock;
   constexpr int kW = 2 * (NG + 1);   // border rows, and border columns per inner row
-  // the border values, staged in LDS behind the plane region
-  T* border = plane + plane_region_elems<T, R>();
   auto border_offset = [](int i) {
     int B, C;
     if (i < kW * Mp) {
@@ -910,26 +908,40 @@ __device__ __forceinline__ void poisson_p3_block(const MeshArgs<T>& a, const Blo
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) plane[e] = wk[e];
   // order 2, evolution: the first pass of the next solve takes this plane's perimeter terms
   // (the same padded plane A's face-layer values, which bval holds) from its `work` plane;
-  // they are summed in LDS behind the border in the first pass's order (the y face, then
-  // the z face), one writer per term in each of two phases around the barrier below
+  // they are summed in LDS right behind the n x n plane (for FP32 plans inside the region
+  // that the transform's split lines take later) in the first pass's order (the y face,
+  // then the z face), one writer per term in each of two phases around the barrier below,
+  // and stored before the transform
   const bool hand_out = NG == 1 && !ADJ && (a.bc_handoff & 2) != 0;
-  double* const pacc = handoff_terms(border + kBorder);
+  double* const pacc = handoff_terms(plane + n * n);
+  static_assert(!std::is_same<T, float>::value ||
+                    (plane_region_elems<T, R>() - (size_t)n * n) * sizeof(float) >=
+                        8 + 4 * (size_t)(n - 1) * sizeof(double),
+                "the perimeter terms fit behind the plane in the FP32 region");
+  T bv[kPerThread];
+#pragma unroll
+  for (int q = 0; q < kPerThread; ++q) bv[q] = T(0);
   if constexpr (!ADJ) {
 #pragma unroll
     for (int q = 0; q < kPerThread; ++q) {
       const int i = q * kBlock + threadIdx.x;
-      if (i < kBorder) border[i] = (T)(D1 * bval[q]);
+      if (i < kBorder) bv[q] = (T)(D1 * bval[q]);
       // rows B = 1 and B = M + 1: the y faces of interior rows y = 0 and y = n - 1
       if (hand_out && i >= Mp && i < 3 * Mp) {
         const int C = i - (i >= 2 * Mp ? 2 * Mp : Mp);
         if (C >= 2 && C <= M) pacc[perimeter_index(i < 2 * Mp ? 0 : n - 1, C - 2, n)] = bval[q];
       }
     }
-    if (a.ov_phi)
-      for (int i = threadIdx.x; i < kBorder; i += blockDim.x) {
-        const int o = border_offset(i);
-        border[i] = full_at(a.ov_phi, a.ov_N, t, A - NG, o / Mp - NG, o - (o / Mp) * Mp - NG);
+    if (a.ov_phi) {
+#pragma unroll
+      for (int q = 0; q < kPerThread; ++q) {
+        const int i = q * kBlock + threadIdx.x;
+        if (i < kBorder) {
+          const int o = border_offset(i);
+          bv[q] = full_at(a.ov_phi, a.ov_N, t, A - NG, o / Mp - NG, o - (o / Mp) * Mp - NG);
+        }
       }
+    }
   }
   __syncthreads();
   if (hand_out) {
@@ -946,13 +958,13 @@ __device__ __forceinline__ void poisson_p3_block(const MeshArgs<T>& a, const Blo
         }
       }
     }
-  }
-  plane_transform<T, R>(plane, smem, op);
-  if (hand_out) {
-    // the work plane was read into LDS before the barriers of the transform
+    __syncthreads();
+    // every thread's loads of the work plane ended before the barrier above; the
+    // transform's first barrier orders these reads of pacc before its split lines
     double* const out = handoff_terms(a.work + base);
     for (int i = threadIdx.x; i < 4 * (n - 1); i += blockDim.x) out[i] = pacc[i];
   }
+  plane_transform<T, R>(plane, smem, op);
   if constexpr (ADJ) {
     // lam_rho = lam_delta', and the plane of `work` is cleared (the next reverse step
     // accumulates into a zeroed source)
@@ -998,7 +1010,11 @@ __device__ __forceinline__ void poisson_p3_block(const MeshArgs<T>& a, const Blo
     const int y = e / n, z = e - (e / n) * n;
     out[(y + 1 + NG) * Mp + z + 1 + NG] = plane[e];
   }
-  for (int i = threadIdx.x; i < kBorder; i += blockDim.x) out[border_offset(i)] = border[i];
+#pragma unroll
+  for (int q = 0; q < kPerThread; ++q) {
+    const int i = q * kBlock + threadIdx.x;
+    if (i < kBorder) out[border_offset(i)] = bv[q];
+  }
 }
 
 }  // namespace
